@@ -1,0 +1,175 @@
+"""Pins for the oracle's discrete operator A, its adjoint, the multilayer
+reflection chain and the preconditioner.
+
+* closed form of curl curl on a single 3-D Fourier mode;
+* curl curl annihilates gradients built with an explicit D_z matrix (PML on);
+* hermiticity of A when PML, loss and multilayer are off;
+* matrix-free A equals A assembled from explicit DFT matrices;
+* the discrete R_ml applied to the sampled incident wave equals the analytic
+  reflected background;
+* <u, A v> = <A^H u, v>;
+* the damping multiplier reduces to min(1, k_bg^2/k^2) with the baseline
+  parameters, and M = I when m_min = 1.
+"""
+
+import numpy as np
+import pytest
+
+from oracle import psfd_ref as R
+from psfd_synth import random_field
+
+from conftest import small_cfg
+
+
+def _uniform_problem(nx, ny, nz, eps_val, theta=9.0, phi=35.0):
+    cfg = small_cfg(nx=nx, ny=ny, nz_abs=nz, t_abs=nz * 1.5, theta_deg=theta, phi_deg=phi,
+                    pml=False, ml=False, nz_pml=0, nz_gap=0)
+    return R.Problem(cfg, np.full((nz, ny, nx), eps_val, np.complex128))
+
+
+def test_single_mode_closed_form(rng):
+    """Paper, equation vector_helmholtz_operator: on e exp(i k.r) the operator
+    is (|k|^2 I - k k^T - k0^2 eps) e."""
+    nx, ny, nz = 6, 5, 8
+    eps_val = 0.9 + 0.07j
+    P = _uniform_problem(nx, ny, nz, eps_val)
+    g = P.g
+    for (l, n, m) in [(1, 2, 3), (7, 4, 5), (4, 0, 0), (3, 3, 1)]:  # fftfreq indices
+        e = rng.standard_normal(3) + 1j * rng.standard_normal(3)
+        jz, jy, jx = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+        wave = np.exp(2j * np.pi * (l * jz / nz + n * jy / ny + m * jx / nx))
+        x = e[:, None, None, None] * wave[None]
+        k = np.array([g.kx[m], g.ky[n], g.kz[l]])
+        Mk = (k @ k) * np.eye(3) - np.outer(k, k) - g.k0 ** 2 * eps_val * np.eye(3)
+        expect = (Mk @ e)[:, None, None, None] * wave[None]
+        y = R.apply_A(P, x)
+        scale = np.abs(Mk).max() * np.abs(e).max()
+        assert np.abs(y - expect).max() <= 1e-13 * scale
+
+
+def _explicit_dz(g):
+    nz = g.nz
+    j = np.arange(nz)
+    F = np.exp(-2j * np.pi * np.outer(j, j) / nz)
+    return np.diag(1 / g.s) @ (np.conj(F).T / nz) @ np.diag(1j * g.kz) @ F
+
+
+def test_curlcurl_annihilates_gradients(rng):
+    """curl curl grad phi = 0 with PML-stretched axial derivatives."""
+    cfg = small_cfg(nx=6, ny=4, nz_abs=4, ml=False)
+    P = R.Problem(cfg, np.full((4, 4, 6), 1.0 + 0j))   # eps = eps_bg: A = curl curl - kbg^2
+    g = P.g
+    phi = random_field((g.nz, g.ny, g.nx), rng)
+    Ph = np.fft.fft2(phi)
+    Dz = _explicit_dz(g)
+    gx = np.fft.ifft2(1j * g.kx[None, None, :] * Ph)
+    gy = np.fft.ifft2(1j * g.ky[None, :, None] * Ph)
+    gz = np.einsum("ij,jkl->ikl", Dz, phi)
+    grad = np.stack([gx, gy, gz])
+    y = R.apply_A(P, grad) + g.kbg ** 2 * grad
+    kmax2 = (np.abs(g.kx).max() ** 2 + np.abs(g.ky).max() ** 2 + np.abs(g.kz).max() ** 2)
+    assert np.linalg.norm(y) <= 1e-12 * kmax2 * np.linalg.norm(grad)
+
+
+def test_hermitian_without_pml_loss_multilayer(rng):
+    cfg = small_cfg(nx=4, ny=3, nz_abs=3, pml=False, ml=False, theta_deg=11.0)
+    a = rng.uniform(0, 1, (3, 4))
+    eps = R.eps_from_fill(cfg, a, 0.8 + 0j)
+    P = R.Problem(cfg, eps)
+    A = R.dense_by_columns(P)
+    assert np.abs(A - A.conj().T).max() <= 1e-13 * np.abs(A).max()
+
+
+@pytest.mark.parametrize("pol", [0, 1])
+def test_matrix_free_equals_kronecker(rng, pol):
+    cfg = small_cfg(nx=4, ny=3, nz_abs=3, pol=pol)
+    eps = 1.0 + rng.uniform(-0.2, 0.1, (3, 3, 4)) + 1j * rng.uniform(0, 0.1, (3, 3, 4))
+    P = R.Problem(cfg, eps)
+    A1 = R.dense_by_columns(P)
+    A2 = R.dense_kronecker(P)
+    assert np.abs(A1 - A2).max() <= 1e-12 * np.abs(A2).max()
+
+
+@pytest.mark.parametrize("pol", [0, 1])
+def test_discrete_ml_chain_matches_analytic_background(pol):
+    """R_ml applied to the grid-sampled incident wave (an exactly representable
+    single lateral mode) gives the analytic reflected background."""
+    cfg = small_cfg(nx=6, ny=4, nz_abs=5, pol=pol, theta_deg=8.0, phi_deg=30.0)
+    P = R.Problem(cfg, np.full((5, 4, 6), 0.9 + 0.05j))
+    g = P.g
+    e_in, _ = R.incident_vectors(g, pol)
+    inc = e_in[:, None] * np.exp(-1j * g.kz0 * g.z)[None, :]
+    x = np.broadcast_to(inc[:, :, None, None], g.shape).astype(np.complex128)
+    V = R.ml_field_hat(g, P.basis, P.r_te, P.r_pe, R.fft2(x)[0:2, g.j_ev], g.abs_rows)
+    e_ml = R.ifft2(V)
+    expect = R.background_field(g, cfg, g.abs_rows) - inc[:, g.abs_rows]
+    np.testing.assert_allclose(e_ml, np.broadcast_to(expect[:, :, None, None], e_ml.shape),
+                               rtol=0, atol=1e-13)
+
+
+@pytest.mark.parametrize("pol", [0, 1])
+def test_adjoint_inner_product(rng, pol):
+    cfg = small_cfg(nx=6, ny=4, nz_abs=4, pol=pol)
+    eps = 0.9 + rng.uniform(-0.1, 0.1, (4, 4, 6)) + 1j * rng.uniform(0, 0.08, (4, 4, 6))
+    P = R.Problem(cfg, eps)
+    u = random_field(P.g.shape, rng)
+    v = random_field(P.g.shape, rng)
+    lhs = np.vdot(u, R.apply_A(P, v))
+    rhs = np.vdot(R.apply_AH(P, u), v)
+    scale = np.linalg.norm(u) * np.linalg.norm(R.apply_A(P, v))
+    assert abs(lhs - rhs) <= 1e-13 * scale
+
+
+def test_adjoint_dense_is_conjugate_transpose(rng):
+    cfg = small_cfg(nx=3, ny=2, nz_abs=2, pol=1)
+    eps = 0.9 + 1j * rng.uniform(0, 0.1, (2, 2, 3))
+    P = R.Problem(cfg, eps)
+    A = R.dense_by_columns(P)
+    AH = R.dense_by_columns(P, lambda u: R.apply_AH(P, u))
+    assert np.abs(AH - A.conj().T).max() <= 1e-12 * np.abs(A).max()
+
+
+def test_damping_baseline_reduces_to_min():
+    """Paper: m_min = 0, gamma = 1, reg -> 0, k_ref = k_bg gives min(1, k_bg^2/k^2)."""
+    kbg = 2 * np.pi / 13.5
+    k2 = np.linspace(0, 40 * kbg * kbg, 1001)
+    m = R.damping_multiplier(k2, kbg, 0.0, 1.0, 0.0)
+    with np.errstate(divide="ignore"):
+        ref = np.minimum(1.0, kbg * kbg / k2)
+    np.testing.assert_allclose(m, ref, rtol=1e-15, atol=0)
+
+
+def test_damping_floor_and_exponent():
+    kref = 0.5
+    k2 = np.array([0.0, 0.25, 1.0, 4.0])
+    m = R.damping_multiplier(k2, kref, 0.1, 2.0, 0.0)
+    np.testing.assert_allclose(m, [1.0, 1.0, 0.1 + 0.9 * (0.25 / 1.0) ** 2, 0.1 + 0.9 * (0.25 / 4.0) ** 2])
+    assert np.all(R.damping_multiplier(k2, kref, 1.0, 3.0, 0.0) == 1.0)
+
+
+def test_preconditioner_identity_and_single_mode(rng):
+    cfg = small_cfg(nx=6, ny=4, nz_abs=4)
+    P = R.Problem(cfg, np.full((4, 4, 6), 0.9 + 0.05j))
+    g = P.g
+    x = random_field(g.shape, rng)
+    cfg1 = dict(cfg, pc_mmin=1.0)
+    np.testing.assert_allclose(R.apply_M(R.Problem(cfg1, np.full((4, 4, 6), 1.0 + 0j)), x), x,
+                               rtol=0, atol=1e-14 * np.abs(x).max())
+    l, n, m = 5, 3, 2
+    jz, jy, jx = np.meshgrid(np.arange(g.nz), np.arange(g.ny), np.arange(g.nx), indexing="ij")
+    wave = np.exp(2j * np.pi * (l * jz / g.nz + n * jy / g.ny + m * jx / g.nx))
+    k2 = g.kx[m] ** 2 + g.ky[n] ** 2 + g.kz[l] ** 2
+    mk = min(1.0, g.kbg ** 2 / k2)
+    y = R.apply_M(P, np.stack([wave, 2 * wave, -wave]))
+    np.testing.assert_allclose(y, mk * np.stack([wave, 2 * wave, -wave]), rtol=0, atol=1e-14)
+
+
+def test_smoothing_single_mode_and_constant():
+    cfg = small_cfg(nx=16, ny=8)
+    jy, jx = np.meshgrid(np.arange(8), np.arange(16), indexing="ij")
+    a = 0.5 + 0.4 * np.cos(2 * np.pi * 3 * jx / 16)
+    kx = 2 * np.pi * 3 / (16 * cfg["dx"])
+    sig = cfg["smooth_sigma"] * cfg["dx"]
+    expect = 0.5 + 0.4 * np.exp(-0.5 * sig * sig * kx * kx) * np.cos(2 * np.pi * 3 * jx / 16)
+    np.testing.assert_allclose(R.smooth_layout(cfg, a), expect, atol=1e-15)
+    np.testing.assert_allclose(R.smooth_layout(cfg, np.ones((8, 16))), 1.0, atol=1e-15)
