@@ -1,0 +1,187 @@
+/*
+ * psfd.h -- C ABI of the MI355X PSFD solver library (libpsfd.so).
+ *
+ * The library solves the background-decomposed, right-preconditioned
+ * pseudo-spectral frequency-domain (PSFD) full-vector scattering equations
+ * of an EUV mask absorber above a multilayer mirror:
+ *
+ *     A E = b,   A = curl curl - k0^2 eps - k0^2 d_eps R_ml,
+ *     b = k0^2 d_eps (E_inc + R_ml E_inc)
+ *
+ * (paper: section 2.2, equations vector_helmholtz_operator and bg_source,
+ * and the definition of the multilayer reflection operator R_ml), with
+ * BiCGSTAB, the spectral damping right preconditioner M and the affine warm
+ * start E = E_base + M y (Results, "PINO warm-start" paragraph, equations
+ * spectral_damping_action, spectral_damping_mask, right_preconditioned,
+ * right_correction_solution, right_preconditioned_system,
+ * relative_residual).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Grid.  Axial rows from the bottom: nz_pml PML | nz_gap_bot gap |
+ *   nz_abs absorber | nz_gap_top gap | nz_pml PML;
+ *   Nz = nz_abs + nz_gap_bot + nz_gap_top + 2 nz_pml.  Rows are
+ *   cell-centred, z = 0 is the absorber's bottom face (the multilayer
+ *   interface), the z axis is periodic.  Lateral grid nx x ny, periodic,
+ *   with Bloch-shifted wavenumbers for oblique incidence.
+ * Field layout.  Structure of arrays [3][Nz][ny][nx] (component x, y, z;
+ *   then row; then y; x fastest), each element an interleaved complex pair
+ *   (re, im).  Element type complex128 (two doubles) unless an entry point
+ *   says complex64.
+ * Memory.  Every field pointer is a caller-owned DEVICE pointer on the
+ *   device current when the plan was made, 16-byte aligned (8-byte for
+ *   complex64).  Inputs and outputs must not overlap unless stated.  The
+ *   plan owns its workspace.  Host pointers appear only inside psfd_desc
+ *   (the multilayer tables) and for psfd_info.
+ * Streams.  Work is enqueued on the HIP stream given to psfd_plan (NULL =
+ *   the default stream).  Calls are asynchronous unless stated otherwise;
+ *   psfd_solve synchronises the stream to test convergence.
+ * Errors.  No exception crosses the ABI.  A non-zero psfd_status is
+ *   returned and psfd_last_error() gives a message (thread-local).  Invalid
+ *   arguments return PSFD_ERR_ARG before any buffer is touched.
+ * Threads.  A plan may be used by one host thread at a time.
+ */
+#ifndef PSFD_H
+#define PSFD_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct psfd_plan* psfd_plan_t;
+
+typedef enum {
+  PSFD_OK = 0,
+  PSFD_ERR_ARG = 1,        /* invalid argument or unsupported size          */
+  PSFD_ERR_ALLOC = 2,      /* device allocation failed                      */
+  PSFD_ERR_HIP = 3,        /* a HIP runtime call or kernel launch failed    */
+  PSFD_NOT_CONVERGED = 4,  /* maxit reached before the tolerance            */
+  PSFD_BREAKDOWN = 5       /* BiCGSTAB broke down and restarts were used up */
+} psfd_status;
+
+typedef enum {
+  PSFD_C128 = 0,              /* complex128 everywhere                                  */
+  PSFD_C64_REFINE64 = 1,      /* complex64 operator/preconditioner/Krylov vectors,
+                                 FP64 true residual and refinement updates              */
+  PSFD_C64_BF16PC_REFINE64 = 2 /* as 1, preconditioner multiplier rounded to bfloat16   */
+} psfd_precision;
+
+/* Plan descriptor.  Lengths in nm, angles in radians.
+ * Supported sizes: nx, ny in {16, 32, 64, 128, 192, 256, 512, 1024};
+ * Nz in {24, 32, 48, 64, 96, 128}; nz_abs >= 1; nz_gap_bot >= 1 (the
+ * evaluation row of the multilayer split is the last bottom-gap row). */
+typedef struct {
+  int32_t nx, ny, nz_abs, nz_gap_bot, nz_gap_top, nz_pml;
+  double dx, dy, dz, lambda;
+  double theta, phi;             /* incidence polar / azimuth angle               */
+  int32_t pol;                   /* 0 = TE (s), 1 = TM (p)                        */
+  double eps_bg;                 /* real background permittivity of the domain   */
+  int32_t n_ml;                  /* number of multilayer layers (may be 0)       */
+  const double* ml_eps;          /* host, [n_ml][2] complex permittivity, top->bottom */
+  const double* ml_thick;        /* host, [n_ml] thickness                        */
+  double eps_sub[2];             /* substrate permittivity (complex)             */
+  double pml_sigma0;             /* PML stretch s = 1 + i sigma0 (d/D)^order      */
+  int32_t pml_order;
+  int32_t precond;               /* 0 = none, 1 = spectral damping M              */
+  double pc_mmin, pc_kref, pc_gamma, pc_reg; /* m(k) parameters; pc_kref <= 0 -> k0 sqrt(eps_bg) */
+  int32_t prec;                  /* psfd_precision                                */
+} psfd_desc;
+
+typedef struct {
+  int32_t iters;        /* BiCGSTAB iterations (one = two operator applies)          */
+  int32_t status;       /* psfd_status of the solve                                  */
+  int32_t restarts;     /* residual replacements / refinement steps taken           */
+  int32_t applies;      /* operator applies in the working precision                 */
+  double rrel_true;     /* ||b - A E|| / ||b|| recomputed in FP64 at exit            */
+  double rrel_hist_last;/* last recursive residual seen by the Krylov loop           */
+} psfd_info;
+
+/* Gaussian smoothing of a binary layout and material map (paper, section
+ * 2.1 closing paragraphs and Results, "PINO surrogate": the binary indicator
+ * is Gaussian-smoothed on the grid, and the same smoothing is applied to the
+ * structure of the rigorous PSFD solve).
+ *   a_bin_dev  device, [ny][nx] double, values in {0, 1}
+ *   eps_abs    absorber permittivity (re, im)
+ *   sigma      smoothing width in lateral cells
+ *   eps_out    device, [nz_abs][ny][nx] complex128: eps = eps_bg + a (eps_abs - eps_bg),
+ *              a = clip(periodic Gaussian smoothing of a_bin, 0, 1), same on every row.
+ * Uses d->nx, ny, nz_abs, dx, dy, eps_bg only.  Allocates and frees a
+ * temporary workspace and synchronises the stream. */
+psfd_status psfd_layout_eps(const psfd_desc* d, const double* a_bin_dev, const double eps_abs[2],
+                            double sigma, void* eps_out, void* hip_stream);
+
+/* Build a plan (paper, section 2.2: lateral Bloch wavenumbers, PML stretch,
+ * per-mode multilayer reflections r_TE and r_pE by the transfer-matrix
+ * method, permittivity contrast).  eps_abs_dev: device, [nz_abs][ny][nx]
+ * complex128 permittivity on absorber rows (copied; the caller may free it).
+ * The multilayer tables in d are copied.  The TMM runs on the device. */
+psfd_status psfd_plan(const psfd_desc* d, const void* eps_abs_dev, void* hip_stream,
+                      psfd_plan_t* out);
+
+/* Replace the permittivity of an existing plan (same sizes).  eps_abs_dev as
+ * in psfd_plan.  Used for gradient checks and design loops. */
+psfd_status psfd_set_eps(psfd_plan_t p, const void* eps_abs_dev);
+
+/* b = k0^2 d_eps (E_inc + R_ml E_inc) (equation bg_source): incident plane
+ * wave of unit amplitude, phase 0 at x = 0, z = 0, and its analytic
+ * multilayer reflection.  b: device [3][Nz][ny][nx] complex128 (zero outside
+ * absorber rows). */
+psfd_status psfd_rhs(psfd_plan_t p, void* b);
+
+/* y = A x (equation vector_helmholtz_operator with R_ml inside the operator:
+ * lateral FFTs, axial pseudo-spectral derivatives with PML stretching,
+ * curl curl, -k0^2 eps, and -k0^2 d_eps times the reflected multilayer field
+ * of x).  x, y: device [3][Nz][ny][nx] complex128, must not overlap. */
+psfd_status psfd_apply(psfd_plan_t p, const void* x, void* y);
+
+/* y = A^H x (adjoint for the inner product sum conj(u) v over the grid). */
+psfd_status psfd_adjoint(psfd_plan_t p, const void* x, void* y);
+
+/* y = M x: per component F3^-1[m(k) F3 x] (equations spectral_damping_action
+ * and spectral_damping_mask, |k| from the Bloch-shifted wavenumbers).  M is
+ * Hermitian.  Applied regardless of d->precond. */
+psfd_status psfd_precond(psfd_plan_t p, const void* x, void* y);
+
+/* complex64 variants of apply / adjoint / precond (single-precision
+ * kernels).  x, y: device [3][Nz][ny][nx] complex64. */
+psfd_status psfd_apply_c64(psfd_plan_t p, const void* x, void* y);
+psfd_status psfd_adjoint_c64(psfd_plan_t p, const void* x, void* y);
+psfd_status psfd_precond_c64(psfd_plan_t p, const void* x, void* y);
+
+/* Solve A E = b (adjoint = 0) or A^H E = b (adjoint = 1) by right-
+ * preconditioned BiCGSTAB with the affine warm start E = x0 + M y,
+ * A M y = b - A x0 (equations right_correction_solution and
+ * right_preconditioned_system), stopping when the FP64 true relative
+ * residual ||b - A E|| / ||b|| (equation relative_residual) is <= tol.
+ *   b      device complex128 field, or NULL for the analytic source psfd_rhs
+ *   x0     device complex128 field, or NULL for E_base = 0
+ *   E      device complex128 field (output; may alias x0)
+ *   maxit  iteration cap (one iteration = two operator applies)
+ *   info   host, optional (may be NULL)
+ * ||b|| = 0 gives E = 0, iters = 0, PSFD_OK.  For PSFD_C64_* plans the
+ * Krylov iteration runs in complex64 inside an FP64 iterative-refinement
+ * loop.  Returns PSFD_NOT_CONVERGED / PSFD_BREAKDOWN when the tolerance was
+ * not reached (E then holds the best iterate).  Synchronises the stream. */
+psfd_status psfd_solve(psfd_plan_t p, const void* b, const void* x0, void* E, double tol,
+                       int32_t maxit, int32_t adjoint, psfd_info* info);
+
+/* Copy the plan's per-mode multilayer reflections (transfer-matrix method,
+ * paper section 2.2 step (iii)): r_te, r_pe device [ny][nx] complex128.
+ * r_pe is the tangential-electric-field TM coefficient. */
+psfd_status psfd_ml_reflection(psfd_plan_t p, void* r_te, void* r_pe);
+
+/* Total number of complex elements of one field, 3 * Nz * ny * nx. */
+int64_t psfd_field_size(psfd_plan_t p);
+
+void psfd_destroy(psfd_plan_t p);
+
+/* Message of the last error on this thread ("" if none). */
+const char* psfd_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PSFD_H */

@@ -1,0 +1,321 @@
+// Axial column kernel: everything the operator does along z for one lateral
+// Fourier mode (kx, ky), fused in one pass over the lateral spectrum.
+//
+// Input S holds the lateral Fourier coefficients X(kx, ky, z) of the three
+// components.  With D = diag(1/s) G, G = F_z^-1 diag(i kz) F_z (PML-stretched
+// pseudo-spectral d/dz), curl curl per mode is
+//   Ux = ky^2 Px - kx ky Py + D(-D Px + i kx Pz)
+//   Uy = -kx ky Px + kx^2 Py + D(-D Py + i ky Pz)
+//   Uz = i kx D Px + i ky D Py + kt^2 Pz
+// (the operator matrix of the paper's vector Helmholtz equation written as
+// curl of curl, four G applications per column), minus kbg^2 P.  P = X for
+// the plain operator and P = M X for the fused operator-times-preconditioner
+// (F_z, multiply by the damping m(k), and the D of P shares that forward
+// transform).  The multilayer branch takes the tangential P at the
+// evaluation row (purely downgoing there), projects it on the TE/TM basis,
+// multiplies by r_TE / r_pE and propagates it up to the absorber rows:
+//   W = P + E_ML on absorber rows,  so that  y = F2^-1[U] - k0^2 d_eps F2^-1[W].
+// The adjoint replaces D by -D^H = G diag(1/conj(s)) and the multilayer
+// branch by its adjoint applied to F2[conj(k0^2 d_eps) x] (extra input planes),
+// which lands on the evaluation row.
+#include "fft_core.h"
+#include "psfd_internal.h"
+
+namespace psfd {
+
+bool axial_size_ok(int n) {
+  switch (n) {
+    case 24: case 32: case 48: case 64: case 96: case 128: return true;
+    default: return false;
+  }
+}
+
+template <typename T>
+struct ColInfo {
+  T kx, ky, kt2, sx, sy, tx, ty;
+  T kzr, kzi;          // background axial wavenumber kzr + i kzi (one of them is 0)
+  cplx<T> ktkz, down;  // kt / kz,  exp(-i kz dz / 2)
+  cplx<T> rte, rpe;
+  cplx<T> a0, a1;      // forward: upgoing (TE, TM) amplitudes; adjoint: evaluation-row terms
+  int live;
+};
+
+__device__ __forceinline__ float round_bf16(float x) {
+  unsigned u = __float_as_uint(x);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return __uint_as_float(u & 0xFFFF0000u);
+}
+__device__ __forceinline__ double round_bf16(double x) { return (double)round_bf16((float)x); }
+
+template <typename T>
+__device__ __forceinline__ T damping(T k2, const OpTables<T>& t) {
+  T core = T(1);
+  if (k2 > t.pc_kref2) {
+    const T q = t.pc_kref2 / (k2 + t.pc_reg);
+    core = (t.pc_gamma == T(1)) ? q : pow(q, t.pc_gamma);
+  }
+  T m = t.pc_mmin + (T(1) - t.pc_mmin) * core;
+  if (t.pc_bf16) m = round_bf16(m);
+  return m;
+}
+
+// exp(i kz z) for kz = kzr + i kzi
+template <typename T>
+__device__ __forceinline__ cplx<T> up_phase(const ColInfo<T>& c, T z) {
+  T s, co;
+  sc(c.kzr * z, &s, &co);
+  const T m = exp(-c.kzi * z);
+  return {m * co, m * s};
+}
+
+template <typename T>
+__device__ void column_info(ColInfo<T>& c, const OpTables<T>& t, int ix, int iy) {
+  c.kx = t.kx[ix];
+  c.ky = t.ky[iy];
+  c.kt2 = c.kx * c.kx + c.ky * c.ky;
+  const T kt = sqrt(c.kt2);
+  if (kt == T(0)) {
+    c.sx = -t.sphi; c.sy = t.cphi; c.tx = t.cphi; c.ty = t.sphi;
+  } else {
+    c.sx = -c.ky / kt; c.sy = c.kx / kt; c.tx = c.kx / kt; c.ty = c.ky / kt;
+  }
+  const T q2 = t.kbg2 - c.kt2;
+  if (q2 >= T(0)) { c.kzr = sqrt(q2); c.kzi = T(0); }
+  else { c.kzr = T(0); c.kzi = sqrt(-q2); }
+  const T kzabs = c.kzr + c.kzi;
+  c.live = kzabs >= T(1e-9) * t.k0;
+  if (!c.live) c.ktkz = {T(0), T(0)};
+  else if (c.kzi == T(0)) c.ktkz = {kt / c.kzr, T(0)};
+  else c.ktkz = {T(0), -kt / c.kzi};
+  const T h = T(0.5) * t.dz;
+  T s, co;
+  sc(c.kzr * h, &s, &co);
+  const T m = exp(c.kzi * h);
+  c.down = {m * co, -m * s};
+  const int64_t mode = (int64_t)iy * t.nx + ix;
+  c.rte = t.r_te[mode];
+  c.rpe = t.r_pe[mode];
+}
+
+template <typename T, int NZ>
+constexpr int ax_tile() {
+  int tx = sizeof(T) == 8 ? 8 : 16;
+  while (tx > 1 && 5 * NZ * tx * (int)sizeof(cplx<T>) > 65536) tx /= 2;
+  return tx;
+}
+
+template <typename T, int NZ, int TX, int MODE>
+__global__ void __launch_bounds__(256)
+k_axial(const cplx<T>* __restrict__ S, cplx<T>* __restrict__ UW, const OpTables<T> t) {
+  if (t.skip && *t.skip) return;
+  constexpr int NT = 256;
+  constexpr int PITCH = TX;
+  constexpr int VS = NZ * PITCH;
+  constexpr int NV = (MODE == AX_M) ? 3 : 5;
+  using Addr = AddrVec<TX, PITCH, VS>;
+  __shared__ cplx<T> buf[NV * VS];
+  __shared__ ColInfo<T> ci[TX];
+
+  const int tid = threadIdx.x;
+  const int iy = blockIdx.y;
+  const int kx0 = blockIdx.x * TX;
+  const int64_t plane = (int64_t)t.nx * t.ny;
+  const int64_t colbase = (int64_t)iy * t.nx + kx0;
+  const T inz = T(1) / T(NZ);
+
+  for (int e = tid; e < 3 * NZ * TX; e += NT) {
+    const int c = e / (NZ * TX), rem = e % (NZ * TX);
+    const int z = rem / TX, cc = rem % TX;
+    buf[c * VS + z * PITCH + cc] = S[(int64_t)(c * NZ + z) * plane + colbase + cc];
+  }
+  if (tid < TX) column_info(ci[tid], t, kx0 + tid, iy);
+  __syncthreads();
+
+  if constexpr (MODE == AX_AM || MODE == AX_M) {
+    lds_fft<T, NZ, 3 * TX, NT, false, true>(buf, t.tw_z, Addr{}, tid);
+    for (int e = tid; e < NZ * TX; e += NT) {
+      const int l = e / TX, cc = e % TX;
+      const T kzl = t.kz[l];
+      const T m = damping(ci[cc].kt2 + kzl * kzl, t) * inz;
+      cplx<T>* b0 = &buf[l * PITCH + cc];
+      const cplx<T> p0 = m * b0[0], p1 = m * b0[VS], p2 = m * b0[2 * VS];
+      b0[0] = p0;
+      b0[VS] = p1;
+      b0[2 * VS] = p2;
+      if constexpr (MODE == AX_AM) {
+        b0[3 * VS] = kzl * mul_i(p0);
+        b0[4 * VS] = kzl * mul_i(p1);
+      }
+    }
+    __syncthreads();
+    lds_fft<T, NZ, (MODE == AX_AM ? 5 : 3) * TX, NT, true, true>(buf, t.tw_z, Addr{}, tid);
+    if constexpr (MODE == AX_M) {
+      for (int e = tid; e < 3 * NZ * TX; e += NT) {
+        const int c = e / (NZ * TX), rem = e % (NZ * TX);
+        const int z = rem / TX, cc = rem % TX;
+        UW[(int64_t)(c * NZ + z) * plane + colbase + cc] = buf[c * VS + z * PITCH + cc];
+      }
+      return;
+    }
+  } else {
+    for (int e = tid; e < NZ * TX; e += NT) {
+      const int z = e / TX, cc = e % TX;
+      cplx<T> a = buf[z * PITCH + cc], b = buf[VS + z * PITCH + cc];
+      if constexpr (MODE == AX_AH) {
+        const cplx<T> is = t.inv_s[z];
+        a = cmulc(is, a);
+        b = cmulc(is, b);
+      }
+      buf[3 * VS + z * PITCH + cc] = a;
+      buf[4 * VS + z * PITCH + cc] = b;
+    }
+    __syncthreads();
+    lds_fft<T, NZ, 2 * TX, NT, false, true>(buf + 3 * VS, t.tw_z, Addr{}, tid);
+    for (int e = tid; e < NZ * TX; e += NT) {
+      const int l = e / TX, cc = e % TX;
+      const T f = t.kz[l] * inz;
+      buf[3 * VS + l * PITCH + cc] = f * mul_i(buf[3 * VS + l * PITCH + cc]);
+      buf[4 * VS + l * PITCH + cc] = f * mul_i(buf[4 * VS + l * PITCH + cc]);
+    }
+    __syncthreads();
+    lds_fft<T, NZ, 2 * TX, NT, true, true>(buf + 3 * VS, t.tw_z, Addr{}, tid);
+  }
+
+  // Multilayer branch amplitudes (one thread per column).
+  if (tid < TX) {
+    ColInfo<T>& c = ci[tid];
+    if constexpr (MODE != AX_AH) {
+      const cplx<T> px = buf[t.jev * PITCH + tid], py = buf[VS + t.jev * PITCH + tid];
+      const cplx<T> as = (c.sx * px + c.sy * py) * c.down;
+      const cplx<T> ap = (c.tx * px + c.ty * py) * c.down;
+      c.a0 = c.live ? c.rte * as : cplx<T>{T(0), T(0)};
+      c.a1 = c.live ? c.rpe * ap : cplx<T>{T(0), T(0)};
+    } else {
+      cplx<T> cs = {T(0), T(0)}, cp = {T(0), T(0)};
+      for (int ja = 0; ja < t.nabs; ++ja) {
+        const cplx<T> qx = S[(int64_t)(3 * NZ + ja) * plane + colbase + tid];
+        const cplx<T> qy = S[(int64_t)(3 * NZ + t.nabs + ja) * plane + colbase + tid];
+        const cplx<T> qz = S[(int64_t)(3 * NZ + 2 * t.nabs + ja) * plane + colbase + tid];
+        const cplx<T> ph = conj(up_phase(c, t.zabs[ja]));
+        cs = cs + ph * (c.sx * qx + c.sy * qy);
+        cp = cp + ph * (c.tx * qx + c.ty * qy - cmulc(c.ktkz, qz));
+      }
+      cs = c.live ? cmulc(c.rte, cs) : cplx<T>{T(0), T(0)};
+      cp = c.live ? cmulc(c.rpe, cp) : cplx<T>{T(0), T(0)};
+      c.a0 = cmulc(c.down, c.sx * cs + c.tx * cp);
+      c.a1 = cmulc(c.down, c.sy * cs + c.ty * cp);
+    }
+  }
+
+  // Uz and the inner curl vectors w = -D P_t + i k_t P_z.
+  for (int e = tid; e < NZ * TX; e += NT) {
+    const int z = e / TX, cc = e % TX;
+    const ColInfo<T>& c = ci[cc];
+    const int o = z * PITCH + cc;
+    cplx<T> dpx = buf[3 * VS + o], dpy = buf[4 * VS + o];
+    if constexpr (MODE != AX_AH) {
+      const cplx<T> is = t.inv_s[z];
+      dpx = dpx * is;
+      dpy = dpy * is;
+    }
+    const cplx<T> pz = buf[2 * VS + o];
+    const cplx<T> uz = c.kx * mul_i(dpx) + c.ky * mul_i(dpy) + (c.kt2 - t.kbg2) * pz;
+    UW[(int64_t)(2 * NZ + z) * plane + colbase + cc] = uz;
+    cplx<T> wx = c.kx * mul_i(pz) - dpx;
+    cplx<T> wy = c.ky * mul_i(pz) - dpy;
+    if constexpr (MODE == AX_AH) {
+      const cplx<T> is = t.inv_s[z];
+      wx = cmulc(is, wx);
+      wy = cmulc(is, wy);
+    }
+    buf[3 * VS + o] = wx;
+    buf[4 * VS + o] = wy;
+  }
+  __syncthreads();
+  lds_fft<T, NZ, 2 * TX, NT, false, true>(buf + 3 * VS, t.tw_z, Addr{}, tid);
+  for (int e = tid; e < NZ * TX; e += NT) {
+    const int l = e / TX, cc = e % TX;
+    const T f = t.kz[l] * inz;
+    buf[3 * VS + l * PITCH + cc] = f * mul_i(buf[3 * VS + l * PITCH + cc]);
+    buf[4 * VS + l * PITCH + cc] = f * mul_i(buf[4 * VS + l * PITCH + cc]);
+  }
+  __syncthreads();
+  lds_fft<T, NZ, 2 * TX, NT, true, true>(buf + 3 * VS, t.tw_z, Addr{}, tid);
+
+  for (int e = tid; e < NZ * TX; e += NT) {
+    const int z = e / TX, cc = e % TX;
+    const ColInfo<T>& c = ci[cc];
+    const int o = z * PITCH + cc;
+    cplx<T> dwx = buf[3 * VS + o], dwy = buf[4 * VS + o];
+    if constexpr (MODE != AX_AH) {
+      const cplx<T> is = t.inv_s[z];
+      dwx = dwx * is;
+      dwy = dwy * is;
+    }
+    const cplx<T> px = buf[o], py = buf[VS + o];
+    cplx<T> ux = (c.ky * c.ky - t.kbg2) * px - (c.kx * c.ky) * py + dwx;
+    cplx<T> uy = (c.kx * c.kx - t.kbg2) * py - (c.kx * c.ky) * px + dwy;
+    if constexpr (MODE == AX_AH) {
+      if (z == t.jev) {
+        ux = ux - c.a0;
+        uy = uy - c.a1;
+      }
+    }
+    UW[(int64_t)z * plane + colbase + cc] = ux;
+    UW[(int64_t)(NZ + z) * plane + colbase + cc] = uy;
+  }
+
+  if constexpr (MODE != AX_AH) {
+    for (int e = tid; e < t.nabs * TX; e += NT) {
+      const int ja = e / TX, cc = e % TX;
+      const ColInfo<T>& c = ci[cc];
+      const int z = t.j0 + ja;
+      const cplx<T> ph = up_phase(c, t.zabs[ja]);
+      const cplx<T> vs = c.a0 * ph, vp = c.a1 * ph;
+      const cplx<T> vx = c.sx * vs + c.tx * vp;
+      const cplx<T> vy = c.sy * vs + c.ty * vp;
+      const cplx<T> vz = -(c.ktkz * vp);
+      const int o = z * PITCH + cc;
+      const int64_t wb = (int64_t)3 * NZ;
+      UW[(wb + ja) * plane + colbase + cc] = buf[o] + vx;
+      UW[(wb + t.nabs + ja) * plane + colbase + cc] = buf[VS + o] + vy;
+      UW[(wb + 2 * t.nabs + ja) * plane + colbase + cc] = buf[2 * VS + o] + vz;
+    }
+  }
+}
+
+template <typename T, int NZ>
+static hipError_t axial_n(const OpTables<T>& t, const cplx<T>* S, cplx<T>* UW, int mode,
+                          hipStream_t st) {
+  constexpr int TX = ax_tile<T, NZ>();
+  if (t.nx % TX) return hipErrorInvalidValue;
+  dim3 g(t.nx / TX, t.ny), b(256);
+  switch (mode) {
+    case AX_A: hipLaunchKernelGGL((k_axial<T, NZ, TX, AX_A>), g, b, 0, st, S, UW, t); break;
+    case AX_AM: hipLaunchKernelGGL((k_axial<T, NZ, TX, AX_AM>), g, b, 0, st, S, UW, t); break;
+    case AX_AH: hipLaunchKernelGGL((k_axial<T, NZ, TX, AX_AH>), g, b, 0, st, S, UW, t); break;
+    default: hipLaunchKernelGGL((k_axial<T, NZ, TX, AX_M>), g, b, 0, st, S, UW, t); break;
+  }
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_axial(const OpTables<T>& t, const cplx<T>* S, cplx<T>* UW, int mode,
+                        hipStream_t st) {
+  switch (t.nz) {
+    case 24: return axial_n<T, 24>(t, S, UW, mode, st);
+    case 32: return axial_n<T, 32>(t, S, UW, mode, st);
+    case 48: return axial_n<T, 48>(t, S, UW, mode, st);
+    case 64: return axial_n<T, 64>(t, S, UW, mode, st);
+    case 96: return axial_n<T, 96>(t, S, UW, mode, st);
+    case 128: return axial_n<T, 128>(t, S, UW, mode, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template hipError_t launch_axial<double>(const OpTables<double>&, const cplx<double>*,
+                                         cplx<double>*, int, hipStream_t);
+template hipError_t launch_axial<float>(const OpTables<float>&, const cplx<float>*,
+                                        cplx<float>*, int, hipStream_t);
+
+}  // namespace psfd

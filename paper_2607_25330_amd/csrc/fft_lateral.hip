@@ -1,0 +1,263 @@
+// Lateral (x, y) FFT passes of the operator apply.
+//
+// Every field is [3][Nz][ny][nx] with x fastest.  The 2-D lateral transform
+// of every (component, row) plane is done in two HBM passes: an x pass over
+// contiguous rows (a block owns B whole rows, fully coalesced) and a y pass
+// over a tile of TX adjacent columns of one plane (each tile row is a
+// contiguous TX-element segment).  The inverse x pass carries the pointwise
+// epilogue of the operator:  y = F2^-1[U] - k0^2 d_eps F2^-1[W]  on absorber
+// rows (forward operator) or  y = F2^-1[U] - conj(k0^2 d_eps) x  (adjoint).
+#include "fft_core.h"
+#include "psfd_internal.h"
+
+namespace psfd {
+
+bool lateral_size_ok(int n) {
+  switch (n) {
+    case 16: case 32: case 64: case 128: case 192: case 256: case 512: case 1024: return true;
+    default: return false;
+  }
+}
+
+template <typename T>
+constexpr int x_elems() { return sizeof(T) == 8 ? 2048 : 4096; }
+
+template <typename T, int N>
+constexpr int x_rows() {
+  int b = 1;
+  while (2 * b * N <= x_elems<T>()) b *= 2;
+  return b;
+}
+
+template <typename T, int N>
+constexpr int y_tile() {
+  int tx = 65536 / (N * (int)sizeof(cplx<T>));
+  return tx > 16 ? 16 : tx;
+}
+
+// ------------------------------------------------------------------ kernels
+
+template <typename T, int N, int B>
+__global__ void __launch_bounds__(B * Radices<N>::TPR)
+k_xfft_fwd(const cplx<T>* __restrict__ in, cplx<T>* __restrict__ out,
+           const cplx<T>* __restrict__ tw, int64_t nrows_main, int64_t nrows_total, int ny,
+           int nz, int j0, int nabs, const cplx<T>* __restrict__ kd,
+           const int* __restrict__ skip) {
+  if (skip && *skip) return;
+  constexpr int NT = B * Radices<N>::TPR;
+  __shared__ cplx<T> s[B * N];
+  const int tid = threadIdx.x;
+  const int64_t row0 = (int64_t)blockIdx.x * B;
+  for (int e = tid; e < B * N; e += NT) {
+    const int64_t row = row0 + e / N;
+    const int xi = e % N;
+    cplx<T> val = {T(0), T(0)};
+    if (row < nrows_main) {
+      val = in[row * N + xi];
+    } else if (row < nrows_total) {
+      const int64_t r = row - nrows_main;
+      const int plane = (int)(r / ny), yy = (int)(r % ny);
+      const int c = plane / nabs, ja = plane % nabs;
+      const int64_t src = ((int64_t)(c * nz + j0 + ja) * ny + yy) * N + xi;
+      val = cmulc(kd[((int64_t)ja * ny + yy) * N + xi], in[src]);
+    }
+    s[e] = val;
+  }
+  __syncthreads();
+  lds_fft<T, N, B, NT, false, false>(s, tw, AddrRow<N>{}, tid);
+  for (int e = tid; e < B * N; e += NT) {
+    const int64_t row = row0 + e / N;
+    if (row < nrows_total) out[row * N + (e % N)] = s[e];
+  }
+}
+
+template <typename T, int N, int B, int CM>
+__global__ void __launch_bounds__(B * Radices<N>::TPR)
+k_xfft_inv(const cplx<T>* __restrict__ UW, cplx<T>* __restrict__ y,
+           const cplx<T>* __restrict__ tw, int64_t nrows, int ny, int nz, int j0, int nabs,
+           T scale, const cplx<T>* __restrict__ kd, const cplx<T>* __restrict__ x,
+           const int* __restrict__ skip) {
+  if (skip && *skip) return;
+  constexpr int NT = B * Radices<N>::TPR;
+  constexpr int NBUF = (CM == CB_FWD) ? 2 : 1;
+  __shared__ cplx<T> s[NBUF * B * N];
+  const int tid = threadIdx.x;
+  const int64_t row0 = (int64_t)blockIdx.x * B;
+  const int64_t wbase = (int64_t)3 * nz * ny;  // first W row
+  for (int e = tid; e < B * N; e += NT) {
+    const int64_t row = row0 + e / N;
+    const int xi = e % N;
+    cplx<T> u = {T(0), T(0)};
+    cplx<T> w = {T(0), T(0)};
+    if (row < nrows) {
+      u = UW[row * N + xi];
+      if (CM == CB_FWD) {
+        const int plane = (int)(row / ny), yy = (int)(row % ny);
+        const int c = plane / nz, z = plane % nz;
+        if (z >= j0 && z < j0 + nabs)
+          w = UW[(wbase + (int64_t)(c * nabs + z - j0) * ny + yy) * N + xi];
+      }
+    }
+    s[e] = u;
+    if (CM == CB_FWD) s[B * N + e] = w;
+  }
+  __syncthreads();
+  lds_fft<T, N, NBUF * B, NT, true, false>(s, tw, AddrRow<N>{}, tid);
+  for (int e = tid; e < B * N; e += NT) {
+    const int64_t row = row0 + e / N;
+    if (row >= nrows) continue;
+    const int xi = e % N;
+    cplx<T> out = scale * s[e];
+    if (CM != CB_PLAIN) {
+      const int plane = (int)(row / ny), yy = (int)(row % ny);
+      const int z = plane % nz;
+      if (z >= j0 && z < j0 + nabs) {
+        const cplx<T> kdv = kd[((int64_t)(z - j0) * ny + yy) * N + xi];
+        if (CM == CB_FWD) out = out - scale * (kdv * s[B * N + e]);
+        else out = out - cmulc(kdv, x[row * N + xi]);
+      }
+    }
+    y[row * N + xi] = out;
+  }
+}
+
+template <typename T, int N, int TX, bool INV>
+__global__ void __launch_bounds__(TX * Radices<N>::TPR)
+k_yfft(cplx<T>* __restrict__ buf, const cplx<T>* __restrict__ tw, int nx,
+       const int* __restrict__ skip) {
+  if (skip && *skip) return;
+  constexpr int NT = TX * Radices<N>::TPR;
+  __shared__ cplx<T> s[N * TX];
+  const int tid = threadIdx.x;
+  const int64_t base = (int64_t)blockIdx.y * N * nx + (int64_t)blockIdx.x * TX;
+  for (int e = tid; e < N * TX; e += NT) s[e] = buf[base + (int64_t)(e / TX) * nx + (e % TX)];
+  __syncthreads();
+  lds_fft<T, N, TX, NT, INV, true>(s, tw, AddrCol<TX>{}, tid);
+  for (int e = tid; e < N * TX; e += NT) buf[base + (int64_t)(e / TX) * nx + (e % TX)] = s[e];
+}
+
+// ---------------------------------------------------------------- launchers
+
+template <typename T, int N>
+static hipError_t xfwd_n(const OpTables<T>& t, const cplx<T>* in, cplx<T>* out,
+                         int64_t nmain, int64_t ntot, int ny, hipStream_t st) {
+  constexpr int B = x_rows<T, N>();
+  constexpr int NT = B * Radices<N>::TPR;
+  const int64_t nblk = (ntot + B - 1) / B;
+  hipLaunchKernelGGL((k_xfft_fwd<T, N, B>), dim3((unsigned)nblk), dim3(NT), 0, st, in, out,
+                     t.tw_x, nmain, ntot, ny, t.nz, t.j0, t.nabs, t.kd, t.skip);
+  return hipGetLastError();
+}
+
+template <typename T, int N>
+static hipError_t xinv_n(const OpTables<T>& t, const cplx<T>* UW, cplx<T>* y, int64_t nrows,
+                         int ny, int cmode, const cplx<T>* x, T scale, hipStream_t st) {
+  constexpr int B = x_rows<T, N>();
+  constexpr int NT = B * Radices<N>::TPR;
+  const int64_t nblk = (nrows + B - 1) / B;
+  dim3 g((unsigned)nblk), b(NT);
+  switch (cmode) {
+    case CB_PLAIN:
+      hipLaunchKernelGGL((k_xfft_inv<T, N, B, CB_PLAIN>), g, b, 0, st, UW, y, t.tw_x, nrows, ny,
+                         t.nz, t.j0, t.nabs, scale, t.kd, x, t.skip);
+      break;
+    case CB_FWD:
+      hipLaunchKernelGGL((k_xfft_inv<T, N, B, CB_FWD>), g, b, 0, st, UW, y, t.tw_x, nrows, ny,
+                         t.nz, t.j0, t.nabs, scale, t.kd, x, t.skip);
+      break;
+    default:
+      hipLaunchKernelGGL((k_xfft_inv<T, N, B, CB_ADJ>), g, b, 0, st, UW, y, t.tw_x, nrows, ny,
+                         t.nz, t.j0, t.nabs, scale, t.kd, x, t.skip);
+      break;
+  }
+  return hipGetLastError();
+}
+
+template <typename T, int N>
+static hipError_t y_n(const cplx<T>* tw, cplx<T>* buf, int nx, int nplanes, bool inv,
+                      const int* skip, hipStream_t st) {
+  constexpr int TX = y_tile<T, N>();
+  constexpr int NT = TX * Radices<N>::TPR;
+  if (nx % TX) return hipErrorInvalidValue;
+  dim3 g(nx / TX, nplanes);
+  if (inv) hipLaunchKernelGGL((k_yfft<T, N, TX, true>), g, dim3(NT), 0, st, buf, tw, nx, skip);
+  else hipLaunchKernelGGL((k_yfft<T, N, TX, false>), g, dim3(NT), 0, st, buf, tw, nx, skip);
+  return hipGetLastError();
+}
+
+#define PSFD_LATERAL_SWITCH(N, CALL)              \
+  switch (N) {                                    \
+    case 16: return CALL(16);                     \
+    case 32: return CALL(32);                     \
+    case 64: return CALL(64);                     \
+    case 128: return CALL(128);                   \
+    case 192: return CALL(192);                   \
+    case 256: return CALL(256);                   \
+    case 512: return CALL(512);                   \
+    case 1024: return CALL(1024);                 \
+    default: return hipErrorInvalidValue;         \
+  }
+
+template <typename T>
+hipError_t launch_xfft_fwd(const OpTables<T>& t, const cplx<T>* in, cplx<T>* out, bool adj_extra,
+                           hipStream_t st) {
+  const int64_t nmain = (int64_t)3 * t.nz * t.ny;
+  const int64_t ntot = nmain + (adj_extra ? (int64_t)3 * t.nabs * t.ny : 0);
+#define CALL_X(NN) xfwd_n<T, NN>(t, in, out, nmain, ntot, t.ny, st)
+  PSFD_LATERAL_SWITCH(t.nx, CALL_X)
+#undef CALL_X
+}
+
+template <typename T>
+hipError_t launch_yfft(const OpTables<T>& t, cplx<T>* buf, int nplanes, bool inverse,
+                       hipStream_t st) {
+#define CALL_Y(NN) y_n<T, NN>(t.tw_y, buf, t.nx, nplanes, inverse, t.skip, st)
+  PSFD_LATERAL_SWITCH(t.ny, CALL_Y)
+#undef CALL_Y
+}
+
+template <typename T>
+hipError_t launch_xfft_inv(const OpTables<T>& t, const cplx<T>* UW, cplx<T>* y, int cmode,
+                           const cplx<T>* x, hipStream_t st) {
+  const int64_t nrows = (int64_t)3 * t.nz * t.ny;
+  const T scale = T(1) / (T(t.nx) * T(t.ny));
+#define CALL_XI(NN) xinv_n<T, NN>(t, UW, y, nrows, t.ny, cmode, x, scale, st)
+  PSFD_LATERAL_SWITCH(t.nx, CALL_XI)
+#undef CALL_XI
+}
+
+template <typename T>
+hipError_t launch_plane_fft(const OpTables<T>& t, cplx<T>* in, cplx<T>* out, bool inverse,
+                            hipStream_t st) {
+  hipError_t e;
+  if (!inverse) {
+#define CALL_PX(NN) xfwd_n<T, NN>(t, in, out, t.ny, t.ny, t.ny, st)
+    e = [&]() -> hipError_t { PSFD_LATERAL_SWITCH(t.nx, CALL_PX) }();
+#undef CALL_PX
+    if (e != hipSuccess) return e;
+    return launch_yfft<T>(t, out, 1, false, st);
+  }
+  // inverse: y pass in place on `in`, then x pass into `out` (unnormalised)
+  e = launch_yfft<T>(t, in, 1, true, st);
+  if (e != hipSuccess) return e;
+#define CALL_PXI(NN) xinv_n<T, NN>(t, in, out, t.ny, t.ny, CB_PLAIN, nullptr, T(1), st)
+  PSFD_LATERAL_SWITCH(t.nx, CALL_PXI)
+#undef CALL_PXI
+}
+
+template hipError_t launch_xfft_fwd<double>(const OpTables<double>&, const cplx<double>*,
+                                            cplx<double>*, bool, hipStream_t);
+template hipError_t launch_xfft_fwd<float>(const OpTables<float>&, const cplx<float>*,
+                                           cplx<float>*, bool, hipStream_t);
+template hipError_t launch_yfft<double>(const OpTables<double>&, cplx<double>*, int, bool,
+                                        hipStream_t);
+template hipError_t launch_yfft<float>(const OpTables<float>&, cplx<float>*, int, bool,
+                                       hipStream_t);
+template hipError_t launch_xfft_inv<double>(const OpTables<double>&, const cplx<double>*,
+                                            cplx<double>*, int, const cplx<double>*, hipStream_t);
+template hipError_t launch_xfft_inv<float>(const OpTables<float>&, const cplx<float>*,
+                                           cplx<float>*, int, const cplx<float>*, hipStream_t);
+template hipError_t launch_plane_fft<double>(const OpTables<double>&, cplx<double>*,
+                                             cplx<double>*, bool, hipStream_t);
+
+}  // namespace psfd

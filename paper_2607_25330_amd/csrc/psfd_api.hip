@@ -1,0 +1,693 @@
+// Host side of libpsfd: plan construction, operator pipelines, the BiCGSTAB
+// driver and the C ABI declared in include/psfd.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "psfd.h"
+#include "psfd_internal.h"
+
+using namespace psfd;
+
+namespace {
+
+thread_local std::string g_err;
+
+psfd_status fail(psfd_status s, const std::string& msg) {
+  g_err = msg;
+  return s;
+}
+
+#define CHK(...)                                                                         \
+  do {                                                                                   \
+    hipError_t e_ = (__VA_ARGS__);                                                       \
+    if (e_ != hipSuccess)                                                                \
+      return fail(PSFD_ERR_HIP, std::string(#__VA_ARGS__) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+#define CHKS(...)                           \
+  do {                                      \
+    psfd_status s_ = (__VA_ARGS__);         \
+    if (s_ != PSFD_OK) return s_;           \
+  } while (0)
+
+constexpr double kTwoPi = 6.283185307179586476925286766559;
+constexpr int kChunk = 16;         // BiCGSTAB iterations queued between convergence checks
+constexpr int kMaxRestarts = 10;   // residual replacements (FP64) / refinement steps (mixed)
+
+enum { OP_A = 0, OP_AM = 1, OP_AH = 2, OP_M = 3 };
+enum { V_R = 0, V_RH, V_P, V_V, V_S, V_T, V_Y, V_W, V_COUNT };
+
+int fftfreq(int m, int n) { return (m < (n + 1) / 2) ? m : m - n; }
+
+std::vector<cplx<double>> twiddles(int n) {
+  std::vector<cplx<double>> w(n);
+  for (int m = 0; m < n; ++m) {
+    const long double a = -2.0L * 3.14159265358979323846264338327950288L * m / n;
+    w[m] = {(double)cosl(a), (double)sinl(a)};
+  }
+  return w;
+}
+
+}  // namespace
+
+struct psfd_plan {
+  psfd_desc d{};
+  std::vector<double> ml_eps_h, ml_d_h;
+  int nx = 0, ny = 0, nz = 0, nabs = 0, j0 = 0, jev = 0;
+  double k0 = 0, kbg = 0, kx0 = 0, ky0 = 0, kz0 = 0;
+  int64_t plane = 0, nfield = 0, nspec = 0;
+  hipStream_t st = nullptr;
+  int prec = PSFD_C128;
+  bool use_pc = true;
+  std::vector<void*> allocs;
+
+  OpTables<double> t64{};
+  OpTables<float> t32{};
+  cplx<double>* kd64 = nullptr;
+  cplx<float>* kd32 = nullptr;
+  cplx<double>* rte64 = nullptr;
+  cplx<double>* rpe64 = nullptr;
+  double* zabs64 = nullptr;
+
+  cplx<double>* S64 = nullptr;
+  cplx<double>* UW64 = nullptr;
+  cplx<float>* S32 = nullptr;
+  cplx<float>* UW32 = nullptr;
+
+  cplx<double>* v64[V_COUNT] = {};
+  cplx<float>* v32[V_COUNT] = {};
+  cplx<double>* b64 = nullptr;
+  cplx<double>* tmp64 = nullptr;
+  cplx<double>* res64 = nullptr;
+  KState* ks = nullptr;
+  KState* ks_host = nullptr;
+  double* part = nullptr;
+
+  ~psfd_plan() {
+    for (void* p : allocs) (void)hipFree(p);
+    if (ks_host) (void)hipHostFree(ks_host);
+  }
+};
+
+namespace {
+
+template <typename T>
+psfd_status dalloc(struct psfd_plan* P, T** out, size_t count) {
+  void* q = nullptr;
+  const size_t bytes = std::max<size_t>(count, 1) * sizeof(T);
+  hipError_t e = hipMalloc(&q, bytes);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(PSFD_ERR_ALLOC, "hipMalloc of " + std::to_string(bytes) + " bytes failed: " +
+                                    hipGetErrorString(e));
+  }
+  P->allocs.push_back(q);
+  *out = static_cast<T*>(q);
+  return PSFD_OK;
+}
+
+template <typename T>
+psfd_status upload(struct psfd_plan* P, T** out, const std::vector<T>& h) {
+  CHKS(dalloc(P, out, h.size()));
+  CHK(hipMemcpyAsync(*out, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, P->st));
+  return PSFD_OK;
+}
+
+template <typename T>
+std::vector<T> to_t(const std::vector<double>& v) {
+  return std::vector<T>(v.begin(), v.end());
+}
+template <typename T>
+std::vector<cplx<T>> to_tc(const std::vector<cplx<double>>& v) {
+  std::vector<cplx<T>> o(v.size());
+  for (size_t i = 0; i < v.size(); ++i) o[i] = {(T)v[i].re, (T)v[i].im};
+  return o;
+}
+
+psfd_status validate(const psfd_desc* d) {
+  if (!d) return fail(PSFD_ERR_ARG, "desc is NULL");
+  if (!lateral_size_ok(d->nx) || !lateral_size_ok(d->ny))
+    return fail(PSFD_ERR_ARG, "nx, ny must be one of 16, 32, 64, 128, 192, 256, 512, 1024");
+  if (d->nz_abs < 1 || d->nz_gap_bot < 1 || d->nz_gap_top < 0 || d->nz_pml < 0)
+    return fail(PSFD_ERR_ARG, "need nz_abs >= 1, nz_gap_bot >= 1, nz_gap_top >= 0, nz_pml >= 0");
+  const int nz = d->nz_abs + d->nz_gap_bot + d->nz_gap_top + 2 * d->nz_pml;
+  if (!axial_size_ok(nz)) return fail(PSFD_ERR_ARG, "Nz must be one of 24, 32, 48, 64, 96, 128");
+  if (!(d->dx > 0) || !(d->dy > 0) || !(d->dz > 0) || !(d->lambda > 0))
+    return fail(PSFD_ERR_ARG, "dx, dy, dz, lambda must be positive");
+  if (!(d->eps_bg > 0)) return fail(PSFD_ERR_ARG, "eps_bg must be positive");
+  if (d->pol != 0 && d->pol != 1) return fail(PSFD_ERR_ARG, "pol must be 0 (TE) or 1 (TM)");
+  if (d->n_ml < 0 || (d->n_ml > 0 && (!d->ml_eps || !d->ml_thick)))
+    return fail(PSFD_ERR_ARG, "multilayer tables missing");
+  if (d->prec < PSFD_C128 || d->prec > PSFD_C64_BF16PC_REFINE64)
+    return fail(PSFD_ERR_ARG, "unknown precision");
+  if (d->pml_order < 0 || !(d->pml_sigma0 >= 0)) return fail(PSFD_ERR_ARG, "bad PML parameters");
+  if (!(d->pc_mmin >= 0 && d->pc_mmin <= 1) || !(d->pc_gamma > 0) || !(d->pc_reg >= 0))
+    return fail(PSFD_ERR_ARG, "bad preconditioner parameters");
+  if (!std::isfinite(d->theta) || !std::isfinite(d->phi)) return fail(PSFD_ERR_ARG, "bad angles");
+  return PSFD_OK;
+}
+
+template <typename T>
+OpTables<T>& tab(struct psfd_plan* P);
+template <>
+OpTables<double>& tab<double>(struct psfd_plan* P) { return P->t64; }
+template <>
+OpTables<float>& tab<float>(struct psfd_plan* P) { return P->t32; }
+
+template <typename T>
+cplx<T>* wsS(struct psfd_plan* P);
+template <>
+cplx<double>* wsS<double>(struct psfd_plan* P) { return P->S64; }
+template <>
+cplx<float>* wsS<float>(struct psfd_plan* P) { return P->S32; }
+template <typename T>
+cplx<T>* wsUW(struct psfd_plan* P);
+template <>
+cplx<double>* wsUW<double>(struct psfd_plan* P) { return P->UW64; }
+template <>
+cplx<float>* wsUW<float>(struct psfd_plan* P) { return P->UW32; }
+template <typename T>
+cplx<T>** vecs(struct psfd_plan* P);
+template <>
+cplx<double>** vecs<double>(struct psfd_plan* P) { return P->v64; }
+template <>
+cplx<float>** vecs<float>(struct psfd_plan* P) { return P->v32; }
+
+// One operator application (see the kernel files for the math).
+template <typename T>
+hipError_t op_apply(struct psfd_plan* P, const cplx<T>* x, cplx<T>* y, int op, const int* skip) {
+  OpTables<T> t = tab<T>(P);
+  t.skip = skip;
+  cplx<T>* S = wsS<T>(P);
+  cplx<T>* UW = wsUW<T>(P);
+  hipStream_t st = P->st;
+  const int p3 = 3 * P->nz, pa = 3 * P->nabs;
+  hipError_t e;
+  switch (op) {
+    case OP_A:
+    case OP_AM:
+      if ((e = launch_xfft_fwd<T>(t, x, S, false, st)) != hipSuccess) return e;
+      if ((e = launch_yfft<T>(t, S, p3, false, st)) != hipSuccess) return e;
+      if ((e = launch_axial<T>(t, S, UW, op == OP_A ? AX_A : AX_AM, st)) != hipSuccess) return e;
+      if ((e = launch_yfft<T>(t, UW, p3 + pa, true, st)) != hipSuccess) return e;
+      return launch_xfft_inv<T>(t, UW, y, CB_FWD, nullptr, st);
+    case OP_AH:
+      if ((e = launch_xfft_fwd<T>(t, x, S, true, st)) != hipSuccess) return e;
+      if ((e = launch_yfft<T>(t, S, p3 + pa, false, st)) != hipSuccess) return e;
+      if ((e = launch_axial<T>(t, S, UW, AX_AH, st)) != hipSuccess) return e;
+      if ((e = launch_yfft<T>(t, UW, p3, true, st)) != hipSuccess) return e;
+      return launch_xfft_inv<T>(t, UW, y, CB_ADJ, x, st);
+    default:
+      if ((e = launch_xfft_fwd<T>(t, x, S, false, st)) != hipSuccess) return e;
+      if ((e = launch_yfft<T>(t, S, p3, false, st)) != hipSuccess) return e;
+      if ((e = launch_axial<T>(t, S, UW, AX_M, st)) != hipSuccess) return e;
+      if ((e = launch_yfft<T>(t, UW, p3, true, st)) != hipSuccess) return e;
+      return launch_xfft_inv<T>(t, UW, y, CB_PLAIN, nullptr, st);
+  }
+}
+
+psfd_status ensure_fp32(struct psfd_plan* P) {
+  if (P->S32) return PSFD_OK;
+  const int64_t nspec = P->nspec;
+  CHKS(dalloc(P, &P->S32, (size_t)nspec));
+  CHKS(dalloc(P, &P->UW32, (size_t)nspec));
+  return PSFD_OK;
+}
+
+template <typename T>
+psfd_status ensure_krylov(struct psfd_plan* P) {
+  cplx<T>** v = vecs<T>(P);
+  if (v[0]) return PSFD_OK;
+  for (int i = 0; i < V_COUNT; ++i) CHKS(dalloc(P, &v[i], (size_t)P->nfield));
+  return PSFD_OK;
+}
+
+psfd_status ensure_solver_common(struct psfd_plan* P) {
+  if (P->ks) return PSFD_OK;
+  CHKS(dalloc(P, &P->ks, 1));
+  CHKS(dalloc(P, &P->part, (size_t)2048 * 4));
+  CHKS(dalloc(P, &P->b64, (size_t)P->nfield));
+  CHKS(dalloc(P, &P->tmp64, (size_t)P->nfield));
+  CHKS(dalloc(P, &P->res64, (size_t)P->nfield));
+  CHK(hipMemsetAsync(P->ks, 0, sizeof(KState), P->st));
+  CHK(hipHostMalloc((void**)&P->ks_host, sizeof(KState), hipHostMallocDefault));
+  return PSFD_OK;
+}
+
+psfd_status read_state(struct psfd_plan* P) {
+  CHK(hipMemcpyAsync(P->ks_host, P->ks, sizeof(KState), hipMemcpyDeviceToHost, P->st));
+  CHK(hipStreamSynchronize(P->st));
+  return PSFD_OK;
+}
+
+psfd_status norm2_host(struct psfd_plan* P, const cplx<double>* a, double* out) {
+  CHK(launch_k_norm2<double>(a, P->nfield, P->ks, P->part, P->st));
+  CHKS(read_state(P));
+  *out = P->ks_host->red[0];
+  return PSFD_OK;
+}
+
+struct RunResult {
+  int iters = 0;
+  int done = 0;
+  double rrel_rec = 0;
+};
+
+// Right-preconditioned BiCGSTAB on op(prec(y)) = r (r in vecs[V_R]); y in vecs[V_Y].
+template <typename T>
+psfd_status run_bicgstab(struct psfd_plan* P, bool adjoint, double bnorm2, double tol,
+                         int maxit, RunResult* res) {
+  cplx<T>** V = vecs<T>(P);
+  const int64_t n = P->nfield;
+  hipStream_t st = P->st;
+  KState* ks = P->ks;
+  double* part = P->part;
+  const int* skip = &ks->done;
+  const bool pc = P->use_pc;
+  CHK(launch_k_init<T>(V[V_RH], V[V_R], V[V_P], V[V_V], V[V_Y], n, ks, part, bnorm2, tol * tol,
+                       st));
+  auto apply = [&](const cplx<T>* in, cplx<T>* out) -> hipError_t {
+    if (!adjoint) return op_apply<T>(P, in, out, pc ? OP_AM : OP_A, skip);
+    if (!pc) return op_apply<T>(P, in, out, OP_AH, skip);
+    hipError_t e = op_apply<T>(P, in, V[V_W], OP_M, skip);
+    if (e != hipSuccess) return e;
+    return op_apply<T>(P, V[V_W], out, OP_AH, skip);
+  };
+  int launched = 0;
+  res->done = 0;
+  while (launched < maxit) {
+    const int chunk = std::min(kChunk, maxit - launched);
+    for (int i = 0; i < chunk; ++i) {
+      CHK(launch_k_p_update<T>(V[V_P], V[V_R], V[V_V], n, ks, st));
+      CHK(apply(V[V_P], V[V_V]));
+      CHK(launch_k_dot_rv<T>(V[V_RH], V[V_V], n, ks, part, st));
+      CHK(launch_k_s_update<T>(V[V_S], V[V_R], V[V_V], n, ks, part, st));
+      CHK(apply(V[V_S], V[V_T]));
+      CHK(launch_k_dot_ts<T>(V[V_T], V[V_S], n, ks, part, st));
+      CHK(launch_k_xr_update<T>(V[V_Y], V[V_R], V[V_P], V[V_S], V[V_T], V[V_RH], n, ks, part,
+                                st));
+    }
+    launched += chunk;
+    CHKS(read_state(P));
+    if (P->ks_host->done != 0) break;
+  }
+  res->iters = P->ks_host->iter;
+  res->done = P->ks_host->done;
+  res->rrel_rec = std::sqrt(P->ks_host->rnorm2 / bnorm2);
+  return PSFD_OK;
+}
+
+// r = b - op(E) in FP64 (op = A or A^H, no preconditioner); returns ||r||^2.
+psfd_status true_residual(struct psfd_plan* P, const cplx<double>* b, const cplx<double>* E,
+                          cplx<double>* r, bool adjoint, double* rr2) {
+  CHK(op_apply<double>(P, E, P->tmp64, adjoint ? OP_AH : OP_A, nullptr));
+  CHK(launch_k_residual<double>(r, b, P->tmp64, P->nfield, P->ks, P->part, P->st));
+  CHKS(read_state(P));
+  *rr2 = P->ks_host->red[0];
+  return PSFD_OK;
+}
+
+double inner_tolerance(double tol, double rrel) {
+  static const double floor_tol = [] {
+    const char* s = std::getenv("PSFD_INNER_TOL");
+    return s ? std::atof(s) : 3e-5;
+  }();
+  double t = 0.3 * tol / rrel;
+  if (t < floor_tol) t = floor_tol;
+  if (t > 0.1) t = 0.1;
+  return t;
+}
+
+psfd_status solve_impl(struct psfd_plan* P, const void* b_in, const void* x0, void* E_out,
+                       double tol, int maxit, bool adjoint, psfd_info* info) {
+  psfd_info loc{};
+  const bool mixed = P->prec != PSFD_C128;
+  CHKS(ensure_solver_common(P));
+  if (mixed) {
+    CHKS(ensure_fp32(P));
+    CHKS(ensure_krylov<float>(P));
+  } else {
+    CHKS(ensure_krylov<double>(P));
+  }
+  const int64_t n = P->nfield;
+  hipStream_t st = P->st;
+  cplx<double>* E = static_cast<cplx<double>*>(E_out);
+  const cplx<double>* b = static_cast<const cplx<double>*>(b_in);
+  if (!b) {
+    if (adjoint) return fail(PSFD_ERR_ARG, "the adjoint solve needs an explicit right-hand side");
+    RhsArgs a{P->nx, P->ny, P->nz, P->nabs, P->j0, P->d.pol, P->k0, P->kz0, P->d.theta, P->d.phi,
+              P->zabs64, P->rte64, P->rpe64, P->kd64};
+    CHK(launch_rhs<double>(a, P->b64, st));
+    b = P->b64;
+  }
+  double bnorm2 = 0;
+  CHKS(norm2_host(P, b, &bnorm2));
+  if (!std::isfinite(bnorm2)) return fail(PSFD_ERR_ARG, "right-hand side is not finite");
+  if (bnorm2 == 0.0) {
+    CHK(hipMemsetAsync(E, 0, sizeof(cplx<double>) * n, st));
+    CHK(hipStreamSynchronize(st));
+    loc.status = PSFD_OK;
+    if (info) *info = loc;
+    return PSFD_OK;
+  }
+  bool base = x0 != nullptr;
+  if (x0 && x0 != E_out)
+    CHK(hipMemcpyAsync(E, x0, sizeof(cplx<double>) * n, hipMemcpyDeviceToDevice, st));
+  if (!x0) CHK(hipMemsetAsync(E, 0, sizeof(cplx<double>) * n, st));
+
+  double rr2 = bnorm2;
+  cplx<double>* r64 = mixed ? P->res64 : P->v64[V_R];
+  if (base) {
+    CHKS(true_residual(P, b, E, r64, adjoint, &rr2));
+    loc.applies += 1;
+  } else {
+    CHK(hipMemcpyAsync(r64, b, sizeof(cplx<double>) * n, hipMemcpyDeviceToDevice, st));
+  }
+  if (!std::isfinite(rr2)) return fail(PSFD_ERR_ARG, "initial guess gives a non-finite residual");
+  psfd_status status = PSFD_NOT_CONVERGED;
+  int total = 0;
+  double rrel = std::sqrt(rr2 / bnorm2);
+  for (int outer = 0;; ++outer) {
+    if (rrel <= tol) {
+      status = PSFD_OK;
+      break;
+    }
+    if (total >= maxit || outer > kMaxRestarts) break;
+    RunResult rr;
+    if (!mixed) {
+      CHKS(run_bicgstab<double>(P, adjoint, bnorm2, tol, maxit - total, &rr));
+      cplx<double>* y = P->v64[V_Y];
+      if (P->use_pc) {
+        CHK(op_apply<double>(P, y, P->tmp64, OP_M, nullptr));
+        CHK(launch_k_axpy<double, double>(E, P->tmp64, 1.0, n, st));
+      } else {
+        CHK(launch_k_axpy<double, double>(E, y, 1.0, n, st));
+      }
+    } else {
+      const double rn = std::sqrt(rr2);
+      CHK(launch_k_scale_copy<float, double>(P->v32[V_R], r64, 1.0 / rn, n, st));
+      CHKS(run_bicgstab<float>(P, adjoint, 1.0, inner_tolerance(tol, rrel), maxit - total, &rr));
+      cplx<float>* y = P->v32[V_Y];
+      if (P->use_pc) {
+        CHK(op_apply<float>(P, y, P->v32[V_W], OP_M, nullptr));
+        CHK(launch_k_axpy<double, float>(E, P->v32[V_W], rn, n, st));
+      } else {
+        CHK(launch_k_axpy<double, float>(E, y, rn, n, st));
+      }
+    }
+    total += rr.iters;
+    loc.applies += 2 * rr.iters + 1;
+    loc.rrel_hist_last = rr.rrel_rec;
+    loc.restarts = outer + 1;
+    CHKS(true_residual(P, b, E, r64, adjoint, &rr2));
+    if (!std::isfinite(rr2)) {
+      status = PSFD_BREAKDOWN;
+      rrel = rr2;
+      break;
+    }
+    rrel = std::sqrt(rr2 / bnorm2);
+    if (rr.done == 3 && rrel > tol && outer >= kMaxRestarts) status = PSFD_BREAKDOWN;
+  }
+  loc.iters = total;
+  loc.rrel_true = rrel;
+  loc.status = status;
+  if (info) *info = loc;
+  if (status != PSFD_OK)
+    return fail(status, "solve stopped at relative residual " + std::to_string(rrel));
+  return PSFD_OK;
+}
+
+psfd_status set_eps_impl(struct psfd_plan* P, const void* eps) {
+  const int n = P->nabs * P->nx * P->ny;
+  CHK(launch_eps_contrast(static_cast<const cplx<double>*>(eps), n, P->k0, P->d.eps_bg, P->kd64,
+                          P->kd32, P->st));
+  CHK(hipStreamSynchronize(P->st));
+  return PSFD_OK;
+}
+
+psfd_status plan_impl(const psfd_desc* d, const void* eps, void* stream, struct psfd_plan** out) {
+  CHKS(validate(d));
+  if (!eps || !out) return fail(PSFD_ERR_ARG, "eps and out must not be NULL");
+  struct psfd_plan* P = new (std::nothrow) struct psfd_plan();
+  if (!P) return fail(PSFD_ERR_ALLOC, "host allocation failed");
+  struct Guard {
+    struct psfd_plan* p;
+    ~Guard() { delete p; }
+  } guard{P};
+  P->d = *d;
+  P->st = static_cast<hipStream_t>(stream);
+  P->prec = d->prec;
+  P->use_pc = d->precond != 0;
+  P->ml_eps_h.assign(d->ml_eps, d->ml_eps + 2 * d->n_ml);
+  P->ml_d_h.assign(d->ml_thick, d->ml_thick + d->n_ml);
+  P->d.ml_eps = nullptr;
+  P->d.ml_thick = nullptr;
+  P->nx = d->nx;
+  P->ny = d->ny;
+  P->nabs = d->nz_abs;
+  P->nz = d->nz_abs + d->nz_gap_bot + d->nz_gap_top + 2 * d->nz_pml;
+  P->j0 = d->nz_pml + d->nz_gap_bot;
+  P->jev = P->j0 - 1;
+  P->plane = (int64_t)d->nx * d->ny;
+  P->nfield = 3 * (int64_t)P->nz * P->plane;
+  P->nspec = (int64_t)(3 * P->nz + 3 * P->nabs) * P->plane;
+  P->k0 = kTwoPi / d->lambda;
+  P->kbg = P->k0 * std::sqrt(d->eps_bg);
+  P->kx0 = P->kbg * std::sin(d->theta) * std::cos(d->phi);
+  P->ky0 = P->kbg * std::sin(d->theta) * std::sin(d->phi);
+  P->kz0 = P->kbg * std::cos(d->theta);
+
+  std::vector<double> kx(P->nx), ky(P->ny), kz(P->nz), zabs(P->nabs);
+  for (int m = 0; m < P->nx; ++m) kx[m] = P->kx0 + kTwoPi * (fftfreq(m, P->nx) / (P->nx * d->dx));
+  for (int m = 0; m < P->ny; ++m) ky[m] = P->ky0 + kTwoPi * (fftfreq(m, P->ny) / (P->ny * d->dy));
+  for (int m = 0; m < P->nz; ++m) kz[m] = kTwoPi * (fftfreq(m, P->nz) / (P->nz * d->dz));
+  for (int j = 0; j < P->nabs; ++j) zabs[j] = (j + 0.5) * d->dz;
+  std::vector<cplx<double>> inv_s(P->nz);
+  const int np = d->nz_pml;
+  for (int j = 0; j < P->nz; ++j) {
+    double dist = -1.0;
+    if (j < np) dist = (np - j - 0.5) * d->dz;
+    else if (j >= P->nz - np) dist = (j - (P->nz - np) + 0.5) * d->dz;
+    cplx<double> s = {1.0, 0.0};
+    if (dist >= 0.0) s.im = d->pml_sigma0 * std::pow(dist / (np * d->dz), (double)d->pml_order);
+    inv_s[j] = cdiv(cplx<double>{1.0, 0.0}, s);
+  }
+  const auto twx = twiddles(P->nx), twy = twiddles(P->ny), twz = twiddles(P->nz);
+
+  OpTables<double>& t = P->t64;
+  t.nx = P->nx; t.ny = P->ny; t.nz = P->nz; t.nabs = P->nabs; t.j0 = P->j0; t.jev = P->jev;
+  double *kx_d, *ky_d, *kz_d;
+  cplx<double>*is_d, *twx_d, *twy_d, *twz_d;
+  CHKS(upload(P, &kx_d, kx));
+  CHKS(upload(P, &ky_d, ky));
+  CHKS(upload(P, &kz_d, kz));
+  CHKS(upload(P, &P->zabs64, zabs));
+  CHKS(upload(P, &is_d, inv_s));
+  CHKS(upload(P, &twx_d, twx));
+  CHKS(upload(P, &twy_d, twy));
+  CHKS(upload(P, &twz_d, twz));
+  t.kx = kx_d; t.ky = ky_d; t.kz = kz_d; t.inv_s = is_d; t.zabs = P->zabs64;
+  t.tw_x = twx_d; t.tw_y = twy_d; t.tw_z = twz_d;
+  t.kbg2 = P->kbg * P->kbg;
+  t.k0 = P->k0;
+  t.dz = d->dz;
+  t.cphi = std::cos(d->phi);
+  t.sphi = std::sin(d->phi);
+  const double kref = d->pc_kref > 0 ? d->pc_kref : P->kbg;
+  t.pc_mmin = d->pc_mmin;
+  t.pc_kref2 = kref * kref;
+  t.pc_gamma = d->pc_gamma;
+  t.pc_reg = d->pc_reg;
+  t.pc_bf16 = d->prec == PSFD_C64_BF16PC_REFINE64;
+
+  // multilayer reflections per lateral mode
+  CHKS(dalloc(P, &P->rte64, (size_t)P->plane));
+  CHKS(dalloc(P, &P->rpe64, (size_t)P->plane));
+  cplx<double>* ml_eps_d = nullptr;
+  double* ml_d_d = nullptr;
+  std::vector<cplx<double>> mle(d->n_ml);
+  for (int i = 0; i < d->n_ml; ++i) mle[i] = {P->ml_eps_h[2 * i], P->ml_eps_h[2 * i + 1]};
+  CHKS(upload(P, &ml_eps_d, mle));
+  CHKS(upload(P, &ml_d_d, P->ml_d_h));
+  TmmArgs ta{P->nx, P->ny, kx_d, ky_d, P->k0, d->eps_bg, d->n_ml, ml_eps_d, ml_d_d,
+             cplx<double>{d->eps_sub[0], d->eps_sub[1]}};
+  CHK(launch_tmm(ta, P->rte64, P->rpe64, P->st));
+  t.r_te = P->rte64;
+  t.r_pe = P->rpe64;
+
+  CHKS(dalloc(P, &P->kd64, (size_t)P->nabs * P->plane));
+  t.kd = P->kd64;
+  CHKS(dalloc(P, &P->S64, (size_t)P->nspec));
+  CHKS(dalloc(P, &P->UW64, (size_t)P->nspec));
+
+  if (P->prec != PSFD_C128) {
+    OpTables<float>& f = P->t32;
+    f.nx = t.nx; f.ny = t.ny; f.nz = t.nz; f.nabs = t.nabs; f.j0 = t.j0; f.jev = t.jev;
+    float *fkx, *fky, *fkz, *fza;
+    cplx<float>*fis, *ftx, *fty, *ftz, *frte, *frpe;
+    CHKS(upload(P, &fkx, to_t<float>(kx)));
+    CHKS(upload(P, &fky, to_t<float>(ky)));
+    CHKS(upload(P, &fkz, to_t<float>(kz)));
+    CHKS(upload(P, &fza, to_t<float>(zabs)));
+    CHKS(upload(P, &fis, to_tc<float>(inv_s)));
+    CHKS(upload(P, &ftx, to_tc<float>(twx)));
+    CHKS(upload(P, &fty, to_tc<float>(twy)));
+    CHKS(upload(P, &ftz, to_tc<float>(twz)));
+    CHKS(dalloc(P, &frte, (size_t)P->plane));
+    CHKS(dalloc(P, &frpe, (size_t)P->plane));
+    CHK(launch_k_scale_copy<float, double>(frte, P->rte64, 1.0, P->plane, P->st));
+    CHK(launch_k_scale_copy<float, double>(frpe, P->rpe64, 1.0, P->plane, P->st));
+    CHKS(dalloc(P, &P->kd32, (size_t)P->nabs * P->plane));
+    f.kx = fkx; f.ky = fky; f.kz = fkz; f.zabs = fza; f.inv_s = fis;
+    f.tw_x = ftx; f.tw_y = fty; f.tw_z = ftz; f.r_te = frte; f.r_pe = frpe; f.kd = P->kd32;
+    f.kbg2 = (float)t.kbg2; f.k0 = (float)t.k0; f.dz = (float)t.dz;
+    f.cphi = (float)t.cphi; f.sphi = (float)t.sphi;
+    f.pc_mmin = (float)t.pc_mmin; f.pc_kref2 = (float)t.pc_kref2;
+    f.pc_gamma = (float)t.pc_gamma; f.pc_reg = (float)t.pc_reg; f.pc_bf16 = t.pc_bf16;
+    CHKS(ensure_fp32(P));
+  }
+  CHKS(set_eps_impl(P, eps));
+  CHK(hipStreamSynchronize(P->st));
+  guard.p = nullptr;
+  *out = P;
+  return PSFD_OK;
+}
+
+psfd_status layout_impl(const psfd_desc* d, const double* a_bin, const double eps_abs[2],
+                        double sigma, void* eps_out, void* stream) {
+  if (!d || !a_bin || !eps_abs || !eps_out) return fail(PSFD_ERR_ARG, "NULL argument");
+  if (!lateral_size_ok(d->nx) || !lateral_size_ok(d->ny) || d->nz_abs < 1)
+    return fail(PSFD_ERR_ARG, "unsupported lateral size or nz_abs < 1");
+  if (!(sigma >= 0) || !(d->dx > 0) || !(d->dy > 0)) return fail(PSFD_ERR_ARG, "bad sigma/dx/dy");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  struct psfd_plan tmp;  // owns the temporaries
+  tmp.st = st;
+  const int nx = d->nx, ny = d->ny;
+  OpTables<double> t{};
+  t.nx = nx; t.ny = ny; t.nz = 1; t.nabs = 1; t.j0 = 0;
+  cplx<double>*twx, *twy, *A, *B;
+  CHKS(upload(&tmp, &twx, twiddles(nx)));
+  CHKS(upload(&tmp, &twy, twiddles(ny)));
+  t.tw_x = twx;
+  t.tw_y = twy;
+  CHKS(dalloc(&tmp, &A, (size_t)nx * ny));
+  CHKS(dalloc(&tmp, &B, (size_t)nx * ny));
+  CHK(launch_real_to_cplx(a_bin, nx * ny, A, st));
+  CHK(launch_plane_fft<double>(t, A, B, false, st));
+  CHK(launch_smooth_mult(B, nx, ny, d->dx, d->dy, sigma, st));
+  CHK(launch_plane_fft<double>(t, B, A, true, st));
+  CHK(launch_fill_eps(A, nx, ny, d->nz_abs, 1.0 / ((double)nx * ny), d->eps_bg,
+                      cplx<double>{eps_abs[0], eps_abs[1]}, static_cast<cplx<double>*>(eps_out),
+                      st));
+  CHK(hipStreamSynchronize(st));
+  return PSFD_OK;
+}
+
+template <typename T>
+psfd_status apply_entry(struct psfd_plan* P, const void* x, void* y, int op) {
+  if (!P || !x || !y) return fail(PSFD_ERR_ARG, "NULL argument");
+  if (x == y) return fail(PSFD_ERR_ARG, "x and y must not overlap");
+  if (sizeof(T) == 4) CHKS(ensure_fp32(P));
+  if (sizeof(T) == 4 && !P->t32.kx)
+    return fail(PSFD_ERR_ARG, "complex64 entry points need a PSFD_C64_* plan");
+  CHK(op_apply<T>(P, static_cast<const cplx<T>*>(x), static_cast<cplx<T>*>(y), op, nullptr));
+  return PSFD_OK;
+}
+
+template <typename F>
+psfd_status guarded(F&& f) {
+  try {
+    g_err.clear();
+    return f();
+  } catch (const std::bad_alloc&) {
+    return fail(PSFD_ERR_ALLOC, "host allocation failed");
+  } catch (...) {
+    return fail(PSFD_ERR_HIP, "unexpected exception");
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+psfd_status psfd_layout_eps(const psfd_desc* d, const double* a_bin_dev, const double eps_abs[2],
+                            double sigma, void* eps_out, void* hip_stream) {
+  return guarded([&] { return layout_impl(d, a_bin_dev, eps_abs, sigma, eps_out, hip_stream); });
+}
+
+psfd_status psfd_plan(const psfd_desc* d, const void* eps_abs_dev, void* hip_stream,
+                      psfd_plan_t* out) {
+  return guarded([&] { return plan_impl(d, eps_abs_dev, hip_stream, out); });
+}
+
+psfd_status psfd_set_eps(psfd_plan_t p, const void* eps_abs_dev) {
+  if (!p || !eps_abs_dev) return fail(PSFD_ERR_ARG, "NULL argument");
+  return guarded([&] { return set_eps_impl(p, eps_abs_dev); });
+}
+
+psfd_status psfd_rhs(psfd_plan_t p, void* b) {
+  if (!p || !b) return fail(PSFD_ERR_ARG, "NULL argument");
+  return guarded([&]() -> psfd_status {
+    RhsArgs a{p->nx, p->ny, p->nz, p->nabs, p->j0, p->d.pol, p->k0, p->kz0, p->d.theta, p->d.phi,
+              p->zabs64, p->rte64, p->rpe64, p->kd64};
+    CHK(launch_rhs<double>(a, static_cast<cplx<double>*>(b), p->st));
+    return PSFD_OK;
+  });
+}
+
+psfd_status psfd_apply(psfd_plan_t p, const void* x, void* y) {
+  return guarded([&] { return apply_entry<double>(p, x, y, OP_A); });
+}
+psfd_status psfd_adjoint(psfd_plan_t p, const void* x, void* y) {
+  return guarded([&] { return apply_entry<double>(p, x, y, OP_AH); });
+}
+psfd_status psfd_precond(psfd_plan_t p, const void* x, void* y) {
+  return guarded([&] { return apply_entry<double>(p, x, y, OP_M); });
+}
+psfd_status psfd_apply_c64(psfd_plan_t p, const void* x, void* y) {
+  return guarded([&] { return apply_entry<float>(p, x, y, OP_A); });
+}
+psfd_status psfd_adjoint_c64(psfd_plan_t p, const void* x, void* y) {
+  return guarded([&] { return apply_entry<float>(p, x, y, OP_AH); });
+}
+psfd_status psfd_precond_c64(psfd_plan_t p, const void* x, void* y) {
+  return guarded([&] { return apply_entry<float>(p, x, y, OP_M); });
+}
+
+psfd_status psfd_solve(psfd_plan_t p, const void* b, const void* x0, void* E, double tol,
+                       int32_t maxit, int32_t adjoint, psfd_info* info) {
+  if (!p || !E) return fail(PSFD_ERR_ARG, "NULL argument");
+  if (!(tol > 0) || maxit < 0) return fail(PSFD_ERR_ARG, "need tol > 0 and maxit >= 0");
+  if (b && b == E) return fail(PSFD_ERR_ARG, "b and E must not overlap");
+  return guarded([&] { return solve_impl(p, b, x0, E, tol, maxit, adjoint != 0, info); });
+}
+
+psfd_status psfd_ml_reflection(psfd_plan_t p, void* r_te, void* r_pe) {
+  if (!p || !r_te || !r_pe) return fail(PSFD_ERR_ARG, "NULL argument");
+  return guarded([&]() -> psfd_status {
+    const size_t bytes = sizeof(cplx<double>) * (size_t)p->plane;
+    CHK(hipMemcpyAsync(r_te, p->rte64, bytes, hipMemcpyDeviceToDevice, p->st));
+    CHK(hipMemcpyAsync(r_pe, p->rpe64, bytes, hipMemcpyDeviceToDevice, p->st));
+    return PSFD_OK;
+  });
+}
+
+int64_t psfd_field_size(psfd_plan_t p) { return p ? p->nfield : 0; }
+
+void psfd_destroy(psfd_plan_t p) {
+  if (!p) return;
+  if (p->st) (void)hipStreamSynchronize(p->st);
+  else (void)hipDeviceSynchronize();
+  delete p;
+}
+
+const char* psfd_last_error(void) { return g_err.c_str(); }
+
+}  // extern "C"

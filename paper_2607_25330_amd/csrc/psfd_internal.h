@@ -1,0 +1,154 @@
+// Internal declarations shared by the host driver and the kernel files.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+
+#include "cplx.h"
+
+namespace psfd {
+
+// Sizes the kernels are instantiated for.
+bool lateral_size_ok(int n);
+bool axial_size_ok(int n);
+
+// Grid geometry and per-axis tables shared by the operator kernels.
+template <typename T>
+struct OpTables {
+  int nx, ny, nz, nabs, j0, jev;
+  const T* kx;              // [nx] Bloch-shifted lateral wavenumbers
+  const T* ky;              // [ny]
+  const T* kz;              // [nz] axial wavenumbers (fftfreq order)
+  const cplx<T>* inv_s;     // [nz] 1 / s(z), PML stretch
+  const T* zabs;            // [nabs] z of the absorber row centres (z_ml = 0)
+  const cplx<T>* r_te;      // [ny][nx] multilayer reflection, TE
+  const cplx<T>* r_pe;      // [ny][nx] multilayer reflection, TM (tangential E)
+  const cplx<T>* kd;        // [nabs][ny][nx] k0^2 (eps - eps_bg)
+  const cplx<T>* tw_x;      // twiddles exp(-2 pi i m / nx)
+  const cplx<T>* tw_y;
+  const cplx<T>* tw_z;
+  T kbg2;                   // (k0 sqrt(eps_bg))^2
+  T k0;
+  T dz;
+  T cphi, sphi;             // incidence-plane basis at kt = 0
+  // spectral damping multiplier m(k)
+  T pc_mmin, pc_kref2, pc_gamma, pc_reg;
+  int pc_bf16;              // round m(k) to bfloat16
+  const int* skip;          // device flag: when non-null and set, operator kernels return at once
+};
+
+enum AxialMode { AX_A = 0, AX_AM = 1, AX_AH = 2, AX_M = 3 };
+enum CombineMode { CB_PLAIN = 0, CB_FWD = 1, CB_ADJ = 2 };
+
+// ---- lateral FFT launchers (fft_lateral.hip)
+// Forward x-FFT of rows.  nrows_main rows come straight from `in`; for the
+// adjoint, extra = 3 * nabs planes follow whose rows are conj(kd) * in on the
+// absorber rows.
+template <typename T>
+hipError_t launch_xfft_fwd(const OpTables<T>& t, const cplx<T>* in, cplx<T>* out, bool adj_extra,
+                           hipStream_t st);
+// In-place y-FFT of nplanes planes of ny x nx.
+template <typename T>
+hipError_t launch_yfft(const OpTables<T>& t, cplx<T>* buf, int nplanes, bool inverse,
+                       hipStream_t st);
+// Inverse x-FFT of the 3 Nz U planes (+ W planes) with the combine epilogue.
+template <typename T>
+hipError_t launch_xfft_inv(const OpTables<T>& t, const cplx<T>* UW, cplx<T>* y, int cmode,
+                           const cplx<T>* x, hipStream_t st);
+// 2-D FFT of a single plane (layout smoothing).  Forward: in -> out.
+// Inverse (unnormalised): y pass in place on `in`, x pass into `out`.
+template <typename T>
+hipError_t launch_plane_fft(const OpTables<T>& t, cplx<T>* in, cplx<T>* out, bool inverse,
+                            hipStream_t st);
+
+// ---- axial launcher (axial.hip)
+template <typename T>
+hipError_t launch_axial(const OpTables<T>& t, const cplx<T>* S, cplx<T>* UW, int mode,
+                        hipStream_t st);
+
+// ---- setup kernels (setup.hip)
+struct TmmArgs {
+  int nx, ny;
+  const double* kx;
+  const double* ky;
+  double k0, eps_bg;
+  int nl;
+  const cplx<double>* eps_l;  // device [nl]
+  const double* d_l;          // device [nl]
+  cplx<double> eps_sub;
+};
+hipError_t launch_tmm(const TmmArgs& a, cplx<double>* r_te, cplx<double>* r_pe, hipStream_t st);
+
+struct RhsArgs {
+  int nx, ny, nz, nabs, j0, pol;
+  double k0, kz0, theta, phi;
+  const double* zabs;
+  const cplx<double>* r_te;  // mode (0, 0) is the incidence mode
+  const cplx<double>* r_pe;
+  const cplx<double>* kd;
+};
+template <typename T>
+hipError_t launch_rhs(const RhsArgs& a, cplx<T>* b, hipStream_t st);
+
+hipError_t launch_eps_contrast(const cplx<double>* eps, int n, double k0, double eps_bg,
+                               cplx<double>* kd64, cplx<float>* kd32, hipStream_t st);
+hipError_t launch_smooth_mult(cplx<double>* plane, int nx, int ny, double dx, double dy,
+                              double sigma, hipStream_t st);
+hipError_t launch_fill_eps(const cplx<double>* plane, int nx, int ny, int nabs, double scale,
+                           double eps_bg, cplx<double> eps_abs, cplx<double>* eps_out,
+                           hipStream_t st);
+hipError_t launch_real_to_cplx(const double* a, int n, cplx<double>* out, hipStream_t st);
+
+// ---- Krylov kernels (krylov.hip)
+struct KState {
+  double rho[2], rho_prev[2], alpha[2], omega[2];
+  double rv[2], ts[2], tt;
+  double snorm2, rnorm2, bnorm2, tol2, rh_norm2;
+  double red[4];        // generic reduction outputs
+  int iter, done, status, half;
+  unsigned int ticket;
+  unsigned int pad[3];
+};
+
+constexpr int KRED_BLOCKS = 512;
+constexpr int KRED_THREADS = 256;
+
+template <typename T>
+hipError_t launch_k_p_update(cplx<T>* p, const cplx<T>* r, const cplx<T>* v, int64_t n,
+                             KState* ks, hipStream_t st);
+template <typename T>
+hipError_t launch_k_dot_rv(const cplx<T>* rh, const cplx<T>* v, int64_t n, KState* ks,
+                           double* part, hipStream_t st);
+template <typename T>
+hipError_t launch_k_s_update(cplx<T>* s, const cplx<T>* r, const cplx<T>* v, int64_t n,
+                             KState* ks, double* part, hipStream_t st);
+template <typename T>
+hipError_t launch_k_dot_ts(const cplx<T>* t, const cplx<T>* s, int64_t n, KState* ks,
+                           double* part, hipStream_t st);
+template <typename T>
+hipError_t launch_k_xr_update(cplx<T>* y, cplx<T>* r, const cplx<T>* p, const cplx<T>* s,
+                              const cplx<T>* t, const cplx<T>* rh, int64_t n, KState* ks,
+                              double* part, hipStream_t st);
+// Start a BiCGSTAB run: rh = r, rho = <r, r>, p = v = y = 0, scalars reset.
+template <typename T>
+hipError_t launch_k_init(cplx<T>* rh, const cplx<T>* r, cplx<T>* p, cplx<T>* v, cplx<T>* y,
+                         int64_t n, KState* ks, double* part, double bnorm2, double tol2,
+                         hipStream_t st);
+// out = a - b (residual), ||out||^2 -> ks->red[0]
+template <typename T>
+hipError_t launch_k_residual(cplx<T>* out, const cplx<T>* a, const cplx<T>* b, int64_t n,
+                             KState* ks, double* part, hipStream_t st);
+// ||a||^2 -> ks->red[0]
+template <typename T>
+hipError_t launch_k_norm2(const cplx<T>* a, int64_t n, KState* ks, double* part,
+                          hipStream_t st);
+// y += a * x with a a real scalar held on the host
+template <typename TY, typename TX>
+hipError_t launch_k_axpy(cplx<TY>* y, const cplx<TX>* x, double a, int64_t n, hipStream_t st);
+// y = a * x (precision conversion with scaling)
+template <typename TY, typename TX>
+hipError_t launch_k_scale_copy(cplx<TY>* y, const cplx<TX>* x, double a, int64_t n,
+                               hipStream_t st);
+
+}  // namespace psfd

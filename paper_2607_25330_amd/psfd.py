@@ -1,0 +1,271 @@
+"""Thin ctypes binding of libpsfd.so (the C ABI in include/psfd.h).
+
+Argument marshalling only: every step of the solve runs in the library's HIP
+kernels.  PyTorch provides device memory and the current stream.  The
+library must be built (``__graft_entry__.build()`` or
+``python -m paper_2607_25330_amd.build``); importing works without it, but
+the first call raises ``PsfdLibraryMissing``.
+"""
+
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpsfd.so")
+HEADER_PATH = os.path.join(os.path.dirname(_HERE), "include", "psfd.h")
+
+PSFD_OK, PSFD_ERR_ARG, PSFD_ERR_ALLOC, PSFD_ERR_HIP, PSFD_NOT_CONVERGED, PSFD_BREAKDOWN = range(6)
+STATUS_NAMES = {0: "OK", 1: "ERR_ARG", 2: "ERR_ALLOC", 3: "ERR_HIP", 4: "NOT_CONVERGED",
+                5: "BREAKDOWN"}
+PSFD_C128, PSFD_C64_REFINE64, PSFD_C64_BF16PC_REFINE64 = 0, 1, 2
+
+
+class PsfdLibraryMissing(ImportError):
+    pass
+
+
+class PsfdError(RuntimeError):
+    def __init__(self, func, status, msg):
+        super().__init__(f"{func}: {STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+c_int32, c_int64, c_double, c_void_p = ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_void_p
+c_dp = ctypes.POINTER(c_double)
+
+
+class Desc(ctypes.Structure):
+    _fields_ = [
+        ("nx", c_int32), ("ny", c_int32), ("nz_abs", c_int32), ("nz_gap_bot", c_int32),
+        ("nz_gap_top", c_int32), ("nz_pml", c_int32),
+        ("dx", c_double), ("dy", c_double), ("dz", c_double), ("lambda_", c_double),
+        ("theta", c_double), ("phi", c_double), ("pol", c_int32),
+        ("eps_bg", c_double),
+        ("n_ml", c_int32), ("ml_eps", c_dp), ("ml_thick", c_dp), ("eps_sub", c_double * 2),
+        ("pml_sigma0", c_double), ("pml_order", c_int32), ("precond", c_int32),
+        ("pc_mmin", c_double), ("pc_kref", c_double), ("pc_gamma", c_double), ("pc_reg", c_double),
+        ("prec", c_int32),
+    ]
+
+
+class Info(ctypes.Structure):
+    _fields_ = [("iters", c_int32), ("status", c_int32), ("restarts", c_int32),
+                ("applies", c_int32), ("rrel_true", c_double), ("rrel_hist_last", c_double)]
+
+
+_SIGS = {
+    "psfd_layout_eps": [ctypes.POINTER(Desc), c_void_p, c_dp, c_double, c_void_p, c_void_p],
+    "psfd_plan": [ctypes.POINTER(Desc), c_void_p, c_void_p, ctypes.POINTER(c_void_p)],
+    "psfd_set_eps": [c_void_p, c_void_p],
+    "psfd_rhs": [c_void_p, c_void_p],
+    "psfd_apply": [c_void_p, c_void_p, c_void_p],
+    "psfd_adjoint": [c_void_p, c_void_p, c_void_p],
+    "psfd_precond": [c_void_p, c_void_p, c_void_p],
+    "psfd_apply_c64": [c_void_p, c_void_p, c_void_p],
+    "psfd_adjoint_c64": [c_void_p, c_void_p, c_void_p],
+    "psfd_precond_c64": [c_void_p, c_void_p, c_void_p],
+    "psfd_solve": [c_void_p, c_void_p, c_void_p, c_void_p, c_double, c_int32, c_int32,
+                   ctypes.POINTER(Info)],
+    "psfd_ml_reflection": [c_void_p, c_void_p, c_void_p],
+}
+
+_lib = None
+
+
+def lib():
+    """Load libpsfd.so (raises PsfdLibraryMissing if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise PsfdLibraryMissing(f"{LIB_PATH} is not built: run __graft_entry__.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, args in _SIGS.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = c_int32
+        L.psfd_field_size.argtypes = [c_void_p]
+        L.psfd_field_size.restype = c_int64
+        L.psfd_destroy.argtypes = [c_void_p]
+        L.psfd_destroy.restype = None
+        L.psfd_last_error.argtypes = []
+        L.psfd_last_error.restype = ctypes.c_char_p
+        _lib = L
+    return _lib
+
+
+def _call(name, *args):
+    st = getattr(lib(), name)(*args)
+    if st != PSFD_OK:
+        raise PsfdError(name, st, lib().psfd_last_error().decode())
+    return st
+
+
+def make_desc(cfg, prec=PSFD_C128):
+    """psfd_desc from a configuration dict (keys as in psfd_synth.configs); returns (desc, keepalive)."""
+    n_ml = len(cfg["ml_eps"])
+    eps_arr = (c_double * max(2 * n_ml, 1))(*[v for e in cfg["ml_eps"] for v in (e.real, e.imag)])
+    d_arr = (c_double * max(n_ml, 1))(*cfg["ml_thick"])
+    es = complex(cfg["eps_sub"])
+    d = Desc(
+        nx=cfg["nx"], ny=cfg["ny"], nz_abs=cfg["nz_abs"], nz_gap_bot=cfg["nz_gap_bot"],
+        nz_gap_top=cfg["nz_gap_top"], nz_pml=cfg["nz_pml"],
+        dx=cfg["dx"], dy=cfg["dy"], dz=cfg["dz"], lambda_=cfg["lam"],
+        theta=cfg["theta"], phi=cfg["phi"], pol=cfg["pol"], eps_bg=float(cfg["eps_bg"]),
+        n_ml=n_ml, ml_eps=ctypes.cast(eps_arr, c_dp), ml_thick=ctypes.cast(d_arr, c_dp),
+        eps_sub=(c_double * 2)(es.real, es.imag),
+        pml_sigma0=cfg["pml_sigma0"], pml_order=cfg["pml_order"], precond=int(cfg["precond"]),
+        pc_mmin=cfg["pc_mmin"], pc_kref=cfg["pc_kref"], pc_gamma=cfg["pc_gamma"],
+        pc_reg=cfg["pc_reg"], prec=int(prec))
+    return d, (eps_arr, d_arr)
+
+
+def _stream_handle():
+    return c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t, dtype, shape=None, name="tensor"):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise ValueError(f"{name} must be a CUDA tensor")
+    if t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+    return c_void_p(t.data_ptr())
+
+
+def nz_of(cfg):
+    return cfg["nz_abs"] + cfg["nz_gap_bot"] + cfg["nz_gap_top"] + 2 * cfg["nz_pml"]
+
+
+def psfd_layout_eps(cfg, a_bin, eps_abs, sigma=None):
+    """Smoothed-layout permittivity on absorber rows, (nz_abs, ny, nx) complex128."""
+    d, keep = make_desc(cfg)
+    a = a_bin.to(torch.float64).contiguous()
+    out = torch.empty((cfg["nz_abs"], cfg["ny"], cfg["nx"]), dtype=torch.complex128, device=a.device)
+    e = complex(eps_abs)
+    ea = (c_double * 2)(e.real, e.imag)
+    sig = cfg.get("smooth_sigma", 1.0) if sigma is None else sigma
+    _call("psfd_layout_eps", ctypes.byref(d), _ptr(a, torch.float64, (cfg["ny"], cfg["nx"]), "a_bin"),
+          ctypes.cast(ea, c_dp), c_double(sig), _ptr(out, torch.complex128), _stream_handle())
+    return out
+
+
+class Plan:
+    """A psfd_plan bound to the current torch stream."""
+
+    def __init__(self, cfg, eps, prec=PSFD_C128):
+        self.cfg = dict(cfg)
+        self.prec = prec
+        self.nz = nz_of(cfg)
+        self.shape = (3, self.nz, cfg["ny"], cfg["nx"])
+        self.eps_shape = (cfg["nz_abs"], cfg["ny"], cfg["nx"])
+        d, keep = make_desc(cfg, prec)
+        h = c_void_p()
+        _call("psfd_plan", ctypes.byref(d), _ptr(eps, torch.complex128, self.eps_shape, "eps"),
+              _stream_handle(), ctypes.byref(h))
+        self._h = h
+        self.device = eps.device
+
+    def _field(self, dtype=torch.complex128):
+        return torch.empty(self.shape, dtype=dtype, device=self.device)
+
+    def _unary(self, name, x, out, dtype):
+        y = self._field(dtype) if out is None else out
+        _call(name, self._h, _ptr(x, dtype, self.shape, "x"), _ptr(y, dtype, self.shape, "y"))
+        return y
+
+    def apply(self, x, out=None):
+        return self._unary("psfd_apply", x, out, torch.complex128)
+
+    def adjoint(self, x, out=None):
+        return self._unary("psfd_adjoint", x, out, torch.complex128)
+
+    def precond(self, x, out=None):
+        return self._unary("psfd_precond", x, out, torch.complex128)
+
+    def apply_c64(self, x, out=None):
+        return self._unary("psfd_apply_c64", x, out, torch.complex64)
+
+    def adjoint_c64(self, x, out=None):
+        return self._unary("psfd_adjoint_c64", x, out, torch.complex64)
+
+    def precond_c64(self, x, out=None):
+        return self._unary("psfd_precond_c64", x, out, torch.complex64)
+
+    def rhs(self, out=None):
+        b = self._field() if out is None else out
+        _call("psfd_rhs", self._h, _ptr(b, torch.complex128, self.shape, "b"))
+        return b
+
+    def set_eps(self, eps):
+        _call("psfd_set_eps", self._h, _ptr(eps, torch.complex128, self.eps_shape, "eps"))
+
+    def ml_reflection(self):
+        n = (self.cfg["ny"], self.cfg["nx"])
+        rte = torch.empty(n, dtype=torch.complex128, device=self.device)
+        rpe = torch.empty(n, dtype=torch.complex128, device=self.device)
+        _call("psfd_ml_reflection", self._h, _ptr(rte, torch.complex128), _ptr(rpe, torch.complex128))
+        return rte, rpe
+
+    def solve(self, b=None, x0=None, tol=1e-6, maxit=20000, adjoint=False, out=None,
+              check=True):
+        """Returns (E, info dict).  With check=False a non-converged solve returns its status."""
+        E = self._field() if out is None else out
+        info = Info()
+        bp = c_void_p(None) if b is None else _ptr(b, torch.complex128, self.shape, "b")
+        xp = c_void_p(None) if x0 is None else _ptr(x0, torch.complex128, self.shape, "x0")
+        st = lib().psfd_solve(self._h, bp, xp, _ptr(E, torch.complex128, self.shape, "E"),
+                              c_double(tol), c_int32(maxit), c_int32(1 if adjoint else 0),
+                              ctypes.byref(info))
+        if check and st != PSFD_OK:
+            raise PsfdError("psfd_solve", st, lib().psfd_last_error().decode())
+        return E, {"iters": info.iters, "status": STATUS_NAMES.get(st, st),
+                   "restarts": info.restarts, "applies": info.applies,
+                   "rrel": info.rrel_true, "rrel_rec": info.rrel_hist_last}
+
+    def field_size(self):
+        return int(lib().psfd_field_size(self._h))
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().psfd_destroy(self._h)
+            self._h = c_void_p(None)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# Module-level names matching the C ABI.
+def psfd_plan(cfg, eps, prec=PSFD_C128):
+    return Plan(cfg, eps, prec)
+
+
+def psfd_apply(plan, x, y=None):
+    return plan.apply(x, y)
+
+
+def psfd_adjoint(plan, x, y=None):
+    return plan.adjoint(x, y)
+
+
+def psfd_precond(plan, x, y=None):
+    return plan.precond(x, y)
+
+
+def psfd_rhs(plan, b=None):
+    return plan.rhs(b)
+
+
+def psfd_solve(plan, b=None, x0=None, tol=1e-6, maxit=20000, adjoint=False):
+    return plan.solve(b, x0, tol, maxit, adjoint)
+
+
+def psfd_destroy(plan):
+    plan.close()
