@@ -1,0 +1,216 @@
+"""PSFD solves/s at relative residual 1e-6 on one MI355X.
+
+Workload (one "step"): one seeded 256 x 256 mask clip (2 nm pitch, 32
+absorber cells over 60 nm, Nz = 48), alternating line/space and contact-hole
+layouts, solved for TE and TM at 6 deg incidence: layout smoothing -> plan
+(TMM per lateral mode) -> source -> right-preconditioned BiCGSTAB to a true
+FP64 relative residual of 1e-6 -> field.  Two solves per step.
+
+The headline value is the mixed path (complex64 operator, preconditioner and
+Krylov vectors inside FP64 iterative refinement); the plain FP64 path is
+timed on the same layouts and reported beside it.  Inputs (binary layouts)
+are resident on the device before the timed region starts.
+
+Prints one JSON line.  `--gpus N` with N > 1 is not supported (one GPU).
+"""
+
+import argparse
+import json
+import math
+import os
+import subprocess
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "PSFD solves/s at rel. residual 1e-6 (mixed/batched vs FP64 plain); HBM GB/s"
+HBM_PEAK_GBS = 8000.0
+WORKLOAD = ("256x256 lateral @2nm, 32 absorber cells / 60 nm (Nz=48), seeded line/space + "
+            "contact layouts, TE+TM, 6 deg, tol 1e-6, plan+TMM+source+solve")
+
+
+def layouts(n, nx, ny, dx):
+    import numpy as np
+    from psfd_synth import contact_holes, line_space
+    out = []
+    for i in range(n):
+        rng = np.random.default_rng(100 + i)
+        out.append(line_space(nx, ny, dx, rng) if i % 2 == 0 else contact_holes(nx, ny, dx, rng))
+    return out
+
+
+def run_steps(psfd, cfgs, a_dev, idx, prec, tol, maxit, profile=None):
+    """Solve every (layout, polarisation); returns list of infos and profile sums."""
+    from psfd_synth import eps_absorber_default
+    eps_abs = eps_absorber_default()
+    infos = []
+    prof = [0.0, 0, 0.0]
+    for i in idx:
+        for cfg in cfgs:
+            eps = psfd.psfd_layout_eps(cfg, a_dev[i], eps_abs)
+            plan = psfd.Plan(cfg, eps, prec)
+            if profile:
+                plan.profile_enable(profile)
+            _, info = plan.solve(tol=tol, maxit=maxit, check=False)
+            if profile:
+                ms, n, b = plan.profile_read()
+                prof[0] += ms
+                prof[1] += n
+                prof[2] += b
+            plan.close()
+            infos.append(info)
+    return infos, prof
+
+
+def cpu_leg(iters_proj, sample_iters):
+    """Oracle timing on the host: setup + `sample_iters` BiCGSTAB iterations of the
+    same workload (first layout, TE), projected to a full solve with the GPU's
+    FP64 iteration count.  Runs single-threaded (pocketfft is single-threaded;
+    BLAS threads are pinned to 1 by the caller)."""
+    import numpy as np
+    from oracle import psfd_ref as R
+    from psfd_synth import config_c2, eps_absorber_default
+    cfg = config_c2(0)
+    a = layouts(1, cfg["nx"], cfg["ny"], cfg["dx"])[0]
+    t0 = time.perf_counter()
+    P = R.Problem(cfg, R.eps_from_fill(cfg, R.smooth_layout(cfg, a), eps_absorber_default()))
+    b = R.rhs(P)
+    t1 = time.perf_counter()
+    bnorm = float(np.linalg.norm(b))
+    _, iters, _ = R.bicgstab_core(lambda u: R.apply_A(P, u), lambda u: R.apply_M(P, u), b, bnorm,
+                                  1e-30, sample_iters)
+    t2 = time.perf_counter()
+    info = {"iters": iters}
+    per_iter = (t2 - t1) / max(iters, 1)
+    setup = t1 - t0
+    solve_s = setup + per_iter * iters_proj
+    return {"value": 1.0 / solve_s, "unit": "solves/s", "cores": 1, "kind": "oracle",
+            "sample": (f"numpy FP64 oracle, first layout TE: setup {setup:.2f} s + "
+                       f"{info['iters']} BiCGSTAB iterations at {per_iter:.2f} s/iteration, "
+                       f"projected to {iters_proj:.0f} iterations (GPU FP64 mean); wall "
+                       f"{t2 - t0:.1f} s"),
+            "s_per_iteration": per_iter, "setup_s": setup, "projected": True}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=4)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--tol", type=float, default=1e-6)
+    ap.add_argument("--maxit", type=int, default=20000)
+    ap.add_argument("--roofline-kernel", default="axial", choices=["axial", "yfft", "xfwd", "xinv"])
+    ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 leg")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample-iters", type=int, default=4)
+    ap.add_argument("--cpu-leg", type=float, default=None, help=argparse.SUPPRESS)
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="also run one device copy of this size (for counter calibration)")
+    args = ap.parse_args()
+
+    if args.cpu_leg is not None:
+        print(json.dumps(cpu_leg(args.cpu_leg, args.cpu_sample_iters)))
+        return 0
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: the PSFD solve here is a single-GPU path "
+              "(independent solves shard trivially across GPUs; see the design notes). "
+              "Run with --gpus 1.", file=sys.stderr)
+        return 2
+
+    import torch
+    import paper_2607_25330_amd as psfd
+    from psfd_synth import config_c2
+
+    dev = torch.device("cuda:0")
+    cfgs = [config_c2(0), config_c2(1)]
+    nx, ny, dx = cfgs[0]["nx"], cfgs[0]["ny"], cfgs[0]["dx"]
+    K, W = args.steps, args.warmup
+    a_dev = [torch.from_numpy(a).to(dev) for a in layouts(W + K, nx, ny, dx)]
+    torch.cuda.synchronize()
+    print(f"bench: workload ready ({W} warmup + {K} timed steps, 2 solves each)",
+          file=sys.stderr, flush=True)
+
+    if args.calib_copy_mib:
+        n = args.calib_copy_mib * 1024 * 1024 // 16
+        src = torch.ones(n, dtype=torch.complex128, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+
+    prec_mixed = psfd.PSFD_C64_REFINE64
+    if W:
+        run_steps(psfd, cfgs, a_dev, range(K, K + W), prec_mixed, args.tol, args.maxit)
+        if not args.no_fp64:
+            run_steps(psfd, cfgs, a_dev, range(K, K + W), psfd.PSFD_C128, args.tol, args.maxit)
+    torch.cuda.synchronize()
+
+    # ---- timed: mixed precision (headline)
+    t0 = time.perf_counter()
+    infos_m, prof = run_steps(psfd, cfgs, a_dev, range(K), prec_mixed, args.tol, args.maxit,
+                              profile=args.roofline_kernel)
+    torch.cuda.synchronize()
+    t_mixed = time.perf_counter() - t0
+    print(f"bench: mixed leg {t_mixed:.3f} s", file=sys.stderr, flush=True)
+
+    res = {}
+    if not args.no_fp64:
+        t0 = time.perf_counter()
+        infos_d, _ = run_steps(psfd, cfgs, a_dev, range(K), psfd.PSFD_C128, args.tol, args.maxit)
+        torch.cuda.synchronize()
+        t_fp64 = time.perf_counter() - t0
+        print(f"bench: fp64 leg {t_fp64:.3f} s", file=sys.stderr, flush=True)
+        res["fp64"] = (t_fp64, infos_d)
+
+    nsolve = 2 * K
+    ok_m = all(i["status"] == "OK" and i["rrel"] <= args.tol for i in infos_m)
+    value = nsolve / t_mixed
+    ms, nl, by = prof
+    achieved = (by / (ms * 1e-3)) / 1e9 if ms > 0 else 0.0
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "kernel": args.roofline_kernel, "launches": nl,
+                "avg_launch_us": round(1e3 * ms / max(nl, 1), 2),
+                "bytes_per_launch": by / max(nl, 1)}
+    out = {
+        "metric": METRIC, "value": round(value, 4), "unit": "solves/s", "n_gpus": 1,
+        "steps": K, "warmup": W, "ms_per_step": round(1e3 * t_mixed / K, 2),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32+f64", "data": "synthetic",
+        "config": {"workload": WORKLOAD, "solves_per_step": 2, "grid": [256, 256, 48],
+                   "precision": "complex64 operator/Krylov, FP64 residual + refinement"},
+        "converged": ok_m,
+        "iters_mixed": [i["iters"] for i in infos_m],
+        "rrel_mixed_max": max(i["rrel"] for i in infos_m),
+        "roofline": roofline,
+    }
+    if "fp64" in res:
+        t_fp64, infos_d = res["fp64"]
+        out["fp64_plain"] = {"value": round(nsolve / t_fp64, 4), "unit": "solves/s",
+                             "ms_per_step": round(1e3 * t_fp64 / K, 2),
+                             "iters": [i["iters"] for i in infos_d],
+                             "converged": all(i["status"] == "OK" for i in infos_d)}
+        out["mixed_vs_fp64"] = round(t_fp64 / t_mixed, 3)
+    if not args.no_cpu_baseline:
+        iters_proj = (sum(i["iters"] for i in res["fp64"][1]) / nsolve if "fp64" in res
+                      else sum(i["iters"] for i in infos_m) / nsolve)
+        env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1",
+                   MKL_NUM_THREADS="1", HIP_VISIBLE_DEVICES="", CUDA_VISIBLE_DEVICES="")
+        print("bench: cpu baseline (oracle) ...", file=sys.stderr, flush=True)
+        cp = subprocess.run([sys.executable, os.path.abspath(__file__), "--cpu-leg",
+                             str(iters_proj), "--cpu-sample-iters", str(args.cpu_sample_iters)],
+                            capture_output=True, text=True, env=env, timeout=600)
+        if cp.returncode == 0:
+            out["cpu_baseline"] = json.loads(cp.stdout.strip().splitlines()[-1])
+        else:
+            out["cpu_baseline"] = {"error": cp.stderr[-500:]}
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -172,6 +172,17 @@ psfd_status psfd_solve(psfd_plan_t p, const void* b, const void* x0, void* E, do
  * r_pe is the tangential-electric-field TM coefficient. */
 psfd_status psfd_ml_reflection(psfd_plan_t p, void* r_te, void* r_pe);
 
+/* Kernel timing (measurement aid; not needed for solving).  kernel selects
+ * which launches of this plan are bracketed by HIP events on the plan's
+ * stream: 0 = off, 1 = axial column kernel, 2 = y-pass FFT, 3 = forward
+ * x-pass FFT, 4 = inverse x-pass FFT with the combine epilogue.  Enabling
+ * resets the counters.  psfd_profile_read returns (all host pointers):
+ * total event time in ms, number of timed launches, and the algorithmic
+ * bytes those launches move (each launch counts the complex elements it
+ * must read and write once, at its element size). */
+psfd_status psfd_profile_enable(psfd_plan_t p, int32_t kernel);
+psfd_status psfd_profile_read(psfd_plan_t p, double* total_ms, int64_t* launches, double* bytes);
+
 /* Total number of complex elements of one field, 3 * Nz * ny * nx. */
 int64_t psfd_field_size(psfd_plan_t p);
 

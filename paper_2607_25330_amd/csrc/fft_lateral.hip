@@ -9,6 +9,7 @@
 // rows (forward operator) or  y = F2^-1[U] - conj(k0^2 d_eps) x  (adjoint).
 #include "fft_core.h"
 #include "psfd_internal.h"
+#include "reduce.h"
 
 namespace psfd {
 
@@ -37,32 +38,55 @@ constexpr int y_tile() {
 
 // ------------------------------------------------------------------ kernels
 
-template <typename T, int N, int B>
+template <typename T>
+__device__ __forceinline__ cplx<double> ldks(const double* a) { return {a[0], a[1]}; }
+
+template <typename T, int N, int B, int PRE>
 __global__ void __launch_bounds__(B * Radices<N>::TPR)
 k_xfft_fwd(const cplx<T>* __restrict__ in, cplx<T>* __restrict__ out,
            const cplx<T>* __restrict__ tw, int64_t nrows_main, int64_t nrows_total, int ny,
            int nz, int j0, int nabs, const cplx<T>* __restrict__ kd,
-           const int* __restrict__ skip) {
+           const int* __restrict__ skip, const PreOp<T> pre) {
   if (skip && *skip) return;
   constexpr int NT = B * Radices<N>::TPR;
   __shared__ cplx<T> s[B * N];
   const int tid = threadIdx.x;
   const int64_t row0 = (int64_t)blockIdx.x * B;
+  // scalars of the fused vector update
+  cplx<T> c1 = {T(0), T(0)}, c2 = {T(0), T(0)};
+  if constexpr (PRE == PRE_P) {
+    const cplx<double> rho = ldks<T>(pre.ks->rho), rho_p = ldks<T>(pre.ks->rho_prev);
+    const cplx<double> al = ldks<T>(pre.ks->alpha), om = ldks<T>(pre.ks->omega);
+    c1 = cast<T>(cdiv(rho, rho_p) * cdiv(al, om));  // beta
+    c2 = cast<T>(om);
+  } else if constexpr (PRE == PRE_S) {
+    c1 = cast<T>(ldks<T>(pre.ks->alpha));
+  }
+  auto value = [&](int64_t idx) -> cplx<T> {
+    if constexpr (PRE == PRE_P) return pre.r[idx] + c1 * (pre.pv[idx] - c2 * pre.v[idx]);
+    else if constexpr (PRE == PRE_S) return pre.r[idx] - c1 * pre.v[idx];
+    else return in[idx];
+  };
+  double acc[1] = {0.0};
   for (int e = tid; e < B * N; e += NT) {
     const int64_t row = row0 + e / N;
     const int xi = e % N;
     cplx<T> val = {T(0), T(0)};
     if (row < nrows_main) {
-      val = in[row * N + xi];
+      const int64_t idx = row * N + xi;
+      val = value(idx);
+      if constexpr (PRE != PRE_NONE) pre.pv[idx] = val;
+      if constexpr (PRE == PRE_S) acc[0] += norm2(cast<double>(val));
     } else if (row < nrows_total) {
       const int64_t r = row - nrows_main;
       const int plane = (int)(r / ny), yy = (int)(r % ny);
       const int c = plane / nabs, ja = plane % nabs;
       const int64_t src = ((int64_t)(c * nz + j0 + ja) * ny + yy) * N + xi;
-      val = cmulc(kd[((int64_t)ja * ny + yy) * N + xi], in[src]);
+      val = cmulc(kd[((int64_t)ja * ny + yy) * N + xi], value(src));
     }
     s[e] = val;
   }
+  if constexpr (PRE == PRE_S) block_partials<1, NT>(acc, pre.part);
   __syncthreads();
   lds_fft<T, N, B, NT, false, false>(s, tw, AddrRow<N>{}, tid);
   for (int e = tid; e < B * N; e += NT) {
@@ -71,12 +95,12 @@ k_xfft_fwd(const cplx<T>* __restrict__ in, cplx<T>* __restrict__ out,
   }
 }
 
-template <typename T, int N, int B, int CM>
+template <typename T, int N, int B, int CM, int POST>
 __global__ void __launch_bounds__(B * Radices<N>::TPR)
 k_xfft_inv(const cplx<T>* __restrict__ UW, cplx<T>* __restrict__ y,
            const cplx<T>* __restrict__ tw, int64_t nrows, int ny, int nz, int j0, int nabs,
            T scale, const cplx<T>* __restrict__ kd, const cplx<T>* __restrict__ x,
-           const int* __restrict__ skip) {
+           const int* __restrict__ skip, const PostOp<T> post) {
   if (skip && *skip) return;
   constexpr int NT = B * Radices<N>::TPR;
   constexpr int NBUF = (CM == CB_FWD) ? 2 : 1;
@@ -103,22 +127,31 @@ k_xfft_inv(const cplx<T>* __restrict__ UW, cplx<T>* __restrict__ y,
   }
   __syncthreads();
   lds_fft<T, N, NBUF * B, NT, true, false>(s, tw, AddrRow<N>{}, tid);
+  double acc[3] = {0.0, 0.0, 0.0};
   for (int e = tid; e < B * N; e += NT) {
     const int64_t row = row0 + e / N;
     if (row >= nrows) continue;
     const int xi = e % N;
-    cplx<T> out = scale * s[e];
+    const int64_t idx = row * N + xi;
+    cplx<T> o = scale * s[e];
     if (CM != CB_PLAIN) {
       const int plane = (int)(row / ny), yy = (int)(row % ny);
       const int z = plane % nz;
       if (z >= j0 && z < j0 + nabs) {
         const cplx<T> kdv = kd[((int64_t)(z - j0) * ny + yy) * N + xi];
-        if (CM == CB_FWD) out = out - scale * (kdv * s[B * N + e]);
-        else out = out - cmulc(kdv, x[row * N + xi]);
+        if (CM == CB_FWD) o = o - scale * (kdv * s[B * N + e]);
+        else o = o - cmulc(kdv, x[idx]);
       }
     }
-    y[row * N + xi] = out;
+    y[idx] = o;
+    if constexpr (POST == POST_DOT) {
+      const cplx<double> a = cast<double>(post.d[idx]), b = cast<double>(o);
+      acc[0] += a.re * b.re + a.im * b.im;
+      acc[1] += a.re * b.im - a.im * b.re;
+      acc[2] += b.re * b.re + b.im * b.im;
+    }
   }
+  if constexpr (POST == POST_DOT) block_partials<3, NT>(acc, post.part);
 }
 
 template <typename T, int N, int TX, bool INV>
@@ -140,35 +173,56 @@ k_yfft(cplx<T>* __restrict__ buf, const cplx<T>* __restrict__ tw, int nx,
 
 template <typename T, int N>
 static hipError_t xfwd_n(const OpTables<T>& t, const cplx<T>* in, cplx<T>* out,
-                         int64_t nmain, int64_t ntot, int ny, hipStream_t st) {
+                         int64_t nmain, int64_t ntot, int ny, const PreOp<T>& pre, int* nblk_out,
+                         hipStream_t st) {
   constexpr int B = x_rows<T, N>();
   constexpr int NT = B * Radices<N>::TPR;
   const int64_t nblk = (ntot + B - 1) / B;
-  hipLaunchKernelGGL((k_xfft_fwd<T, N, B>), dim3((unsigned)nblk), dim3(NT), 0, st, in, out,
-                     t.tw_x, nmain, ntot, ny, t.nz, t.j0, t.nabs, t.kd, t.skip);
+  if (nblk_out) *nblk_out = (int)nblk;
+  dim3 g((unsigned)nblk), b(NT);
+  switch (pre.mode) {
+    case PRE_P:
+      hipLaunchKernelGGL((k_xfft_fwd<T, N, B, PRE_P>), g, b, 0, st, in, out, t.tw_x, nmain, ntot,
+                         ny, t.nz, t.j0, t.nabs, t.kd, t.skip, pre);
+      break;
+    case PRE_S:
+      hipLaunchKernelGGL((k_xfft_fwd<T, N, B, PRE_S>), g, b, 0, st, in, out, t.tw_x, nmain, ntot,
+                         ny, t.nz, t.j0, t.nabs, t.kd, t.skip, pre);
+      break;
+    default:
+      hipLaunchKernelGGL((k_xfft_fwd<T, N, B, PRE_NONE>), g, b, 0, st, in, out, t.tw_x, nmain,
+                         ntot, ny, t.nz, t.j0, t.nabs, t.kd, t.skip, pre);
+      break;
+  }
   return hipGetLastError();
+}
+
+template <typename T, int N, int CM>
+static void xinv_launch(dim3 g, dim3 b, const OpTables<T>& t, const cplx<T>* UW, cplx<T>* y,
+                        int64_t nrows, int ny, const cplx<T>* x, T scale, const PostOp<T>& post,
+                        hipStream_t st) {
+  constexpr int B = x_rows<T, N>();
+  if (post.mode == POST_DOT)
+    hipLaunchKernelGGL((k_xfft_inv<T, N, B, CM, POST_DOT>), g, b, 0, st, UW, y, t.tw_x, nrows,
+                       ny, t.nz, t.j0, t.nabs, scale, t.kd, x, t.skip, post);
+  else
+    hipLaunchKernelGGL((k_xfft_inv<T, N, B, CM, POST_NONE>), g, b, 0, st, UW, y, t.tw_x, nrows,
+                       ny, t.nz, t.j0, t.nabs, scale, t.kd, x, t.skip, post);
 }
 
 template <typename T, int N>
 static hipError_t xinv_n(const OpTables<T>& t, const cplx<T>* UW, cplx<T>* y, int64_t nrows,
-                         int ny, int cmode, const cplx<T>* x, T scale, hipStream_t st) {
+                         int ny, int cmode, const cplx<T>* x, T scale, const PostOp<T>& post,
+                         int* nblk_out, hipStream_t st) {
   constexpr int B = x_rows<T, N>();
   constexpr int NT = B * Radices<N>::TPR;
   const int64_t nblk = (nrows + B - 1) / B;
+  if (nblk_out) *nblk_out = (int)nblk;
   dim3 g((unsigned)nblk), b(NT);
   switch (cmode) {
-    case CB_PLAIN:
-      hipLaunchKernelGGL((k_xfft_inv<T, N, B, CB_PLAIN>), g, b, 0, st, UW, y, t.tw_x, nrows, ny,
-                         t.nz, t.j0, t.nabs, scale, t.kd, x, t.skip);
-      break;
-    case CB_FWD:
-      hipLaunchKernelGGL((k_xfft_inv<T, N, B, CB_FWD>), g, b, 0, st, UW, y, t.tw_x, nrows, ny,
-                         t.nz, t.j0, t.nabs, scale, t.kd, x, t.skip);
-      break;
-    default:
-      hipLaunchKernelGGL((k_xfft_inv<T, N, B, CB_ADJ>), g, b, 0, st, UW, y, t.tw_x, nrows, ny,
-                         t.nz, t.j0, t.nabs, scale, t.kd, x, t.skip);
-      break;
+    case CB_PLAIN: xinv_launch<T, N, CB_PLAIN>(g, b, t, UW, y, nrows, ny, x, scale, post, st); break;
+    case CB_FWD: xinv_launch<T, N, CB_FWD>(g, b, t, UW, y, nrows, ny, x, scale, post, st); break;
+    default: xinv_launch<T, N, CB_ADJ>(g, b, t, UW, y, nrows, ny, x, scale, post, st); break;
   }
   return hipGetLastError();
 }
@@ -200,10 +254,10 @@ static hipError_t y_n(const cplx<T>* tw, cplx<T>* buf, int nx, int nplanes, bool
 
 template <typename T>
 hipError_t launch_xfft_fwd(const OpTables<T>& t, const cplx<T>* in, cplx<T>* out, bool adj_extra,
-                           hipStream_t st) {
+                           const PreOp<T>& pre, int* nblk, hipStream_t st) {
   const int64_t nmain = (int64_t)3 * t.nz * t.ny;
   const int64_t ntot = nmain + (adj_extra ? (int64_t)3 * t.nabs * t.ny : 0);
-#define CALL_X(NN) xfwd_n<T, NN>(t, in, out, nmain, ntot, t.ny, st)
+#define CALL_X(NN) xfwd_n<T, NN>(t, in, out, nmain, ntot, t.ny, pre, nblk, st)
   PSFD_LATERAL_SWITCH(t.nx, CALL_X)
 #undef CALL_X
 }
@@ -218,10 +272,10 @@ hipError_t launch_yfft(const OpTables<T>& t, cplx<T>* buf, int nplanes, bool inv
 
 template <typename T>
 hipError_t launch_xfft_inv(const OpTables<T>& t, const cplx<T>* UW, cplx<T>* y, int cmode,
-                           const cplx<T>* x, hipStream_t st) {
+                           const cplx<T>* x, const PostOp<T>& post, int* nblk, hipStream_t st) {
   const int64_t nrows = (int64_t)3 * t.nz * t.ny;
   const T scale = T(1) / (T(t.nx) * T(t.ny));
-#define CALL_XI(NN) xinv_n<T, NN>(t, UW, y, nrows, t.ny, cmode, x, scale, st)
+#define CALL_XI(NN) xinv_n<T, NN>(t, UW, y, nrows, t.ny, cmode, x, scale, post, nblk, st)
   PSFD_LATERAL_SWITCH(t.nx, CALL_XI)
 #undef CALL_XI
 }
@@ -231,7 +285,7 @@ hipError_t launch_plane_fft(const OpTables<T>& t, cplx<T>* in, cplx<T>* out, boo
                             hipStream_t st) {
   hipError_t e;
   if (!inverse) {
-#define CALL_PX(NN) xfwd_n<T, NN>(t, in, out, t.ny, t.ny, t.ny, st)
+#define CALL_PX(NN) xfwd_n<T, NN>(t, in, out, t.ny, t.ny, t.ny, PreOp<T>{}, nullptr, st)
     e = [&]() -> hipError_t { PSFD_LATERAL_SWITCH(t.nx, CALL_PX) }();
 #undef CALL_PX
     if (e != hipSuccess) return e;
@@ -240,23 +294,27 @@ hipError_t launch_plane_fft(const OpTables<T>& t, cplx<T>* in, cplx<T>* out, boo
   // inverse: y pass in place on `in`, then x pass into `out` (unnormalised)
   e = launch_yfft<T>(t, in, 1, true, st);
   if (e != hipSuccess) return e;
-#define CALL_PXI(NN) xinv_n<T, NN>(t, in, out, t.ny, t.ny, CB_PLAIN, nullptr, T(1), st)
+#define CALL_PXI(NN) xinv_n<T, NN>(t, in, out, t.ny, t.ny, CB_PLAIN, nullptr, T(1), PostOp<T>{}, nullptr, st)
   PSFD_LATERAL_SWITCH(t.nx, CALL_PXI)
 #undef CALL_PXI
 }
 
 template hipError_t launch_xfft_fwd<double>(const OpTables<double>&, const cplx<double>*,
-                                            cplx<double>*, bool, hipStream_t);
+                                            cplx<double>*, bool, const PreOp<double>&, int*,
+                                            hipStream_t);
 template hipError_t launch_xfft_fwd<float>(const OpTables<float>&, const cplx<float>*,
-                                           cplx<float>*, bool, hipStream_t);
+                                           cplx<float>*, bool, const PreOp<float>&, int*,
+                                           hipStream_t);
 template hipError_t launch_yfft<double>(const OpTables<double>&, cplx<double>*, int, bool,
                                         hipStream_t);
 template hipError_t launch_yfft<float>(const OpTables<float>&, cplx<float>*, int, bool,
                                        hipStream_t);
 template hipError_t launch_xfft_inv<double>(const OpTables<double>&, const cplx<double>*,
-                                            cplx<double>*, int, const cplx<double>*, hipStream_t);
+                                            cplx<double>*, int, const cplx<double>*,
+                                            const PostOp<double>&, int*, hipStream_t);
 template hipError_t launch_xfft_inv<float>(const OpTables<float>&, const cplx<float>*,
-                                           cplx<float>*, int, const cplx<float>*, hipStream_t);
+                                           cplx<float>*, int, const cplx<float>*,
+                                           const PostOp<float>&, int*, hipStream_t);
 template hipError_t launch_plane_fft<double>(const OpTables<double>&, cplx<double>*,
                                              cplx<double>*, bool, hipStream_t);
 

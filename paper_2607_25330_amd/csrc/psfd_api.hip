@@ -8,6 +8,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "psfd.h"
@@ -90,7 +91,16 @@ struct psfd_plan {
   KState* ks_host = nullptr;
   double* part = nullptr;
 
+  // kernel timing (psfd_profile_enable)
+  int prof_kernel = 0;
+  std::vector<hipEvent_t> ev_pool;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_open;
+  double prof_ms = 0.0, prof_bytes = 0.0;
+  int64_t prof_launches = 0;
+
   ~psfd_plan() {
+    for (auto& pr : ev_open) { ev_pool.push_back(pr.first); ev_pool.push_back(pr.second); }
+    for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
     for (void* p : allocs) (void)hipFree(p);
     if (ks_host) (void)hipHostFree(ks_host);
   }
@@ -180,37 +190,101 @@ cplx<double>** vecs<double>(struct psfd_plan* P) { return P->v64; }
 template <>
 cplx<float>** vecs<float>(struct psfd_plan* P) { return P->v32; }
 
-// One operator application (see the kernel files for the math).
+enum { PROF_OFF = 0, PROF_AXIAL = 1, PROF_YFFT = 2, PROF_XFWD = 3, PROF_XINV = 4 };
+
+hipEvent_t take_event(struct psfd_plan* P) {
+  if (!P->ev_pool.empty()) {
+    hipEvent_t e = P->ev_pool.back();
+    P->ev_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Launch `fn` and, when kernel `which` is being timed, bracket it with events.
+template <typename F>
+hipError_t timed(struct psfd_plan* P, int which, double bytes, F&& fn) {
+  if (P->prof_kernel != which) return fn();
+  hipEvent_t a = take_event(P), b = take_event(P);
+  if (!a || !b) return hipErrorOutOfMemory;
+  hipError_t e = hipEventRecord(a, P->st);
+  if (e != hipSuccess) return e;
+  e = fn();
+  if (e != hipSuccess) return e;
+  e = hipEventRecord(b, P->st);
+  if (e != hipSuccess) return e;
+  P->ev_open.emplace_back(a, b);
+  P->prof_bytes += bytes;
+  P->prof_launches += 1;
+  return hipSuccess;
+}
+
+// Fold completed event pairs into the totals (call after a stream sync).
+void collect_events(struct psfd_plan* P) {
+  for (auto& pr : P->ev_open) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, pr.first, pr.second) == hipSuccess) P->prof_ms += ms;
+    P->ev_pool.push_back(pr.first);
+    P->ev_pool.push_back(pr.second);
+  }
+  P->ev_open.clear();
+}
+
+// Fusion hooks of one operator application: a vector update folded into the
+// first x pass (with an optional finalize launched right after it) and inner
+// products folded into the last x pass.
 template <typename T>
-hipError_t op_apply(struct psfd_plan* P, const cplx<T>* x, cplx<T>* y, int op, const int* skip) {
+struct Fuse {
+  PreOp<T> pre;
+  int fin_first = -1;  // finalize stage after the first x pass (partials from pre)
+  PostOp<T> post;
+  int* nblk_post = nullptr;  // receives the number of partials written by post
+};
+
+// One operator application (see the kernel files for the math).  The
+// algorithmic bytes of each launch count every complex element it must read
+// or write once.
+template <typename T>
+hipError_t op_apply(struct psfd_plan* P, const cplx<T>* x, cplx<T>* y, int op, const int* skip,
+                    const Fuse<T>& fz = Fuse<T>()) {
   OpTables<T> t = tab<T>(P);
   t.skip = skip;
   cplx<T>* S = wsS<T>(P);
   cplx<T>* UW = wsUW<T>(P);
   hipStream_t st = P->st;
   const int p3 = 3 * P->nz, pa = 3 * P->nabs;
+  const double pl = (double)P->plane * sizeof(cplx<T>);  // bytes of one plane
   hipError_t e;
-  switch (op) {
-    case OP_A:
-    case OP_AM:
-      if ((e = launch_xfft_fwd<T>(t, x, S, false, st)) != hipSuccess) return e;
-      if ((e = launch_yfft<T>(t, S, p3, false, st)) != hipSuccess) return e;
-      if ((e = launch_axial<T>(t, S, UW, op == OP_A ? AX_A : AX_AM, st)) != hipSuccess) return e;
-      if ((e = launch_yfft<T>(t, UW, p3 + pa, true, st)) != hipSuccess) return e;
-      return launch_xfft_inv<T>(t, UW, y, CB_FWD, nullptr, st);
-    case OP_AH:
-      if ((e = launch_xfft_fwd<T>(t, x, S, true, st)) != hipSuccess) return e;
-      if ((e = launch_yfft<T>(t, S, p3 + pa, false, st)) != hipSuccess) return e;
-      if ((e = launch_axial<T>(t, S, UW, AX_AH, st)) != hipSuccess) return e;
-      if ((e = launch_yfft<T>(t, UW, p3, true, st)) != hipSuccess) return e;
-      return launch_xfft_inv<T>(t, UW, y, CB_ADJ, x, st);
-    default:
-      if ((e = launch_xfft_fwd<T>(t, x, S, false, st)) != hipSuccess) return e;
-      if ((e = launch_yfft<T>(t, S, p3, false, st)) != hipSuccess) return e;
-      if ((e = launch_axial<T>(t, S, UW, AX_M, st)) != hipSuccess) return e;
-      if ((e = launch_yfft<T>(t, UW, p3, true, st)) != hipSuccess) return e;
-      return launch_xfft_inv<T>(t, UW, y, CB_PLAIN, nullptr, st);
+  const bool adj = op == OP_AH;
+  const int nin = adj ? p3 + pa : p3;  // planes through the forward lateral transform
+  const int ax_mode = op == OP_A ? AX_A : (op == OP_AM ? AX_AM : (adj ? AX_AH : AX_M));
+  const int nout = (op == OP_A || op == OP_AM) ? p3 + pa : p3;  // planes out of the axial kernel
+  const int cmode = (op == OP_A || op == OP_AM) ? CB_FWD : (adj ? CB_ADJ : CB_PLAIN);
+  const int npre = fz.pre.mode == PRE_P ? 3 + 1 : (fz.pre.mode == PRE_S ? 2 + 1 : 1);
+  int nb_first = 0;
+  // x pass (forward): read the field (+ conj(kd) and absorber rows for the adjoint), write nin planes
+  e = timed(P, PROF_XFWD, pl * (p3 * npre + nin + (adj ? pa + P->nabs : 0)),
+            [&] { return launch_xfft_fwd<T>(t, x, S, adj, fz.pre, &nb_first, st); });
+  if (e != hipSuccess) return e;
+  if (fz.fin_first >= 0) {
+    e = launch_finalize(fz.fin_first, P->ks, fz.pre.part, nb_first, 0.0, 0.0, st);
+    if (e != hipSuccess) return e;
   }
+  e = timed(P, PROF_YFFT, 2.0 * pl * nin, [&] { return launch_yfft<T>(t, S, nin, false, st); });
+  if (e != hipSuccess) return e;
+  e = timed(P, PROF_AXIAL, pl * (nin + nout),
+            [&] { return launch_axial<T>(t, S, UW, ax_mode, st); });
+  if (e != hipSuccess) return e;
+  e = timed(P, PROF_YFFT, 2.0 * pl * nout, [&] { return launch_yfft<T>(t, UW, nout, true, st); });
+  if (e != hipSuccess) return e;
+  double comb = cmode == CB_FWD ? pl * (nout + P->nabs + p3)
+                                : (cmode == CB_ADJ ? pl * (p3 + pa + P->nabs + p3) : 2.0 * pl * p3);
+  if (fz.post.mode == POST_DOT) comb += pl * p3;
+  return timed(P, PROF_XINV, comb, [&] {
+    return launch_xfft_inv<T>(t, UW, y, cmode, adj ? x : nullptr, fz.post, fz.nblk_post, st);
+  });
 }
 
 psfd_status ensure_fp32(struct psfd_plan* P) {
@@ -232,7 +306,8 @@ psfd_status ensure_krylov(struct psfd_plan* P) {
 psfd_status ensure_solver_common(struct psfd_plan* P) {
   if (P->ks) return PSFD_OK;
   CHKS(dalloc(P, &P->ks, 1));
-  CHKS(dalloc(P, &P->part, (size_t)2048 * 4));
+  // one partial set per block of the largest reducing grid (x pass rows, or 2048)
+  CHKS(dalloc(P, &P->part, (size_t)(3 * P->nz * P->ny + 3 * P->nabs * P->ny + 2048) * 4));
   CHKS(dalloc(P, &P->b64, (size_t)P->nfield));
   CHKS(dalloc(P, &P->tmp64, (size_t)P->nfield));
   CHKS(dalloc(P, &P->res64, (size_t)P->nfield));
@@ -244,11 +319,13 @@ psfd_status ensure_solver_common(struct psfd_plan* P) {
 psfd_status read_state(struct psfd_plan* P) {
   CHK(hipMemcpyAsync(P->ks_host, P->ks, sizeof(KState), hipMemcpyDeviceToHost, P->st));
   CHK(hipStreamSynchronize(P->st));
+  if (!P->ev_open.empty()) collect_events(P);
   return PSFD_OK;
 }
 
 psfd_status norm2_host(struct psfd_plan* P, const cplx<double>* a, double* out) {
-  CHK(launch_k_norm2<double>(a, P->nfield, P->ks, P->part, P->st));
+  CHK(launch_k_norm2<double>(a, P->nfield, P->part, P->st));
+  CHK(launch_finalize(FIN_RED0, P->ks, P->part, red_blocks(P->nfield), 0.0, 0.0, P->st));
   CHKS(read_state(P));
   *out = P->ks_host->red[0];
   return PSFD_OK;
@@ -261,6 +338,12 @@ struct RunResult {
 };
 
 // Right-preconditioned BiCGSTAB on op(prec(y)) = r (r in vecs[V_R]); y in vecs[V_Y].
+// One iteration, with the vector updates and inner products fused into the
+// operator's x passes:
+//   [p = r + beta(p - omega v) -> x-FFT] ... [x-IFFT -> v, <rh, v>]  fin: alpha
+//   [s = r - alpha v, ||s|| -> x-FFT]  fin: half-step test
+//   ... [x-IFFT -> t, <t, s>, ||t||]  fin: omega
+//   [y += alpha p + omega s, r = s - omega t, ||r||, <rh, r>]  fin: rho, beta, stop test
 template <typename T>
 psfd_status run_bicgstab(struct psfd_plan* P, bool adjoint, double bnorm2, double tol,
                          int maxit, RunResult* res) {
@@ -271,28 +354,65 @@ psfd_status run_bicgstab(struct psfd_plan* P, bool adjoint, double bnorm2, doubl
   double* part = P->part;
   const int* skip = &ks->done;
   const bool pc = P->use_pc;
-  CHK(launch_k_init<T>(V[V_RH], V[V_R], V[V_P], V[V_V], V[V_Y], n, ks, part, bnorm2, tol * tol,
-                       st));
-  auto apply = [&](const cplx<T>* in, cplx<T>* out) -> hipError_t {
-    if (!adjoint) return op_apply<T>(P, in, out, pc ? OP_AM : OP_A, skip);
-    if (!pc) return op_apply<T>(P, in, out, OP_AH, skip);
-    hipError_t e = op_apply<T>(P, in, V[V_W], OP_M, skip);
+  CHK(launch_k_init<T>(V[V_RH], V[V_R], V[V_P], V[V_V], V[V_Y], n, part, st));
+  CHK(launch_finalize(FIN_INIT, ks, part, red_blocks(n), bnorm2, tol * tol, st));
+
+  // The first operator of a composite (M then A^H) carries the update; the last carries the dot.
+  auto apply = [&](const cplx<T>* in, cplx<T>* out, Fuse<T>& fz) -> hipError_t {
+    if (!adjoint) return op_apply<T>(P, in, out, pc ? OP_AM : OP_A, skip, fz);
+    if (!pc) return op_apply<T>(P, in, out, OP_AH, skip, fz);
+    Fuse<T> f1, f2;
+    f1.pre = fz.pre;
+    f1.fin_first = fz.fin_first;
+    f2.post = fz.post;
+    f2.nblk_post = fz.nblk_post;
+    hipError_t e = op_apply<T>(P, in, V[V_W], OP_M, skip, f1);
     if (e != hipSuccess) return e;
-    return op_apply<T>(P, V[V_W], out, OP_AH, skip);
+    return op_apply<T>(P, V[V_W], out, OP_AH, skip, f2);
   };
+  // the unpreconditioned adjoint transforms extra rows of the input: update p separately
+  const bool fuse_p = !(adjoint && !pc);
+  int nb_v = 0, nb_t = 0;
   int launched = 0;
   res->done = 0;
   while (launched < maxit) {
     const int chunk = std::min(kChunk, maxit - launched);
     for (int i = 0; i < chunk; ++i) {
-      CHK(launch_k_p_update<T>(V[V_P], V[V_R], V[V_V], n, ks, st));
-      CHK(apply(V[V_P], V[V_V]));
-      CHK(launch_k_dot_rv<T>(V[V_RH], V[V_V], n, ks, part, st));
-      CHK(launch_k_s_update<T>(V[V_S], V[V_R], V[V_V], n, ks, part, st));
-      CHK(apply(V[V_S], V[V_T]));
-      CHK(launch_k_dot_ts<T>(V[V_T], V[V_S], n, ks, part, st));
+      Fuse<T> fa;
+      if (fuse_p) {
+        fa.pre.mode = PRE_P;
+        fa.pre.r = V[V_R];
+        fa.pre.pv = V[V_P];
+        fa.pre.v = V[V_V];
+        fa.pre.ks = ks;
+      } else {
+        CHK(launch_k_p_update<T>(V[V_P], V[V_R], V[V_V], n, ks, st));
+      }
+      fa.post.mode = POST_DOT;
+      fa.post.d = V[V_RH];
+      fa.post.part = part;
+      fa.nblk_post = &nb_v;
+      CHK(apply(V[V_P], V[V_V], fa));
+      CHK(launch_finalize(FIN_ALPHA, ks, part, nb_v, 0.0, 0.0, st));
+
+      Fuse<T> fb;
+      fb.pre.mode = PRE_S;
+      fb.pre.r = V[V_R];
+      fb.pre.pv = V[V_S];
+      fb.pre.v = V[V_V];
+      fb.pre.ks = ks;
+      fb.pre.part = part;
+      fb.fin_first = FIN_SNORM;
+      fb.post.mode = POST_DOT;
+      fb.post.d = V[V_S];
+      fb.post.part = part;
+      fb.nblk_post = &nb_t;
+      CHK(apply(V[V_S], V[V_T], fb));
+      CHK(launch_finalize(FIN_OMEGA, ks, part, nb_t, 0.0, 0.0, st));
+
       CHK(launch_k_xr_update<T>(V[V_Y], V[V_R], V[V_P], V[V_S], V[V_T], V[V_RH], n, ks, part,
                                 st));
+      CHK(launch_finalize(FIN_RHO, ks, part, red_blocks(n), 0.0, 0.0, st));
     }
     launched += chunk;
     CHKS(read_state(P));
@@ -308,7 +428,8 @@ psfd_status run_bicgstab(struct psfd_plan* P, bool adjoint, double bnorm2, doubl
 psfd_status true_residual(struct psfd_plan* P, const cplx<double>* b, const cplx<double>* E,
                           cplx<double>* r, bool adjoint, double* rr2) {
   CHK(op_apply<double>(P, E, P->tmp64, adjoint ? OP_AH : OP_A, nullptr));
-  CHK(launch_k_residual<double>(r, b, P->tmp64, P->nfield, P->ks, P->part, P->st));
+  CHK(launch_k_residual<double>(r, b, P->tmp64, P->nfield, P->part, P->st));
+  CHK(launch_finalize(FIN_RED0, P->ks, P->part, red_blocks(P->nfield), 0.0, 0.0, P->st));
   CHKS(read_state(P));
   *rr2 = P->ks_host->red[0];
   return PSFD_OK;
@@ -675,6 +796,31 @@ psfd_status psfd_ml_reflection(psfd_plan_t p, void* r_te, void* r_pe) {
     const size_t bytes = sizeof(cplx<double>) * (size_t)p->plane;
     CHK(hipMemcpyAsync(r_te, p->rte64, bytes, hipMemcpyDeviceToDevice, p->st));
     CHK(hipMemcpyAsync(r_pe, p->rpe64, bytes, hipMemcpyDeviceToDevice, p->st));
+    return PSFD_OK;
+  });
+}
+
+psfd_status psfd_profile_enable(psfd_plan_t p, int32_t kernel) {
+  if (!p || kernel < PROF_OFF || kernel > PROF_XINV) return fail(PSFD_ERR_ARG, "bad argument");
+  return guarded([&]() -> psfd_status {
+    CHK(p->st ? hipStreamSynchronize(p->st) : hipDeviceSynchronize());
+    collect_events(p);
+    p->prof_kernel = kernel;
+    p->prof_ms = 0.0;
+    p->prof_bytes = 0.0;
+    p->prof_launches = 0;
+    return PSFD_OK;
+  });
+}
+
+psfd_status psfd_profile_read(psfd_plan_t p, double* total_ms, int64_t* launches, double* bytes) {
+  if (!p || !total_ms || !launches || !bytes) return fail(PSFD_ERR_ARG, "NULL argument");
+  return guarded([&]() -> psfd_status {
+    CHK(p->st ? hipStreamSynchronize(p->st) : hipDeviceSynchronize());
+    collect_events(p);
+    *total_ms = p->prof_ms;
+    *launches = p->prof_launches;
+    *bytes = p->prof_bytes;
     return PSFD_OK;
   });
 }

@@ -41,13 +41,39 @@ struct OpTables {
 enum AxialMode { AX_A = 0, AX_AM = 1, AX_AH = 2, AX_M = 3 };
 enum CombineMode { CB_PLAIN = 0, CB_FWD = 1, CB_ADJ = 2 };
 
+struct KState;
+
+// Vector update fused into the forward x pass of an operator apply:
+//   PRE_P: p = r + beta (p - omega v)  (p overwritten, then transformed)
+//   PRE_S: s = r - alpha v             (s written, then transformed; partials ||s||^2)
+enum { PRE_NONE = 0, PRE_P = 1, PRE_S = 2 };
+template <typename T>
+struct PreOp {
+  int mode = PRE_NONE;
+  const cplx<T>* r = nullptr;
+  cplx<T>* pv = nullptr;  // p (in/out) or s (out)
+  const cplx<T>* v = nullptr;
+  const KState* ks = nullptr;
+  double* part = nullptr;
+};
+// Inner products fused into the inverse x pass: partials of
+//   sum conj(d) y  and  sum |y|^2  over the operator output y.
+enum { POST_NONE = 0, POST_DOT = 1 };
+template <typename T>
+struct PostOp {
+  int mode = POST_NONE;
+  const cplx<T>* d = nullptr;
+  double* part = nullptr;
+};
+
 // ---- lateral FFT launchers (fft_lateral.hip)
 // Forward x-FFT of rows.  nrows_main rows come straight from `in`; for the
 // adjoint, extra = 3 * nabs planes follow whose rows are conj(kd) * in on the
 // absorber rows.
+// *nblk receives the grid size (number of partials for PRE_S).
 template <typename T>
 hipError_t launch_xfft_fwd(const OpTables<T>& t, const cplx<T>* in, cplx<T>* out, bool adj_extra,
-                           hipStream_t st);
+                           const PreOp<T>& pre, int* nblk, hipStream_t st);
 // In-place y-FFT of nplanes planes of ny x nx.
 template <typename T>
 hipError_t launch_yfft(const OpTables<T>& t, cplx<T>* buf, int nplanes, bool inverse,
@@ -55,7 +81,7 @@ hipError_t launch_yfft(const OpTables<T>& t, cplx<T>* buf, int nplanes, bool inv
 // Inverse x-FFT of the 3 Nz U planes (+ W planes) with the combine epilogue.
 template <typename T>
 hipError_t launch_xfft_inv(const OpTables<T>& t, const cplx<T>* UW, cplx<T>* y, int cmode,
-                           const cplx<T>* x, hipStream_t st);
+                           const cplx<T>* x, const PostOp<T>& post, int* nblk, hipStream_t st);
 // 2-D FFT of a single plane (layout smoothing).  Forward: in -> out.
 // Inverse (unnormalised): y pass in place on `in`, x pass into `out`.
 template <typename T>
@@ -107,42 +133,34 @@ struct KState {
   double snorm2, rnorm2, bnorm2, tol2, rh_norm2;
   double red[4];        // generic reduction outputs
   int iter, done, status, half;
-  unsigned int ticket;
-  unsigned int pad[3];
 };
 
-constexpr int KRED_BLOCKS = 512;
 constexpr int KRED_THREADS = 256;
+int red_blocks(int64_t n);  // grid of the streaming vector kernels
+
+enum FinStage { FIN_INIT = 0, FIN_ALPHA, FIN_SNORM, FIN_OMEGA, FIN_RHO, FIN_RED0 };
+// Sum `nblocks` partials and update the scalars for one stage of the recurrence.
+hipError_t launch_finalize(int stage, KState* ks, const double* part, int nblocks, double a0,
+                           double a1, hipStream_t st);
 
 template <typename T>
-hipError_t launch_k_p_update(cplx<T>* p, const cplx<T>* r, const cplx<T>* v, int64_t n,
-                             KState* ks, hipStream_t st);
-template <typename T>
-hipError_t launch_k_dot_rv(const cplx<T>* rh, const cplx<T>* v, int64_t n, KState* ks,
-                           double* part, hipStream_t st);
-template <typename T>
-hipError_t launch_k_s_update(cplx<T>* s, const cplx<T>* r, const cplx<T>* v, int64_t n,
-                             KState* ks, double* part, hipStream_t st);
-template <typename T>
-hipError_t launch_k_dot_ts(const cplx<T>* t, const cplx<T>* s, int64_t n, KState* ks,
-                           double* part, hipStream_t st);
-template <typename T>
 hipError_t launch_k_xr_update(cplx<T>* y, cplx<T>* r, const cplx<T>* p, const cplx<T>* s,
-                              const cplx<T>* t, const cplx<T>* rh, int64_t n, KState* ks,
+                              const cplx<T>* t, const cplx<T>* rh, int64_t n, const KState* ks,
                               double* part, hipStream_t st);
-// Start a BiCGSTAB run: rh = r, rho = <r, r>, p = v = y = 0, scalars reset.
+template <typename T>
+hipError_t launch_k_p_update(cplx<T>* p, const cplx<T>* r, const cplx<T>* v, int64_t n,
+                             const KState* ks, hipStream_t st);
+// Start a BiCGSTAB run: rh = r, p = v = y = 0, partials ||r||^2 (then FIN_INIT).
 template <typename T>
 hipError_t launch_k_init(cplx<T>* rh, const cplx<T>* r, cplx<T>* p, cplx<T>* v, cplx<T>* y,
-                         int64_t n, KState* ks, double* part, double bnorm2, double tol2,
-                         hipStream_t st);
-// out = a - b (residual), ||out||^2 -> ks->red[0]
+                         int64_t n, double* part, hipStream_t st);
+// out = a - b, partials ||out||^2 (then FIN_RED0)
 template <typename T>
 hipError_t launch_k_residual(cplx<T>* out, const cplx<T>* a, const cplx<T>* b, int64_t n,
-                             KState* ks, double* part, hipStream_t st);
-// ||a||^2 -> ks->red[0]
+                             double* part, hipStream_t st);
+// partials ||a||^2 (then FIN_RED0)
 template <typename T>
-hipError_t launch_k_norm2(const cplx<T>* a, int64_t n, KState* ks, double* part,
-                          hipStream_t st);
+hipError_t launch_k_norm2(const cplx<T>* a, int64_t n, double* part, hipStream_t st);
 // y += a * x with a a real scalar held on the host
 template <typename TY, typename TX>
 hipError_t launch_k_axpy(cplx<TY>* y, const cplx<TX>* x, double a, int64_t n, hipStream_t st);

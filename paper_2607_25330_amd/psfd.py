@@ -69,7 +69,12 @@ _SIGS = {
     "psfd_solve": [c_void_p, c_void_p, c_void_p, c_void_p, c_double, c_int32, c_int32,
                    ctypes.POINTER(Info)],
     "psfd_ml_reflection": [c_void_p, c_void_p, c_void_p],
+    "psfd_profile_enable": [c_void_p, c_int32],
+    "psfd_profile_read": [c_void_p, c_dp, ctypes.POINTER(c_int64), c_dp],
 }
+
+# kernel ids for Plan.profile_enable
+PROFILE_KERNELS = {"off": 0, "axial": 1, "yfft": 2, "xfwd": 3, "xinv": 4}
 
 _lib = None
 
@@ -226,6 +231,16 @@ class Plan:
         return E, {"iters": info.iters, "status": STATUS_NAMES.get(st, st),
                    "restarts": info.restarts, "applies": info.applies,
                    "rrel": info.rrel_true, "rrel_rec": info.rrel_hist_last}
+
+    def profile_enable(self, kernel):
+        """Time every launch of one kernel class with HIP events (see PROFILE_KERNELS)."""
+        _call("psfd_profile_enable", self._h, c_int32(PROFILE_KERNELS.get(kernel, kernel)))
+
+    def profile_read(self):
+        """(total ms, launches, algorithmic bytes) of the timed launches."""
+        ms, n, b = c_double(), c_int64(), c_double()
+        _call("psfd_profile_read", self._h, ctypes.byref(ms), ctypes.byref(n), ctypes.byref(b))
+        return ms.value, n.value, b.value
 
     def field_size(self):
         return int(lib().psfd_field_size(self._h))

@@ -68,7 +68,7 @@ APPLY_CASES = {
 @pytest.mark.parametrize("name", list(APPLY_CASES))
 def test_operator_pieces(psfd, name):
     cfg = APPLY_CASES[name]
-    a, eps = case(cfg, seed=hash(name) % 1000)
+    a, eps = case(cfg, seed=sum(map(ord, name)))
     P = R.Problem(cfg, eps)
     plan = psfd.Plan(cfg, dev(eps))
     rng = np.random.default_rng(5)
