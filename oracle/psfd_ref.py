@@ -215,7 +215,8 @@ class Basis:
 
     s_hat = (-ky, kx, 0)/kt, t_hat = (kx, ky, 0)/kt; at kt = 0 the basis of
     the incidence plane is used.  kz = sqrt(kbg^2 - kt^2) with Im kz >= 0.
-    Modes with |kz| < 1e-9 k0 (grazing) get no multilayer response."""
+    Grazing modes, |kz| < max(ml_kz_min, 1e-9) k0, get no multilayer
+    response (the paper is silent on grazing orders)."""
 
     def __init__(self, g):
         KX = np.broadcast_to(g.kx[None, :], (g.ny, g.nx))
@@ -231,7 +232,8 @@ class Basis:
         self.kt = kt
         self.kt2 = kt2
         self.kzb = principal_sqrt(g.kbg * g.kbg - kt2)
-        self.live = np.abs(self.kzb) >= 1e-9 * g.k0
+        kz_min = max(float(g.cfg.get("ml_kz_min", 0.0)), 1e-9)
+        self.live = np.abs(self.kzb) >= kz_min * g.k0
         kzn = np.where(self.live, self.kzb, 1.0)
         self.ktkz = np.where(self.live, kt / kzn, 0.0)
 
@@ -440,10 +442,17 @@ def _nrm(u):
     return float(np.linalg.norm(u.ravel()))
 
 
+OMEGA_LIMIT = 0.7
+
+
 def bicgstab_core(op, prec, r0, bnorm, tol, maxit, history=None):
     """Right-preconditioned BiCGSTAB on  op(prec(y)) = r0,  y0 = 0.
 
-    Standard van der Vorst recurrences, shadow residual = r0.  Returns
+    Van der Vorst recurrences, shadow residual = r0, with the stabilising
+    step omega = <t,s>/<t,t> limited as proposed by Sleijpen and van der
+    Vorst (1995): if |<t,s>| < kappa ||t|| ||s|| (kappa = 0.7) omega is
+    scaled by kappa ||t|| ||s|| / |<t,s>|.  The paper names BiCGSTAB without
+    a variant; the limited step has the same fixed point.  Returns
     (y_hat, iterations, status) where y_hat = prec(y) accumulated directly,
     status 'converged', 'maxit' or 'breakdown'."""
     r = r0.copy()
@@ -472,11 +481,16 @@ def bicgstab_core(op, prec, r0, bnorm, tol, maxit, history=None):
             return yh, it, "converged"
         sh = prec(s)
         t = op(sh)
-        tt = _dot(t, t)
+        tt = _dot(t, t).real
         if tt == 0:
             yh = yh + alpha * ph
             return yh, it, "breakdown"
-        omega = _dot(t, s) / tt
+        ts = _dot(t, s)
+        omega = ts / tt
+        # omega limiting: keep |<t,s>| / (||t|| ||s||) from falling below kappa
+        c = abs(ts) / (np.sqrt(tt) * sn)
+        if 0.0 < c < OMEGA_LIMIT:
+            omega *= OMEGA_LIMIT / c
         yh = yh + alpha * ph + omega * sh
         r = s - omega * t
         rn = _nrm(r)
