@@ -87,6 +87,8 @@ typedef struct {
   int32_t precond;               /* 0 = none, 1 = spectral damping M              */
   double pc_mmin, pc_kref, pc_gamma, pc_reg; /* m(k) parameters; pc_kref <= 0 -> k0 sqrt(eps_bg) */
   int32_t prec;                  /* psfd_precision                                */
+  double ml_kz_min;              /* lateral modes with |kz| < max(ml_kz_min, 1e-9) k0 get no
+                                    multilayer response (grazing orders); 0 = default   */
 } psfd_desc;
 
 typedef struct {
@@ -175,7 +177,9 @@ psfd_status psfd_ml_reflection(psfd_plan_t p, void* r_te, void* r_pe);
 /* Kernel timing (measurement aid; not needed for solving).  kernel selects
  * which launches of this plan are bracketed by HIP events on the plan's
  * stream: 0 = off, 1 = axial column kernel, 2 = y-pass FFT, 3 = forward
- * x-pass FFT, 4 = inverse x-pass FFT with the combine epilogue.  Enabling
+ * x-pass FFT, 4 = inverse x-pass FFT with the combine epilogue.  Only
+ * launches in the plan's working precision are timed (complex64 for the
+ * PSFD_C64_* plans, whose FP64 residual applies are not counted).  Enabling
  * resets the counters.  psfd_profile_read returns (all host pointers):
  * total event time in ms, number of timed launches, and the algorithmic
  * bytes those launches move (each launch counts the complex elements it

@@ -83,7 +83,7 @@ __device__ void column_info(ColInfo<T>& c, const OpTables<T>& t, int ix, int iy)
   if (q2 >= T(0)) { c.kzr = sqrt(q2); c.kzi = T(0); }
   else { c.kzr = T(0); c.kzi = sqrt(-q2); }
   const T kzabs = c.kzr + c.kzi;
-  c.live = kzabs >= T(1e-9) * t.k0;
+  c.live = kzabs >= t.kz_live;
   if (!c.live) c.ktkz = {T(0), T(0)};
   else if (c.kzi == T(0)) c.ktkz = {kt / c.kzr, T(0)};
   else c.ktkz = {T(0), -kt / c.kzi};

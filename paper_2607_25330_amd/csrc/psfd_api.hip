@@ -93,6 +93,7 @@ struct psfd_plan {
 
   // kernel timing (psfd_profile_enable)
   int prof_kernel = 0;
+  int prof_elem = 16;  // element size of the timed launches (the working precision)
   std::vector<hipEvent_t> ev_pool;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_open;
   double prof_ms = 0.0, prof_bytes = 0.0;
@@ -161,6 +162,7 @@ psfd_status validate(const psfd_desc* d) {
   if (!(d->pc_mmin >= 0 && d->pc_mmin <= 1) || !(d->pc_gamma > 0) || !(d->pc_reg >= 0))
     return fail(PSFD_ERR_ARG, "bad preconditioner parameters");
   if (!std::isfinite(d->theta) || !std::isfinite(d->phi)) return fail(PSFD_ERR_ARG, "bad angles");
+  if (!(d->ml_kz_min >= 0.0 && d->ml_kz_min <= 1.0)) return fail(PSFD_ERR_ARG, "bad ml_kz_min");
   return PSFD_OK;
 }
 
@@ -205,8 +207,8 @@ hipEvent_t take_event(struct psfd_plan* P) {
 
 // Launch `fn` and, when kernel `which` is being timed, bracket it with events.
 template <typename F>
-hipError_t timed(struct psfd_plan* P, int which, double bytes, F&& fn) {
-  if (P->prof_kernel != which) return fn();
+hipError_t timed(struct psfd_plan* P, int which, int elem, double bytes, F&& fn) {
+  if (P->prof_kernel != which || P->prof_elem != elem) return fn();
   hipEvent_t a = take_event(P), b = take_event(P);
   if (!a || !b) return hipErrorOutOfMemory;
   hipError_t e = hipEventRecord(a, P->st);
@@ -265,24 +267,24 @@ hipError_t op_apply(struct psfd_plan* P, const cplx<T>* x, cplx<T>* y, int op, c
   const int npre = fz.pre.mode == PRE_P ? 3 + 1 : (fz.pre.mode == PRE_S ? 2 + 1 : 1);
   int nb_first = 0;
   // x pass (forward): read the field (+ conj(kd) and absorber rows for the adjoint), write nin planes
-  e = timed(P, PROF_XFWD, pl * (p3 * npre + nin + (adj ? pa + P->nabs : 0)),
+  e = timed(P, PROF_XFWD, (int)sizeof(cplx<T>), pl * (p3 * npre + nin + (adj ? pa + P->nabs : 0)),
             [&] { return launch_xfft_fwd<T>(t, x, S, adj, fz.pre, &nb_first, st); });
   if (e != hipSuccess) return e;
   if (fz.fin_first >= 0) {
     e = launch_finalize(fz.fin_first, P->ks, fz.pre.part, nb_first, 0.0, 0.0, st);
     if (e != hipSuccess) return e;
   }
-  e = timed(P, PROF_YFFT, 2.0 * pl * nin, [&] { return launch_yfft<T>(t, S, nin, false, st); });
+  e = timed(P, PROF_YFFT, (int)sizeof(cplx<T>), 2.0 * pl * nin, [&] { return launch_yfft<T>(t, S, nin, false, st); });
   if (e != hipSuccess) return e;
-  e = timed(P, PROF_AXIAL, pl * (nin + nout),
+  e = timed(P, PROF_AXIAL, (int)sizeof(cplx<T>), pl * (nin + nout),
             [&] { return launch_axial<T>(t, S, UW, ax_mode, st); });
   if (e != hipSuccess) return e;
-  e = timed(P, PROF_YFFT, 2.0 * pl * nout, [&] { return launch_yfft<T>(t, UW, nout, true, st); });
+  e = timed(P, PROF_YFFT, (int)sizeof(cplx<T>), 2.0 * pl * nout, [&] { return launch_yfft<T>(t, UW, nout, true, st); });
   if (e != hipSuccess) return e;
   double comb = cmode == CB_FWD ? pl * (nout + P->nabs + p3)
                                 : (cmode == CB_ADJ ? pl * (p3 + pa + P->nabs + p3) : 2.0 * pl * p3);
   if (fz.post.mode == POST_DOT) comb += pl * p3;
-  return timed(P, PROF_XINV, comb, [&] {
+  return timed(P, PROF_XINV, (int)sizeof(cplx<T>), comb, [&] {
     return launch_xfft_inv<T>(t, UW, y, cmode, adj ? x : nullptr, fz.post, fz.nblk_post, st);
   });
 }
@@ -618,6 +620,7 @@ psfd_status plan_impl(const psfd_desc* d, const void* eps, void* stream, struct 
   t.tw_x = twx_d; t.tw_y = twy_d; t.tw_z = twz_d;
   t.kbg2 = P->kbg * P->kbg;
   t.k0 = P->k0;
+  t.kz_live = std::max(d->ml_kz_min, 1e-9) * P->k0;
   t.dz = d->dz;
   t.cphi = std::cos(d->phi);
   t.sphi = std::sin(d->phi);
@@ -668,7 +671,7 @@ psfd_status plan_impl(const psfd_desc* d, const void* eps, void* stream, struct 
     CHKS(dalloc(P, &P->kd32, (size_t)P->nabs * P->plane));
     f.kx = fkx; f.ky = fky; f.kz = fkz; f.zabs = fza; f.inv_s = fis;
     f.tw_x = ftx; f.tw_y = fty; f.tw_z = ftz; f.r_te = frte; f.r_pe = frpe; f.kd = P->kd32;
-    f.kbg2 = (float)t.kbg2; f.k0 = (float)t.k0; f.dz = (float)t.dz;
+    f.kbg2 = (float)t.kbg2; f.k0 = (float)t.k0; f.dz = (float)t.dz; f.kz_live = (float)t.kz_live;
     f.cphi = (float)t.cphi; f.sphi = (float)t.sphi;
     f.pc_mmin = (float)t.pc_mmin; f.pc_kref2 = (float)t.pc_kref2;
     f.pc_gamma = (float)t.pc_gamma; f.pc_reg = (float)t.pc_reg; f.pc_bf16 = t.pc_bf16;
@@ -806,6 +809,7 @@ psfd_status psfd_profile_enable(psfd_plan_t p, int32_t kernel) {
     CHK(p->st ? hipStreamSynchronize(p->st) : hipDeviceSynchronize());
     collect_events(p);
     p->prof_kernel = kernel;
+    p->prof_elem = p->prec == PSFD_C128 ? 16 : 8;
     p->prof_ms = 0.0;
     p->prof_bytes = 0.0;
     p->prof_launches = 0;

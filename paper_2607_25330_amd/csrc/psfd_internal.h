@@ -30,6 +30,7 @@ struct OpTables {
   const cplx<T>* tw_z;
   T kbg2;                   // (k0 sqrt(eps_bg))^2
   T k0;
+  T kz_live;                // |kz| below this (absolute) gets no multilayer response
   T dz;
   T cphi, sphi;             // incidence-plane basis at kt = 0
   // spectral damping multiplier m(k)

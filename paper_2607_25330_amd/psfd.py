@@ -46,7 +46,7 @@ class Desc(ctypes.Structure):
         ("n_ml", c_int32), ("ml_eps", c_dp), ("ml_thick", c_dp), ("eps_sub", c_double * 2),
         ("pml_sigma0", c_double), ("pml_order", c_int32), ("precond", c_int32),
         ("pc_mmin", c_double), ("pc_kref", c_double), ("pc_gamma", c_double), ("pc_reg", c_double),
-        ("prec", c_int32),
+        ("prec", c_int32), ("ml_kz_min", c_double),
     ]
 
 
@@ -122,7 +122,7 @@ def make_desc(cfg, prec=PSFD_C128):
         eps_sub=(c_double * 2)(es.real, es.imag),
         pml_sigma0=cfg["pml_sigma0"], pml_order=cfg["pml_order"], precond=int(cfg["precond"]),
         pc_mmin=cfg["pc_mmin"], pc_kref=cfg["pc_kref"], pc_gamma=cfg["pc_gamma"],
-        pc_reg=cfg["pc_reg"], prec=int(prec))
+        pc_reg=cfg["pc_reg"], prec=int(prec), ml_kz_min=float(cfg.get("ml_kz_min", 0.0)))
     return d, (eps_arr, d_arr)
 
 

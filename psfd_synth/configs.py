@@ -60,6 +60,7 @@ def base_config(nx, ny, nz_abs, t_abs, dx=2.0, dy=None, theta_deg=6.0, phi_deg=0
         "precond": int(precond),
         "pc_mmin": 0.0, "pc_kref": 0.0, "pc_gamma": 1.0, "pc_reg": 0.0,
         "smooth_sigma": 1.0,
+        "ml_kz_min": 0.0,
     }
 
 

@@ -62,6 +62,7 @@ APPLY_CASES = {
     "nz96": _cfg(16, 32, 80, 100.0, theta_deg=6.0, pol=1),
     "nz128": _cfg(16, 16, 112, 140.0, theta_deg=3.0),
     "no_ml_no_pml": dict(_cfg(32, 32, 16, 30.0, multilayer=False), pml_sigma0=0.0),
+    "grazing_cut": dict(_cfg(64, 64, 32, 60.0, theta_deg=6.0, pol=1), ml_kz_min=0.3),
 }
 
 

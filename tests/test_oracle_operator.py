@@ -173,3 +173,21 @@ def test_smoothing_single_mode_and_constant():
     expect = 0.5 + 0.4 * np.exp(-0.5 * sig * sig * kx * kx) * np.cos(2 * np.pi * 3 * jx / 16)
     np.testing.assert_allclose(R.smooth_layout(cfg, a), expect, atol=1e-15)
     np.testing.assert_allclose(R.smooth_layout(cfg, np.ones((8, 16))), 1.0, atol=1e-15)
+
+
+def test_grazing_cutoff_zeroes_only_grazing_modes(rng):
+    """With ml_kz_min the multilayer response of modes with |kz| < ml_kz_min k0
+    vanishes and every other mode keeps it unchanged."""
+    cfg = small_cfg(nx=16, ny=8, nz_abs=4, dx=4.0, theta_deg=6.0)
+    eps = np.full((4, 8, 16), 0.9 + 0.05j)
+    P0 = R.Problem(cfg, eps)
+    P1 = R.Problem(dict(cfg, ml_kz_min=0.5), eps)
+    g = P0.g
+    cut = np.abs(P0.basis.kzb) < 0.5 * g.k0
+    assert cut.any() and (~cut).any()
+    Xt = random_field((2, g.ny, g.nx), rng)
+    V0 = R.ml_field_hat(g, P0.basis, P0.r_te, P0.r_pe, Xt, g.abs_rows)
+    V1 = R.ml_field_hat(g, P1.basis, P1.r_te, P1.r_pe, Xt, g.abs_rows)
+    assert np.all(V1[:, :, cut] == 0)
+    np.testing.assert_array_equal(V1[:, :, ~cut], V0[:, :, ~cut])
+    assert np.abs(V0[:, :, cut]).max() > 0
