@@ -115,6 +115,9 @@ k_axial(const cplx<T>* __restrict__ S, cplx<T>* __restrict__ UW, const OpTables<
   using Addr = AddrVec<TX, PITCH, VS>;
   __shared__ cplx<T> buf[NV * VS];
   __shared__ ColInfo<T> ci[TX];
+  __shared__ cplx<T> twz[NZ];
+  __shared__ cplx<T> invs[NZ];
+  __shared__ T kzs[NZ];
 
   const int tid = threadIdx.x;
   const int iy = blockIdx.y;
@@ -122,6 +125,9 @@ k_axial(const cplx<T>* __restrict__ S, cplx<T>* __restrict__ UW, const OpTables<
   const int64_t plane = (int64_t)t.nx * t.ny;
   const int64_t colbase = (int64_t)iy * t.nx + kx0;
   const T inz = T(1) / T(NZ);
+  // pointwise stages: each thread keeps one column and walks z
+  constexpr int ZS = NT / TX;
+  const int cc = tid % TX, z0 = tid / TX;
 
   for (int e = tid; e < 3 * NZ * TX; e += NT) {
     const int c = e / (NZ * TX), rem = e % (NZ * TX);
@@ -129,14 +135,19 @@ k_axial(const cplx<T>* __restrict__ S, cplx<T>* __restrict__ UW, const OpTables<
     buf[c * VS + z * PITCH + cc] = S[(int64_t)(c * NZ + z) * plane + colbase + cc];
   }
   if (tid < TX) column_info(ci[tid], t, kx0 + tid, iy);
+  for (int i = tid; i < NZ; i += NT) {
+    twz[i] = t.tw_z[i];
+    invs[i] = t.inv_s[i];
+    kzs[i] = t.kz[i];
+  }
   __syncthreads();
 
   if constexpr (MODE == AX_AM || MODE == AX_M) {
-    lds_fft<T, NZ, 3 * TX, NT, false, true>(buf, t.tw_z, Addr{}, tid);
-    for (int e = tid; e < NZ * TX; e += NT) {
-      const int l = e / TX, cc = e % TX;
-      const T kzl = t.kz[l];
-      const T m = damping(ci[cc].kt2 + kzl * kzl, t) * inz;
+    lds_fft<T, NZ, 3 * TX, NT, false, true>(buf, twz, Addr{}, tid);
+    const T kt2 = ci[cc].kt2;
+    for (int l = z0; l < NZ; l += ZS) {
+      const T kzl = kzs[l];
+      const T m = damping(kt2 + kzl * kzl, t) * inz;
       cplx<T>* b0 = &buf[l * PITCH + cc];
       const cplx<T> p0 = m * b0[0], p1 = m * b0[VS], p2 = m * b0[2 * VS];
       b0[0] = p0;
@@ -148,7 +159,7 @@ k_axial(const cplx<T>* __restrict__ S, cplx<T>* __restrict__ UW, const OpTables<
       }
     }
     __syncthreads();
-    lds_fft<T, NZ, (MODE == AX_AM ? 5 : 3) * TX, NT, true, true>(buf, t.tw_z, Addr{}, tid);
+    lds_fft<T, NZ, (MODE == AX_AM ? 5 : 3) * TX, NT, true, true>(buf, twz, Addr{}, tid);
     if constexpr (MODE == AX_M) {
       for (int e = tid; e < 3 * NZ * TX; e += NT) {
         const int c = e / (NZ * TX), rem = e % (NZ * TX);
@@ -158,11 +169,10 @@ k_axial(const cplx<T>* __restrict__ S, cplx<T>* __restrict__ UW, const OpTables<
       return;
     }
   } else {
-    for (int e = tid; e < NZ * TX; e += NT) {
-      const int z = e / TX, cc = e % TX;
+    for (int z = z0; z < NZ; z += ZS) {
       cplx<T> a = buf[z * PITCH + cc], b = buf[VS + z * PITCH + cc];
       if constexpr (MODE == AX_AH) {
-        const cplx<T> is = t.inv_s[z];
+        const cplx<T> is = invs[z];
         a = cmulc(is, a);
         b = cmulc(is, b);
       }
@@ -170,15 +180,14 @@ k_axial(const cplx<T>* __restrict__ S, cplx<T>* __restrict__ UW, const OpTables<
       buf[4 * VS + z * PITCH + cc] = b;
     }
     __syncthreads();
-    lds_fft<T, NZ, 2 * TX, NT, false, true>(buf + 3 * VS, t.tw_z, Addr{}, tid);
-    for (int e = tid; e < NZ * TX; e += NT) {
-      const int l = e / TX, cc = e % TX;
-      const T f = t.kz[l] * inz;
+    lds_fft<T, NZ, 2 * TX, NT, false, true>(buf + 3 * VS, twz, Addr{}, tid);
+    for (int l = z0; l < NZ; l += ZS) {
+      const T f = kzs[l] * inz;
       buf[3 * VS + l * PITCH + cc] = f * mul_i(buf[3 * VS + l * PITCH + cc]);
       buf[4 * VS + l * PITCH + cc] = f * mul_i(buf[4 * VS + l * PITCH + cc]);
     }
     __syncthreads();
-    lds_fft<T, NZ, 2 * TX, NT, true, true>(buf + 3 * VS, t.tw_z, Addr{}, tid);
+    lds_fft<T, NZ, 2 * TX, NT, true, true>(buf + 3 * VS, twz, Addr{}, tid);
   }
 
   // Multilayer branch amplitudes (one thread per column).
@@ -208,23 +217,22 @@ k_axial(const cplx<T>* __restrict__ S, cplx<T>* __restrict__ UW, const OpTables<
   }
 
   // Uz and the inner curl vectors w = -D P_t + i k_t P_z.
-  for (int e = tid; e < NZ * TX; e += NT) {
-    const int z = e / TX, cc = e % TX;
-    const ColInfo<T>& c = ci[cc];
+  const T ckx = ci[cc].kx, cky = ci[cc].ky, ckt2 = ci[cc].kt2;
+  for (int z = z0; z < NZ; z += ZS) {
     const int o = z * PITCH + cc;
     cplx<T> dpx = buf[3 * VS + o], dpy = buf[4 * VS + o];
     if constexpr (MODE != AX_AH) {
-      const cplx<T> is = t.inv_s[z];
+      const cplx<T> is = invs[z];
       dpx = dpx * is;
       dpy = dpy * is;
     }
     const cplx<T> pz = buf[2 * VS + o];
-    const cplx<T> uz = c.kx * mul_i(dpx) + c.ky * mul_i(dpy) + (c.kt2 - t.kbg2) * pz;
+    const cplx<T> uz = ckx * mul_i(dpx) + cky * mul_i(dpy) + (ckt2 - t.kbg2) * pz;
     UW[(int64_t)(2 * NZ + z) * plane + colbase + cc] = uz;
-    cplx<T> wx = c.kx * mul_i(pz) - dpx;
-    cplx<T> wy = c.ky * mul_i(pz) - dpy;
+    cplx<T> wx = ckx * mul_i(pz) - dpx;
+    cplx<T> wy = cky * mul_i(pz) - dpy;
     if constexpr (MODE == AX_AH) {
-      const cplx<T> is = t.inv_s[z];
+      const cplx<T> is = invs[z];
       wx = cmulc(is, wx);
       wy = cmulc(is, wy);
     }
@@ -232,33 +240,31 @@ k_axial(const cplx<T>* __restrict__ S, cplx<T>* __restrict__ UW, const OpTables<
     buf[4 * VS + o] = wy;
   }
   __syncthreads();
-  lds_fft<T, NZ, 2 * TX, NT, false, true>(buf + 3 * VS, t.tw_z, Addr{}, tid);
-  for (int e = tid; e < NZ * TX; e += NT) {
-    const int l = e / TX, cc = e % TX;
-    const T f = t.kz[l] * inz;
+  lds_fft<T, NZ, 2 * TX, NT, false, true>(buf + 3 * VS, twz, Addr{}, tid);
+  for (int l = z0; l < NZ; l += ZS) {
+    const T f = kzs[l] * inz;
     buf[3 * VS + l * PITCH + cc] = f * mul_i(buf[3 * VS + l * PITCH + cc]);
     buf[4 * VS + l * PITCH + cc] = f * mul_i(buf[4 * VS + l * PITCH + cc]);
   }
   __syncthreads();
-  lds_fft<T, NZ, 2 * TX, NT, true, true>(buf + 3 * VS, t.tw_z, Addr{}, tid);
+  lds_fft<T, NZ, 2 * TX, NT, true, true>(buf + 3 * VS, twz, Addr{}, tid);
 
-  for (int e = tid; e < NZ * TX; e += NT) {
-    const int z = e / TX, cc = e % TX;
-    const ColInfo<T>& c = ci[cc];
+  const cplx<T> ca0 = ci[cc].a0, ca1 = ci[cc].a1;
+  for (int z = z0; z < NZ; z += ZS) {
     const int o = z * PITCH + cc;
     cplx<T> dwx = buf[3 * VS + o], dwy = buf[4 * VS + o];
     if constexpr (MODE != AX_AH) {
-      const cplx<T> is = t.inv_s[z];
+      const cplx<T> is = invs[z];
       dwx = dwx * is;
       dwy = dwy * is;
     }
     const cplx<T> px = buf[o], py = buf[VS + o];
-    cplx<T> ux = (c.ky * c.ky - t.kbg2) * px - (c.kx * c.ky) * py + dwx;
-    cplx<T> uy = (c.kx * c.kx - t.kbg2) * py - (c.kx * c.ky) * px + dwy;
+    cplx<T> ux = (cky * cky - t.kbg2) * px - (ckx * cky) * py + dwx;
+    cplx<T> uy = (ckx * ckx - t.kbg2) * py - (ckx * cky) * px + dwy;
     if constexpr (MODE == AX_AH) {
       if (z == t.jev) {
-        ux = ux - c.a0;
-        uy = uy - c.a1;
+        ux = ux - ca0;
+        uy = uy - ca1;
       }
     }
     UW[(int64_t)z * plane + colbase + cc] = ux;
@@ -266,9 +272,8 @@ k_axial(const cplx<T>* __restrict__ S, cplx<T>* __restrict__ UW, const OpTables<
   }
 
   if constexpr (MODE != AX_AH) {
-    for (int e = tid; e < t.nabs * TX; e += NT) {
-      const int ja = e / TX, cc = e % TX;
-      const ColInfo<T>& c = ci[cc];
+    const ColInfo<T> c = ci[cc];
+    for (int ja = z0; ja < t.nabs; ja += ZS) {
       const int z = t.j0 + ja;
       const cplx<T> ph = up_phase(c, t.zabs[ja]);
       const cplx<T> vs = c.a0 * ph, vp = c.a1 * ph;

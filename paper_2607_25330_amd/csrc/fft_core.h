@@ -134,6 +134,16 @@ template <int PITCH>
 struct AddrRow {  // transform b is a contiguous row
   __device__ __forceinline__ int operator()(int b, int i) const { return b * PITCH + i; }
 };
+// Contiguous rows with one element of padding per 256 bytes, so that the
+// stride-R writes of the first Stockham passes spread over all LDS banks.
+template <int N, int PADP>
+struct AddrRowPad {
+  static constexpr int PITCH = N + N / PADP;
+  __device__ __forceinline__ int operator()(int b, int i) const { return b * PITCH + i + i / PADP; }
+};
+template <typename T>
+constexpr int lds_pad_period() { return 256 / (int)sizeof(cplx<T>); }
+
 template <int PITCH>
 struct AddrCol {  // transform b is a column of a [N][PITCH] tile
   __device__ __forceinline__ int operator()(int b, int i) const { return i * PITCH + b; }

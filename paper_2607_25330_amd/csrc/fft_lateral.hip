@@ -30,6 +30,13 @@ constexpr int x_rows() {
   return b;
 }
 
+// rows per block of the inverse x pass: the combine needs a second buffer (W rows)
+template <typename T, int N, int CM>
+constexpr int xinv_rows() {
+  constexpr int b = x_rows<T, N>();
+  return (CM == CB_FWD && b > 1 && (b / 2) * Radices<N>::TPR >= 64) ? b / 2 : b;
+}
+
 template <typename T, int N>
 constexpr int y_tile() {
   int tx = 65536 / (N * (int)sizeof(cplx<T>));
@@ -49,9 +56,29 @@ k_xfft_fwd(const cplx<T>* __restrict__ in, cplx<T>* __restrict__ out,
            const int* __restrict__ skip, const PreOp<T> pre) {
   if (skip && *skip) return;
   constexpr int NT = B * Radices<N>::TPR;
-  __shared__ cplx<T> s[B * N];
+  using Addr = AddrRowPad<N, lds_pad_period<T>()>;
+  __shared__ cplx<T> s[B * Addr::PITCH];
+  __shared__ cplx<T> tws[N];
+  __shared__ int64_t rsrc[B];  // element offset of the source row (-1: past the end)
+  __shared__ int64_t rkd[B];   // element offset of the conj(kd) row (-1: none)
   const int tid = threadIdx.x;
   const int64_t row0 = (int64_t)blockIdx.x * B;
+  for (int i = tid; i < N; i += NT) tws[i] = tw[i];
+  if (tid < B) {
+    const int64_t row = row0 + tid;
+    int64_t src = -1, kro = -1;
+    if (row < nrows_main) {
+      src = row * N;
+    } else if (row < nrows_total) {
+      const int64_t r = row - nrows_main;
+      const int plane = (int)(r / ny), yy = (int)(r % ny);
+      const int c = plane / nabs, ja = plane % nabs;
+      src = ((int64_t)(c * nz + j0 + ja) * ny + yy) * N;
+      kro = ((int64_t)ja * ny + yy) * N;
+    }
+    rsrc[tid] = src;
+    rkd[tid] = kro;
+  }
   // scalars of the fused vector update
   cplx<T> c1 = {T(0), T(0)}, c2 = {T(0), T(0)};
   if constexpr (PRE == PRE_P) {
@@ -67,31 +94,31 @@ k_xfft_fwd(const cplx<T>* __restrict__ in, cplx<T>* __restrict__ out,
     else if constexpr (PRE == PRE_S) return pre.r[idx] - c1 * pre.v[idx];
     else return in[idx];
   };
+  __syncthreads();
   double acc[1] = {0.0};
   for (int e = tid; e < B * N; e += NT) {
-    const int64_t row = row0 + e / N;
-    const int xi = e % N;
+    const int rr = e / N, xi = e % N;
+    const int64_t src = rsrc[rr];
     cplx<T> val = {T(0), T(0)};
-    if (row < nrows_main) {
-      const int64_t idx = row * N + xi;
-      val = value(idx);
-      if constexpr (PRE != PRE_NONE) pre.pv[idx] = val;
-      if constexpr (PRE == PRE_S) acc[0] += norm2(cast<double>(val));
-    } else if (row < nrows_total) {
-      const int64_t r = row - nrows_main;
-      const int plane = (int)(r / ny), yy = (int)(r % ny);
-      const int c = plane / nabs, ja = plane % nabs;
-      const int64_t src = ((int64_t)(c * nz + j0 + ja) * ny + yy) * N + xi;
-      val = cmulc(kd[((int64_t)ja * ny + yy) * N + xi], value(src));
+    if (src >= 0) {
+      const int64_t kro = rkd[rr];
+      if (kro < 0) {
+        val = value(src + xi);
+        if constexpr (PRE != PRE_NONE) pre.pv[src + xi] = val;
+        if constexpr (PRE == PRE_S) acc[0] += norm2(cast<double>(val));
+      } else {
+        val = cmulc(kd[kro + xi], value(src + xi));
+      }
     }
-    s[e] = val;
+    s[Addr{}(rr, xi)] = val;
   }
   if constexpr (PRE == PRE_S) block_partials<1, NT>(acc, pre.part);
   __syncthreads();
-  lds_fft<T, N, B, NT, false, false>(s, tw, AddrRow<N>{}, tid);
+  lds_fft<T, N, B, NT, false, false>(s, tws, Addr{}, tid);
   for (int e = tid; e < B * N; e += NT) {
-    const int64_t row = row0 + e / N;
-    if (row < nrows_total) out[row * N + (e % N)] = s[e];
+    const int rr = e / N;
+    const int64_t row = row0 + rr;
+    if (row < nrows_total) out[row * N + (e % N)] = s[Addr{}(rr, e % N)];
   }
 }
 
@@ -104,42 +131,58 @@ k_xfft_inv(const cplx<T>* __restrict__ UW, cplx<T>* __restrict__ y,
   if (skip && *skip) return;
   constexpr int NT = B * Radices<N>::TPR;
   constexpr int NBUF = (CM == CB_FWD) ? 2 : 1;
-  __shared__ cplx<T> s[NBUF * B * N];
+  using Addr = AddrRowPad<N, lds_pad_period<T>()>;
+  __shared__ cplx<T> s[NBUF * B * Addr::PITCH];
+  __shared__ cplx<T> tws[N];
+  __shared__ int64_t rw[B];   // element offset of the W row (-1: not an absorber row)
+  __shared__ int64_t rkd[B];  // element offset of the kd row (-1: none)
   const int tid = threadIdx.x;
   const int64_t row0 = (int64_t)blockIdx.x * B;
-  const int64_t wbase = (int64_t)3 * nz * ny;  // first W row
+  for (int i = tid; i < N; i += NT) tws[i] = tw[i];
+  if (tid < B) {
+    const int64_t row = row0 + tid;
+    int64_t wo = -1, ko = -1;
+    if (row < nrows && CM != CB_PLAIN) {
+      const int plane = (int)(row / ny), yy = (int)(row % ny);
+      const int c = plane / nz, z = plane % nz;
+      if (z >= j0 && z < j0 + nabs) {
+        wo = ((int64_t)3 * nz * ny + (int64_t)(c * nabs + z - j0) * ny + yy) * N;
+        ko = ((int64_t)(z - j0) * ny + yy) * N;
+      }
+    }
+    rw[tid] = wo;
+    rkd[tid] = ko;
+  }
+  __syncthreads();
   for (int e = tid; e < B * N; e += NT) {
-    const int64_t row = row0 + e / N;
-    const int xi = e % N;
+    const int rr = e / N, xi = e % N;
+    const int64_t row = row0 + rr;
     cplx<T> u = {T(0), T(0)};
     cplx<T> w = {T(0), T(0)};
     if (row < nrows) {
       u = UW[row * N + xi];
       if (CM == CB_FWD) {
-        const int plane = (int)(row / ny), yy = (int)(row % ny);
-        const int c = plane / nz, z = plane % nz;
-        if (z >= j0 && z < j0 + nabs)
-          w = UW[(wbase + (int64_t)(c * nabs + z - j0) * ny + yy) * N + xi];
+        const int64_t wo = rw[rr];
+        if (wo >= 0) w = UW[wo + xi];
       }
     }
-    s[e] = u;
-    if (CM == CB_FWD) s[B * N + e] = w;
+    s[Addr{}(rr, xi)] = u;
+    if (CM == CB_FWD) s[Addr{}(B + rr, xi)] = w;
   }
   __syncthreads();
-  lds_fft<T, N, NBUF * B, NT, true, false>(s, tw, AddrRow<N>{}, tid);
+  lds_fft<T, N, NBUF * B, NT, true, false>(s, tws, Addr{}, tid);
   double acc[3] = {0.0, 0.0, 0.0};
   for (int e = tid; e < B * N; e += NT) {
-    const int64_t row = row0 + e / N;
+    const int rr = e / N, xi = e % N;
+    const int64_t row = row0 + rr;
     if (row >= nrows) continue;
-    const int xi = e % N;
     const int64_t idx = row * N + xi;
-    cplx<T> o = scale * s[e];
+    cplx<T> o = scale * s[Addr{}(rr, xi)];
     if (CM != CB_PLAIN) {
-      const int plane = (int)(row / ny), yy = (int)(row % ny);
-      const int z = plane % nz;
-      if (z >= j0 && z < j0 + nabs) {
-        const cplx<T> kdv = kd[((int64_t)(z - j0) * ny + yy) * N + xi];
-        if (CM == CB_FWD) o = o - scale * (kdv * s[B * N + e]);
+      const int64_t ko = rkd[rr];
+      if (ko >= 0) {
+        const cplx<T> kdv = kd[ko + xi];
+        if (CM == CB_FWD) o = o - scale * (kdv * s[Addr{}(B + rr, xi)]);
         else o = o - cmulc(kdv, x[idx]);
       }
     }
@@ -161,11 +204,13 @@ k_yfft(cplx<T>* __restrict__ buf, const cplx<T>* __restrict__ tw, int nx,
   if (skip && *skip) return;
   constexpr int NT = TX * Radices<N>::TPR;
   __shared__ cplx<T> s[N * TX];
+  __shared__ cplx<T> tws[N];
   const int tid = threadIdx.x;
   const int64_t base = (int64_t)blockIdx.y * N * nx + (int64_t)blockIdx.x * TX;
+  for (int i = tid; i < N; i += NT) tws[i] = tw[i];
   for (int e = tid; e < N * TX; e += NT) s[e] = buf[base + (int64_t)(e / TX) * nx + (e % TX)];
   __syncthreads();
-  lds_fft<T, N, TX, NT, INV, true>(s, tw, AddrCol<TX>{}, tid);
+  lds_fft<T, N, TX, NT, INV, true>(s, tws, AddrCol<TX>{}, tid);
   for (int e = tid; e < N * TX; e += NT) buf[base + (int64_t)(e / TX) * nx + (e % TX)] = s[e];
 }
 
@@ -198,10 +243,14 @@ static hipError_t xfwd_n(const OpTables<T>& t, const cplx<T>* in, cplx<T>* out,
 }
 
 template <typename T, int N, int CM>
-static void xinv_launch(dim3 g, dim3 b, const OpTables<T>& t, const cplx<T>* UW, cplx<T>* y,
-                        int64_t nrows, int ny, const cplx<T>* x, T scale, const PostOp<T>& post,
+static void xinv_launch(const OpTables<T>& t, const cplx<T>* UW, cplx<T>* y, int64_t nrows,
+                        int ny, const cplx<T>* x, T scale, const PostOp<T>& post, int* nblk_out,
                         hipStream_t st) {
-  constexpr int B = x_rows<T, N>();
+  constexpr int B = xinv_rows<T, N, CM>();
+  constexpr int NT = B * Radices<N>::TPR;
+  const int64_t nblk = (nrows + B - 1) / B;
+  if (nblk_out) *nblk_out = (int)nblk;
+  dim3 g((unsigned)nblk), b(NT);
   if (post.mode == POST_DOT)
     hipLaunchKernelGGL((k_xfft_inv<T, N, B, CM, POST_DOT>), g, b, 0, st, UW, y, t.tw_x, nrows,
                        ny, t.nz, t.j0, t.nabs, scale, t.kd, x, t.skip, post);
@@ -214,15 +263,10 @@ template <typename T, int N>
 static hipError_t xinv_n(const OpTables<T>& t, const cplx<T>* UW, cplx<T>* y, int64_t nrows,
                          int ny, int cmode, const cplx<T>* x, T scale, const PostOp<T>& post,
                          int* nblk_out, hipStream_t st) {
-  constexpr int B = x_rows<T, N>();
-  constexpr int NT = B * Radices<N>::TPR;
-  const int64_t nblk = (nrows + B - 1) / B;
-  if (nblk_out) *nblk_out = (int)nblk;
-  dim3 g((unsigned)nblk), b(NT);
   switch (cmode) {
-    case CB_PLAIN: xinv_launch<T, N, CB_PLAIN>(g, b, t, UW, y, nrows, ny, x, scale, post, st); break;
-    case CB_FWD: xinv_launch<T, N, CB_FWD>(g, b, t, UW, y, nrows, ny, x, scale, post, st); break;
-    default: xinv_launch<T, N, CB_ADJ>(g, b, t, UW, y, nrows, ny, x, scale, post, st); break;
+    case CB_PLAIN: xinv_launch<T, N, CB_PLAIN>(t, UW, y, nrows, ny, x, scale, post, nblk_out, st); break;
+    case CB_FWD: xinv_launch<T, N, CB_FWD>(t, UW, y, nrows, ny, x, scale, post, nblk_out, st); break;
+    default: xinv_launch<T, N, CB_ADJ>(t, UW, y, nrows, ny, x, scale, post, nblk_out, st); break;
   }
   return hipGetLastError();
 }
