@@ -91,6 +91,12 @@ struct psfd_plan {
   KState* ks_host = nullptr;
   double* part = nullptr;
 
+  // solves run on a private non-blocking stream (capturable), joined to the caller's
+  hipStream_t own_st = nullptr;
+  hipEvent_t join_ev = nullptr;
+  hipGraphExec_t gexec[2][2] = {};  // captured iteration chunk [complex64?][adjoint?]
+  bool use_graphs = true;
+
   // kernel timing (psfd_profile_enable)
   int prof_kernel = 0;
   int prof_elem = 16;  // element size of the timed launches (the working precision)
@@ -100,6 +106,11 @@ struct psfd_plan {
   int64_t prof_launches = 0;
 
   ~psfd_plan() {
+    for (auto& row : gexec)
+      for (auto& g : row)
+        if (g) (void)hipGraphExecDestroy(g);
+    if (own_st) (void)hipStreamDestroy(own_st);
+    if (join_ev) (void)hipEventDestroy(join_ev);
     for (auto& pr : ev_open) { ev_pool.push_back(pr.first); ev_pool.push_back(pr.second); }
     for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
     for (void* p : allocs) (void)hipFree(p);
@@ -375,11 +386,8 @@ psfd_status run_bicgstab(struct psfd_plan* P, bool adjoint, double bnorm2, doubl
   // the unpreconditioned adjoint transforms extra rows of the input: update p separately
   const bool fuse_p = !(adjoint && !pc);
   int nb_v = 0, nb_t = 0;
-  int launched = 0;
-  res->done = 0;
-  while (launched < maxit) {
-    const int chunk = std::min(kChunk, maxit - launched);
-    for (int i = 0; i < chunk; ++i) {
+  auto launch_iters = [&](int count) -> psfd_status {
+    for (int i = 0; i < count; ++i) {
       Fuse<T> fa;
       if (fuse_p) {
         fa.pre.mode = PRE_P;
@@ -416,6 +424,36 @@ psfd_status run_bicgstab(struct psfd_plan* P, bool adjoint, double bnorm2, doubl
                                 st));
       CHK(launch_finalize(FIN_RHO, ks, part, red_blocks(n), 0.0, 0.0, st));
     }
+    return PSFD_OK;
+  };
+  // A full chunk is captured once per plan into a HIP graph and replayed:
+  // every launch argument is fixed per plan and convergence is tested on
+  // the device, so the same graph serves every chunk of every solve.
+  hipGraphExec_t& gx = P->gexec[sizeof(T) == 4 ? 1 : 0][adjoint ? 1 : 0];
+  const bool graphs = P->use_graphs && P->prof_kernel == PROF_OFF;
+  int launched = 0;
+  res->done = 0;
+  while (launched < maxit) {
+    const int chunk = std::min(kChunk, maxit - launched);
+    if (graphs && chunk == kChunk) {
+      if (!gx) {
+        hipGraph_t g = nullptr;
+        CHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+        psfd_status cs = launch_iters(chunk);
+        hipError_t ce = hipStreamEndCapture(st, &g);
+        if (cs != PSFD_OK) {
+          if (g) (void)hipGraphDestroy(g);
+          return cs;
+        }
+        CHK(ce);
+        hipError_t ie = hipGraphInstantiate(&gx, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        CHK(ie);
+      }
+      CHK(hipGraphLaunch(gx, st));
+    } else {
+      CHKS(launch_iters(chunk));
+    }
     launched += chunk;
     CHKS(read_state(P));
     if (P->ks_host->done != 0) break;
@@ -448,7 +486,25 @@ double inner_tolerance(double tol, double rrel) {
   return t;
 }
 
+psfd_status solve_body(struct psfd_plan* P, const void* b_in, const void* x0, void* E_out,
+                       double tol, int maxit, bool adjoint, psfd_info* info);
+
+// The solve runs on the plan's private stream, after the work already queued on
+// the caller's stream; it returns with that private stream drained.
 psfd_status solve_impl(struct psfd_plan* P, const void* b_in, const void* x0, void* E_out,
+                       double tol, int maxit, bool adjoint, psfd_info* info) {
+  CHK(hipEventRecord(P->join_ev, P->st));
+  CHK(hipStreamWaitEvent(P->own_st, P->join_ev, 0));
+  hipStream_t user = P->st;
+  P->st = P->own_st;
+  psfd_status s = solve_body(P, b_in, x0, E_out, tol, maxit, adjoint, info);
+  hipError_t e = hipStreamSynchronize(P->own_st);
+  P->st = user;
+  if (s == PSFD_OK && e != hipSuccess) return fail(PSFD_ERR_HIP, hipGetErrorString(e));
+  return s;
+}
+
+psfd_status solve_body(struct psfd_plan* P, const void* b_in, const void* x0, void* E_out,
                        double tol, int maxit, bool adjoint, psfd_info* info) {
   psfd_info loc{};
   const bool mixed = P->prec != PSFD_C128;
@@ -677,6 +733,9 @@ psfd_status plan_impl(const psfd_desc* d, const void* eps, void* stream, struct 
     f.pc_gamma = (float)t.pc_gamma; f.pc_reg = (float)t.pc_reg; f.pc_bf16 = t.pc_bf16;
     CHKS(ensure_fp32(P));
   }
+  CHK(hipStreamCreateWithFlags(&P->own_st, hipStreamNonBlocking));
+  CHK(hipEventCreateWithFlags(&P->join_ev, hipEventDisableTiming));
+  P->use_graphs = std::getenv("PSFD_NO_GRAPH") == nullptr;
   CHKS(set_eps_impl(P, eps));
   CHK(hipStreamSynchronize(P->st));
   guard.p = nullptr;
