@@ -169,6 +169,45 @@ psfd_status psfd_precond_c64(psfd_plan_t p, const void* x, void* y);
 psfd_status psfd_solve(psfd_plan_t p, const void* b, const void* x0, void* E, double tol,
                        int32_t maxit, int32_t adjoint, psfd_info* info);
 
+/* r = b - A E in FP64 (b = NULL: the analytic source psfd_rhs) and, if
+ * norm2 != NULL, ||r||^2 (host, synchronises).  E, r: device complex128
+ * fields; r must not overlap E or b.  The residual of equation
+ * relative_residual, and the residual term of the physics loss of the paper
+ * (section 2.2, equation loss, first term). */
+psfd_status psfd_residual(psfd_plan_t p, const void* b, const void* E, void* r, double* norm2);
+
+/* Sensitivity of the PSFD system to the permittivity (adjoint method):
+ *   grad[v] = scale * sum_alpha u_alpha(v) conj(Psi_alpha(v)),
+ *   Psi = E + R_ml[E] + (E_inc + R_ml E_inc)   on absorber voxels v,
+ * i.e. the field that d_eps multiplies in A E - b (equations bg_source and
+ * vector_helmholtz_operator with R_ml inside A).  With u = A^{-H} g and
+ * scale = k0^2 this is dL/d eps for a loss L(E) whose gradient with respect
+ * to the solution E = A^{-1} b is g (PyTorch convention: grad = dL/dRe +
+ * i dL/dIm).  E, u: device complex128 fields; grad: device [nz_abs][ny][nx]
+ * complex128 (overwritten). */
+psfd_status psfd_eps_grad(psfd_plan_t p, const void* E, const void* u, double scale, void* grad);
+
+/* Batched solves of independent problems (mask clips x incidence angles x
+ * polarisations, uneven sizes allowed).  psfd_plan_batch validates and
+ * records n problems: the descriptors and multilayer tables are copied; the
+ * permittivity pointers eps_abs_dev[i] (as in psfd_plan) are kept and must
+ * stay valid until psfd_solve_batch returns.  The returned handle is only
+ * usable with psfd_solve_batch and psfd_destroy.  psfd_solve_batch solves
+ * every problem (source b = psfd_rhs of that problem, E_i = x0[i] + M y,
+ * as psfd_solve) after the work queued on the batch's stream: problems run
+ * largest first on a pool of host workers, each with its own non-blocking
+ * stream, plan and captured iteration graphs, so that independent solves
+ * overlap on the device.  x0 may be NULL (all zero) or hold NULL entries;
+ * E[i] are device complex128 fields of problem i's shape; infos is a host
+ * array of n entries (required).  Returns PSFD_OK when every problem
+ * converged, else the status of the first failing problem (all problems
+ * are attempted).  PSFD_BATCH_WORKERS (environment) sets the pool size
+ * (default 4). */
+psfd_status psfd_plan_batch(int32_t n, const psfd_desc* descs, const void* const* eps_abs_dev,
+                            void* hip_stream, psfd_plan_t* out);
+psfd_status psfd_solve_batch(psfd_plan_t batch, const void* const* x0, void* const* E, double tol,
+                             int32_t maxit, psfd_info* infos);
+
 /* Copy the plan's per-mode multilayer reflections (transfer-matrix method,
  * paper section 2.2 step (iii)): r_te, r_pe device [ny][nx] complex128.
  * r_pe is the tangential-electric-field TM coefficient. */

@@ -548,6 +548,39 @@ def solve(P, b=None, x0=None, tol=1e-10, maxit=20000, precond=None, adjoint=Fals
 
 
 # --------------------------------------------------------------------------
+# Sensitivity to the permittivity (adjoint method)
+# --------------------------------------------------------------------------
+
+
+def local_field(P, E):
+    """Psi = E + E_ML[E] + (E_inc + R_ml E_inc) on absorber rows: the field that
+    d_eps multiplies in A E - b (equations bg_source and vector_helmholtz_operator
+    with R_ml inside A), shape (3, nz_abs, ny, nx)."""
+    g = P.g
+    Xh = fft2(E)
+    V = ml_field_hat(g, P.basis, P.r_te, P.r_pe, Xh[0:2, g.j_ev], g.abs_rows)
+    bg = background_field(g, P.cfg, g.abs_rows)
+    return E[:, g.abs_rows] + ifft2(V) + bg[:, :, None, None]
+
+
+def eps_gradient(P, E, u, scale):
+    """scale * sum_alpha u_alpha conj(Psi_alpha) on absorber voxels.
+
+    A E - b depends on eps only through -k0^2 d_eps * Psi(E), so for a loss L
+    of the solution E = A^-1 b with gradient g (dL/dRe E + i dL/dIm E), the
+    gradient with respect to eps is k0^2 sum_alpha mu_alpha conj(Psi_alpha)
+    with mu = A^-H g."""
+    return scale * np.sum(u[:, P.g.abs_rows] * np.conj(local_field(P, E)), axis=0)
+
+
+def residual_loss(P, E):
+    """Mean squared residual (1/N) ||A E - b||^2, N = nx ny nz (paper, equation
+    loss, first term)."""
+    r = apply_A(P, E) - rhs(P)
+    return float(np.vdot(r, r).real) / (P.g.nx * P.g.ny * P.g.nz)
+
+
+# --------------------------------------------------------------------------
 # Outputs and diagnostics
 # --------------------------------------------------------------------------
 

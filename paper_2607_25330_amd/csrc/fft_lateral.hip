@@ -325,6 +325,15 @@ hipError_t launch_xfft_inv(const OpTables<T>& t, const cplx<T>* UW, cplx<T>* y, 
 }
 
 template <typename T>
+hipError_t launch_xfft_inv_rows(const OpTables<T>& t, const cplx<T>* in, cplx<T>* out,
+                                int64_t nrows, hipStream_t st) {
+  const T scale = T(1) / (T(t.nx) * T(t.ny));
+#define CALL_XR(NN) xinv_n<T, NN>(t, in, out, nrows, t.ny, CB_PLAIN, nullptr, scale, PostOp<T>{}, nullptr, st)
+  PSFD_LATERAL_SWITCH(t.nx, CALL_XR)
+#undef CALL_XR
+}
+
+template <typename T>
 hipError_t launch_plane_fft(const OpTables<T>& t, cplx<T>* in, cplx<T>* out, bool inverse,
                             hipStream_t st) {
   hipError_t e;
@@ -359,6 +368,8 @@ template hipError_t launch_xfft_inv<double>(const OpTables<double>&, const cplx<
 template hipError_t launch_xfft_inv<float>(const OpTables<float>&, const cplx<float>*,
                                            cplx<float>*, int, const cplx<float>*,
                                            const PostOp<float>&, int*, hipStream_t);
+template hipError_t launch_xfft_inv_rows<double>(const OpTables<double>&, const cplx<double>*,
+                                                 cplx<double>*, int64_t, hipStream_t);
 template hipError_t launch_plane_fft<double>(const OpTables<double>&, cplx<double>*,
                                              cplx<double>*, bool, hipStream_t);
 

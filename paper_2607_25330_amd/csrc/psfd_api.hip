@@ -3,11 +3,13 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
+#include <thread>
 #include <utility>
 #include <vector>
 
@@ -90,6 +92,12 @@ struct psfd_plan {
   KState* ks = nullptr;
   KState* ks_host = nullptr;
   double* part = nullptr;
+
+  // batch handle (psfd_plan_batch): the recorded problems
+  bool is_batch = false;
+  std::vector<psfd_desc> bdesc;
+  std::vector<std::vector<double>> b_ml_eps, b_ml_d;
+  std::vector<const void*> beps;
 
   // solves run on a private non-blocking stream (capturable), joined to the caller's
   hipStream_t own_st = nullptr;
@@ -776,6 +784,7 @@ psfd_status layout_impl(const psfd_desc* d, const double* a_bin, const double ep
 template <typename T>
 psfd_status apply_entry(struct psfd_plan* P, const void* x, void* y, int op) {
   if (!P || !x || !y) return fail(PSFD_ERR_ARG, "NULL argument");
+  if (P->is_batch) return fail(PSFD_ERR_ARG, "a batch handle only serves psfd_solve_batch");
   if (x == y) return fail(PSFD_ERR_ARG, "x and y must not overlap");
   if (sizeof(T) == 4) CHKS(ensure_fp32(P));
   if (sizeof(T) == 4 && !P->t32.kx)
@@ -796,6 +805,87 @@ psfd_status guarded(F&& f) {
   }
 }
 
+psfd_status plan_batch_impl(int n, const psfd_desc* descs, const void* const* eps, void* stream,
+                            struct psfd_plan** out) {
+  if (n < 1 || !descs || !eps || !out) return fail(PSFD_ERR_ARG, "bad batch arguments");
+  for (int i = 0; i < n; ++i) {
+    psfd_status st = validate(&descs[i]);
+    if (st != PSFD_OK) return fail(st, "problem " + std::to_string(i) + ": " + g_err);
+    if (!eps[i]) return fail(PSFD_ERR_ARG, "problem " + std::to_string(i) + ": eps is NULL");
+  }
+  struct psfd_plan* B = new (std::nothrow) struct psfd_plan();
+  if (!B) return fail(PSFD_ERR_ALLOC, "host allocation failed");
+  B->is_batch = true;
+  B->st = static_cast<hipStream_t>(stream);
+  for (int i = 0; i < n; ++i) {
+    psfd_desc d = descs[i];
+    B->b_ml_eps.emplace_back(d.ml_eps, d.ml_eps + 2 * d.n_ml);
+    B->b_ml_d.emplace_back(d.ml_thick, d.ml_thick + d.n_ml);
+    B->bdesc.push_back(d);
+    B->beps.push_back(eps[i]);
+  }
+  for (int i = 0; i < n; ++i) {  // point the copies at the owned tables
+    B->bdesc[i].ml_eps = B->b_ml_eps[i].data();
+    B->bdesc[i].ml_thick = B->b_ml_d[i].data();
+  }
+  *out = B;
+  return PSFD_OK;
+}
+
+psfd_status solve_batch_impl(struct psfd_plan* B, const void* const* x0, void* const* E, double tol,
+                             int maxit, psfd_info* infos) {
+  if (!B || !B->is_batch || !E || !infos) return fail(PSFD_ERR_ARG, "bad batch arguments");
+  const int n = (int)B->bdesc.size();
+  for (int i = 0; i < n; ++i)
+    if (!E[i]) return fail(PSFD_ERR_ARG, "E[" + std::to_string(i) + "] is NULL");
+  CHK(B->st ? hipStreamSynchronize(B->st) : hipDeviceSynchronize());
+  int dev = 0;
+  CHK(hipGetDevice(&dev));
+  // largest problems first, for load balance
+  std::vector<int> order(n);
+  for (int i = 0; i < n; ++i) order[i] = i;
+  auto size_of = [&](int i) {
+    const psfd_desc& d = B->bdesc[i];
+    return (int64_t)d.nx * d.ny * (d.nz_abs + d.nz_gap_bot + d.nz_gap_top + 2 * d.nz_pml);
+  };
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return size_of(a) > size_of(b); });
+  int workers = 4;
+  if (const char* w = std::getenv("PSFD_BATCH_WORKERS")) workers = std::max(1, std::atoi(w));
+  workers = std::min(workers, n);
+  std::vector<psfd_status> status(n, PSFD_OK);
+  std::vector<std::string> errs(n);
+  std::atomic<int> next(0);
+  auto work = [&]() {
+    if (hipSetDevice(dev) != hipSuccess) return;
+    hipStream_t ws = nullptr;
+    if (hipStreamCreateWithFlags(&ws, hipStreamNonBlocking) != hipSuccess) ws = nullptr;
+    for (int k = next++; k < n; k = next++) {
+      const int i = order[k];
+      infos[i] = psfd_info{};
+      struct psfd_plan* p = nullptr;
+      psfd_status st = guarded([&] { return plan_impl(&B->bdesc[i], B->beps[i], ws, &p); });
+      if (st == PSFD_OK) {
+        st = guarded([&] {
+          return solve_impl(p, nullptr, x0 ? x0[i] : nullptr, E[i], tol, maxit, false, &infos[i]);
+        });
+      }
+      if (st != PSFD_OK) {
+        errs[i] = g_err;
+        infos[i].status = st;
+      }
+      status[i] = st;
+      delete p;
+    }
+    if (ws) (void)hipStreamDestroy(ws);
+  };
+  std::vector<std::thread> pool;
+  for (int w = 0; w < workers; ++w) pool.emplace_back(work);
+  for (auto& t : pool) t.join();
+  for (int i = 0; i < n; ++i)
+    if (status[i] != PSFD_OK) return fail(status[i], "problem " + std::to_string(i) + ": " + errs[i]);
+  return PSFD_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -811,12 +901,12 @@ psfd_status psfd_plan(const psfd_desc* d, const void* eps_abs_dev, void* hip_str
 }
 
 psfd_status psfd_set_eps(psfd_plan_t p, const void* eps_abs_dev) {
-  if (!p || !eps_abs_dev) return fail(PSFD_ERR_ARG, "NULL argument");
+  if (!p || !eps_abs_dev || p->is_batch) return fail(PSFD_ERR_ARG, "NULL argument");
   return guarded([&] { return set_eps_impl(p, eps_abs_dev); });
 }
 
 psfd_status psfd_rhs(psfd_plan_t p, void* b) {
-  if (!p || !b) return fail(PSFD_ERR_ARG, "NULL argument");
+  if (!p || !b || p->is_batch) return fail(PSFD_ERR_ARG, "NULL argument");
   return guarded([&]() -> psfd_status {
     RhsArgs a{p->nx, p->ny, p->nz, p->nabs, p->j0, p->d.pol, p->k0, p->kz0, p->d.theta, p->d.phi,
               p->zabs64, p->rte64, p->rpe64, p->kd64};
@@ -846,14 +936,70 @@ psfd_status psfd_precond_c64(psfd_plan_t p, const void* x, void* y) {
 
 psfd_status psfd_solve(psfd_plan_t p, const void* b, const void* x0, void* E, double tol,
                        int32_t maxit, int32_t adjoint, psfd_info* info) {
-  if (!p || !E) return fail(PSFD_ERR_ARG, "NULL argument");
+  if (!p || !E || p->is_batch) return fail(PSFD_ERR_ARG, "NULL argument or batch handle");
   if (!(tol > 0) || maxit < 0) return fail(PSFD_ERR_ARG, "need tol > 0 and maxit >= 0");
   if (b && b == E) return fail(PSFD_ERR_ARG, "b and E must not overlap");
   return guarded([&] { return solve_impl(p, b, x0, E, tol, maxit, adjoint != 0, info); });
 }
 
+psfd_status psfd_residual(psfd_plan_t p, const void* b, const void* E, void* r, double* norm2) {
+  if (!p || !E || !r || p->is_batch) return fail(PSFD_ERR_ARG, "NULL argument or batch handle");
+  if (r == E || (b && r == b)) return fail(PSFD_ERR_ARG, "r must not overlap E or b");
+  return guarded([&]() -> psfd_status {
+    CHKS(ensure_solver_common(p));
+    const cplx<double>* bb = static_cast<const cplx<double>*>(b);
+    if (!bb) {
+      RhsArgs a{p->nx, p->ny, p->nz, p->nabs, p->j0, p->d.pol, p->k0, p->kz0, p->d.theta,
+                p->d.phi, p->zabs64, p->rte64, p->rpe64, p->kd64};
+      CHK(launch_rhs<double>(a, p->b64, p->st));
+      bb = p->b64;
+    }
+    double rr2 = 0.0;
+    CHKS(true_residual(p, bb, static_cast<const cplx<double>*>(E), static_cast<cplx<double>*>(r),
+                       false, &rr2));
+    if (norm2) *norm2 = rr2;
+    return PSFD_OK;
+  });
+}
+
+psfd_status psfd_eps_grad(psfd_plan_t p, const void* E, const void* u, double scale, void* grad) {
+  if (!p || !E || !u || !grad || p->is_batch) return fail(PSFD_ERR_ARG, "NULL argument or batch handle");
+  return guarded([&]() -> psfd_status {
+    // E + E_ML[E] on absorber rows: forward lateral transform, axial kernel (W planes),
+    // inverse lateral transform of the W planes only
+    OpTables<double> t = p->t64;
+    const int p3 = 3 * p->nz, pa = 3 * p->nabs;
+    cplx<double>* S = p->S64;
+    cplx<double>* UW = p->UW64;
+    cplx<double>* Wr = S;  // reuse: the spectrum is no longer needed once UW is formed
+    CHK(launch_xfft_fwd<double>(t, static_cast<const cplx<double>*>(E), S, false,
+                                PreOp<double>{}, nullptr, p->st));
+    CHK(launch_yfft<double>(t, S, p3, false, p->st));
+    CHK(launch_axial<double>(t, S, UW, AX_A, p->st));
+    cplx<double>* Wp = UW + (int64_t)p3 * p->plane;
+    CHK(launch_yfft<double>(t, Wp, pa, true, p->st));
+    CHK(launch_xfft_inv_rows<double>(t, Wp, Wr, (int64_t)pa * p->ny, p->st));
+    RhsArgs a{p->nx, p->ny, p->nz, p->nabs, p->j0, p->d.pol, p->k0, p->kz0, p->d.theta,
+              p->d.phi, p->zabs64, p->rte64, p->rpe64, p->kd64};
+    CHK(launch_eps_grad(a, Wr, static_cast<const cplx<double>*>(u), scale,
+                        static_cast<cplx<double>*>(grad), p->st));
+    return PSFD_OK;
+  });
+}
+
+psfd_status psfd_plan_batch(int32_t n, const psfd_desc* descs, const void* const* eps_abs_dev,
+                            void* hip_stream, psfd_plan_t* out) {
+  return guarded([&] { return plan_batch_impl(n, descs, eps_abs_dev, hip_stream, out); });
+}
+
+psfd_status psfd_solve_batch(psfd_plan_t batch, const void* const* x0, void* const* E, double tol,
+                             int32_t maxit, psfd_info* infos) {
+  if (!(tol > 0) || maxit < 0) return fail(PSFD_ERR_ARG, "need tol > 0 and maxit >= 0");
+  return guarded([&] { return solve_batch_impl(batch, x0, E, tol, maxit, infos); });
+}
+
 psfd_status psfd_ml_reflection(psfd_plan_t p, void* r_te, void* r_pe) {
-  if (!p || !r_te || !r_pe) return fail(PSFD_ERR_ARG, "NULL argument");
+  if (!p || !r_te || !r_pe || p->is_batch) return fail(PSFD_ERR_ARG, "NULL argument");
   return guarded([&]() -> psfd_status {
     const size_t bytes = sizeof(cplx<double>) * (size_t)p->plane;
     CHK(hipMemcpyAsync(r_te, p->rte64, bytes, hipMemcpyDeviceToDevice, p->st));
@@ -863,7 +1009,7 @@ psfd_status psfd_ml_reflection(psfd_plan_t p, void* r_te, void* r_pe) {
 }
 
 psfd_status psfd_profile_enable(psfd_plan_t p, int32_t kernel) {
-  if (!p || kernel < PROF_OFF || kernel > PROF_XINV) return fail(PSFD_ERR_ARG, "bad argument");
+  if (!p || p->is_batch || kernel < PROF_OFF || kernel > PROF_XINV) return fail(PSFD_ERR_ARG, "bad argument");
   return guarded([&]() -> psfd_status {
     CHK(p->st ? hipStreamSynchronize(p->st) : hipDeviceSynchronize());
     collect_events(p);
@@ -877,7 +1023,7 @@ psfd_status psfd_profile_enable(psfd_plan_t p, int32_t kernel) {
 }
 
 psfd_status psfd_profile_read(psfd_plan_t p, double* total_ms, int64_t* launches, double* bytes) {
-  if (!p || !total_ms || !launches || !bytes) return fail(PSFD_ERR_ARG, "NULL argument");
+  if (!p || p->is_batch || !total_ms || !launches || !bytes) return fail(PSFD_ERR_ARG, "NULL argument");
   return guarded([&]() -> psfd_status {
     CHK(p->st ? hipStreamSynchronize(p->st) : hipDeviceSynchronize());
     collect_events(p);

@@ -83,6 +83,10 @@ hipError_t launch_yfft(const OpTables<T>& t, cplx<T>* buf, int nplanes, bool inv
 template <typename T>
 hipError_t launch_xfft_inv(const OpTables<T>& t, const cplx<T>* UW, cplx<T>* y, int cmode,
                            const cplx<T>* x, const PostOp<T>& post, int* nblk, hipStream_t st);
+// Inverse x pass (no combine, scale 1/(nx ny)) over nrows arbitrary rows.
+template <typename T>
+hipError_t launch_xfft_inv_rows(const OpTables<T>& t, const cplx<T>* in, cplx<T>* out,
+                                int64_t nrows, hipStream_t st);
 // 2-D FFT of a single plane (layout smoothing).  Forward: in -> out.
 // Inverse (unnormalised): y pass in place on `in`, x pass into `out`.
 template <typename T>
@@ -118,6 +122,10 @@ struct RhsArgs {
 template <typename T>
 hipError_t launch_rhs(const RhsArgs& a, cplx<T>* b, hipStream_t st);
 
+// grad[v] = scale * sum_a u_a(v) conj(W_a(v) + bg_a(z_v)) on absorber voxels;
+// W: [3][nabs][ny][nx] real-space E + E_ML on absorber rows; u: full field.
+hipError_t launch_eps_grad(const RhsArgs& a, const cplx<double>* W, const cplx<double>* u,
+                           double scale, cplx<double>* grad, hipStream_t st);
 hipError_t launch_eps_contrast(const cplx<double>* eps, int n, double k0, double eps_bg,
                                cplx<double>* kd64, cplx<float>* kd32, hipStream_t st);
 hipError_t launch_smooth_mult(cplx<double>* plane, int nx, int ny, double dx, double dy,

@@ -93,6 +93,52 @@ hipError_t launch_rhs(const RhsArgs& a, cplx<T>* b, hipStream_t st) {
 template hipError_t launch_rhs<double>(const RhsArgs&, cplx<double>*, hipStream_t);
 template hipError_t launch_rhs<float>(const RhsArgs&, cplx<float>*, hipStream_t);
 
+// Background field E_inc + R_ml E_inc, component c, absorber row ja.
+__device__ cplx<double> background(const RhsArgs& a, int c, int ja) {
+  double sth, cth, sph, cph;
+  sincos(a.theta, &sth, &cth);
+  sincos(a.phi, &sph, &cph);
+  double ein, eup;
+  if (a.pol == 0) {
+    ein = (c == 0) ? -sph : (c == 1 ? cph : 0.0);
+    eup = ein;
+  } else {
+    ein = (c == 0) ? cth * cph : (c == 1 ? cth * sph : sth);
+    eup = (c == 2) ? -sth : ein;
+  }
+  const double zz = a.zabs[ja];
+  const cplx<double> r = (a.pol == 0) ? a.r_te[0] : a.r_pe[0];
+  double s, co;
+  sincos(a.kz0 * zz, &s, &co);
+  const cplx<double> down = {co, -s}, up = {co, s};
+  return ein * down + eup * (r * up);
+}
+
+__global__ void k_eps_grad(const RhsArgs a, const cplx<double>* __restrict__ W,
+                           const cplx<double>* __restrict__ u, double scale,
+                           cplx<double>* __restrict__ grad) {
+  const int64_t plane = (int64_t)a.nx * a.ny;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (int64_t)a.nabs * plane) return;
+  const int ja = (int)(i / plane);
+  const int64_t inplane = i % plane;
+  cplx<double> acc = {0.0, 0.0};
+  for (int c = 0; c < 3; ++c) {
+    const cplx<double> psi = W[((int64_t)c * a.nabs + ja) * plane + inplane] + background(a, c, ja);
+    const cplx<double> uv = u[((int64_t)c * a.nz + a.j0 + ja) * plane + inplane];
+    acc = acc + uv * conj(psi);
+  }
+  grad[i] = scale * acc;
+}
+
+hipError_t launch_eps_grad(const RhsArgs& a, const cplx<double>* W, const cplx<double>* u,
+                           double scale, cplx<double>* grad, hipStream_t st) {
+  const int64_t n = (int64_t)a.nabs * a.nx * a.ny;
+  hipLaunchKernelGGL(k_eps_grad, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, a, W, u,
+                     scale, grad);
+  return hipGetLastError();
+}
+
 __global__ void k_eps_contrast(const cplx<double>* __restrict__ eps, int n, double k02,
                                double eps_bg, cplx<double>* __restrict__ kd64,
                                cplx<float>* __restrict__ kd32) {

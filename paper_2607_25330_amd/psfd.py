@@ -69,6 +69,12 @@ _SIGS = {
     "psfd_solve": [c_void_p, c_void_p, c_void_p, c_void_p, c_double, c_int32, c_int32,
                    ctypes.POINTER(Info)],
     "psfd_ml_reflection": [c_void_p, c_void_p, c_void_p],
+    "psfd_residual": [c_void_p, c_void_p, c_void_p, c_void_p, c_dp],
+    "psfd_eps_grad": [c_void_p, c_void_p, c_void_p, c_double, c_void_p],
+    "psfd_plan_batch": [c_int32, ctypes.POINTER(Desc), ctypes.POINTER(c_void_p), c_void_p,
+                        ctypes.POINTER(c_void_p)],
+    "psfd_solve_batch": [c_void_p, ctypes.POINTER(c_void_p), ctypes.POINTER(c_void_p), c_double,
+                         c_int32, ctypes.POINTER(Info)],
     "psfd_profile_enable": [c_void_p, c_int32],
     "psfd_profile_read": [c_void_p, c_dp, ctypes.POINTER(c_int64), c_dp],
 }
@@ -232,6 +238,27 @@ class Plan:
                    "restarts": info.restarts, "applies": info.applies,
                    "rrel": info.rrel_true, "rrel_rec": info.rrel_hist_last}
 
+    def residual(self, E, b=None, out=None):
+        """(r, ||r||^2) with r = b - A E in FP64 (b = None: the analytic source)."""
+        r = self._field() if out is None else out
+        n2 = c_double()
+        bp = c_void_p(None) if b is None else _ptr(b, torch.complex128, self.shape, "b")
+        _call("psfd_residual", self._h, bp, _ptr(E, torch.complex128, self.shape, "E"),
+              _ptr(r, torch.complex128, self.shape, "r"), ctypes.byref(n2))
+        return r, n2.value
+
+    def eps_grad(self, E, u, scale, out=None):
+        """scale * sum_alpha u_alpha conj(Psi_alpha(E)) on absorber voxels (nz_abs, ny, nx)."""
+        g = torch.empty(self.eps_shape, dtype=torch.complex128, device=self.device) if out is None else out
+        _call("psfd_eps_grad", self._h, _ptr(E, torch.complex128, self.shape, "E"),
+              _ptr(u, torch.complex128, self.shape, "u"), c_double(scale),
+              _ptr(g, torch.complex128, self.eps_shape, "grad"))
+        return g
+
+    @property
+    def k0(self):
+        return 2.0 * 3.141592653589793 / self.cfg["lam"]
+
     def profile_enable(self, kernel):
         """Time every launch of one kernel class with HIP events (see PROFILE_KERNELS)."""
         _call("psfd_profile_enable", self._h, c_int32(PROFILE_KERNELS.get(kernel, kernel)))
@@ -244,6 +271,58 @@ class Plan:
 
     def field_size(self):
         return int(lib().psfd_field_size(self._h))
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().psfd_destroy(self._h)
+            self._h = c_void_p(None)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """psfd_plan_batch / psfd_solve_batch over independent problems of any sizes."""
+
+    def __init__(self, cfgs, eps_list, prec=PSFD_C128):
+        n = len(cfgs)
+        if n == 0 or len(eps_list) != n:
+            raise ValueError("need one permittivity per configuration")
+        descs = (Desc * n)()
+        self._keep = []
+        self.shapes = []
+        ptrs = (c_void_p * n)()
+        for i, (cfg, eps) in enumerate(zip(cfgs, eps_list)):
+            d, keep = make_desc(cfg, prec)
+            descs[i] = d
+            self._keep.append(keep)
+            self.shapes.append((3, nz_of(cfg), cfg["ny"], cfg["nx"]))
+            ptrs[i] = _ptr(eps, torch.complex128, (cfg["nz_abs"], cfg["ny"], cfg["nx"]), "eps")
+        self._eps = list(eps_list)  # must stay alive until solve returns
+        self.device = eps_list[0].device
+        self.n = n
+        h = c_void_p()
+        _call("psfd_plan_batch", c_int32(n), descs, ptrs, _stream_handle(), ctypes.byref(h))
+        self._h = h
+
+    def solve(self, x0=None, tol=1e-6, maxit=20000, check=True):
+        E = [torch.empty(sh, dtype=torch.complex128, device=self.device) for sh in self.shapes]
+        Ep = (c_void_p * self.n)(*[e.data_ptr() for e in E])
+        if x0 is None:
+            xp = ctypes.cast(None, ctypes.POINTER(c_void_p))
+        else:
+            xp = (c_void_p * self.n)(*[0 if x is None else _ptr(x, torch.complex128, sh, "x0").value
+                                       for x, sh in zip(x0, self.shapes)])
+        infos = (Info * self.n)()
+        st = lib().psfd_solve_batch(self._h, xp, Ep, c_double(tol), c_int32(maxit), infos)
+        if check and st != PSFD_OK:
+            raise PsfdError("psfd_solve_batch", st, lib().psfd_last_error().decode())
+        out = [{"iters": i.iters, "status": STATUS_NAMES.get(i.status, i.status),
+                "restarts": i.restarts, "rrel": i.rrel_true} for i in infos]
+        return E, out
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
@@ -284,3 +363,19 @@ def psfd_solve(plan, b=None, x0=None, tol=1e-6, maxit=20000, adjoint=False):
 
 def psfd_destroy(plan):
     plan.close()
+
+
+def psfd_plan_batch(cfgs, eps_list, prec=PSFD_C128):
+    return Batch(cfgs, eps_list, prec)
+
+
+def psfd_solve_batch(batch, x0=None, tol=1e-6, maxit=20000):
+    return batch.solve(x0, tol, maxit)
+
+
+def psfd_residual(plan, E, b=None):
+    return plan.residual(E, b)
+
+
+def psfd_eps_grad(plan, E, u, scale):
+    return plan.eps_grad(E, u, scale)

@@ -1,0 +1,177 @@
+"""GPU tests of the batched solve and of the adjoint gradients.
+
+* psfd_solve_batch over uneven sizes, angles and polarisations reproduces the
+  individual psfd_solve results (same kernels, same arithmetic: identical);
+* psfd_residual and psfd_eps_grad against the oracle on seeded fields;
+* the autograd gradient of the scattered intensity with respect to the
+  permittivity against the oracle's adjoint gradient (small grid) and against
+  central finite differences of FP64 GPU solves (h = 1e-6) on 8 seeded voxels
+  of a 128 x 128 x (32 + 16) clip, for the FP64 and the mixed path;
+* the residual-loss gradients with respect to the field and the permittivity.
+"""
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import psfd_ref as R
+from psfd_synth import base_config, eps_absorber_default, random_field, rect_layout
+
+pytestmark = pytest.mark.gpu
+DEV = torch.device("cuda:0")
+EPS_ABS = eps_absorber_default()
+
+
+@pytest.fixture(scope="module")
+def psfd():
+    import paper_2607_25330_amd as m
+    m.lib()
+    return m
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+def _eps(cfg, seed):
+    rng = np.random.default_rng(seed)
+    a = rect_layout(cfg["nx"], cfg["ny"], rng, wmin=2, wmax=8)
+    return R.eps_from_fill(cfg, R.smooth_layout(cfg, a), EPS_ABS)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_batch_matches_individual_solves(psfd, prec):
+    cfgs = [base_config(32, 32, 16, 30.0, theta_deg=0.0, pol=0),
+            base_config(64, 32, 8, 15.0, theta_deg=5.0, pol=1, dy=2.5),
+            base_config(16, 16, 8, 15.0, theta_deg=10.0, phi_deg=30.0, pol=0),
+            base_config(64, 64, 32, 60.0, theta_deg=2.5, pol=1)]
+    for c in cfgs:
+        c["ml_kz_min"] = 0.1
+    eps = [dev(_eps(c, 10 + i)) for i, c in enumerate(cfgs)]
+    x0 = [None, None, dev(0.01 * random_field((3, 24, 16, 16), np.random.default_rng(1))), None]
+    batch = psfd.Batch(cfgs, eps, prec=prec)
+    E_b, infos = batch.solve(x0=x0, tol=1e-8)
+    batch.close()
+    for i, c in enumerate(cfgs):
+        plan = psfd.Plan(c, eps[i], prec=prec)
+        E_i, info = plan.solve(tol=1e-8, x0=x0[i])
+        plan.close()
+        assert infos[i]["status"] == "OK" and infos[i]["iters"] == info["iters"]
+        assert torch.equal(E_b[i], E_i)
+
+
+def test_residual_and_eps_grad_match_oracle(psfd):
+    cfg = base_config(32, 16, 8, 15.0, theta_deg=6.0, phi_deg=20.0, pol=1, dy=2.5)
+    eps = _eps(cfg, 3)
+    P = R.Problem(cfg, eps)
+    rng = np.random.default_rng(4)
+    E = random_field(P.g.shape, rng)
+    u = random_field(P.g.shape, rng)
+    plan = psfd.Plan(cfg, dev(eps))
+    r, rr = plan.residual(dev(E))
+    r_ref = R.rhs(P) - R.apply_A(P, E)
+    assert np.abs(host(r) - r_ref).max() <= 1e-12 * np.abs(r_ref).max()
+    assert abs(rr - np.vdot(r_ref, r_ref).real) <= 1e-11 * np.vdot(r_ref, r_ref).real
+    g = host(plan.eps_grad(dev(E), dev(u), 0.7))
+    g_ref = R.eps_gradient(P, E, u, 0.7)
+    assert np.abs(g - g_ref).max() <= 1e-12 * np.abs(g_ref).max()
+    plan.close()
+
+
+def test_intensity_gradient_matches_oracle_adjoint(psfd):
+    from paper_2607_25330_amd.autograd import scattered_field
+    cfg = base_config(16, 16, 8, 15.0, theta_deg=6.0, phi_deg=12.0, pol=0)
+    eps = _eps(cfg, 7)
+    P = R.Problem(cfg, eps)
+    E_ref, _ = R.solve(P, tol=1e-13)
+    g = np.zeros_like(E_ref)
+    g[:, P.g.j_obs] = 2 * E_ref[:, P.g.j_obs]
+    mu, _ = R.solve(P, b=g, tol=1e-13, adjoint=True)
+    grad_ref = R.eps_gradient(P, E_ref, mu, P.g.k0 ** 2)
+    e = dev(eps).requires_grad_(True)
+    E = scattered_field(e, cfg, tol=1e-12)
+    J = (E[:, P.g.j_obs].abs() ** 2).sum()
+    J.backward()
+    grad = host(e.grad)
+    assert np.linalg.norm(grad - grad_ref) <= 1e-8 * np.linalg.norm(grad_ref)
+
+
+@pytest.fixture(scope="module")
+def c5_case():
+    cfg = dict(base_config(128, 128, 32, 60.0, theta_deg=6.0, pol=0), ml_kz_min=0.1)
+    eps = _eps(cfg, 21)
+    rng = np.random.default_rng(22)
+    voxels = [(int(rng.integers(0, 32)), int(rng.integers(0, 128)), int(rng.integers(0, 128)))
+              for _ in range(8)]
+    return cfg, eps, voxels
+
+
+def _intensity_gpu(psfd, cfg, eps_t, jobs, tol=1e-12):
+    plan = psfd.Plan(cfg, eps_t)
+    E, info = plan.solve(tol=tol)
+    plan.close()
+    return float((E[:, jobs].abs() ** 2).sum())
+
+
+def _autograd_intensity(psfd, cfg, eps, prec):
+    from paper_2607_25330_amd.autograd import scattered_field
+    jobs = cfg["nz_pml"] + cfg["nz_gap_bot"] + cfg["nz_abs"]
+    e = dev(eps).requires_grad_(True)
+    E = scattered_field(e, cfg, prec=prec, tol=1e-12 if prec == 0 else 1e-10)
+    (E[:, jobs].abs() ** 2).sum().backward()
+    return host(e.grad)
+
+
+def test_mixed_gradient_matches_fp64_gradient(psfd, c5_case):
+    cfg, eps, _ = c5_case
+    g64 = _autograd_intensity(psfd, cfg, eps, 0)
+    g32 = _autograd_intensity(psfd, cfg, eps, 1)
+    assert np.linalg.norm(g32 - g64) <= 1e-6 * np.linalg.norm(g64)
+
+
+# The finite difference is limited by the solves: an error dJ of J in each
+# perturbed solve gives an error ~ dJ / h in the quotient.  Solved to 1e-12,
+# J carries ~4e-11 of noise here, i.e. ~2e-5 in the quotient whatever the size
+# of the gradient component: the bound is 1e-4 relative plus a floor of 1e-4
+# of the largest gradient component.
+@pytest.mark.parametrize("prec", [0, 1])
+def test_intensity_gradient_matches_finite_differences(psfd, c5_case, prec):
+    cfg, eps, voxels = c5_case
+    rtol = 1e-4
+    jobs = cfg["nz_pml"] + cfg["nz_gap_bot"] + cfg["nz_abs"]
+    grad = _autograd_intensity(psfd, cfg, eps, prec)
+    h = 1e-6
+    base = dev(eps)
+    for v in voxels:
+        fd = []
+        for step in (h, 1j * h):
+            ep, em = base.clone(), base.clone()
+            ep[v] += step
+            em[v] -= step
+            fd.append((_intensity_gpu(psfd, cfg, ep, jobs) - _intensity_gpu(psfd, cfg, em, jobs)) / (2 * h))
+        fd = complex(*fd)
+        assert abs(grad[v] - fd) <= rtol * (abs(fd) + np.abs(grad).max()), (v, grad[v], fd)
+
+
+def test_residual_loss_gradients(psfd):
+    from paper_2607_25330_amd.autograd import residual_loss
+    cfg = base_config(32, 32, 8, 15.0, theta_deg=6.0, pol=1)
+    eps = _eps(cfg, 9)
+    P = R.Problem(cfg, eps)
+    E0 = 0.05 * random_field(P.g.shape, np.random.default_rng(5))
+    E = dev(E0).requires_grad_(True)
+    e = dev(eps).requires_grad_(True)
+    J = residual_loss(E, e, cfg)
+    assert abs(float(J.detach()) - R.residual_loss(P, E0)) <= 1e-12 * R.residual_loss(P, E0)
+    J.backward()
+    N = P.g.nx * P.g.ny * P.g.nz
+    r = R.rhs(P) - R.apply_A(P, E0)
+    gE_ref = -(2.0 / N) * R.apply_AH(P, r)
+    ge_ref = R.eps_gradient(P, E0, r, 2 * P.g.k0 ** 2 / N)
+    assert np.abs(host(E.grad) - gE_ref).max() <= 1e-11 * np.abs(gE_ref).max()
+    assert np.abs(host(e.grad) - ge_ref).max() <= 1e-11 * np.abs(ge_ref).max()
