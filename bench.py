@@ -100,6 +100,202 @@ def cpu_leg(iters_proj, sample_iters):
             "s_per_iteration": per_iter, "setup_s": setup, "projected": True}
 
 
+def _sources_hash():
+    """SHA-256 over the library's kernel sources (file name + bytes, sorted by name)."""
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    for p in sorted(glob.glob(os.path.join(ROOT, "paper_2607_25330_amd", "csrc", "*"))):
+        h.update(os.path.basename(p).encode())
+        with open(p, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed counter summary
+    (2 x FETCH_SIZE + WRITE_SIZE, calibrated on a device copy), or None when
+    there is none or the kernel sources changed since the counters were taken."""
+    import re
+    path = os.path.join(ROOT, "profiles", "traffic_256x256x48_mixed.md")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        text = f.read()
+    sha = re.search(r"^sources_sha256: ([0-9a-f]{64})$", text, re.M)
+    row = re.search(r"^traffic_bytes_per_launch %s: ([0-9.eE+]+)$" % re.escape(kernel), text, re.M)
+    if not sha or not row or sha.group(1) != _sources_hash():
+        return None
+    return float(row.group(1))
+
+
+def _sync_time(fn):
+    import torch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    out = fn()
+    torch.cuda.synchronize()
+    return out, time.perf_counter() - t0
+
+
+def workload_c1(psfd, args):
+    """32x32 lateral, 16 absorber cells / 30 nm (Nz = 32), 6 deg TE, plain FP64 to 1e-10."""
+    import numpy as np
+    import torch
+    from psfd_synth import config_c1, eps_absorber_default, rect_layout
+    dev = torch.device("cuda:0")
+    cfg = config_c1(0)
+    lays = [torch.from_numpy(rect_layout(32, 32, np.random.default_rng(s))).to(dev)
+            for s in range(args.warmup + args.steps)]
+
+    def one(a):
+        eps = psfd.psfd_layout_eps(cfg, a, eps_absorber_default())
+        plan = psfd.Plan(cfg, eps, psfd.PSFD_C128)
+        _, info = plan.solve(tol=1e-10, maxit=args.maxit, check=False)
+        plan.close()
+        return info
+    for a in lays[args.steps:]:
+        one(a)
+    infos, dt = _sync_time(lambda: [one(a) for a in lays[:args.steps]])
+    return {"metric": METRIC, "value": round(args.steps / dt, 3), "unit": "solves/s",
+            "ms_per_solve": round(1e3 * dt / args.steps, 2), "dtype": "f64",
+            "config": {"workload": "32x32x(16+16), 2 nm, 30 nm absorber, 6 deg TE, FP64, tol 1e-10, "
+                                   "seeded rectangles (seeds 0..)"},
+            "iters": [i["iters"] for i in infos],
+            "converged": all(i["status"] == "OK" for i in infos)}
+
+
+def workload_c3(psfd, args):
+    """Batched uneven solves: clips of {64,128,192,256}^2 x 48 x 5 angles x 2 polarisations."""
+    import math as m
+    import numpy as np
+    import torch
+    from psfd_synth import base_config, config_c3_sizes, eps_absorber_default, rect_layout
+    dev = torch.device("cuda:0")
+    sizes, angles, pols = config_c3_sizes()
+    rng = np.random.default_rng(300)
+    cfgs, eps = [], []
+    for c in range(args.c3_clips):
+        n = int(rng.choice(sizes))
+        a = torch.from_numpy(rect_layout(n, n, np.random.default_rng(1000 + c))).to(dev)
+        for th in angles:
+            for pol in pols:
+                cfg = dict(base_config(n, n, 32, 60.0, theta_deg=th, pol=pol), ml_kz_min=ML_KZ_MIN)
+                cfgs.append(cfg)
+                eps.append(psfd.psfd_layout_eps(cfg, a, eps_absorber_default()))
+    batch = psfd.Batch(cfgs, eps, prec=psfd.PSFD_C64_REFINE64)
+    (E, infos), dt = _sync_time(lambda: batch.solve(tol=args.tol, maxit=args.maxit, check=False))
+    batch.close()
+    vox = sum(3 * c["nx"] * c["ny"] * (c["nz_abs"] + 16) for c in cfgs)
+    return {"metric": METRIC, "value": round(len(cfgs) / dt, 3), "unit": "solves/s",
+            "seconds": round(dt, 2), "dtype": "f32+f64",
+            "config": {"workload": f"{args.c3_clips} seeded rectangle clips, lateral sizes from "
+                                   "{64,128,192,256}^2, Nz 48, x 5 angles (0-10 deg) x TE/TM, "
+                                   "mixed precision, tol %g, batched" % args.tol,
+                       "solves": len(cfgs), "voxels": vox,
+                       "workers": int(os.environ.get("PSFD_BATCH_WORKERS", "4"))},
+            "iters_mean": round(sum(i["iters"] for i in infos) / len(infos), 1),
+            "iters_max": max(i["iters"] for i in infos),
+            "converged": sum(i["status"] == "OK" for i in infos)}
+
+
+def _smooth_noise(shape, seed, dev, sigma_cells=8.0):
+    """Seeded complex noise on the device, Gaussian-filtered over the lateral axes
+    (periodic, std sigma_cells) - the warm-start perturbation at full size."""
+    import torch
+    g = torch.Generator(device=dev).manual_seed(seed)
+    z = torch.complex(torch.randn(shape, generator=g, device=dev, dtype=torch.float64),
+                      torch.randn(shape, generator=g, device=dev, dtype=torch.float64))
+    fy = torch.fft.fftfreq(shape[-2], device=dev, dtype=torch.float64)
+    fx = torch.fft.fftfreq(shape[-1], device=dev, dtype=torch.float64)
+    h = torch.exp(-2.0 * (torch.pi * sigma_cells) ** 2 * (fy[:, None] ** 2 + fx[None, :] ** 2))
+    for c in range(shape[0]):
+        z[c] = torch.fft.ifft2(torch.fft.fft2(z[c]) * h)
+    return z
+
+
+def _log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def workload_c4(psfd, args):
+    """1024x1024 lateral, 48 absorber cells / 70 nm (Nz = 64), curvilinear layout, 6 deg, TE and
+    TM: FP64 reference to 1e-10, then mixed solves (complex64 Krylov; bf16-rounded damping
+    multiplier as the bf16 preconditioner trial) from null and from a warm start (reference +
+    smooth complex noise scaled to r_rel ~ 0.1)."""
+    import numpy as np
+    import torch
+    from psfd_synth import config_c4, curvilinear, eps_absorber_default
+    dev = torch.device("cuda:0")
+    a = torch.from_numpy(curvilinear(1024, 1024, np.random.default_rng(400))).to(dev)
+    out = {"metric": METRIC, "unit": "solves/s", "dtype": "f32+f64",
+           "config": {"workload": "1024x1024x(48+16), 2 nm, 70 nm absorber, curvilinear, 6 deg, "
+                                  "grazing cutoff 0.1, tol %g" % args.tol}, "legs": {}}
+    for pol in (0, 1):
+        cfg = dict(config_c4(pol), ml_kz_min=ML_KZ_MIN)
+        eps = psfd.psfd_layout_eps(cfg, a, eps_absorber_default())
+        ref = psfd.Plan(cfg, eps, psfd.PSFD_C128)
+        (E_ref, i_ref), t_ref = _sync_time(lambda: ref.solve(tol=1e-10, maxit=args.maxit, check=False))
+        _log(f"c4 pol {pol} fp64 reference: {i_ref['iters']} it, {t_ref:.2f} s, {i_ref['status']}")
+        b = ref.rhs()
+        bn = float(torch.linalg.vector_norm(b))
+        d = _smooth_noise((3, ref.nz, 1024, 1024), 401 + pol, dev)
+        r_d, _ = ref.residual(d, b=torch.zeros_like(b))  # -A d
+        s = 0.1 * bn / float(torch.linalg.vector_norm(r_d))
+        x0 = (E_ref + s * d).contiguous()
+        del d, r_d
+        _, rr0 = ref.residual(x0)
+        leg = {"fp64_ref_iters": i_ref["iters"], "fp64_ref_s": round(t_ref, 3),
+               "x0_rrel": round((rr0 ** 0.5) / bn, 4)}
+        for name, prec, warm in [("mixed_null", psfd.PSFD_C64_REFINE64, False),
+                                 ("mixed_warm", psfd.PSFD_C64_REFINE64, True),
+                                 ("bf16pc_warm", psfd.PSFD_C64_BF16PC_REFINE64, True),
+                                 ("fp64_null", psfd.PSFD_C128, False)]:
+            plan = psfd.Plan(cfg, eps, prec)
+            (E, info), dt = _sync_time(lambda: plan.solve(x0=x0 if warm else None, tol=args.tol,
+                                                          maxit=args.maxit, check=False))
+            _log(f"c4 pol {pol} {name}: {info['iters']} it, {dt:.2f} s, {info['status']}")
+            err = float(torch.linalg.vector_norm(E - E_ref) / torch.linalg.vector_norm(E_ref))
+            leg[name] = {"iters": info["iters"], "s": round(dt, 3), "status": info["status"],
+                         "rrel": info["rrel"], "field_err_vs_ref": err}
+            plan.close()
+            del E
+        ref.close()
+        out["legs"]["TE" if pol == 0 else "TM"] = leg
+    te = out["legs"]["TE"]["mixed_warm"]["s"] + out["legs"]["TM"]["mixed_warm"]["s"]
+    out["value"] = round(2 / te, 4)
+    return out
+
+
+def workload_c5(psfd, args):
+    """Gradients: 16 clips 128x128x(32+16), TE 6 deg; gradient of the summed observation-row
+    intensity w.r.t. eps through the autograd wrapper (mixed forward + adjoint solves)."""
+    import numpy as np
+    import torch
+    from paper_2607_25330_amd.autograd import scattered_field
+    from psfd_synth import config_c5, eps_absorber_default, rect_layout
+    dev = torch.device("cuda:0")
+    cfg = dict(config_c5(), ml_kz_min=ML_KZ_MIN)
+    jobs = cfg["nz_pml"] + cfg["nz_gap_bot"] + cfg["nz_abs"]
+    eps = [psfd.psfd_layout_eps(cfg, torch.from_numpy(rect_layout(128, 128, np.random.default_rng(500 + c))).to(dev),
+                                eps_absorber_default()) for c in range(16)]
+
+    def grads():
+        out = []
+        for e in eps:
+            x = e.clone().requires_grad_(True)
+            E = scattered_field(x, cfg, prec=psfd.PSFD_C64_REFINE64, tol=args.tol)
+            (E[:, jobs].abs() ** 2).sum().backward()
+            out.append(x.grad)
+        return out
+    grads()
+    g, dt = _sync_time(grads)
+    return {"metric": "gradient evaluations/s (forward + adjoint solve)", "value": round(16 / dt, 3),
+            "unit": "gradients/s", "dtype": "f32+f64",
+            "config": {"workload": "16 seeded rectangle clips 128x128x(32+16), TE 6 deg, d(sum |E|^2 "
+                                   "on the observation row)/d eps, mixed, tol %g" % args.tol}}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -114,6 +310,9 @@ def main():
     ap.add_argument("--cpu-leg", type=float, default=None, help=argparse.SUPPRESS)
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run one device copy of this size (for counter calibration)")
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5"],
+                    help="c2 (default) is the headline line; the others print their own line")
+    ap.add_argument("--c3-clips", type=int, default=64)
     args = ap.parse_args()
 
     if args.cpu_leg is not None:
@@ -129,6 +328,14 @@ def main():
     import torch
     import paper_2607_25330_amd as psfd
     from psfd_synth import config_c2
+
+    if args.workload != "c2":
+        fn = {"c1": workload_c1, "c3": workload_c3, "c4": workload_c4, "c5": workload_c5}[args.workload]
+        res = fn(psfd, args)
+        res.update({"n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "data": "synthetic",
+                    "higher_is_better": True, "vs_baseline": None})
+        print(json.dumps(res), flush=True)
+        return 0
 
     dev = torch.device("cuda:0")
     cfgs = [dict(config_c2(pol), ml_kz_min=ML_KZ_MIN) for pol in (0, 1)]
@@ -177,7 +384,8 @@ def main():
     ms, nl, by = prof
     achieved = (by / (ms * 1e-3)) / 1e9 if ms > 0 else 0.0
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": measured_traffic(args.roofline_kernel),
                 "kernel": args.roofline_kernel, "launches": nl,
                 "avg_launch_us": round(1e3 * ms / max(nl, 1), 2),
                 "bytes_per_launch": by / max(nl, 1)}
