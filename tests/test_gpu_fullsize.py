@@ -1,0 +1,135 @@
+"""GPU parity at the full workload sizes, in the configuration the benchmark
+times (mixed-precision plans, grazing cutoff 0.1, device-built permittivity).
+
+* 256 x 256 x 48 (line/space layout, TE and TM): permittivity, operator,
+  preconditioner and source element by element against the FP64 oracle; the
+  mixed solve at 1e-6 is checked through the oracle's own operator, i.e. the
+  oracle's true residual of the library's field is at most the tolerance.
+* 1024 x 1024 x 64: the oracle cannot run that size inside a test, so the
+  permittivity and the input are 4 x 4 tilings of a 256 x 256 cell.  A tiled
+  envelope only populates every 4th lateral order, and order 4m of the
+  1024-cell period has the same Bloch wavevector as order m of the 256-cell
+  period, so A, M and b of the large problem are exactly the tilings of the
+  small problem's (which the oracle computes).  This exercises the large
+  problem's launch geometry and 64-bit offsets end to end; the per-order
+  arithmetic at 1024 cells is covered element by element by the 1024-wide
+  cases of the operator parity tests.
+"""
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import psfd_ref as R
+from psfd_synth import (config_c2, config_c4, curvilinear, eps_absorber_default, line_space,
+                        random_field)
+
+pytestmark = pytest.mark.gpu
+
+DEV = torch.device("cuda:0")
+EPS_ABS = eps_absorber_default()
+KZ_CUT = 0.1
+
+
+@pytest.fixture(scope="module")
+def psfd():
+    import paper_2607_25330_amd as m
+    m.lib()
+    return m
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def relmax(a, b):
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+@pytest.fixture(scope="module", params=[0, 1], ids=["TE", "TM"])
+def c2(request):
+    pol = request.param
+    cfg = dict(config_c2(pol), ml_kz_min=KZ_CUT)
+    a = line_space(cfg["nx"], cfg["ny"], cfg["dx"], np.random.default_rng(100))
+    eps = R.eps_from_fill(cfg, R.smooth_layout(cfg, a), EPS_ABS)
+    return cfg, a, eps, R.Problem(cfg, eps)
+
+
+def test_c2_operator_full_size(psfd, c2):
+    cfg, a, eps, P = c2
+    eps_d = psfd.psfd_layout_eps(cfg, dev(a), EPS_ABS)
+    assert np.abs(host(eps_d) - eps).max() < 1e-13
+    plan = psfd.Plan(cfg, eps_d, prec=psfd.PSFD_C64_REFINE64)
+    x = random_field(P.g.shape, np.random.default_rng(7))
+    xd = dev(x)
+    Ax = R.apply_A(P, x)
+    assert relmax(host(plan.apply(xd)), Ax) < 1e-12
+    assert relmax(host(plan.precond(xd)), R.apply_M(P, x)) < 1e-12
+    assert relmax(host(plan.rhs()), R.rhs(P)) < 1e-12
+    x32 = xd.to(torch.complex64)
+    assert relmax(host(plan.apply_c64(x32)).astype(np.complex128), Ax) < 3e-5
+    plan.close()
+
+
+def test_c2_mixed_solve_oracle_residual(psfd, c2):
+    cfg, a, eps, P = c2
+    plan = psfd.Plan(cfg, psfd.psfd_layout_eps(cfg, dev(a), EPS_ABS), prec=psfd.PSFD_C64_REFINE64)
+    E, info = plan.solve(tol=1e-6)
+    assert info["status"] == "OK"
+    E = host(E)
+    b = R.rhs(P)
+    r = np.linalg.norm(b - R.apply_A(P, E)) / np.linalg.norm(b)
+    assert r <= 1.0e-6 * 1.01
+    assert abs(r - info["rrel"]) <= 1e-3 * r + 1e-12
+    plan.close()
+
+
+def _tiled_case(pol, seed):
+    big = dict(config_c4(pol), ml_kz_min=KZ_CUT)
+    small = dict(big, nx=256, ny=256)
+    a = curvilinear(256, 256, np.random.default_rng(seed), sigma_cells=6.0)
+    eps_s = R.eps_from_fill(small, R.smooth_layout(small, a), EPS_ABS)
+    return big, small, eps_s
+
+
+@pytest.mark.parametrize("pol", [0, 1], ids=["TE", "TM"])
+def test_c4_tiled_operator_full_size(psfd, pol):
+    big, small, eps_s = _tiled_case(pol, 40 + pol)
+    P = R.Problem(small, eps_s)
+    x_s = random_field(P.g.shape, np.random.default_rng(8 + pol))
+    ref_A = R.apply_A(P, x_s)
+    ref_M = R.apply_M(P, x_s)
+    ref_b = R.rhs(P)
+    plan = psfd.Plan(big, dev(np.tile(eps_s, (1, 4, 4))), prec=psfd.PSFD_C64_REFINE64)
+    xd = dev(np.tile(x_s, (1, 1, 4, 4)))
+    for got, ref in ((plan.apply(xd), ref_A), (plan.precond(xd), ref_M), (plan.rhs(), ref_b)):
+        g = host(got)
+        assert relmax(g, np.tile(ref, (1, 1, 4, 4))) < 1e-12
+        del g
+    g = host(plan.apply_c64(xd.to(torch.complex64))).astype(np.complex128)
+    assert relmax(g, np.tile(ref_A, (1, 1, 4, 4))) < 3e-5
+    plan.close()
+
+
+def test_c4_tiled_mixed_solve(psfd):
+    """The large solve from a zero start stays (up to rounding) in the tiled
+    subspace; its first 256 x 256 cell meets the oracle's residual bound."""
+    big, small, eps_s = _tiled_case(0, 44)
+    P = R.Problem(small, eps_s)
+    plan = psfd.Plan(big, dev(np.tile(eps_s, (1, 4, 4))), prec=psfd.PSFD_C64_REFINE64)
+    E, info = plan.solve(tol=1e-6)
+    assert info["status"] == "OK"
+    E = host(E)
+    cell = E[:, :, :256, :256]
+    dev_tiling = max(np.abs(E[:, :, 256 * i:256 * (i + 1), 256 * j:256 * (j + 1)] - cell).max()
+                     for i in range(4) for j in range(4))
+    assert dev_tiling <= 1e-4 * np.abs(cell).max()
+    b = R.rhs(P)
+    r = np.linalg.norm(b - R.apply_A(P, cell)) / np.linalg.norm(b)
+    assert r <= 1.5e-6
+    plan.close()

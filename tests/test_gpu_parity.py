@@ -63,6 +63,10 @@ APPLY_CASES = {
     "nz128": _cfg(16, 16, 112, 140.0, theta_deg=3.0),
     "no_ml_no_pml": dict(_cfg(32, 32, 16, 30.0, multilayer=False), pml_sigma0=0.0),
     "grazing_cut": dict(_cfg(64, 64, 32, 60.0, theta_deg=6.0, pol=1), ml_kz_min=0.3),
+    "nz64": _cfg(32, 16, 48, 70.0, theta_deg=6.0, phi_deg=15.0),
+    "wide_512": _cfg(512, 16, 8, 15.0, theta_deg=4.0, phi_deg=10.0, pol=1),
+    "wide_1024": _cfg(1024, 16, 8, 15.0, theta_deg=4.0, phi_deg=10.0),
+    "tall_1024": _cfg(16, 1024, 8, 15.0, theta_deg=7.0, phi_deg=-35.0, pol=1),
 }
 
 
@@ -85,7 +89,8 @@ def test_operator_pieces(psfd, name):
     plan.close()
 
 
-@pytest.mark.parametrize("name", ["c1", "nonsq_tm_phi", "radix3_lateral"])
+@pytest.mark.parametrize("name", ["c1", "nonsq_tm_phi", "radix3_lateral", "nz64", "wide_1024",
+                                  "tall_1024"])
 def test_operator_pieces_c64(psfd, name):
     cfg = APPLY_CASES[name]
     a, eps = case(cfg, seed=3)
