@@ -19,6 +19,7 @@
 // branch by its adjoint applied to F2[conj(k0^2 d_eps) x] (extra input planes),
 // which lands on the evaluation row.
 #include "fft_core.h"
+#include "lane_fft.h"
 #include "psfd_internal.h"
 
 namespace psfd {
@@ -289,9 +290,197 @@ k_axial(const cplx<T>* __restrict__ S, cplx<T>* __restrict__ UW, const OpTables<
   }
 }
 
+
+// ------------------------------------------------------------------------
+// Register-resident variant for the forward modes (A, AM, M): L lanes own a
+// column (lane t keeps z = t + L m), every z transform is a LaneFft, so the
+// column never goes through LDS and the kernel has no barrier.  Same
+// arithmetic as k_axial above, in the order that keeps at most five column
+// vectors live: P^ (k layout) -> D P -> P_z -> U_z and w -> D w -> P_x, P_y
+// -> U_x, U_y and the absorber-row W planes.
+// Element (row r, column g) of a plane stack lives at r * plane + g; with
+// r = r0 + lt (lt the lane within the column's group) the offset splits into
+// a wave-uniform part r0 * plane and a per-lane byte offset
+// (lt * plane + g) * sizeof, below 4 GiB for every supported size: each
+// access is a scalar base plus one 32-bit lane offset.
+template <typename T, int NZ, int L, int MODE>
+__global__ void __launch_bounds__(256)
+k_axial_reg(const cplx<T>* __restrict__ S, cplx<T>* __restrict__ UW, const OpTables<T> t) {
+  if (t.skip && *t.skip) return;
+  constexpr int E = NZ / L;
+  const int lt = threadIdx.x & (L - 1);
+  const int64_t g = (int64_t)blockIdx.x * (256 / L) + (threadIdx.x / L);
+  const int64_t plane = (int64_t)t.nx * t.ny;
+  const int64_t pb = plane * (int64_t)sizeof(cplx<T>);
+  const uint32_t lane_bo = (uint32_t)((lt * plane + g) * (int64_t)sizeof(cplx<T>));
+  auto ld = [&](int64_t row) -> cplx<T> {  // row of lane 0 of the group
+    return *reinterpret_cast<const cplx<T>*>(reinterpret_cast<const char*>(S) + row * pb + lane_bo);
+  };
+  auto stv = [&](int64_t row, cplx<T> v) {
+    *reinterpret_cast<cplx<T>*>(reinterpret_cast<char*>(UW) + row * pb + lane_bo) = v;
+  };
+  const T inz = T(1) / T(NZ);
+  LaneFft<T, NZ, L> F;
+  F.init(t.tw_z, lt);
+  const int kofs = E * lane_brev<L>(lt);  // k of register k2 is k2 + kofs
+
+  cplx<T> px[E], py[E], pz[E];
+#pragma unroll
+  for (int m = 0; m < E; ++m) {
+    px[m] = ld(L * m);
+    py[m] = ld(NZ + L * m);
+    pz[m] = ld(2 * NZ + L * m);
+  }
+  const int ix = (int)(g % t.nx), iy = (int)(g / t.nx);
+  const T kx = t.kx[ix], ky = t.ky[iy];
+  const T kt2 = kx * kx + ky * ky;
+
+  if constexpr (MODE == AX_M) {
+    F.fwd(px);
+    F.fwd(py);
+    F.fwd(pz);
+#pragma unroll
+    for (int k2 = 0; k2 < E; ++k2) {
+      const T kzl = t.kz[k2 + kofs];
+      const T m = damping(kt2 + kzl * kzl, t) * inz;
+      px[k2] = m * px[k2];
+      py[k2] = m * py[k2];
+      pz[k2] = m * pz[k2];
+    }
+    F.inv(px);
+    F.inv(py);
+    F.inv(pz);
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+      stv(L * m, px[m]);
+      stv(NZ + L * m, py[m]);
+      stv(2 * NZ + L * m, pz[m]);
+    }
+    return;
+  } else {
+    cplx<T> dx[E], dy[E];
+    if constexpr (MODE == AX_AM) {
+      F.fwd(px);
+      F.fwd(py);
+      F.fwd(pz);
+#pragma unroll
+      for (int k2 = 0; k2 < E; ++k2) {
+        const T kzl = t.kz[k2 + kofs];
+        const T m = damping(kt2 + kzl * kzl, t) * inz;
+        px[k2] = m * px[k2];
+        py[k2] = m * py[k2];
+        pz[k2] = m * pz[k2];
+        dx[k2] = kzl * mul_i(px[k2]);
+        dy[k2] = kzl * mul_i(py[k2]);
+      }
+      F.inv(pz);
+    } else {
+#pragma unroll
+      for (int m = 0; m < E; ++m) {
+        dx[m] = px[m];
+        dy[m] = py[m];
+      }
+      F.fwd(dx);
+      F.fwd(dy);
+#pragma unroll
+      for (int k2 = 0; k2 < E; ++k2) {
+        const T f = t.kz[k2 + kofs] * inz;
+        dx[k2] = f * mul_i(dx[k2]);
+        dy[k2] = f * mul_i(dy[k2]);
+      }
+    }
+    F.inv(dx);
+    F.inv(dy);
+    // U_z and the inner curl vectors w = -D P_t + i k_t P_z (z layout)
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+      const cplx<T> is = t.inv_s[lt + L * m];
+      const cplx<T> dpx = dx[m] * is, dpy = dy[m] * is;
+      stv(2 * NZ + L * m, kx * mul_i(dpx) + ky * mul_i(dpy) + (kt2 - t.kbg2) * pz[m]);
+      dx[m] = kx * mul_i(pz[m]) - dpx;
+      dy[m] = ky * mul_i(pz[m]) - dpy;
+    }
+    F.fwd(dx);
+    F.fwd(dy);
+#pragma unroll
+    for (int k2 = 0; k2 < E; ++k2) {
+      const T f = t.kz[k2 + kofs] * inz;
+      dx[k2] = f * mul_i(dx[k2]);
+      dy[k2] = f * mul_i(dy[k2]);
+    }
+    F.inv(dx);
+    F.inv(dy);
+    if constexpr (MODE == AX_AM) {
+      F.inv(px);
+      F.inv(py);
+    }
+
+    // multilayer amplitudes from the tangential P at the evaluation row
+    ColInfo<T> c;
+    column_info(c, t, ix, iy);
+    const int mj = t.jev / L, tj = t.jev % L;
+    cplx<T> ex = {T(0), T(0)}, ey = {T(0), T(0)};
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+      if (m == mj) {
+        ex = px[m];
+        ey = py[m];
+      }
+    }
+    ex = {__shfl(ex.re, tj, L), __shfl(ex.im, tj, L)};
+    ey = {__shfl(ey.re, tj, L), __shfl(ey.im, tj, L)};
+    const cplx<T> as = (c.sx * ex + c.sy * ey) * c.down;
+    const cplx<T> ap = (c.tx * ex + c.ty * ey) * c.down;
+    const cplx<T> a0 = c.live ? c.rte * as : cplx<T>{T(0), T(0)};
+    const cplx<T> a1 = c.live ? c.rpe * ap : cplx<T>{T(0), T(0)};
+
+    const int64_t wb = (int64_t)3 * NZ - t.j0;  // W row of z is wb + (z - j0) + comp * nabs
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+      const int z = lt + L * m;
+      const cplx<T> is = t.inv_s[z];
+      stv(L * m, (ky * ky - t.kbg2) * px[m] - (kx * ky) * py[m] + dx[m] * is);
+      stv(NZ + L * m, (kx * kx - t.kbg2) * py[m] - (kx * ky) * px[m] + dy[m] * is);
+      const int ja = z - t.j0;
+      if (ja >= 0 && ja < t.nabs) {
+        const cplx<T> ph = up_phase(c, t.zabs[ja]);
+        const cplx<T> vs = a0 * ph, vp = a1 * ph;
+        stv(wb + L * m, px[m] + (c.sx * vs + c.tx * vp));
+        stv(wb + t.nabs + L * m, py[m] + (c.sy * vs + c.ty * vp));
+        stv(wb + 2 * t.nabs + L * m, pz[m] - (c.ktkz * vp));
+      }
+    }
+  }
+}
+
+template <typename T, int NZ>
+constexpr int ax_lanes() {
+  // lanes per column for the register kernel (0: LDS kernel only): at most
+  // 6 (FP32) or 3 (FP64) elements per lane keep the kernel near 128 VGPRs
+  constexpr int emax = sizeof(T) == 4 ? 6 : 3;
+  if (NZ > 64) return 0;
+  int l = 1;
+  while ((NZ / l > emax || NZ % l) && l < 16) l *= 2;
+  return l;
+}
+
 template <typename T, int NZ>
 static hipError_t axial_n(const OpTables<T>& t, const cplx<T>* S, cplx<T>* UW, int mode,
                           hipStream_t st) {
+  constexpr int L = ax_lanes<T, NZ>();
+  if constexpr (L > 0) {
+    if (!t.ax_lds && mode != AX_AH) {
+      const int64_t cols = (int64_t)t.nx * t.ny;
+      if ((cols * L) % 256) return hipErrorInvalidValue;
+      dim3 g((unsigned)(cols * L / 256)), b(256);
+      switch (mode) {
+        case AX_A: hipLaunchKernelGGL((k_axial_reg<T, NZ, L, AX_A>), g, b, 0, st, S, UW, t); break;
+        case AX_AM: hipLaunchKernelGGL((k_axial_reg<T, NZ, L, AX_AM>), g, b, 0, st, S, UW, t); break;
+        default: hipLaunchKernelGGL((k_axial_reg<T, NZ, L, AX_M>), g, b, 0, st, S, UW, t); break;
+      }
+      return hipGetLastError();
+    }
+  }
   constexpr int TX = ax_tile<T, NZ>();
   if (t.nx % TX) return hipErrorInvalidValue;
   dim3 g(t.nx / TX, t.ny), b(256);

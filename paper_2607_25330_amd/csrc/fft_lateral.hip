@@ -154,41 +154,67 @@ k_xfft_inv(const cplx<T>* __restrict__ UW, cplx<T>* __restrict__ y,
     rkd[tid] = ko;
   }
   __syncthreads();
-  for (int e = tid; e < B * N; e += NT) {
+  // Every global operand of the block is requested before the first barrier:
+  // the U / W rows, and for the epilogue kd, x (adjoint) and the dot partner d,
+  // so that their latency overlaps instead of being paid again after the FFT.
+  constexpr int EPT = (B * N) / NT;
+  static_assert((B * N) % NT == 0, "rows must split evenly over the block");
+  cplx<T> ru[EPT], rwv[EPT], rkv[EPT], rxv[EPT], rdv[EPT];
+#pragma unroll
+  for (int k = 0; k < EPT; ++k) {
+    const int e = tid + k * NT;
     const int rr = e / N, xi = e % N;
     const int64_t row = row0 + rr;
-    cplx<T> u = {T(0), T(0)};
-    cplx<T> w = {T(0), T(0)};
+    const int64_t idx = row * N + xi;
+    const cplx<T> z0 = {T(0), T(0)};
+    ru[k] = z0;
+    rwv[k] = z0;
+    rkv[k] = z0;
+    rxv[k] = z0;
+    rdv[k] = z0;
     if (row < nrows) {
-      u = UW[row * N + xi];
+      ru[k] = UW[idx];
       if (CM == CB_FWD) {
         const int64_t wo = rw[rr];
-        if (wo >= 0) w = UW[wo + xi];
+        if (wo >= 0) rwv[k] = UW[wo + xi];
       }
+      if (CM != CB_PLAIN) {
+        const int64_t ko = rkd[rr];
+        if (ko >= 0) {
+          rkv[k] = kd[ko + xi];
+          if (CM == CB_ADJ) rxv[k] = x[idx];
+        }
+      }
+      if constexpr (POST == POST_DOT) rdv[k] = post.d[idx];
     }
-    s[Addr{}(rr, xi)] = u;
-    if (CM == CB_FWD) s[Addr{}(B + rr, xi)] = w;
+  }
+#pragma unroll
+  for (int k = 0; k < EPT; ++k) {
+    const int e = tid + k * NT;
+    const int rr = e / N, xi = e % N;
+    s[Addr{}(rr, xi)] = ru[k];
+    if (CM == CB_FWD) s[Addr{}(B + rr, xi)] = rwv[k];
   }
   __syncthreads();
   lds_fft<T, N, NBUF * B, NT, true, false>(s, tws, Addr{}, tid);
   double acc[3] = {0.0, 0.0, 0.0};
-  for (int e = tid; e < B * N; e += NT) {
+#pragma unroll
+  for (int k = 0; k < EPT; ++k) {
+    const int e = tid + k * NT;
     const int rr = e / N, xi = e % N;
     const int64_t row = row0 + rr;
     if (row >= nrows) continue;
     const int64_t idx = row * N + xi;
     cplx<T> o = scale * s[Addr{}(rr, xi)];
     if (CM != CB_PLAIN) {
-      const int64_t ko = rkd[rr];
-      if (ko >= 0) {
-        const cplx<T> kdv = kd[ko + xi];
-        if (CM == CB_FWD) o = o - scale * (kdv * s[Addr{}(B + rr, xi)]);
-        else o = o - cmulc(kdv, x[idx]);
+      if (rkd[rr] >= 0) {
+        if (CM == CB_FWD) o = o - scale * (rkv[k] * s[Addr{}(B + rr, xi)]);
+        else o = o - cmulc(rkv[k], rxv[k]);
       }
     }
     y[idx] = o;
     if constexpr (POST == POST_DOT) {
-      const cplx<double> a = cast<double>(post.d[idx]), b = cast<double>(o);
+      const cplx<double> a = cast<double>(rdv[k]), b = cast<double>(o);
       acc[0] += a.re * b.re + a.im * b.im;
       acc[1] += a.re * b.im - a.im * b.re;
       acc[2] += b.re * b.re + b.im * b.im;

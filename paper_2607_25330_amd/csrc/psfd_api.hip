@@ -694,6 +694,7 @@ psfd_status plan_impl(const psfd_desc* d, const void* eps, void* stream, struct 
   t.pc_gamma = d->pc_gamma;
   t.pc_reg = d->pc_reg;
   t.pc_bf16 = d->prec == PSFD_C64_BF16PC_REFINE64;
+  t.ax_lds = std::getenv("PSFD_AXIAL_LDS") != nullptr;
 
   // multilayer reflections per lateral mode
   CHKS(dalloc(P, &P->rte64, (size_t)P->plane));
@@ -739,6 +740,7 @@ psfd_status plan_impl(const psfd_desc* d, const void* eps, void* stream, struct 
     f.cphi = (float)t.cphi; f.sphi = (float)t.sphi;
     f.pc_mmin = (float)t.pc_mmin; f.pc_kref2 = (float)t.pc_kref2;
     f.pc_gamma = (float)t.pc_gamma; f.pc_reg = (float)t.pc_reg; f.pc_bf16 = t.pc_bf16;
+    f.ax_lds = t.ax_lds;
     CHKS(ensure_fp32(P));
   }
   CHK(hipStreamCreateWithFlags(&P->own_st, hipStreamNonBlocking));

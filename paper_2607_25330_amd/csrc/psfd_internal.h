@@ -36,6 +36,7 @@ struct OpTables {
   // spectral damping multiplier m(k)
   T pc_mmin, pc_kref2, pc_gamma, pc_reg;
   int pc_bf16;              // round m(k) to bfloat16
+  int ax_lds;               // 1: always use the LDS-staged axial kernel
   const int* skip;          // device flag: when non-null and set, operator kernels return at once
 };
 

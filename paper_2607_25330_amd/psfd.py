@@ -13,7 +13,9 @@ import os
 import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libpsfd.so")
+_DEFAULT_LIB = os.path.join(_HERE, "libpsfd.so")
+# PSFD_LIBRARY selects another build of the same library (same ABI).
+LIB_PATH = os.environ.get("PSFD_LIBRARY", _DEFAULT_LIB)
 HEADER_PATH = os.path.join(os.path.dirname(_HERE), "include", "psfd.h")
 
 PSFD_OK, PSFD_ERR_ARG, PSFD_ERR_ALLOC, PSFD_ERR_HIP, PSFD_NOT_CONVERGED, PSFD_BREAKDOWN = range(6)
