@@ -95,22 +95,35 @@ k_xfft_fwd(const cplx<T>* __restrict__ in, cplx<T>* __restrict__ out,
     else return in[idx];
   };
   __syncthreads();
-  double acc[1] = {0.0};
-  for (int e = tid; e < B * N; e += NT) {
+  // all loads of the block are issued before the first LDS write
+  constexpr int EPT = (B * N) / NT;
+  static_assert((B * N) % NT == 0, "rows must split evenly over the block");
+  cplx<T> val[EPT];
+#pragma unroll
+  for (int k = 0; k < EPT; ++k) {
+    const int e = tid + k * NT;
     const int rr = e / N, xi = e % N;
     const int64_t src = rsrc[rr];
-    cplx<T> val = {T(0), T(0)};
+    val[k] = {T(0), T(0)};
     if (src >= 0) {
       const int64_t kro = rkd[rr];
-      if (kro < 0) {
-        val = value(src + xi);
-        if constexpr (PRE != PRE_NONE) pre.pv[src + xi] = val;
-        if constexpr (PRE == PRE_S) acc[0] += norm2(cast<double>(val));
-      } else {
-        val = cmulc(kd[kro + xi], value(src + xi));
+      if (kro < 0) val[k] = value(src + xi);
+      else val[k] = cmulc(kd[kro + xi], value(src + xi));
+    }
+  }
+  double acc[1] = {0.0};
+#pragma unroll
+  for (int k = 0; k < EPT; ++k) {
+    const int e = tid + k * NT;
+    const int rr = e / N, xi = e % N;
+    if constexpr (PRE != PRE_NONE) {
+      const int64_t src = rsrc[rr];
+      if (src >= 0 && rkd[rr] < 0) {
+        pre.pv[src + xi] = val[k];
+        if constexpr (PRE == PRE_S) acc[0] += norm2(cast<double>(val[k]));
       }
     }
-    s[Addr{}(rr, xi)] = val;
+    s[Addr{}(rr, xi)] = val[k];
   }
   if constexpr (PRE == PRE_S) block_partials<1, NT>(acc, pre.part);
   __syncthreads();
@@ -234,10 +247,23 @@ k_yfft(cplx<T>* __restrict__ buf, const cplx<T>* __restrict__ tw, int nx,
   const int tid = threadIdx.x;
   const int64_t base = (int64_t)blockIdx.y * N * nx + (int64_t)blockIdx.x * TX;
   for (int i = tid; i < N; i += NT) tws[i] = tw[i];
-  for (int e = tid; e < N * TX; e += NT) s[e] = buf[base + (int64_t)(e / TX) * nx + (e % TX)];
+  constexpr int EPT = (N * TX) / NT;
+  static_assert((N * TX) % NT == 0, "tile must split evenly over the block");
+  cplx<T> v[EPT];
+#pragma unroll
+  for (int k = 0; k < EPT; ++k) {
+    const int e = tid + k * NT;
+    v[k] = buf[base + (int64_t)(e / TX) * nx + (e % TX)];
+  }
+#pragma unroll
+  for (int k = 0; k < EPT; ++k) s[tid + k * NT] = v[k];
   __syncthreads();
   lds_fft<T, N, TX, NT, INV, true>(s, tws, AddrCol<TX>{}, tid);
-  for (int e = tid; e < N * TX; e += NT) buf[base + (int64_t)(e / TX) * nx + (e % TX)] = s[e];
+#pragma unroll
+  for (int k = 0; k < EPT; ++k) {
+    const int e = tid + k * NT;
+    buf[base + (int64_t)(e / TX) * nx + (e % TX)] = s[e];
+  }
 }
 
 // ---------------------------------------------------------------- launchers
