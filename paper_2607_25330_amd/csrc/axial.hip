@@ -70,13 +70,14 @@ __device__ __forceinline__ cplx<T> up_phase(const ColInfo<T>& c, T z) {
 }
 
 template <typename T>
-__device__ void column_info(ColInfo<T>& c, const OpTables<T>& t, int ix, int iy) {
-  c.kx = t.kx[ix];
-  c.ky = t.ky[iy];
+__device__ void column_info(ColInfo<T>& c, const OpTables<T>& t, int pb, int ix, int iy) {
+  c.kx = t.kx[(int64_t)pb * t.nx + ix];
+  c.ky = t.ky[(int64_t)pb * t.ny + iy];
   c.kt2 = c.kx * c.kx + c.ky * c.ky;
   const T kt = sqrt(c.kt2);
   if (kt == T(0)) {
-    c.sx = -t.sphi; c.sy = t.cphi; c.tx = t.cphi; c.ty = t.sphi;
+    const T cp = t.cphi[pb], sp = t.sphi[pb];
+    c.sx = -sp; c.sy = cp; c.tx = cp; c.ty = sp;
   } else {
     c.sx = -c.ky / kt; c.sy = c.kx / kt; c.tx = c.kx / kt; c.ty = c.ky / kt;
   }
@@ -93,7 +94,7 @@ __device__ void column_info(ColInfo<T>& c, const OpTables<T>& t, int ix, int iy)
   sc(c.kzr * h, &s, &co);
   const T m = exp(c.kzi * h);
   c.down = {m * co, -m * s};
-  const int64_t mode = (int64_t)iy * t.nx + ix;
+  const int64_t mode = ((int64_t)pb * t.ny + iy) * t.nx + ix;
   c.rte = t.r_te[mode];
   c.rpe = t.r_pe[mode];
 }
@@ -107,8 +108,11 @@ constexpr int ax_tile() {
 
 template <typename T, int NZ, int TX, int MODE>
 __global__ void __launch_bounds__(256)
-k_axial(const cplx<T>* __restrict__ S, cplx<T>* __restrict__ UW, const OpTables<T> t) {
-  if (t.skip && *t.skip) return;
+k_axial(const cplx<T>* __restrict__ S_all, cplx<T>* __restrict__ UW_all, const OpTables<T> t) {
+  const int pb = blockIdx.y / t.ny;
+  if (skipped(t, pb)) return;
+  const cplx<T>* S = S_all + pb * t.pspec;
+  cplx<T>* UW = UW_all + pb * t.pspec;
   constexpr int NT = 256;
   constexpr int PITCH = TX;
   constexpr int VS = NZ * PITCH;
@@ -121,7 +125,7 @@ k_axial(const cplx<T>* __restrict__ S, cplx<T>* __restrict__ UW, const OpTables<
   __shared__ T kzs[NZ];
 
   const int tid = threadIdx.x;
-  const int iy = blockIdx.y;
+  const int iy = blockIdx.y % t.ny;
   const int kx0 = blockIdx.x * TX;
   const int64_t plane = (int64_t)t.nx * t.ny;
   const int64_t colbase = (int64_t)iy * t.nx + kx0;
@@ -135,7 +139,7 @@ k_axial(const cplx<T>* __restrict__ S, cplx<T>* __restrict__ UW, const OpTables<
     const int z = rem / TX, cc = rem % TX;
     buf[c * VS + z * PITCH + cc] = S[(int64_t)(c * NZ + z) * plane + colbase + cc];
   }
-  if (tid < TX) column_info(ci[tid], t, kx0 + tid, iy);
+  if (tid < TX) column_info(ci[tid], t, pb, kx0 + tid, iy);
   for (int i = tid; i < NZ; i += NT) {
     twz[i] = t.tw_z[i];
     invs[i] = t.inv_s[i];
@@ -305,19 +309,24 @@ k_axial(const cplx<T>* __restrict__ S, cplx<T>* __restrict__ UW, const OpTables<
 // access is a scalar base plus one 32-bit lane offset.
 template <typename T, int NZ, int L, int MODE>
 __global__ void __launch_bounds__(256)
-k_axial_reg(const cplx<T>* __restrict__ S, cplx<T>* __restrict__ UW, const OpTables<T> t) {
-  if (t.skip && *t.skip) return;
+k_axial_reg(const cplx<T>* __restrict__ S_all, cplx<T>* __restrict__ UW_all, const OpTables<T> t) {
   constexpr int E = NZ / L;
-  const int lt = threadIdx.x & (L - 1);
-  const int64_t g = (int64_t)blockIdx.x * (256 / L) + (threadIdx.x / L);
   const int64_t plane = (int64_t)t.nx * t.ny;
-  const int64_t pb = plane * (int64_t)sizeof(cplx<T>);
+  const int lt = threadIdx.x & (L - 1);
+  const int64_t gg = (int64_t)blockIdx.x * (256 / L) + (threadIdx.x / L);
+  // a block's 256 / L columns lie in one problem (plane is a multiple of 256)
+  const int pb = (int)(gg / plane);
+  if (skipped(t, pb)) return;
+  const int64_t g = gg - pb * plane;
+  const cplx<T>* S = S_all + pb * t.pspec;
+  cplx<T>* UW = UW_all + pb * t.pspec;
+  const int64_t pbytes = plane * (int64_t)sizeof(cplx<T>);
   const uint32_t lane_bo = (uint32_t)((lt * plane + g) * (int64_t)sizeof(cplx<T>));
   auto ld = [&](int64_t row) -> cplx<T> {  // row of lane 0 of the group
-    return *reinterpret_cast<const cplx<T>*>(reinterpret_cast<const char*>(S) + row * pb + lane_bo);
+    return *reinterpret_cast<const cplx<T>*>(reinterpret_cast<const char*>(S) + row * pbytes + lane_bo);
   };
   auto stv = [&](int64_t row, cplx<T> v) {
-    *reinterpret_cast<cplx<T>*>(reinterpret_cast<char*>(UW) + row * pb + lane_bo) = v;
+    *reinterpret_cast<cplx<T>*>(reinterpret_cast<char*>(UW) + row * pbytes + lane_bo) = v;
   };
   const T inz = T(1) / T(NZ);
   LaneFft<T, NZ, L> F;
@@ -332,7 +341,7 @@ k_axial_reg(const cplx<T>* __restrict__ S, cplx<T>* __restrict__ UW, const OpTab
     pz[m] = ld(2 * NZ + L * m);
   }
   const int ix = (int)(g % t.nx), iy = (int)(g / t.nx);
-  const T kx = t.kx[ix], ky = t.ky[iy];
+  const T kx = t.kx[(int64_t)pb * t.nx + ix], ky = t.ky[(int64_t)pb * t.ny + iy];
   const T kt2 = kx * kx + ky * ky;
 
   if constexpr (MODE == AX_M) {
@@ -417,7 +426,7 @@ k_axial_reg(const cplx<T>* __restrict__ S, cplx<T>* __restrict__ UW, const OpTab
 
     // multilayer amplitudes from the tangential P at the evaluation row
     ColInfo<T> c;
-    column_info(c, t, ix, iy);
+    column_info(c, t, pb, ix, iy);
     const int mj = t.jev / L, tj = t.jev % L;
     cplx<T> ex = {T(0), T(0)}, ey = {T(0), T(0)};
 #pragma unroll
@@ -472,7 +481,7 @@ static hipError_t axial_n(const OpTables<T>& t, const cplx<T>* S, cplx<T>* UW, i
     if (!t.ax_lds && mode != AX_AH) {
       const int64_t cols = (int64_t)t.nx * t.ny;
       if ((cols * L) % 256) return hipErrorInvalidValue;
-      dim3 g((unsigned)(cols * L / 256)), b(256);
+      dim3 g((unsigned)(cols * L / 256 * t.nprob)), b(256);
       switch (mode) {
         case AX_A: hipLaunchKernelGGL((k_axial_reg<T, NZ, L, AX_A>), g, b, 0, st, S, UW, t); break;
         case AX_AM: hipLaunchKernelGGL((k_axial_reg<T, NZ, L, AX_AM>), g, b, 0, st, S, UW, t); break;
@@ -483,7 +492,7 @@ static hipError_t axial_n(const OpTables<T>& t, const cplx<T>* S, cplx<T>* UW, i
   }
   constexpr int TX = ax_tile<T, NZ>();
   if (t.nx % TX) return hipErrorInvalidValue;
-  dim3 g(t.nx / TX, t.ny), b(256);
+  dim3 g(t.nx / TX, t.ny * t.nprob), b(256);
   switch (mode) {
     case AX_A: hipLaunchKernelGGL((k_axial<T, NZ, TX, AX_A>), g, b, 0, st, S, UW, t); break;
     case AX_AM: hipLaunchKernelGGL((k_axial<T, NZ, TX, AX_AM>), g, b, 0, st, S, UW, t); break;

@@ -45,16 +45,31 @@ constexpr int y_tile() {
 
 // ------------------------------------------------------------------ kernels
 
+// A launch covers nprob problems: each problem owns bpp consecutive blocks
+// (bpp = ceil(rows per problem / rows per block)), so no block straddles two
+// problems and block partials stay per problem.
+struct RowGroup {
+  int nprob = 1;
+  int bpp = 1;
+  int64_t nmain = 0;       // rows per problem taken straight from the input stack
+  int64_t ntot = 0;        // rows per problem in total (adjoint: + 3 nabs ny extra rows)
+  int64_t in_stride = 0;   // elements per problem of the input stack
+  int64_t out_stride = 0;  // elements per problem of the output stack
+  int64_t kd_stride = 0;   // elements per problem of kd
+  const int* skip = nullptr;
+  int skip_stride = 0;
+};
+
 template <typename T>
 __device__ __forceinline__ cplx<double> ldks(const double* a) { return {a[0], a[1]}; }
 
 template <typename T, int N, int B, int PRE>
 __global__ void __launch_bounds__(B * Radices<N>::TPR)
-k_xfft_fwd(const cplx<T>* __restrict__ in, cplx<T>* __restrict__ out,
-           const cplx<T>* __restrict__ tw, int64_t nrows_main, int64_t nrows_total, int ny,
-           int nz, int j0, int nabs, const cplx<T>* __restrict__ kd,
-           const int* __restrict__ skip, const PreOp<T> pre) {
-  if (skip && *skip) return;
+k_xfft_fwd(const cplx<T>* __restrict__ in_all, cplx<T>* __restrict__ out_all,
+           const cplx<T>* __restrict__ tw, const RowGroup g, int ny, int nz, int j0, int nabs,
+           const cplx<T>* __restrict__ kd_all, const PreOp<T> pre) {
+  const int pb = blockIdx.x / g.bpp;
+  if (g.skip && g.skip[(int64_t)pb * g.skip_stride]) return;
   constexpr int NT = B * Radices<N>::TPR;
   using Addr = AddrRowPad<N, lds_pad_period<T>()>;
   __shared__ cplx<T> s[B * Addr::PITCH];
@@ -62,15 +77,18 @@ k_xfft_fwd(const cplx<T>* __restrict__ in, cplx<T>* __restrict__ out,
   __shared__ int64_t rsrc[B];  // element offset of the source row (-1: past the end)
   __shared__ int64_t rkd[B];   // element offset of the conj(kd) row (-1: none)
   const int tid = threadIdx.x;
-  const int64_t row0 = (int64_t)blockIdx.x * B;
+  const int64_t row0 = (int64_t)(blockIdx.x % g.bpp) * B;
+  const cplx<T>* in = in_all + pb * g.in_stride;
+  cplx<T>* out = out_all + pb * g.out_stride;
+  const cplx<T>* kd = kd_all + pb * g.kd_stride;
   for (int i = tid; i < N; i += NT) tws[i] = tw[i];
   if (tid < B) {
     const int64_t row = row0 + tid;
     int64_t src = -1, kro = -1;
-    if (row < nrows_main) {
+    if (row < g.nmain) {
       src = row * N;
-    } else if (row < nrows_total) {
-      const int64_t r = row - nrows_main;
+    } else if (row < g.ntot) {
+      const int64_t r = row - g.nmain;
       const int plane = (int)(r / ny), yy = (int)(r % ny);
       const int c = plane / nabs, ja = plane % nabs;
       src = ((int64_t)(c * nz + j0 + ja) * ny + yy) * N;
@@ -79,19 +97,21 @@ k_xfft_fwd(const cplx<T>* __restrict__ in, cplx<T>* __restrict__ out,
     rsrc[tid] = src;
     rkd[tid] = kro;
   }
-  // scalars of the fused vector update
+  // scalars of the fused vector update (the input stack is the vector stack)
   cplx<T> c1 = {T(0), T(0)}, c2 = {T(0), T(0)};
+  const int64_t vo = pb * g.in_stride;
   if constexpr (PRE == PRE_P) {
-    const cplx<double> rho = ldks<T>(pre.ks->rho), rho_p = ldks<T>(pre.ks->rho_prev);
-    const cplx<double> al = ldks<T>(pre.ks->alpha), om = ldks<T>(pre.ks->omega);
+    const KState* ks = pre.ks + pb;
+    const cplx<double> rho = ldks<T>(ks->rho), rho_p = ldks<T>(ks->rho_prev);
+    const cplx<double> al = ldks<T>(ks->alpha), om = ldks<T>(ks->omega);
     c1 = cast<T>(cdiv(rho, rho_p) * cdiv(al, om));  // beta
     c2 = cast<T>(om);
   } else if constexpr (PRE == PRE_S) {
-    c1 = cast<T>(ldks<T>(pre.ks->alpha));
+    c1 = cast<T>(ldks<T>((pre.ks + pb)->alpha));
   }
   auto value = [&](int64_t idx) -> cplx<T> {
-    if constexpr (PRE == PRE_P) return pre.r[idx] + c1 * (pre.pv[idx] - c2 * pre.v[idx]);
-    else if constexpr (PRE == PRE_S) return pre.r[idx] - c1 * pre.v[idx];
+    if constexpr (PRE == PRE_P) return pre.r[vo + idx] + c1 * (pre.pv[vo + idx] - c2 * pre.v[vo + idx]);
+    else if constexpr (PRE == PRE_S) return pre.r[vo + idx] - c1 * pre.v[vo + idx];
     else return in[idx];
   };
   __syncthreads();
@@ -119,7 +139,7 @@ k_xfft_fwd(const cplx<T>* __restrict__ in, cplx<T>* __restrict__ out,
     if constexpr (PRE != PRE_NONE) {
       const int64_t src = rsrc[rr];
       if (src >= 0 && rkd[rr] < 0) {
-        pre.pv[src + xi] = val[k];
+        pre.pv[vo + src + xi] = val[k];
         if constexpr (PRE == PRE_S) acc[0] += norm2(cast<double>(val[k]));
       }
     }
@@ -131,17 +151,18 @@ k_xfft_fwd(const cplx<T>* __restrict__ in, cplx<T>* __restrict__ out,
   for (int e = tid; e < B * N; e += NT) {
     const int rr = e / N;
     const int64_t row = row0 + rr;
-    if (row < nrows_total) out[row * N + (e % N)] = s[Addr{}(rr, e % N)];
+    if (row < g.ntot) out[row * N + (e % N)] = s[Addr{}(rr, e % N)];
   }
 }
 
 template <typename T, int N, int B, int CM, int POST>
 __global__ void __launch_bounds__(B * Radices<N>::TPR)
-k_xfft_inv(const cplx<T>* __restrict__ UW, cplx<T>* __restrict__ y,
-           const cplx<T>* __restrict__ tw, int64_t nrows, int ny, int nz, int j0, int nabs,
-           T scale, const cplx<T>* __restrict__ kd, const cplx<T>* __restrict__ x,
-           const int* __restrict__ skip, const PostOp<T> post) {
-  if (skip && *skip) return;
+k_xfft_inv(const cplx<T>* __restrict__ UW_all, cplx<T>* __restrict__ y_all,
+           const cplx<T>* __restrict__ tw, const RowGroup g, int ny, int nz, int j0, int nabs,
+           T scale, const cplx<T>* __restrict__ kd_all, const cplx<T>* __restrict__ x_all,
+           const PostOp<T> post) {
+  const int pb = blockIdx.x / g.bpp;
+  if (g.skip && g.skip[(int64_t)pb * g.skip_stride]) return;
   constexpr int NT = B * Radices<N>::TPR;
   constexpr int NBUF = (CM == CB_FWD) ? 2 : 1;
   using Addr = AddrRowPad<N, lds_pad_period<T>()>;
@@ -150,7 +171,12 @@ k_xfft_inv(const cplx<T>* __restrict__ UW, cplx<T>* __restrict__ y,
   __shared__ int64_t rw[B];   // element offset of the W row (-1: not an absorber row)
   __shared__ int64_t rkd[B];  // element offset of the kd row (-1: none)
   const int tid = threadIdx.x;
-  const int64_t row0 = (int64_t)blockIdx.x * B;
+  const int64_t row0 = (int64_t)(blockIdx.x % g.bpp) * B;
+  const int64_t nrows = g.ntot;
+  const cplx<T>* UW = UW_all + pb * g.in_stride;
+  const int64_t fo = pb * g.out_stride;  // y, x and the dot partner share the field stack
+  cplx<T>* y = y_all + fo;
+  const cplx<T>* kd = kd_all + pb * g.kd_stride;
   for (int i = tid; i < N; i += NT) tws[i] = tw[i];
   if (tid < B) {
     const int64_t row = row0 + tid;
@@ -195,10 +221,10 @@ k_xfft_inv(const cplx<T>* __restrict__ UW, cplx<T>* __restrict__ y,
         const int64_t ko = rkd[rr];
         if (ko >= 0) {
           rkv[k] = kd[ko + xi];
-          if (CM == CB_ADJ) rxv[k] = x[idx];
+          if (CM == CB_ADJ) rxv[k] = x_all[fo + idx];
         }
       }
-      if constexpr (POST == POST_DOT) rdv[k] = post.d[idx];
+      if constexpr (POST == POST_DOT) rdv[k] = post.d[fo + idx];
     }
   }
 #pragma unroll
@@ -236,16 +262,19 @@ k_xfft_inv(const cplx<T>* __restrict__ UW, cplx<T>* __restrict__ y,
   if constexpr (POST == POST_DOT) block_partials<3, NT>(acc, post.part);
 }
 
+// y pass: problem pb's planes start at pb * stride; grid.y = nprob * nplanes.
 template <typename T, int N, int TX, bool INV>
 __global__ void __launch_bounds__(TX * Radices<N>::TPR)
-k_yfft(cplx<T>* __restrict__ buf, const cplx<T>* __restrict__ tw, int nx,
-       const int* __restrict__ skip) {
-  if (skip && *skip) return;
+k_yfft(cplx<T>* __restrict__ buf, const cplx<T>* __restrict__ tw, int nx, int nplanes,
+       int64_t stride, const int* __restrict__ skip, int skip_stride) {
+  const int pb = blockIdx.y / nplanes;
+  if (skip && skip[(int64_t)pb * skip_stride]) return;
   constexpr int NT = TX * Radices<N>::TPR;
   __shared__ cplx<T> s[N * TX];
   __shared__ cplx<T> tws[N];
   const int tid = threadIdx.x;
-  const int64_t base = (int64_t)blockIdx.y * N * nx + (int64_t)blockIdx.x * TX;
+  const int64_t base = pb * stride + (int64_t)(blockIdx.y % nplanes) * N * nx +
+                       (int64_t)blockIdx.x * TX;
   for (int i = tid; i < N; i += NT) tws[i] = tw[i];
   constexpr int EPT = (N * TX) / NT;
   static_assert((N * TX) % NT == 0, "tile must split evenly over the block");
@@ -268,27 +297,43 @@ k_yfft(cplx<T>* __restrict__ buf, const cplx<T>* __restrict__ tw, int nx,
 
 // ---------------------------------------------------------------- launchers
 
+template <typename T>
+static RowGroup group_of(const OpTables<T>& t, int64_t nmain, int64_t ntot, int64_t in_stride,
+                         int64_t out_stride, int rows_per_block) {
+  RowGroup g;
+  g.nprob = t.nprob;
+  g.bpp = (int)((ntot + rows_per_block - 1) / rows_per_block);
+  g.nmain = nmain;
+  g.ntot = ntot;
+  g.in_stride = in_stride;
+  g.out_stride = out_stride;
+  g.kd_stride = (int64_t)t.nabs * t.nx * t.ny;
+  g.skip = t.skip;
+  g.skip_stride = t.skip_stride;
+  return g;
+}
+
 template <typename T, int N>
-static hipError_t xfwd_n(const OpTables<T>& t, const cplx<T>* in, cplx<T>* out,
-                         int64_t nmain, int64_t ntot, int ny, const PreOp<T>& pre, int* nblk_out,
-                         hipStream_t st) {
+static hipError_t xfwd_n(const OpTables<T>& t, const cplx<T>* in, cplx<T>* out, int64_t nmain,
+                         int64_t ntot, int64_t in_stride, int64_t out_stride, const PreOp<T>& pre,
+                         int* nblk_out, hipStream_t st) {
   constexpr int B = x_rows<T, N>();
   constexpr int NT = B * Radices<N>::TPR;
-  const int64_t nblk = (ntot + B - 1) / B;
-  if (nblk_out) *nblk_out = (int)nblk;
-  dim3 g((unsigned)nblk), b(NT);
+  const RowGroup g = group_of(t, nmain, ntot, in_stride, out_stride, B);
+  if (nblk_out) *nblk_out = g.bpp;
+  dim3 grid((unsigned)((int64_t)g.bpp * g.nprob)), b(NT);
   switch (pre.mode) {
     case PRE_P:
-      hipLaunchKernelGGL((k_xfft_fwd<T, N, B, PRE_P>), g, b, 0, st, in, out, t.tw_x, nmain, ntot,
-                         ny, t.nz, t.j0, t.nabs, t.kd, t.skip, pre);
+      hipLaunchKernelGGL((k_xfft_fwd<T, N, B, PRE_P>), grid, b, 0, st, in, out, t.tw_x, g, t.ny,
+                         t.nz, t.j0, t.nabs, t.kd, pre);
       break;
     case PRE_S:
-      hipLaunchKernelGGL((k_xfft_fwd<T, N, B, PRE_S>), g, b, 0, st, in, out, t.tw_x, nmain, ntot,
-                         ny, t.nz, t.j0, t.nabs, t.kd, t.skip, pre);
+      hipLaunchKernelGGL((k_xfft_fwd<T, N, B, PRE_S>), grid, b, 0, st, in, out, t.tw_x, g, t.ny,
+                         t.nz, t.j0, t.nabs, t.kd, pre);
       break;
     default:
-      hipLaunchKernelGGL((k_xfft_fwd<T, N, B, PRE_NONE>), g, b, 0, st, in, out, t.tw_x, nmain,
-                         ntot, ny, t.nz, t.j0, t.nabs, t.kd, t.skip, pre);
+      hipLaunchKernelGGL((k_xfft_fwd<T, N, B, PRE_NONE>), grid, b, 0, st, in, out, t.tw_x, g,
+                         t.ny, t.nz, t.j0, t.nabs, t.kd, pre);
       break;
   }
   return hipGetLastError();
@@ -296,42 +341,46 @@ static hipError_t xfwd_n(const OpTables<T>& t, const cplx<T>* in, cplx<T>* out,
 
 template <typename T, int N, int CM>
 static void xinv_launch(const OpTables<T>& t, const cplx<T>* UW, cplx<T>* y, int64_t nrows,
-                        int ny, const cplx<T>* x, T scale, const PostOp<T>& post, int* nblk_out,
-                        hipStream_t st) {
+                        int64_t in_stride, int64_t out_stride, const cplx<T>* x, T scale,
+                        const PostOp<T>& post, int* nblk_out, hipStream_t st) {
   constexpr int B = xinv_rows<T, N, CM>();
   constexpr int NT = B * Radices<N>::TPR;
-  const int64_t nblk = (nrows + B - 1) / B;
-  if (nblk_out) *nblk_out = (int)nblk;
-  dim3 g((unsigned)nblk), b(NT);
+  const RowGroup g = group_of(t, nrows, nrows, in_stride, out_stride, B);
+  if (nblk_out) *nblk_out = g.bpp;
+  dim3 grid((unsigned)((int64_t)g.bpp * g.nprob)), b(NT);
   if (post.mode == POST_DOT)
-    hipLaunchKernelGGL((k_xfft_inv<T, N, B, CM, POST_DOT>), g, b, 0, st, UW, y, t.tw_x, nrows,
-                       ny, t.nz, t.j0, t.nabs, scale, t.kd, x, t.skip, post);
+    hipLaunchKernelGGL((k_xfft_inv<T, N, B, CM, POST_DOT>), grid, b, 0, st, UW, y, t.tw_x, g,
+                       t.ny, t.nz, t.j0, t.nabs, scale, t.kd, x, post);
   else
-    hipLaunchKernelGGL((k_xfft_inv<T, N, B, CM, POST_NONE>), g, b, 0, st, UW, y, t.tw_x, nrows,
-                       ny, t.nz, t.j0, t.nabs, scale, t.kd, x, t.skip, post);
+    hipLaunchKernelGGL((k_xfft_inv<T, N, B, CM, POST_NONE>), grid, b, 0, st, UW, y, t.tw_x, g,
+                       t.ny, t.nz, t.j0, t.nabs, scale, t.kd, x, post);
 }
 
 template <typename T, int N>
 static hipError_t xinv_n(const OpTables<T>& t, const cplx<T>* UW, cplx<T>* y, int64_t nrows,
-                         int ny, int cmode, const cplx<T>* x, T scale, const PostOp<T>& post,
-                         int* nblk_out, hipStream_t st) {
+                         int64_t in_stride, int64_t out_stride, int cmode, const cplx<T>* x,
+                         T scale, const PostOp<T>& post, int* nblk_out, hipStream_t st) {
   switch (cmode) {
-    case CB_PLAIN: xinv_launch<T, N, CB_PLAIN>(t, UW, y, nrows, ny, x, scale, post, nblk_out, st); break;
-    case CB_FWD: xinv_launch<T, N, CB_FWD>(t, UW, y, nrows, ny, x, scale, post, nblk_out, st); break;
-    default: xinv_launch<T, N, CB_ADJ>(t, UW, y, nrows, ny, x, scale, post, nblk_out, st); break;
+    case CB_PLAIN: xinv_launch<T, N, CB_PLAIN>(t, UW, y, nrows, in_stride, out_stride, x, scale, post, nblk_out, st); break;
+    case CB_FWD: xinv_launch<T, N, CB_FWD>(t, UW, y, nrows, in_stride, out_stride, x, scale, post, nblk_out, st); break;
+    default: xinv_launch<T, N, CB_ADJ>(t, UW, y, nrows, in_stride, out_stride, x, scale, post, nblk_out, st); break;
   }
   return hipGetLastError();
 }
 
 template <typename T, int N>
-static hipError_t y_n(const cplx<T>* tw, cplx<T>* buf, int nx, int nplanes, bool inv,
-                      const int* skip, hipStream_t st) {
+static hipError_t y_n(const OpTables<T>& t, cplx<T>* buf, int nplanes, int64_t stride, bool inv,
+                      hipStream_t st) {
   constexpr int TX = y_tile<T, N>();
   constexpr int NT = TX * Radices<N>::TPR;
-  if (nx % TX) return hipErrorInvalidValue;
-  dim3 g(nx / TX, nplanes);
-  if (inv) hipLaunchKernelGGL((k_yfft<T, N, TX, true>), g, dim3(NT), 0, st, buf, tw, nx, skip);
-  else hipLaunchKernelGGL((k_yfft<T, N, TX, false>), g, dim3(NT), 0, st, buf, tw, nx, skip);
+  if (t.nx % TX) return hipErrorInvalidValue;
+  dim3 g(t.nx / TX, (unsigned)(nplanes * t.nprob));
+  if (inv)
+    hipLaunchKernelGGL((k_yfft<T, N, TX, true>), g, dim3(NT), 0, st, buf, t.tw_y, t.nx, nplanes,
+                       stride, t.skip, t.skip_stride);
+  else
+    hipLaunchKernelGGL((k_yfft<T, N, TX, false>), g, dim3(NT), 0, st, buf, t.tw_y, t.nx, nplanes,
+                       stride, t.skip, t.skip_stride);
   return hipGetLastError();
 }
 
@@ -353,7 +402,7 @@ hipError_t launch_xfft_fwd(const OpTables<T>& t, const cplx<T>* in, cplx<T>* out
                            const PreOp<T>& pre, int* nblk, hipStream_t st) {
   const int64_t nmain = (int64_t)3 * t.nz * t.ny;
   const int64_t ntot = nmain + (adj_extra ? (int64_t)3 * t.nabs * t.ny : 0);
-#define CALL_X(NN) xfwd_n<T, NN>(t, in, out, nmain, ntot, t.ny, pre, nblk, st)
+#define CALL_X(NN) xfwd_n<T, NN>(t, in, out, nmain, ntot, t.pfield, t.pspec, pre, nblk, st)
   PSFD_LATERAL_SWITCH(t.nx, CALL_X)
 #undef CALL_X
 }
@@ -361,7 +410,7 @@ hipError_t launch_xfft_fwd(const OpTables<T>& t, const cplx<T>* in, cplx<T>* out
 template <typename T>
 hipError_t launch_yfft(const OpTables<T>& t, cplx<T>* buf, int nplanes, bool inverse,
                        hipStream_t st) {
-#define CALL_Y(NN) y_n<T, NN>(t.tw_y, buf, t.nx, nplanes, inverse, t.skip, st)
+#define CALL_Y(NN) y_n<T, NN>(t, buf, nplanes, t.pspec, inverse, st)
   PSFD_LATERAL_SWITCH(t.ny, CALL_Y)
 #undef CALL_Y
 }
@@ -371,7 +420,7 @@ hipError_t launch_xfft_inv(const OpTables<T>& t, const cplx<T>* UW, cplx<T>* y, 
                            const cplx<T>* x, const PostOp<T>& post, int* nblk, hipStream_t st) {
   const int64_t nrows = (int64_t)3 * t.nz * t.ny;
   const T scale = T(1) / (T(t.nx) * T(t.ny));
-#define CALL_XI(NN) xinv_n<T, NN>(t, UW, y, nrows, t.ny, cmode, x, scale, post, nblk, st)
+#define CALL_XI(NN) xinv_n<T, NN>(t, UW, y, nrows, t.pspec, t.pfield, cmode, x, scale, post, nblk, st)
   PSFD_LATERAL_SWITCH(t.nx, CALL_XI)
 #undef CALL_XI
 }
@@ -380,7 +429,10 @@ template <typename T>
 hipError_t launch_xfft_inv_rows(const OpTables<T>& t, const cplx<T>* in, cplx<T>* out,
                                 int64_t nrows, hipStream_t st) {
   const T scale = T(1) / (T(t.nx) * T(t.ny));
-#define CALL_XR(NN) xinv_n<T, NN>(t, in, out, nrows, t.ny, CB_PLAIN, nullptr, scale, PostOp<T>{}, nullptr, st)
+  OpTables<T> one = t;  // a single problem, no skip
+  one.nprob = 1;
+  one.skip = nullptr;
+#define CALL_XR(NN) xinv_n<T, NN>(one, in, out, nrows, 0, 0, CB_PLAIN, nullptr, scale, PostOp<T>{}, nullptr, st)
   PSFD_LATERAL_SWITCH(t.nx, CALL_XR)
 #undef CALL_XR
 }
@@ -389,17 +441,28 @@ template <typename T>
 hipError_t launch_plane_fft(const OpTables<T>& t, cplx<T>* in, cplx<T>* out, bool inverse,
                             hipStream_t st) {
   hipError_t e;
+  OpTables<T> one = t;  // a single plane of a single problem
+  one.nprob = 1;
+  one.skip = nullptr;
   if (!inverse) {
-#define CALL_PX(NN) xfwd_n<T, NN>(t, in, out, t.ny, t.ny, t.ny, PreOp<T>{}, nullptr, st)
+#define CALL_PX(NN) xfwd_n<T, NN>(one, in, out, t.ny, t.ny, 0, 0, PreOp<T>{}, nullptr, st)
     e = [&]() -> hipError_t { PSFD_LATERAL_SWITCH(t.nx, CALL_PX) }();
 #undef CALL_PX
     if (e != hipSuccess) return e;
-    return launch_yfft<T>(t, out, 1, false, st);
+    return [&]() -> hipError_t {
+#define CALL_PY(NN) y_n<T, NN>(one, out, 1, 0, false, st)
+      PSFD_LATERAL_SWITCH(t.ny, CALL_PY)
+#undef CALL_PY
+    }();
   }
   // inverse: y pass in place on `in`, then x pass into `out` (unnormalised)
-  e = launch_yfft<T>(t, in, 1, true, st);
+  e = [&]() -> hipError_t {
+#define CALL_PYI(NN) y_n<T, NN>(one, in, 1, 0, true, st)
+    PSFD_LATERAL_SWITCH(t.ny, CALL_PYI)
+#undef CALL_PYI
+  }();
   if (e != hipSuccess) return e;
-#define CALL_PXI(NN) xinv_n<T, NN>(t, in, out, t.ny, t.ny, CB_PLAIN, nullptr, T(1), PostOp<T>{}, nullptr, st)
+#define CALL_PXI(NN) xinv_n<T, NN>(one, in, out, t.ny, 0, 0, CB_PLAIN, nullptr, T(1), PostOp<T>{}, nullptr, st)
   PSFD_LATERAL_SWITCH(t.nx, CALL_PXI)
 #undef CALL_PXI
 }

@@ -8,7 +8,12 @@
 // product write one FP64 partial per block; a one-block finalize kernel adds
 // them in a fixed order and updates the scalars and the flags:
 //   done = 0 running, 1 converged, 2 pending half step (y += alpha p only),
-//   3 breakdown or divergence (the host restarts from the current field).
+//   3 breakdown or divergence (the host restarts from the current field),
+//   4 idle (the problem is not part of this run),
+//   5 iteration budget of the run used up.
+// A plan may hold a group of problems: every kernel here covers all of them,
+// each block working for one problem (its index from the block index), and
+// the finalize kernel runs one block per problem.
 // Operator kernels skip when done != 0, so launches queued after
 // convergence cost almost nothing.
 //
@@ -22,12 +27,15 @@
 
 namespace psfd {
 
-enum { KS_RUN = 0, KS_CONV = 1, KS_HALF = 2, KS_BREAK = 3 };
+enum { KS_RUN = 0, KS_CONV = 1, KS_HALF = 2, KS_BREAK = 3, KS_IDLE = 4, KS_MAXIT = 5 };
 constexpr double kOmegaLimit = 0.7;
 
-int red_blocks(int64_t n) {
+int red_blocks(int64_t n, int nprob) {
+  // at most 2048 blocks per problem and about 32k blocks per launch
   int64_t b = (n + KRED_THREADS - 1) / KRED_THREADS;
-  if (b > 2048) b = 2048;
+  int64_t cap = 32768 / (nprob > 0 ? nprob : 1);
+  if (cap > 2048) cap = 2048;
+  if (b > cap) b = cap;
   if (b < 1) b = 1;
   return (int)b;
 }
@@ -38,7 +46,10 @@ __device__ __forceinline__ void st2(double* a, cplx<double> v) { a[0] = v.re; a[
 // ---------------------------------------------------------------- finalize
 template <int STAGE>
 __global__ void __launch_bounds__(1024)
-k_finalize(KState* ks, const double* __restrict__ part, int nblocks, double a0, double a1) {
+k_finalize(KState* ks_all, const double* __restrict__ part_all, int nblocks,
+           const ProbParams* __restrict__ pp) {
+  KState* ks = ks_all + blockIdx.x;
+  const double* part = part_all + (size_t)blockIdx.x * nblocks * KPART;
   const int d = ks->done;
   bool run;
   if (STAGE == FIN_INIT || STAGE == FIN_RED0) run = true;
@@ -71,15 +82,17 @@ k_finalize(KState* ks, const double* __restrict__ part, int nblocks, double a0, 
     acc[k] = s;
   }
   if constexpr (STAGE == FIN_INIT) {
+    const ProbParams q = pp[blockIdx.x];
     ks->rho[0] = acc[0];
     ks->rho[1] = 0.0;
     ks->rho_prev[0] = ks->alpha[0] = ks->omega[0] = 1.0;
     ks->rho_prev[1] = ks->alpha[1] = ks->omega[1] = 0.0;
     ks->rh_norm2 = acc[0];
     ks->rnorm2 = acc[0];
-    ks->bnorm2 = a0;
-    ks->tol2 = a1;
-    ks->done = KS_RUN;
+    ks->bnorm2 = q.bnorm2;
+    ks->tol2 = q.tol2;
+    ks->itmax = (int)q.itmax;
+    ks->done = (q.tol2 < 0.0) ? KS_IDLE : (ks->itmax <= 0 ? KS_MAXIT : KS_RUN);
     ks->half = 0;
     ks->status = 0;
     ks->iter = 0;
@@ -133,6 +146,8 @@ k_finalize(KState* ks, const double* __restrict__ part, int nblocks, double a0, 
     st2(ks->rho, rho_new);
     if (acc[0] <= ks->tol2 * ks->bnorm2) {
       ks->done = KS_CONV;
+    } else if (ks->iter >= ks->itmax) {
+      ks->done = KS_MAXIT;
     } else if (!(acc[0] < 1e24 * ks->bnorm2)) {
       ks->status = 2;
       ks->done = KS_BREAK;
@@ -147,21 +162,29 @@ k_finalize(KState* ks, const double* __restrict__ part, int nblocks, double a0, 
   }
 }
 
-hipError_t launch_finalize(int stage, KState* ks, const double* part, int nblocks, double a0,
-                           double a1, hipStream_t st) {
-  dim3 g(1), b(1024);
+hipError_t launch_finalize(int stage, KState* ks, const double* part, int nblocks, int nprob,
+                           const ProbParams* pp, hipStream_t st) {
+  dim3 g(nprob), b(1024);
   switch (stage) {
-    case FIN_INIT: hipLaunchKernelGGL(k_finalize<FIN_INIT>, g, b, 0, st, ks, part, nblocks, a0, a1); break;
-    case FIN_ALPHA: hipLaunchKernelGGL(k_finalize<FIN_ALPHA>, g, b, 0, st, ks, part, nblocks, a0, a1); break;
-    case FIN_SNORM: hipLaunchKernelGGL(k_finalize<FIN_SNORM>, g, b, 0, st, ks, part, nblocks, a0, a1); break;
-    case FIN_OMEGA: hipLaunchKernelGGL(k_finalize<FIN_OMEGA>, g, b, 0, st, ks, part, nblocks, a0, a1); break;
-    case FIN_RHO: hipLaunchKernelGGL(k_finalize<FIN_RHO>, g, b, 0, st, ks, part, nblocks, a0, a1); break;
-    default: hipLaunchKernelGGL(k_finalize<FIN_RED0>, g, b, 0, st, ks, part, nblocks, a0, a1); break;
+    case FIN_INIT: hipLaunchKernelGGL(k_finalize<FIN_INIT>, g, b, 0, st, ks, part, nblocks, pp); break;
+    case FIN_ALPHA: hipLaunchKernelGGL(k_finalize<FIN_ALPHA>, g, b, 0, st, ks, part, nblocks, pp); break;
+    case FIN_SNORM: hipLaunchKernelGGL(k_finalize<FIN_SNORM>, g, b, 0, st, ks, part, nblocks, pp); break;
+    case FIN_OMEGA: hipLaunchKernelGGL(k_finalize<FIN_OMEGA>, g, b, 0, st, ks, part, nblocks, pp); break;
+    case FIN_RHO: hipLaunchKernelGGL(k_finalize<FIN_RHO>, g, b, 0, st, ks, part, nblocks, pp); break;
+    default: hipLaunchKernelGGL(k_finalize<FIN_RED0>, g, b, 0, st, ks, part, nblocks, pp); break;
   }
   return hipGetLastError();
 }
 
 // ------------------------------------------------------------- vector kernels
+// Block -> (problem pb, block within the problem lb); problem pb's elements
+// start at pb * n; element loop i = lb * NT + tid, step bpp * NT.
+#define PSFD_GROUP_LOOP(i)                                                           \
+  const int bpp = gridDim.x / nprob;                                                 \
+  const int pb = blockIdx.x / bpp, lb = blockIdx.x % bpp;                            \
+  const int64_t off = (int64_t)pb * n;                                               \
+  for (int64_t i = off + (int64_t)lb * blockDim.x + threadIdx.x; i < off + n;        \
+       i += (int64_t)bpp * blockDim.x)
 
 // y += alpha p + omega s;  r = s - omega t;  partials ||r||^2, sum conj(rh) r.
 // In the pending-half-step state only y += alpha p.
@@ -169,19 +192,18 @@ template <typename T>
 __global__ void __launch_bounds__(KRED_THREADS)
 k_xr_update(cplx<T>* __restrict__ y, cplx<T>* __restrict__ r, const cplx<T>* __restrict__ p,
             const cplx<T>* __restrict__ s, const cplx<T>* __restrict__ t,
-            const cplx<T>* __restrict__ rh, int64_t n, const KState* __restrict__ ks,
+            const cplx<T>* __restrict__ rh, int64_t n, int nprob, const KState* __restrict__ ks_all,
             double* __restrict__ part) {
+  const KState* ks = ks_all + blockIdx.x / (gridDim.x / nprob);
   const int d = ks->done;
   if (d != KS_RUN && d != KS_HALF) return;
   const cplx<T> al = cast<T>(ld2(ks->alpha));
   double acc[3] = {0.0, 0.0, 0.0};
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   if (d == KS_HALF) {
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
-      y[i] = y[i] + al * p[i];
+    PSFD_GROUP_LOOP(i) y[i] = y[i] + al * p[i];
   } else {
     const cplx<T> om = cast<T>(ld2(ks->omega));
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    PSFD_GROUP_LOOP(i) {
       const cplx<T> si = s[i];
       y[i] = y[i] + al * p[i] + om * si;
       const cplx<T> ri = si - om * t[i];
@@ -200,24 +222,23 @@ k_xr_update(cplx<T>* __restrict__ y, cplx<T>* __restrict__ r, const cplx<T>* __r
 template <typename T>
 __global__ void __launch_bounds__(KRED_THREADS)
 k_p_update(cplx<T>* __restrict__ p, const cplx<T>* __restrict__ r, const cplx<T>* __restrict__ v,
-           int64_t n, const KState* __restrict__ ks) {
+           int64_t n, int nprob, const KState* __restrict__ ks_all) {
+  const KState* ks = ks_all + blockIdx.x / (gridDim.x / nprob);
   if (ks->done != KS_RUN) return;
   const cplx<double> beta = cdiv(ld2(ks->rho), ld2(ks->rho_prev)) * cdiv(ld2(ks->alpha), ld2(ks->omega));
   const cplx<T> b = cast<T>(beta), w = cast<T>(ld2(ks->omega));
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * blockDim.x)
-    p[i] = r[i] + b * (p[i] - w * v[i]);
+  PSFD_GROUP_LOOP(i) p[i] = r[i] + b * (p[i] - w * v[i]);
 }
 
 // rh = r; p = v = y = 0; partials ||r||^2.
 template <typename T>
 __global__ void __launch_bounds__(KRED_THREADS)
 k_init(cplx<T>* __restrict__ rh, const cplx<T>* __restrict__ r, cplx<T>* __restrict__ p,
-       cplx<T>* __restrict__ v, cplx<T>* __restrict__ y, int64_t n, double* __restrict__ part) {
+       cplx<T>* __restrict__ v, cplx<T>* __restrict__ y, int64_t n, int nprob,
+       double* __restrict__ part) {
   double acc[1] = {0.0};
   const cplx<T> zero = {T(0), T(0)};
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * blockDim.x) {
+  PSFD_GROUP_LOOP(i) {
     const cplx<T> ri = r[i];
     rh[i] = ri;
     p[i] = zero;
@@ -231,10 +252,9 @@ k_init(cplx<T>* __restrict__ rh, const cplx<T>* __restrict__ r, cplx<T>* __restr
 template <typename T>
 __global__ void __launch_bounds__(KRED_THREADS)
 k_residual(cplx<T>* __restrict__ out, const cplx<T>* __restrict__ a, const cplx<T>* __restrict__ b,
-           int64_t n, double* __restrict__ part) {
+           int64_t n, int nprob, double* __restrict__ part) {
   double acc[1] = {0.0};
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * blockDim.x) {
+  PSFD_GROUP_LOOP(i) {
     const cplx<T> d = a[i] - b[i];
     out[i] = d;
     acc[0] += norm2(cast<double>(d));
@@ -244,19 +264,19 @@ k_residual(cplx<T>* __restrict__ out, const cplx<T>* __restrict__ a, const cplx<
 
 template <typename T>
 __global__ void __launch_bounds__(KRED_THREADS)
-k_norm2(const cplx<T>* __restrict__ a, int64_t n, double* __restrict__ part) {
+k_norm2(const cplx<T>* __restrict__ a, int64_t n, int nprob, double* __restrict__ part) {
   double acc[1] = {0.0};
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * blockDim.x)
-    acc[0] += norm2(cast<double>(a[i]));
+  PSFD_GROUP_LOOP(i) acc[0] += norm2(cast<double>(a[i]));
   block_partials<1, KRED_THREADS>(acc, part);
 }
 
 template <typename TY, typename TX>
 __global__ void __launch_bounds__(KRED_THREADS)
-k_axpy(cplx<TY>* __restrict__ y, const cplx<TX>* __restrict__ x, double a, int64_t n) {
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * blockDim.x) {
+k_axpy(cplx<TY>* __restrict__ y, const cplx<TX>* __restrict__ x,
+       const ProbParams* __restrict__ pp, int64_t n, int nprob) {
+  const double a = pp[blockIdx.x / (gridDim.x / nprob)].scale;
+  if (a == 0.0) return;
+  PSFD_GROUP_LOOP(i) {
     const cplx<TY> xv = cast<TY>(x[i]);
     y[i] = y[i] + TY(a) * xv;
   }
@@ -264,83 +284,83 @@ k_axpy(cplx<TY>* __restrict__ y, const cplx<TX>* __restrict__ x, double a, int64
 
 template <typename TY, typename TX>
 __global__ void __launch_bounds__(KRED_THREADS)
-k_scale_copy(cplx<TY>* __restrict__ y, const cplx<TX>* __restrict__ x, double a, int64_t n) {
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * blockDim.x) {
+k_scale_copy(cplx<TY>* __restrict__ y, const cplx<TX>* __restrict__ x,
+             const ProbParams* __restrict__ pp, int64_t n, int nprob) {
+  const double a = pp ? pp[blockIdx.x / (gridDim.x / nprob)].iscale : 1.0;
+  PSFD_GROUP_LOOP(i) {
     const cplx<double> xv = cast<double>(x[i]);
     y[i] = cast<TY>(a * xv);
   }
 }
 
 // ---------------------------------------------------------------- launchers
-#define KGRID dim3(red_blocks(n)), dim3(KRED_THREADS), 0, st
+#define KGRID dim3(nprob * red_blocks(n, nprob)), dim3(KRED_THREADS), 0, st
 
 template <typename T>
 hipError_t launch_k_xr_update(cplx<T>* y, cplx<T>* r, const cplx<T>* p, const cplx<T>* s,
-                              const cplx<T>* t, const cplx<T>* rh, int64_t n, const KState* ks,
-                              double* part, hipStream_t st) {
-  hipLaunchKernelGGL((k_xr_update<T>), KGRID, y, r, p, s, t, rh, n, ks, part);
+                              const cplx<T>* t, const cplx<T>* rh, int64_t n, int nprob,
+                              const KState* ks, double* part, hipStream_t st) {
+  hipLaunchKernelGGL((k_xr_update<T>), KGRID, y, r, p, s, t, rh, n, nprob, ks, part);
   return hipGetLastError();
 }
 template <typename T>
 hipError_t launch_k_p_update(cplx<T>* p, const cplx<T>* r, const cplx<T>* v, int64_t n,
-                             const KState* ks, hipStream_t st) {
-  hipLaunchKernelGGL((k_p_update<T>), KGRID, p, r, v, n, ks);
+                             int nprob, const KState* ks, hipStream_t st) {
+  hipLaunchKernelGGL((k_p_update<T>), KGRID, p, r, v, n, nprob, ks);
   return hipGetLastError();
 }
 template <typename T>
 hipError_t launch_k_init(cplx<T>* rh, const cplx<T>* r, cplx<T>* p, cplx<T>* v, cplx<T>* y,
-                         int64_t n, double* part, hipStream_t st) {
-  hipLaunchKernelGGL((k_init<T>), KGRID, rh, r, p, v, y, n, part);
+                         int64_t n, int nprob, double* part, hipStream_t st) {
+  hipLaunchKernelGGL((k_init<T>), KGRID, rh, r, p, v, y, n, nprob, part);
   return hipGetLastError();
 }
 template <typename T>
 hipError_t launch_k_residual(cplx<T>* out, const cplx<T>* a, const cplx<T>* b, int64_t n,
-                             double* part, hipStream_t st) {
-  hipLaunchKernelGGL((k_residual<T>), KGRID, out, a, b, n, part);
+                             int nprob, double* part, hipStream_t st) {
+  hipLaunchKernelGGL((k_residual<T>), KGRID, out, a, b, n, nprob, part);
   return hipGetLastError();
 }
 template <typename T>
-hipError_t launch_k_norm2(const cplx<T>* a, int64_t n, double* part, hipStream_t st) {
-  hipLaunchKernelGGL((k_norm2<T>), KGRID, a, n, part);
+hipError_t launch_k_norm2(const cplx<T>* a, int64_t n, int nprob, double* part, hipStream_t st) {
+  hipLaunchKernelGGL((k_norm2<T>), KGRID, a, n, nprob, part);
   return hipGetLastError();
 }
 template <typename TY, typename TX>
-hipError_t launch_k_axpy(cplx<TY>* y, const cplx<TX>* x, double a, int64_t n, hipStream_t st) {
-  hipLaunchKernelGGL((k_axpy<TY, TX>), KGRID, y, x, a, n);
+hipError_t launch_k_axpy(cplx<TY>* y, const cplx<TX>* x, const ProbParams* pp, int64_t n,
+                         int nprob, hipStream_t st) {
+  hipLaunchKernelGGL((k_axpy<TY, TX>), KGRID, y, x, pp, n, nprob);
   return hipGetLastError();
 }
 template <typename TY, typename TX>
-hipError_t launch_k_scale_copy(cplx<TY>* y, const cplx<TX>* x, double a, int64_t n,
-                               hipStream_t st) {
-  hipLaunchKernelGGL((k_scale_copy<TY, TX>), KGRID, y, x, a, n);
+hipError_t launch_k_scale_copy(cplx<TY>* y, const cplx<TX>* x, const ProbParams* pp, int64_t n,
+                               int nprob, hipStream_t st) {
+  hipLaunchKernelGGL((k_scale_copy<TY, TX>), KGRID, y, x, pp, n, nprob);
   return hipGetLastError();
 }
 
 #define PSFD_INST_K(T)                                                                        \
   template hipError_t launch_k_xr_update<T>(cplx<T>*, cplx<T>*, const cplx<T>*,               \
                                             const cplx<T>*, const cplx<T>*, const cplx<T>*,   \
-                                            int64_t, const KState*, double*, hipStream_t);    \
+                                            int64_t, int, const KState*, double*, hipStream_t); \
   template hipError_t launch_k_p_update<T>(cplx<T>*, const cplx<T>*, const cplx<T>*, int64_t, \
-                                           const KState*, hipStream_t);                       \
+                                           int, const KState*, hipStream_t);                  \
   template hipError_t launch_k_init<T>(cplx<T>*, const cplx<T>*, cplx<T>*, cplx<T>*,          \
-                                       cplx<T>*, int64_t, double*, hipStream_t);              \
+                                       cplx<T>*, int64_t, int, double*, hipStream_t);         \
   template hipError_t launch_k_residual<T>(cplx<T>*, const cplx<T>*, const cplx<T>*, int64_t, \
-                                           double*, hipStream_t);                             \
-  template hipError_t launch_k_norm2<T>(const cplx<T>*, int64_t, double*, hipStream_t);
+                                           int, double*, hipStream_t);                        \
+  template hipError_t launch_k_norm2<T>(const cplx<T>*, int64_t, int, double*, hipStream_t);
 
 PSFD_INST_K(double)
 PSFD_INST_K(float)
 
-template hipError_t launch_k_axpy<double, double>(cplx<double>*, const cplx<double>*, double,
-                                                  int64_t, hipStream_t);
-template hipError_t launch_k_axpy<double, float>(cplx<double>*, const cplx<float>*, double,
-                                                 int64_t, hipStream_t);
-template hipError_t launch_k_scale_copy<float, double>(cplx<float>*, const cplx<double>*, double,
-                                                       int64_t, hipStream_t);
-template hipError_t launch_k_scale_copy<double, float>(cplx<double>*, const cplx<float>*, double,
-                                                       int64_t, hipStream_t);
-template hipError_t launch_k_scale_copy<double, double>(cplx<double>*, const cplx<double>*,
-                                                        double, int64_t, hipStream_t);
+#define PSFD_INST_AX(TY, TX)                                                                  \
+  template hipError_t launch_k_axpy<TY, TX>(cplx<TY>*, const cplx<TX>*, const ProbParams*,    \
+                                            int64_t, int, hipStream_t);                       \
+  template hipError_t launch_k_scale_copy<TY, TX>(cplx<TY>*, const cplx<TX>*,                 \
+                                                  const ProbParams*, int64_t, int, hipStream_t);
+PSFD_INST_AX(double, double)
+PSFD_INST_AX(double, float)
+PSFD_INST_AX(float, double)
 
 }  // namespace psfd

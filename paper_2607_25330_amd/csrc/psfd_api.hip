@@ -1,5 +1,12 @@
 // Host side of libpsfd: plan construction, operator pipelines, the BiCGSTAB
 // driver and the C ABI declared in include/psfd.h.
+//
+// A plan holds a group of G >= 1 problems of one shape (same grid, optics,
+// multilayer, PML, preconditioner and precision; angle, polarisation and
+// permittivity may differ).  psfd_plan makes G = 1; psfd_solve_batch forms
+// groups of compatible problems.  Every launch covers the whole group, the
+// Krylov scalars are per problem on the device, and a converged problem is
+// skipped by every kernel while the rest of its group iterates.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -15,6 +22,7 @@
 
 #include "psfd.h"
 #include "psfd_internal.h"
+#include "reduce.h"
 
 using namespace psfd;
 
@@ -60,12 +68,21 @@ std::vector<cplx<double>> twiddles(int n) {
 
 }  // namespace
 
+
+// Per-problem host data of a group.
+struct ProbInfo {
+  double theta = 0, phi = 0, kx0 = 0, ky0 = 0, kz0 = 0;
+  int pol = 0;
+};
+
 struct psfd_plan {
-  psfd_desc d{};
+  psfd_desc d{};  // problem 0's descriptor (shared fields for the whole group)
   std::vector<double> ml_eps_h, ml_d_h;
+  int G = 1;
+  std::vector<ProbInfo> prob;
   int nx = 0, ny = 0, nz = 0, nabs = 0, j0 = 0, jev = 0;
-  double k0 = 0, kbg = 0, kx0 = 0, ky0 = 0, kz0 = 0;
-  int64_t plane = 0, nfield = 0, nspec = 0;
+  double k0 = 0, kbg = 0;
+  int64_t plane = 0, nfield = 0, nspec = 0;  // per problem
   hipStream_t st = nullptr;
   int prec = PSFD_C128;
   bool use_pc = true;
@@ -89,8 +106,13 @@ struct psfd_plan {
   cplx<double>* b64 = nullptr;
   cplx<double>* tmp64 = nullptr;
   cplx<double>* res64 = nullptr;
+  cplx<double>* E64 = nullptr;  // stacked solution of a batch group
   KState* ks = nullptr;
   KState* ks_host = nullptr;
+  ProbParams* pp = nullptr;
+  ProbParams* pp_host = nullptr;
+  int* idle = nullptr;  // [G] 1: problem finished (skipped by operator kernels)
+  int* idle_host = nullptr;
   double* part = nullptr;
 
   // batch handle (psfd_plan_batch): the recorded problems
@@ -123,6 +145,8 @@ struct psfd_plan {
     for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
     for (void* p : allocs) (void)hipFree(p);
     if (ks_host) (void)hipHostFree(ks_host);
+    if (pp_host) (void)hipHostFree(pp_host);
+    if (idle_host) (void)hipHostFree(idle_host);
   }
 };
 
@@ -183,6 +207,27 @@ psfd_status validate(const psfd_desc* d) {
   if (!std::isfinite(d->theta) || !std::isfinite(d->phi)) return fail(PSFD_ERR_ARG, "bad angles");
   if (!(d->ml_kz_min >= 0.0 && d->ml_kz_min <= 1.0)) return fail(PSFD_ERR_ARG, "bad ml_kz_min");
   return PSFD_OK;
+}
+
+// Problems that may share a plan: everything but angle, polarisation and
+// permittivity must agree.
+bool same_group(const psfd_desc& a, const psfd_desc& b) {
+  if (a.nx != b.nx || a.ny != b.ny || a.nz_abs != b.nz_abs || a.nz_gap_bot != b.nz_gap_bot ||
+      a.nz_gap_top != b.nz_gap_top || a.nz_pml != b.nz_pml)
+    return false;
+  if (a.dx != b.dx || a.dy != b.dy || a.dz != b.dz || a.lambda != b.lambda || a.eps_bg != b.eps_bg)
+    return false;
+  if (a.n_ml != b.n_ml || a.eps_sub[0] != b.eps_sub[0] || a.eps_sub[1] != b.eps_sub[1]) return false;
+  for (int i = 0; i < a.n_ml; ++i)
+    if (a.ml_eps[2 * i] != b.ml_eps[2 * i] || a.ml_eps[2 * i + 1] != b.ml_eps[2 * i + 1] ||
+        a.ml_thick[i] != b.ml_thick[i])
+      return false;
+  if (a.pml_sigma0 != b.pml_sigma0 || a.pml_order != b.pml_order || a.precond != b.precond)
+    return false;
+  if (a.pc_mmin != b.pc_mmin || a.pc_kref != b.pc_kref || a.pc_gamma != b.pc_gamma ||
+      a.pc_reg != b.pc_reg || a.prec != b.prec || a.ml_kz_min != b.ml_kz_min)
+    return false;
+  return true;
 }
 
 template <typename T>
@@ -261,22 +306,27 @@ struct Fuse {
   PreOp<T> pre;
   int fin_first = -1;  // finalize stage after the first x pass (partials from pre)
   PostOp<T> post;
-  int* nblk_post = nullptr;  // receives the number of partials written by post
+  int* nblk_post = nullptr;  // receives the number of partials per problem written by post
 };
 
-// One operator application (see the kernel files for the math).  The
-// algorithmic bytes of each launch count every complex element it must read
-// or write once.
+constexpr int kKsStride = (int)(sizeof(KState) / sizeof(int));
+static_assert(sizeof(KState) % sizeof(int) == 0, "KState must hold whole ints");
+
+// One operator application over the group (see the kernel files for the
+// math).  skip/skip_stride: per-problem flags that make the kernels return.
+// The algorithmic bytes of each launch count every complex element it must
+// read or write once.
 template <typename T>
 hipError_t op_apply(struct psfd_plan* P, const cplx<T>* x, cplx<T>* y, int op, const int* skip,
-                    const Fuse<T>& fz = Fuse<T>()) {
+                    int skip_stride, const Fuse<T>& fz = Fuse<T>()) {
   OpTables<T> t = tab<T>(P);
   t.skip = skip;
+  t.skip_stride = skip_stride;
   cplx<T>* S = wsS<T>(P);
   cplx<T>* UW = wsUW<T>(P);
   hipStream_t st = P->st;
   const int p3 = 3 * P->nz, pa = 3 * P->nabs;
-  const double pl = (double)P->plane * sizeof(cplx<T>);  // bytes of one plane
+  const double pl = (double)P->plane * P->G * sizeof(cplx<T>);  // bytes of one plane, whole group
   hipError_t e;
   const bool adj = op == OP_AH;
   const int nin = adj ? p3 + pa : p3;  // planes through the forward lateral transform
@@ -290,7 +340,7 @@ hipError_t op_apply(struct psfd_plan* P, const cplx<T>* x, cplx<T>* y, int op, c
             [&] { return launch_xfft_fwd<T>(t, x, S, adj, fz.pre, &nb_first, st); });
   if (e != hipSuccess) return e;
   if (fz.fin_first >= 0) {
-    e = launch_finalize(fz.fin_first, P->ks, fz.pre.part, nb_first, 0.0, 0.0, st);
+    e = launch_finalize(fz.fin_first, P->ks, fz.pre.part, nb_first, P->G, P->pp, st);
     if (e != hipSuccess) return e;
   }
   e = timed(P, PROF_YFFT, (int)sizeof(cplx<T>), 2.0 * pl * nin, [&] { return launch_yfft<T>(t, S, nin, false, st); });
@@ -310,9 +360,8 @@ hipError_t op_apply(struct psfd_plan* P, const cplx<T>* x, cplx<T>* y, int op, c
 
 psfd_status ensure_fp32(struct psfd_plan* P) {
   if (P->S32) return PSFD_OK;
-  const int64_t nspec = P->nspec;
-  CHKS(dalloc(P, &P->S32, (size_t)nspec));
-  CHKS(dalloc(P, &P->UW32, (size_t)nspec));
+  CHKS(dalloc(P, &P->S32, (size_t)(P->nspec * P->G)));
+  CHKS(dalloc(P, &P->UW32, (size_t)(P->nspec * P->G)));
   return PSFD_OK;
 }
 
@@ -320,76 +369,88 @@ template <typename T>
 psfd_status ensure_krylov(struct psfd_plan* P) {
   cplx<T>** v = vecs<T>(P);
   if (v[0]) return PSFD_OK;
-  for (int i = 0; i < V_COUNT; ++i) CHKS(dalloc(P, &v[i], (size_t)P->nfield));
+  for (int i = 0; i < V_COUNT; ++i) CHKS(dalloc(P, &v[i], (size_t)(P->nfield * P->G)));
   return PSFD_OK;
 }
 
 psfd_status ensure_solver_common(struct psfd_plan* P) {
   if (P->ks) return PSFD_OK;
-  CHKS(dalloc(P, &P->ks, 1));
-  // one partial set per block of the largest reducing grid (x pass rows, or 2048)
-  CHKS(dalloc(P, &P->part, (size_t)(3 * P->nz * P->ny + 3 * P->nabs * P->ny + 2048) * 4));
-  CHKS(dalloc(P, &P->b64, (size_t)P->nfield));
-  CHKS(dalloc(P, &P->tmp64, (size_t)P->nfield));
-  CHKS(dalloc(P, &P->res64, (size_t)P->nfield));
-  CHK(hipMemsetAsync(P->ks, 0, sizeof(KState), P->st));
-  CHK(hipHostMalloc((void**)&P->ks_host, sizeof(KState), hipHostMallocDefault));
+  const int G = P->G;
+  CHKS(dalloc(P, &P->ks, (size_t)G));
+  CHKS(dalloc(P, &P->pp, (size_t)G));
+  CHKS(dalloc(P, &P->idle, (size_t)G));
+  // per problem: one partial set per block of the largest reducing grid
+  // (x pass rows, or the streaming kernels' blocks)
+  const int64_t per = (int64_t)(3 * P->nz + 3 * P->nabs) * P->ny + 2048;
+  CHKS(dalloc(P, &P->part, (size_t)(per * KPART * G)));
+  CHKS(dalloc(P, &P->b64, (size_t)(P->nfield * G)));
+  CHKS(dalloc(P, &P->tmp64, (size_t)(P->nfield * G)));
+  CHKS(dalloc(P, &P->res64, (size_t)(P->nfield * G)));
+  CHK(hipMemsetAsync(P->ks, 0, sizeof(KState) * G, P->st));
+  CHK(hipMemsetAsync(P->idle, 0, sizeof(int) * G, P->st));
+  CHK(hipHostMalloc((void**)&P->ks_host, sizeof(KState) * G, hipHostMallocDefault));
+  CHK(hipHostMalloc((void**)&P->pp_host, sizeof(ProbParams) * G, hipHostMallocDefault));
+  CHK(hipHostMalloc((void**)&P->idle_host, sizeof(int) * G, hipHostMallocDefault));
+  std::memset(P->pp_host, 0, sizeof(ProbParams) * G);
+  std::memset(P->idle_host, 0, sizeof(int) * G);
   return PSFD_OK;
 }
 
 psfd_status read_state(struct psfd_plan* P) {
-  CHK(hipMemcpyAsync(P->ks_host, P->ks, sizeof(KState), hipMemcpyDeviceToHost, P->st));
+  CHK(hipMemcpyAsync(P->ks_host, P->ks, sizeof(KState) * P->G, hipMemcpyDeviceToHost, P->st));
   CHK(hipStreamSynchronize(P->st));
   if (!P->ev_open.empty()) collect_events(P);
   return PSFD_OK;
 }
 
-psfd_status norm2_host(struct psfd_plan* P, const cplx<double>* a, double* out) {
-  CHK(launch_k_norm2<double>(a, P->nfield, P->part, P->st));
-  CHK(launch_finalize(FIN_RED0, P->ks, P->part, red_blocks(P->nfield), 0.0, 0.0, P->st));
-  CHKS(read_state(P));
-  *out = P->ks_host->red[0];
+psfd_status push_params(struct psfd_plan* P) {
+  CHK(hipMemcpyAsync(P->pp, P->pp_host, sizeof(ProbParams) * P->G, hipMemcpyHostToDevice, P->st));
+  CHK(hipMemcpyAsync(P->idle, P->idle_host, sizeof(int) * P->G, hipMemcpyHostToDevice, P->st));
   return PSFD_OK;
 }
 
-struct RunResult {
-  int iters = 0;
-  int done = 0;
-  double rrel_rec = 0;
-};
+// ||a_b||^2 per problem into ks_host[b].red[0]
+psfd_status norm2_group(struct psfd_plan* P, const cplx<double>* a) {
+  CHK(launch_k_norm2<double>(a, P->nfield, P->G, P->part, P->st));
+  CHK(launch_finalize(FIN_RED0, P->ks, P->part, red_blocks(P->nfield, P->G), P->G, P->pp, P->st));
+  return read_state(P);
+}
 
-// Right-preconditioned BiCGSTAB on op(prec(y)) = r (r in vecs[V_R]); y in vecs[V_Y].
-// One iteration, with the vector updates and inner products fused into the
-// operator's x passes:
+// Right-preconditioned BiCGSTAB on op(prec(y)) = r (r in vecs[V_R]); y in
+// vecs[V_Y]; per-problem ||b||^2, tolerance and budget from P->pp (pushed by
+// the caller).  One iteration, with the vector updates and inner products
+// fused into the operator's x passes:
 //   [p = r + beta(p - omega v) -> x-FFT] ... [x-IFFT -> v, <rh, v>]  fin: alpha
 //   [s = r - alpha v, ||s|| -> x-FFT]  fin: half-step test
 //   ... [x-IFFT -> t, <t, s>, ||t||]  fin: omega
 //   [y += alpha p + omega s, r = s - omega t, ||r||, <rh, r>]  fin: rho, beta, stop test
+// Returns when every problem of the group has stopped (converged, budget
+// used, breakdown or idle) or after `maxit` launched iterations.
 template <typename T>
-psfd_status run_bicgstab(struct psfd_plan* P, bool adjoint, double bnorm2, double tol,
-                         int maxit, RunResult* res) {
+psfd_status run_bicgstab(struct psfd_plan* P, bool adjoint, int maxit) {
   cplx<T>** V = vecs<T>(P);
   const int64_t n = P->nfield;
+  const int G = P->G;
   hipStream_t st = P->st;
   KState* ks = P->ks;
   double* part = P->part;
   const int* skip = &ks->done;
   const bool pc = P->use_pc;
-  CHK(launch_k_init<T>(V[V_RH], V[V_R], V[V_P], V[V_V], V[V_Y], n, part, st));
-  CHK(launch_finalize(FIN_INIT, ks, part, red_blocks(n), bnorm2, tol * tol, st));
+  CHK(launch_k_init<T>(V[V_RH], V[V_R], V[V_P], V[V_V], V[V_Y], n, G, part, st));
+  CHK(launch_finalize(FIN_INIT, ks, part, red_blocks(n, G), G, P->pp, st));
 
   // The first operator of a composite (M then A^H) carries the update; the last carries the dot.
   auto apply = [&](const cplx<T>* in, cplx<T>* out, Fuse<T>& fz) -> hipError_t {
-    if (!adjoint) return op_apply<T>(P, in, out, pc ? OP_AM : OP_A, skip, fz);
-    if (!pc) return op_apply<T>(P, in, out, OP_AH, skip, fz);
+    if (!adjoint) return op_apply<T>(P, in, out, pc ? OP_AM : OP_A, skip, kKsStride, fz);
+    if (!pc) return op_apply<T>(P, in, out, OP_AH, skip, kKsStride, fz);
     Fuse<T> f1, f2;
     f1.pre = fz.pre;
     f1.fin_first = fz.fin_first;
     f2.post = fz.post;
     f2.nblk_post = fz.nblk_post;
-    hipError_t e = op_apply<T>(P, in, V[V_W], OP_M, skip, f1);
+    hipError_t e = op_apply<T>(P, in, V[V_W], OP_M, skip, kKsStride, f1);
     if (e != hipSuccess) return e;
-    return op_apply<T>(P, V[V_W], out, OP_AH, skip, f2);
+    return op_apply<T>(P, V[V_W], out, OP_AH, skip, kKsStride, f2);
   };
   // the unpreconditioned adjoint transforms extra rows of the input: update p separately
   const bool fuse_p = !(adjoint && !pc);
@@ -404,14 +465,14 @@ psfd_status run_bicgstab(struct psfd_plan* P, bool adjoint, double bnorm2, doubl
         fa.pre.v = V[V_V];
         fa.pre.ks = ks;
       } else {
-        CHK(launch_k_p_update<T>(V[V_P], V[V_R], V[V_V], n, ks, st));
+        CHK(launch_k_p_update<T>(V[V_P], V[V_R], V[V_V], n, G, ks, st));
       }
       fa.post.mode = POST_DOT;
       fa.post.d = V[V_RH];
       fa.post.part = part;
       fa.nblk_post = &nb_v;
       CHK(apply(V[V_P], V[V_V], fa));
-      CHK(launch_finalize(FIN_ALPHA, ks, part, nb_v, 0.0, 0.0, st));
+      CHK(launch_finalize(FIN_ALPHA, ks, part, nb_v, G, P->pp, st));
 
       Fuse<T> fb;
       fb.pre.mode = PRE_S;
@@ -426,28 +487,27 @@ psfd_status run_bicgstab(struct psfd_plan* P, bool adjoint, double bnorm2, doubl
       fb.post.part = part;
       fb.nblk_post = &nb_t;
       CHK(apply(V[V_S], V[V_T], fb));
-      CHK(launch_finalize(FIN_OMEGA, ks, part, nb_t, 0.0, 0.0, st));
+      CHK(launch_finalize(FIN_OMEGA, ks, part, nb_t, G, P->pp, st));
 
-      CHK(launch_k_xr_update<T>(V[V_Y], V[V_R], V[V_P], V[V_S], V[V_T], V[V_RH], n, ks, part,
+      CHK(launch_k_xr_update<T>(V[V_Y], V[V_R], V[V_P], V[V_S], V[V_T], V[V_RH], n, G, ks, part,
                                 st));
-      CHK(launch_finalize(FIN_RHO, ks, part, red_blocks(n), 0.0, 0.0, st));
+      CHK(launch_finalize(FIN_RHO, ks, part, red_blocks(n, G), G, P->pp, st));
     }
     return PSFD_OK;
   };
   // A full chunk is captured once per plan into a HIP graph and replayed:
-  // every launch argument is fixed per plan and convergence is tested on
-  // the device, so the same graph serves every chunk of every solve.
+  // every launch argument is fixed per plan, per-problem budgets and
+  // convergence are tested on the device, so the same graph serves every
+  // chunk of every solve.
   hipGraphExec_t& gx = P->gexec[sizeof(T) == 4 ? 1 : 0][adjoint ? 1 : 0];
   const bool graphs = P->use_graphs && P->prof_kernel == PROF_OFF;
   int launched = 0;
-  res->done = 0;
   while (launched < maxit) {
-    const int chunk = std::min(kChunk, maxit - launched);
-    if (graphs && chunk == kChunk) {
+    if (graphs) {
       if (!gx) {
         hipGraph_t g = nullptr;
         CHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
-        psfd_status cs = launch_iters(chunk);
+        psfd_status cs = launch_iters(kChunk);
         hipError_t ce = hipStreamEndCapture(st, &g);
         if (cs != PSFD_OK) {
           if (g) (void)hipGraphDestroy(g);
@@ -459,28 +519,28 @@ psfd_status run_bicgstab(struct psfd_plan* P, bool adjoint, double bnorm2, doubl
         CHK(ie);
       }
       CHK(hipGraphLaunch(gx, st));
+      launched += kChunk;
     } else {
+      const int chunk = std::min(kChunk, maxit - launched);
       CHKS(launch_iters(chunk));
+      launched += chunk;
     }
-    launched += chunk;
     CHKS(read_state(P));
-    if (P->ks_host->done != 0) break;
+    bool all = true;
+    for (int b = 0; b < G && all; ++b) all = P->ks_host[b].done != 0;
+    if (all) break;
   }
-  res->iters = P->ks_host->iter;
-  res->done = P->ks_host->done;
-  res->rrel_rec = std::sqrt(P->ks_host->rnorm2 / bnorm2);
   return PSFD_OK;
 }
 
-// r = b - op(E) in FP64 (op = A or A^H, no preconditioner); returns ||r||^2.
+// r = b - op(E) in FP64 (op = A or A^H, no preconditioner) for every problem
+// not marked idle; ||r_b||^2 lands in ks_host[b].red[0].
 psfd_status true_residual(struct psfd_plan* P, const cplx<double>* b, const cplx<double>* E,
-                          cplx<double>* r, bool adjoint, double* rr2) {
-  CHK(op_apply<double>(P, E, P->tmp64, adjoint ? OP_AH : OP_A, nullptr));
-  CHK(launch_k_residual<double>(r, b, P->tmp64, P->nfield, P->part, P->st));
-  CHK(launch_finalize(FIN_RED0, P->ks, P->part, red_blocks(P->nfield), 0.0, 0.0, P->st));
-  CHKS(read_state(P));
-  *rr2 = P->ks_host->red[0];
-  return PSFD_OK;
+                          cplx<double>* r, bool adjoint) {
+  CHK(op_apply<double>(P, E, P->tmp64, adjoint ? OP_AH : OP_A, P->idle, 1));
+  CHK(launch_k_residual<double>(r, b, P->tmp64, P->nfield, P->G, P->part, P->st));
+  CHK(launch_finalize(FIN_RED0, P->ks, P->part, red_blocks(P->nfield, P->G), P->G, P->pp, P->st));
+  return read_state(P);
 }
 
 double inner_tolerance(double tol, double rrel) {
@@ -494,28 +554,49 @@ double inner_tolerance(double tol, double rrel) {
   return t;
 }
 
-psfd_status solve_body(struct psfd_plan* P, const void* b_in, const void* x0, void* E_out,
-                       double tol, int maxit, bool adjoint, psfd_info* info);
+RhsArgs rhs_args(const struct psfd_plan* P, int b) {
+  const ProbInfo& q = P->prob[b];
+  return RhsArgs{P->nx, P->ny, P->nz, P->nabs, P->j0, q.pol, P->k0, q.kz0, q.theta, q.phi,
+                 P->zabs64, P->rte64 + (int64_t)b * P->plane, P->rpe64 + (int64_t)b * P->plane,
+                 P->kd64 + (int64_t)b * P->nabs * P->plane};
+}
+
+psfd_status rhs_group(struct psfd_plan* P, cplx<double>* b) {
+  for (int i = 0; i < P->G; ++i) CHK(launch_rhs<double>(rhs_args(P, i), b + i * P->nfield, P->st));
+  return PSFD_OK;
+}
+
+psfd_status solve_body(struct psfd_plan* P, const cplx<double>* b_in, const cplx<double>* x0,
+                       cplx<double>* E, double tol, int maxit, bool adjoint, psfd_info* infos);
 
 // The solve runs on the plan's private stream, after the work already queued on
-// the caller's stream; it returns with that private stream drained.
+// the caller's stream; it returns with that private stream drained.  b_in, x0,
+// E: stacked [G] fields; infos: [G].
 psfd_status solve_impl(struct psfd_plan* P, const void* b_in, const void* x0, void* E_out,
-                       double tol, int maxit, bool adjoint, psfd_info* info) {
+                       double tol, int maxit, bool adjoint, psfd_info* infos) {
   CHK(hipEventRecord(P->join_ev, P->st));
   CHK(hipStreamWaitEvent(P->own_st, P->join_ev, 0));
   hipStream_t user = P->st;
   P->st = P->own_st;
-  psfd_status s = solve_body(P, b_in, x0, E_out, tol, maxit, adjoint, info);
+  psfd_status s = solve_body(P, static_cast<const cplx<double>*>(b_in),
+                             static_cast<const cplx<double>*>(x0), static_cast<cplx<double>*>(E_out),
+                             tol, maxit, adjoint, infos);
   hipError_t e = hipStreamSynchronize(P->own_st);
   P->st = user;
   if (s == PSFD_OK && e != hipSuccess) return fail(PSFD_ERR_HIP, hipGetErrorString(e));
   return s;
 }
 
-psfd_status solve_body(struct psfd_plan* P, const void* b_in, const void* x0, void* E_out,
-                       double tol, int maxit, bool adjoint, psfd_info* info) {
-  psfd_info loc{};
+// Every problem of the group is solved to FP64 true r_rel <= tol:
+//   FP64 plans: BiCGSTAB with residual replacement (restart from the current
+//   field) when the recursive residual drifts from the true one;
+//   mixed plans: iterative refinement, each step a complex64 BiCGSTAB on the
+//   normalised FP64 residual to a relative tolerance of about 0.3 tol / r_rel.
+// A problem that has finished is idle in the group's later runs.
+psfd_status solve_body(struct psfd_plan* P, const cplx<double>* b_in, const cplx<double>* x0,
+                       cplx<double>* E, double tol, int maxit, bool adjoint, psfd_info* infos) {
   const bool mixed = P->prec != PSFD_C128;
+  const int G = P->G;
   CHKS(ensure_solver_common(P));
   if (mixed) {
     CHKS(ensure_fp32(P));
@@ -525,103 +606,168 @@ psfd_status solve_body(struct psfd_plan* P, const void* b_in, const void* x0, vo
   }
   const int64_t n = P->nfield;
   hipStream_t st = P->st;
-  cplx<double>* E = static_cast<cplx<double>*>(E_out);
-  const cplx<double>* b = static_cast<const cplx<double>*>(b_in);
+  const cplx<double>* b = b_in;
   if (!b) {
     if (adjoint) return fail(PSFD_ERR_ARG, "the adjoint solve needs an explicit right-hand side");
-    RhsArgs a{P->nx, P->ny, P->nz, P->nabs, P->j0, P->d.pol, P->k0, P->kz0, P->d.theta, P->d.phi,
-              P->zabs64, P->rte64, P->rpe64, P->kd64};
-    CHK(launch_rhs<double>(a, P->b64, st));
+    CHKS(rhs_group(P, P->b64));
     b = P->b64;
   }
-  double bnorm2 = 0;
-  CHKS(norm2_host(P, b, &bnorm2));
-  if (!std::isfinite(bnorm2)) return fail(PSFD_ERR_ARG, "right-hand side is not finite");
-  if (bnorm2 == 0.0) {
-    CHK(hipMemsetAsync(E, 0, sizeof(cplx<double>) * n, st));
-    CHK(hipStreamSynchronize(st));
-    loc.status = PSFD_OK;
-    if (info) *info = loc;
-    return PSFD_OK;
+  CHKS(norm2_group(P, b));
+  std::vector<double> bn2(G), rrel(G, 0.0), rn(G, 0.0);
+  std::vector<int> fin(G, 0), outer(G, 0), total(G, 0);
+  std::vector<psfd_status> status(G, PSFD_NOT_CONVERGED);
+  std::vector<psfd_info> loc(G);
+  for (int i = 0; i < G; ++i) {
+    bn2[i] = P->ks_host[i].red[0];
+    if (!std::isfinite(bn2[i])) return fail(PSFD_ERR_ARG, "right-hand side is not finite");
   }
-  bool base = x0 != nullptr;
-  if (x0 && x0 != E_out)
-    CHK(hipMemcpyAsync(E, x0, sizeof(cplx<double>) * n, hipMemcpyDeviceToDevice, st));
-  if (!x0) CHK(hipMemsetAsync(E, 0, sizeof(cplx<double>) * n, st));
-
-  double rr2 = bnorm2;
-  cplx<double>* r64 = mixed ? P->res64 : P->v64[V_R];
-  if (base) {
-    CHKS(true_residual(P, b, E, r64, adjoint, &rr2));
-    loc.applies += 1;
-  } else {
-    CHK(hipMemcpyAsync(r64, b, sizeof(cplx<double>) * n, hipMemcpyDeviceToDevice, st));
-  }
-  if (!std::isfinite(rr2)) return fail(PSFD_ERR_ARG, "initial guess gives a non-finite residual");
-  psfd_status status = PSFD_NOT_CONVERGED;
-  int total = 0;
-  double rrel = std::sqrt(rr2 / bnorm2);
-  for (int outer = 0;; ++outer) {
-    if (rrel <= tol) {
-      status = PSFD_OK;
-      break;
+  if (x0 && x0 != E)
+    CHK(hipMemcpyAsync(E, x0, sizeof(cplx<double>) * n * G, hipMemcpyDeviceToDevice, st));
+  if (!x0) CHK(hipMemsetAsync(E, 0, sizeof(cplx<double>) * n * G, st));
+  for (int i = 0; i < G; ++i) {
+    P->idle_host[i] = 0;
+    if (bn2[i] == 0.0) {  // zero right-hand side: E = 0
+      CHK(hipMemsetAsync(E + i * n, 0, sizeof(cplx<double>) * n, st));
+      fin[i] = 1;
+      status[i] = PSFD_OK;
+      P->idle_host[i] = 1;
     }
-    if (total >= maxit || outer > kMaxRestarts) break;
-    RunResult rr;
-    if (!mixed) {
-      CHKS(run_bicgstab<double>(P, adjoint, bnorm2, tol, maxit - total, &rr));
-      cplx<double>* y = P->v64[V_Y];
-      if (P->use_pc) {
-        CHK(op_apply<double>(P, y, P->tmp64, OP_M, nullptr));
-        CHK(launch_k_axpy<double, double>(E, P->tmp64, 1.0, n, st));
-      } else {
-        CHK(launch_k_axpy<double, double>(E, y, 1.0, n, st));
+  }
+  CHKS(push_params(P));
+
+  cplx<double>* r64 = mixed ? P->res64 : P->v64[V_R];
+  if (x0) {
+    CHKS(true_residual(P, b, E, r64, adjoint));
+    for (int i = 0; i < G; ++i) {
+      if (fin[i]) continue;
+      loc[i].applies += 1;
+      const double rr2 = P->ks_host[i].red[0];
+      if (!std::isfinite(rr2)) return fail(PSFD_ERR_ARG, "initial guess gives a non-finite residual");
+      rrel[i] = std::sqrt(rr2 / bn2[i]);
+      rn[i] = std::sqrt(rr2);
+    }
+  } else {
+    CHK(hipMemcpyAsync(r64, b, sizeof(cplx<double>) * n * G, hipMemcpyDeviceToDevice, st));
+    for (int i = 0; i < G; ++i)
+      if (!fin[i]) {
+        rrel[i] = 1.0;
+        rn[i] = std::sqrt(bn2[i]);
       }
-    } else {
-      const double rn = std::sqrt(rr2);
-      CHK(launch_k_scale_copy<float, double>(P->v32[V_R], r64, 1.0 / rn, n, st));
-      CHKS(run_bicgstab<float>(P, adjoint, 1.0, inner_tolerance(tol, rrel), maxit - total, &rr));
+  }
+  for (;;) {
+    int active = 0, budget = 0;
+    for (int i = 0; i < G; ++i) {
+      if (fin[i]) continue;
+      if (rrel[i] <= tol) {
+        status[i] = PSFD_OK;
+        fin[i] = 1;
+      } else if (total[i] >= maxit || outer[i] > kMaxRestarts) {
+        fin[i] = 1;  // status stays NOT_CONVERGED or BREAKDOWN
+      } else {
+        ++active;
+        budget = std::max(budget, maxit - total[i]);
+      }
+    }
+    if (!active) break;
+    for (int i = 0; i < G; ++i) {
+      ProbParams& q = P->pp_host[i];
+      q = ProbParams{};
+      P->idle_host[i] = fin[i];
+      if (fin[i]) {
+        q.tol2 = -1.0;
+        continue;
+      }
+      q.itmax = (double)(maxit - total[i]);
+      if (mixed) {
+        const double it = inner_tolerance(tol, rrel[i]);
+        q.bnorm2 = 1.0;  // the run solves for the normalised residual
+        q.tol2 = it * it;
+        q.iscale = 1.0 / rn[i];
+        q.scale = rn[i];
+      } else {
+        q.bnorm2 = bn2[i];
+        q.tol2 = tol * tol;
+        q.scale = 1.0;
+      }
+    }
+    CHKS(push_params(P));
+    if (mixed) {
+      CHK(launch_k_scale_copy<float, double>(P->v32[V_R], r64, P->pp, n, G, st));
+      CHKS(run_bicgstab<float>(P, adjoint, budget));
       cplx<float>* y = P->v32[V_Y];
       if (P->use_pc) {
-        CHK(op_apply<float>(P, y, P->v32[V_W], OP_M, nullptr));
-        CHK(launch_k_axpy<double, float>(E, P->v32[V_W], rn, n, st));
+        CHK(op_apply<float>(P, y, P->v32[V_W], OP_M, P->idle, 1));
+        CHK(launch_k_axpy<double, float>(E, P->v32[V_W], P->pp, n, G, st));
       } else {
-        CHK(launch_k_axpy<double, float>(E, y, rn, n, st));
+        CHK(launch_k_axpy<double, float>(E, y, P->pp, n, G, st));
+      }
+    } else {
+      CHKS(run_bicgstab<double>(P, adjoint, budget));
+      cplx<double>* y = P->v64[V_Y];
+      if (P->use_pc) {
+        CHK(op_apply<double>(P, y, P->tmp64, OP_M, P->idle, 1));
+        CHK(launch_k_axpy<double, double>(E, P->tmp64, P->pp, n, G, st));
+      } else {
+        CHK(launch_k_axpy<double, double>(E, y, P->pp, n, G, st));
       }
     }
-    total += rr.iters;
-    loc.applies += 2 * rr.iters + 1;
-    loc.rrel_hist_last = rr.rrel_rec;
-    loc.restarts = outer + 1;
-    CHKS(true_residual(P, b, E, r64, adjoint, &rr2));
-    if (!std::isfinite(rr2)) {
-      status = PSFD_BREAKDOWN;
-      rrel = rr2;
-      break;
+    std::vector<int> run_done(G, 0);
+    for (int i = 0; i < G; ++i) {
+      if (fin[i]) continue;
+      const KState& k = P->ks_host[i];
+      total[i] += k.iter;
+      loc[i].applies += 2 * k.iter + 1;
+      loc[i].rrel_hist_last = k.bnorm2 > 0 ? std::sqrt(k.rnorm2 / k.bnorm2) : 0.0;
+      loc[i].restarts = outer[i] + 1;
+      run_done[i] = k.done;
     }
-    rrel = std::sqrt(rr2 / bnorm2);
-    if (rr.done == 3 && rrel > tol && outer >= kMaxRestarts) status = PSFD_BREAKDOWN;
+    CHKS(true_residual(P, b, E, r64, adjoint));
+    for (int i = 0; i < G; ++i) {
+      if (fin[i]) continue;
+      const double rr2 = P->ks_host[i].red[0];
+      if (!std::isfinite(rr2)) {
+        status[i] = PSFD_BREAKDOWN;
+        rrel[i] = rr2;
+        fin[i] = 1;
+        continue;
+      }
+      rrel[i] = std::sqrt(rr2 / bn2[i]);
+      rn[i] = std::sqrt(rr2);
+      if (run_done[i] == 3 && rrel[i] > tol && outer[i] >= kMaxRestarts) status[i] = PSFD_BREAKDOWN;
+      outer[i] += 1;
+    }
   }
-  loc.iters = total;
-  loc.rrel_true = rrel;
-  loc.status = status;
-  if (info) *info = loc;
-  if (status != PSFD_OK)
-    return fail(status, "solve stopped at relative residual " + std::to_string(rrel));
+  for (int i = 0; i < G; ++i) {
+    loc[i].iters = total[i];
+    loc[i].rrel_true = rrel[i];
+    loc[i].status = status[i];
+    if (infos) infos[i] = loc[i];
+  }
+  if (G == 1 && status[0] != PSFD_OK)
+    return fail(status[0], "solve stopped at relative residual " + std::to_string(rrel[0]));
   return PSFD_OK;
 }
 
-psfd_status set_eps_impl(struct psfd_plan* P, const void* eps) {
-  const int n = P->nabs * P->nx * P->ny;
-  CHK(launch_eps_contrast(static_cast<const cplx<double>*>(eps), n, P->k0, P->d.eps_bg, P->kd64,
-                          P->kd32, P->st));
+psfd_status set_eps_impl(struct psfd_plan* P, const void* const* eps) {
+  const int64_t n = (int64_t)P->nabs * P->nx * P->ny;
+  for (int i = 0; i < P->G; ++i)
+    CHK(launch_eps_contrast(static_cast<const cplx<double>*>(eps[i]), (int)n, P->k0, P->d.eps_bg,
+                            P->kd64 + i * n, P->kd32 ? P->kd32 + i * n : nullptr, P->st));
   CHK(hipStreamSynchronize(P->st));
   return PSFD_OK;
 }
 
-psfd_status plan_impl(const psfd_desc* d, const void* eps, void* stream, struct psfd_plan** out) {
-  CHKS(validate(d));
-  if (!eps || !out) return fail(PSFD_ERR_ARG, "eps and out must not be NULL");
+psfd_status plan_group_impl(int G, const psfd_desc* descs, const void* const* eps, void* stream,
+                            struct psfd_plan** out) {
+  if (G < 1 || !descs || !eps || !out) return fail(PSFD_ERR_ARG, "NULL argument");
+  for (int i = 0; i < G; ++i) {
+    CHKS(validate(&descs[i]));
+    if (!eps[i]) return fail(PSFD_ERR_ARG, "eps must not be NULL");
+    if (i > 0 && !same_group(descs[0], descs[i]))
+      return fail(PSFD_ERR_ARG, "problems of a group must share everything but angle, "
+                                "polarisation and permittivity");
+  }
+  const psfd_desc* d = &descs[0];
   struct psfd_plan* P = new (std::nothrow) struct psfd_plan();
   if (!P) return fail(PSFD_ERR_ALLOC, "host allocation failed");
   struct Guard {
@@ -629,6 +775,7 @@ psfd_status plan_impl(const psfd_desc* d, const void* eps, void* stream, struct 
     ~Guard() { delete p; }
   } guard{P};
   P->d = *d;
+  P->G = G;
   P->st = static_cast<hipStream_t>(stream);
   P->prec = d->prec;
   P->use_pc = d->precond != 0;
@@ -647,13 +794,27 @@ psfd_status plan_impl(const psfd_desc* d, const void* eps, void* stream, struct 
   P->nspec = (int64_t)(3 * P->nz + 3 * P->nabs) * P->plane;
   P->k0 = kTwoPi / d->lambda;
   P->kbg = P->k0 * std::sqrt(d->eps_bg);
-  P->kx0 = P->kbg * std::sin(d->theta) * std::cos(d->phi);
-  P->ky0 = P->kbg * std::sin(d->theta) * std::sin(d->phi);
-  P->kz0 = P->kbg * std::cos(d->theta);
+  P->prob.resize(G);
+  for (int i = 0; i < G; ++i) {
+    ProbInfo& q = P->prob[i];
+    q.theta = descs[i].theta;
+    q.phi = descs[i].phi;
+    q.pol = descs[i].pol;
+    q.kx0 = P->kbg * std::sin(q.theta) * std::cos(q.phi);
+    q.ky0 = P->kbg * std::sin(q.theta) * std::sin(q.phi);
+    q.kz0 = P->kbg * std::cos(q.theta);
+  }
 
-  std::vector<double> kx(P->nx), ky(P->ny), kz(P->nz), zabs(P->nabs);
-  for (int m = 0; m < P->nx; ++m) kx[m] = P->kx0 + kTwoPi * (fftfreq(m, P->nx) / (P->nx * d->dx));
-  for (int m = 0; m < P->ny; ++m) ky[m] = P->ky0 + kTwoPi * (fftfreq(m, P->ny) / (P->ny * d->dy));
+  std::vector<double> kx((size_t)G * P->nx), ky((size_t)G * P->ny), kz(P->nz), zabs(P->nabs);
+  std::vector<double> cphi(G), sphi(G);
+  for (int i = 0; i < G; ++i) {
+    for (int m = 0; m < P->nx; ++m)
+      kx[(size_t)i * P->nx + m] = P->prob[i].kx0 + kTwoPi * (fftfreq(m, P->nx) / (P->nx * d->dx));
+    for (int m = 0; m < P->ny; ++m)
+      ky[(size_t)i * P->ny + m] = P->prob[i].ky0 + kTwoPi * (fftfreq(m, P->ny) / (P->ny * d->dy));
+    cphi[i] = std::cos(P->prob[i].phi);
+    sphi[i] = std::sin(P->prob[i].phi);
+  }
   for (int m = 0; m < P->nz; ++m) kz[m] = kTwoPi * (fftfreq(m, P->nz) / (P->nz * d->dz));
   for (int j = 0; j < P->nabs; ++j) zabs[j] = (j + 0.5) * d->dz;
   std::vector<cplx<double>> inv_s(P->nz);
@@ -670,7 +831,8 @@ psfd_status plan_impl(const psfd_desc* d, const void* eps, void* stream, struct 
 
   OpTables<double>& t = P->t64;
   t.nx = P->nx; t.ny = P->ny; t.nz = P->nz; t.nabs = P->nabs; t.j0 = P->j0; t.jev = P->jev;
-  double *kx_d, *ky_d, *kz_d;
+  t.nprob = G; t.pfield = P->nfield; t.pspec = P->nspec;
+  double *kx_d, *ky_d, *kz_d, *cphi_d, *sphi_d;
   cplx<double>*is_d, *twx_d, *twy_d, *twz_d;
   CHKS(upload(P, &kx_d, kx));
   CHKS(upload(P, &ky_d, ky));
@@ -680,14 +842,15 @@ psfd_status plan_impl(const psfd_desc* d, const void* eps, void* stream, struct 
   CHKS(upload(P, &twx_d, twx));
   CHKS(upload(P, &twy_d, twy));
   CHKS(upload(P, &twz_d, twz));
+  CHKS(upload(P, &cphi_d, cphi));
+  CHKS(upload(P, &sphi_d, sphi));
   t.kx = kx_d; t.ky = ky_d; t.kz = kz_d; t.inv_s = is_d; t.zabs = P->zabs64;
   t.tw_x = twx_d; t.tw_y = twy_d; t.tw_z = twz_d;
+  t.cphi = cphi_d; t.sphi = sphi_d;
   t.kbg2 = P->kbg * P->kbg;
   t.k0 = P->k0;
   t.kz_live = std::max(d->ml_kz_min, 1e-9) * P->k0;
   t.dz = d->dz;
-  t.cphi = std::cos(d->phi);
-  t.sphi = std::sin(d->phi);
   const double kref = d->pc_kref > 0 ? d->pc_kref : P->kbg;
   t.pc_mmin = d->pc_mmin;
   t.pc_kref2 = kref * kref;
@@ -696,48 +859,53 @@ psfd_status plan_impl(const psfd_desc* d, const void* eps, void* stream, struct 
   t.pc_bf16 = d->prec == PSFD_C64_BF16PC_REFINE64;
   t.ax_lds = std::getenv("PSFD_AXIAL_LDS") != nullptr;
 
-  // multilayer reflections per lateral mode
-  CHKS(dalloc(P, &P->rte64, (size_t)P->plane));
-  CHKS(dalloc(P, &P->rpe64, (size_t)P->plane));
+  // multilayer reflections per lateral mode, per problem
+  CHKS(dalloc(P, &P->rte64, (size_t)(P->plane * G)));
+  CHKS(dalloc(P, &P->rpe64, (size_t)(P->plane * G)));
   cplx<double>* ml_eps_d = nullptr;
   double* ml_d_d = nullptr;
   std::vector<cplx<double>> mle(d->n_ml);
   for (int i = 0; i < d->n_ml; ++i) mle[i] = {P->ml_eps_h[2 * i], P->ml_eps_h[2 * i + 1]};
   CHKS(upload(P, &ml_eps_d, mle));
   CHKS(upload(P, &ml_d_d, P->ml_d_h));
-  TmmArgs ta{P->nx, P->ny, kx_d, ky_d, P->k0, d->eps_bg, d->n_ml, ml_eps_d, ml_d_d,
-             cplx<double>{d->eps_sub[0], d->eps_sub[1]}};
-  CHK(launch_tmm(ta, P->rte64, P->rpe64, P->st));
+  for (int i = 0; i < G; ++i) {
+    TmmArgs ta{P->nx, P->ny, kx_d + (int64_t)i * P->nx, ky_d + (int64_t)i * P->ny, P->k0,
+               d->eps_bg, d->n_ml, ml_eps_d, ml_d_d, cplx<double>{d->eps_sub[0], d->eps_sub[1]}};
+    CHK(launch_tmm(ta, P->rte64 + i * P->plane, P->rpe64 + i * P->plane, P->st));
+  }
   t.r_te = P->rte64;
   t.r_pe = P->rpe64;
 
-  CHKS(dalloc(P, &P->kd64, (size_t)P->nabs * P->plane));
+  CHKS(dalloc(P, &P->kd64, (size_t)((int64_t)P->nabs * P->plane * G)));
   t.kd = P->kd64;
-  CHKS(dalloc(P, &P->S64, (size_t)P->nspec));
-  CHKS(dalloc(P, &P->UW64, (size_t)P->nspec));
+  CHKS(dalloc(P, &P->S64, (size_t)(P->nspec * G)));
+  CHKS(dalloc(P, &P->UW64, (size_t)(P->nspec * G)));
 
   if (P->prec != PSFD_C128) {
     OpTables<float>& f = P->t32;
     f.nx = t.nx; f.ny = t.ny; f.nz = t.nz; f.nabs = t.nabs; f.j0 = t.j0; f.jev = t.jev;
-    float *fkx, *fky, *fkz, *fza;
+    f.nprob = G; f.pfield = t.pfield; f.pspec = t.pspec;
+    float *fkx, *fky, *fkz, *fza, *fcp, *fsp;
     cplx<float>*fis, *ftx, *fty, *ftz, *frte, *frpe;
     CHKS(upload(P, &fkx, to_t<float>(kx)));
     CHKS(upload(P, &fky, to_t<float>(ky)));
     CHKS(upload(P, &fkz, to_t<float>(kz)));
     CHKS(upload(P, &fza, to_t<float>(zabs)));
+    CHKS(upload(P, &fcp, to_t<float>(cphi)));
+    CHKS(upload(P, &fsp, to_t<float>(sphi)));
     CHKS(upload(P, &fis, to_tc<float>(inv_s)));
     CHKS(upload(P, &ftx, to_tc<float>(twx)));
     CHKS(upload(P, &fty, to_tc<float>(twy)));
     CHKS(upload(P, &ftz, to_tc<float>(twz)));
-    CHKS(dalloc(P, &frte, (size_t)P->plane));
-    CHKS(dalloc(P, &frpe, (size_t)P->plane));
-    CHK(launch_k_scale_copy<float, double>(frte, P->rte64, 1.0, P->plane, P->st));
-    CHK(launch_k_scale_copy<float, double>(frpe, P->rpe64, 1.0, P->plane, P->st));
-    CHKS(dalloc(P, &P->kd32, (size_t)P->nabs * P->plane));
+    CHKS(dalloc(P, &frte, (size_t)(P->plane * G)));
+    CHKS(dalloc(P, &frpe, (size_t)(P->plane * G)));
+    CHK(launch_k_scale_copy<float, double>(frte, P->rte64, nullptr, P->plane, G, P->st));
+    CHK(launch_k_scale_copy<float, double>(frpe, P->rpe64, nullptr, P->plane, G, P->st));
+    CHKS(dalloc(P, &P->kd32, (size_t)((int64_t)P->nabs * P->plane * G)));
     f.kx = fkx; f.ky = fky; f.kz = fkz; f.zabs = fza; f.inv_s = fis;
     f.tw_x = ftx; f.tw_y = fty; f.tw_z = ftz; f.r_te = frte; f.r_pe = frpe; f.kd = P->kd32;
+    f.cphi = fcp; f.sphi = fsp;
     f.kbg2 = (float)t.kbg2; f.k0 = (float)t.k0; f.dz = (float)t.dz; f.kz_live = (float)t.kz_live;
-    f.cphi = (float)t.cphi; f.sphi = (float)t.sphi;
     f.pc_mmin = (float)t.pc_mmin; f.pc_kref2 = (float)t.pc_kref2;
     f.pc_gamma = (float)t.pc_gamma; f.pc_reg = (float)t.pc_reg; f.pc_bf16 = t.pc_bf16;
     f.ax_lds = t.ax_lds;
@@ -751,6 +919,11 @@ psfd_status plan_impl(const psfd_desc* d, const void* eps, void* stream, struct 
   guard.p = nullptr;
   *out = P;
   return PSFD_OK;
+}
+
+psfd_status plan_impl(const psfd_desc* d, const void* eps, void* stream, struct psfd_plan** out) {
+  const void* e[1] = {eps};
+  return plan_group_impl(1, d, e, stream, out);
 }
 
 psfd_status layout_impl(const psfd_desc* d, const double* a_bin, const double eps_abs[2],
@@ -788,10 +961,10 @@ psfd_status apply_entry(struct psfd_plan* P, const void* x, void* y, int op) {
   if (!P || !x || !y) return fail(PSFD_ERR_ARG, "NULL argument");
   if (P->is_batch) return fail(PSFD_ERR_ARG, "a batch handle only serves psfd_solve_batch");
   if (x == y) return fail(PSFD_ERR_ARG, "x and y must not overlap");
-  if (sizeof(T) == 4) CHKS(ensure_fp32(P));
   if (sizeof(T) == 4 && !P->t32.kx)
     return fail(PSFD_ERR_ARG, "complex64 entry points need a PSFD_C64_* plan");
-  CHK(op_apply<T>(P, static_cast<const cplx<T>*>(x), static_cast<cplx<T>*>(y), op, nullptr));
+  if (sizeof(T) == 4) CHKS(ensure_fp32(P));
+  CHK(op_apply<T>(P, static_cast<const cplx<T>*>(x), static_cast<cplx<T>*>(y), op, nullptr, 0));
   return PSFD_OK;
 }
 
@@ -834,6 +1007,10 @@ psfd_status plan_batch_impl(int n, const psfd_desc* descs, const void* const* ep
   return PSFD_OK;
 }
 
+// Problems are grouped (same shape and shared parameters, at most
+// kGroupVoxels voxels and kGroupMax problems per group, largest first); each
+// group is one plan whose launches cover all its members.  Groups run on
+// PSFD_BATCH_WORKERS host threads (default 2), each with its own stream.
 psfd_status solve_batch_impl(struct psfd_plan* B, const void* const* x0, void* const* E, double tol,
                              int maxit, psfd_info* infos) {
   if (!B || !B->is_batch || !E || !infos) return fail(PSFD_ERR_ARG, "bad batch arguments");
@@ -843,17 +1020,39 @@ psfd_status solve_batch_impl(struct psfd_plan* B, const void* const* x0, void* c
   CHK(B->st ? hipStreamSynchronize(B->st) : hipDeviceSynchronize());
   int dev = 0;
   CHK(hipGetDevice(&dev));
-  // largest problems first, for load balance
-  std::vector<int> order(n);
-  for (int i = 0; i < n; ++i) order[i] = i;
-  auto size_of = [&](int i) {
+  auto voxels = [&](int i) {
     const psfd_desc& d = B->bdesc[i];
     return (int64_t)d.nx * d.ny * (d.nz_abs + d.nz_gap_bot + d.nz_gap_top + 2 * d.nz_pml);
   };
-  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return size_of(a) > size_of(b); });
-  int workers = 4;
+  std::vector<int> order(n);
+  for (int i = 0; i < n; ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return voxels(a) > voxels(b); });
+  int64_t max_vox = (int64_t)1 << 26;
+  if (const char* v = std::getenv("PSFD_GROUP_VOXELS")) max_vox = std::max<int64_t>(1, std::atoll(v));
+  int max_g = 256;
+  if (const char* v = std::getenv("PSFD_GROUP_MAX")) max_g = std::max(1, std::atoi(v));
+  std::vector<std::vector<int>> groups;
+  std::vector<int64_t> gvox;
+  for (int i : order) {
+    int at = -1;
+    for (size_t g = 0; g < groups.size(); ++g) {
+      if ((int)groups[g].size() < max_g && gvox[g] + voxels(i) <= max_vox &&
+          same_group(B->bdesc[groups[g][0]], B->bdesc[i])) {
+        at = (int)g;
+        break;
+      }
+    }
+    if (at < 0) {
+      groups.emplace_back();
+      gvox.push_back(0);
+      at = (int)groups.size() - 1;
+    }
+    groups[at].push_back(i);
+    gvox[at] += voxels(i);
+  }
+  int workers = 2;
   if (const char* w = std::getenv("PSFD_BATCH_WORKERS")) workers = std::max(1, std::atoi(w));
-  workers = std::min(workers, n);
+  workers = std::min<int>(workers, (int)groups.size());
   std::vector<psfd_status> status(n, PSFD_OK);
   std::vector<std::string> errs(n);
   std::atomic<int> next(0);
@@ -861,21 +1060,48 @@ psfd_status solve_batch_impl(struct psfd_plan* B, const void* const* x0, void* c
     if (hipSetDevice(dev) != hipSuccess) return;
     hipStream_t ws = nullptr;
     if (hipStreamCreateWithFlags(&ws, hipStreamNonBlocking) != hipSuccess) ws = nullptr;
-    for (int k = next++; k < n; k = next++) {
-      const int i = order[k];
-      infos[i] = psfd_info{};
+    for (int k = next++; k < (int)groups.size(); k = next++) {
+      const std::vector<int>& mem = groups[k];
+      const int G = (int)mem.size();
+      std::vector<psfd_desc> ds(G);
+      std::vector<const void*> es(G);
+      for (int j = 0; j < G; ++j) {
+        ds[j] = B->bdesc[mem[j]];
+        es[j] = B->beps[mem[j]];
+      }
+      std::vector<psfd_info> inf(G);
       struct psfd_plan* p = nullptr;
-      psfd_status st = guarded([&] { return plan_impl(&B->bdesc[i], B->beps[i], ws, &p); });
+      psfd_status st = guarded([&] { return plan_group_impl(G, ds.data(), es.data(), ws, &p); });
       if (st == PSFD_OK) {
-        st = guarded([&] {
-          return solve_impl(p, nullptr, x0 ? x0[i] : nullptr, E[i], tol, maxit, false, &infos[i]);
+        st = guarded([&]() -> psfd_status {
+          CHKS(dalloc(p, &p->E64, (size_t)(p->nfield * G)));
+          const size_t fb = sizeof(cplx<double>) * (size_t)p->nfield;
+          if (x0) {
+            for (int j = 0; j < G; ++j) {
+              if (x0[mem[j]]) CHK(hipMemcpyAsync(p->E64 + j * p->nfield, x0[mem[j]], fb,
+                                                 hipMemcpyDeviceToDevice, ws));
+              else CHK(hipMemsetAsync(p->E64 + j * p->nfield, 0, fb, ws));
+            }
+          }
+          CHKS(solve_impl(p, nullptr, x0 ? p->E64 : nullptr, p->E64, tol, maxit, false, inf.data()));
+          for (int j = 0; j < G; ++j)
+            CHK(hipMemcpyAsync(E[mem[j]], p->E64 + j * p->nfield, fb, hipMemcpyDeviceToDevice, ws));
+          CHK(hipStreamSynchronize(ws));
+          return PSFD_OK;
         });
       }
-      if (st != PSFD_OK) {
-        errs[i] = g_err;
-        infos[i].status = st;
+      for (int j = 0; j < G; ++j) {
+        const int i = mem[j];
+        infos[i] = inf[j];
+        if (st != PSFD_OK) {
+          errs[i] = g_err;
+          infos[i].status = st;
+          status[i] = st;
+        } else if (inf[j].status != PSFD_OK) {
+          status[i] = (psfd_status)inf[j].status;
+          errs[i] = "stopped at relative residual " + std::to_string(inf[j].rrel_true);
+        }
       }
-      status[i] = st;
       delete p;
     }
     if (ws) (void)hipStreamDestroy(ws);
@@ -904,17 +1130,13 @@ psfd_status psfd_plan(const psfd_desc* d, const void* eps_abs_dev, void* hip_str
 
 psfd_status psfd_set_eps(psfd_plan_t p, const void* eps_abs_dev) {
   if (!p || !eps_abs_dev || p->is_batch) return fail(PSFD_ERR_ARG, "NULL argument");
-  return guarded([&] { return set_eps_impl(p, eps_abs_dev); });
+  const void* e[1] = {eps_abs_dev};
+  return guarded([&] { return set_eps_impl(p, e); });
 }
 
 psfd_status psfd_rhs(psfd_plan_t p, void* b) {
   if (!p || !b || p->is_batch) return fail(PSFD_ERR_ARG, "NULL argument");
-  return guarded([&]() -> psfd_status {
-    RhsArgs a{p->nx, p->ny, p->nz, p->nabs, p->j0, p->d.pol, p->k0, p->kz0, p->d.theta, p->d.phi,
-              p->zabs64, p->rte64, p->rpe64, p->kd64};
-    CHK(launch_rhs<double>(a, static_cast<cplx<double>*>(b), p->st));
-    return PSFD_OK;
-  });
+  return guarded([&] { return rhs_group(p, static_cast<cplx<double>*>(b)); });
 }
 
 psfd_status psfd_apply(psfd_plan_t p, const void* x, void* y) {
@@ -951,15 +1173,14 @@ psfd_status psfd_residual(psfd_plan_t p, const void* b, const void* E, void* r, 
     CHKS(ensure_solver_common(p));
     const cplx<double>* bb = static_cast<const cplx<double>*>(b);
     if (!bb) {
-      RhsArgs a{p->nx, p->ny, p->nz, p->nabs, p->j0, p->d.pol, p->k0, p->kz0, p->d.theta,
-                p->d.phi, p->zabs64, p->rte64, p->rpe64, p->kd64};
-      CHK(launch_rhs<double>(a, p->b64, p->st));
+      CHKS(rhs_group(p, p->b64));
       bb = p->b64;
     }
-    double rr2 = 0.0;
+    p->idle_host[0] = 0;
+    CHKS(push_params(p));
     CHKS(true_residual(p, bb, static_cast<const cplx<double>*>(E), static_cast<cplx<double>*>(r),
-                       false, &rr2));
-    if (norm2) *norm2 = rr2;
+                       false));
+    if (norm2) *norm2 = p->ks_host[0].red[0];
     return PSFD_OK;
   });
 }
@@ -981,9 +1202,7 @@ psfd_status psfd_eps_grad(psfd_plan_t p, const void* E, const void* u, double sc
     cplx<double>* Wp = UW + (int64_t)p3 * p->plane;
     CHK(launch_yfft<double>(t, Wp, pa, true, p->st));
     CHK(launch_xfft_inv_rows<double>(t, Wp, Wr, (int64_t)pa * p->ny, p->st));
-    RhsArgs a{p->nx, p->ny, p->nz, p->nabs, p->j0, p->d.pol, p->k0, p->kz0, p->d.theta,
-              p->d.phi, p->zabs64, p->rte64, p->rpe64, p->kd64};
-    CHK(launch_eps_grad(a, Wr, static_cast<const cplx<double>*>(u), scale,
+    CHK(launch_eps_grad(rhs_args(p, 0), Wr, static_cast<const cplx<double>*>(u), scale,
                         static_cast<cplx<double>*>(grad), p->st));
     return PSFD_OK;
   });

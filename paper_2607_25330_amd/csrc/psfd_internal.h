@@ -16,29 +16,44 @@ bool axial_size_ok(int n);
 // Grid geometry and per-axis tables shared by the operator kernels.
 template <typename T>
 struct OpTables {
+  // A plan holds nprob problems of one shape ("group"); fields are stacked
+  // [nprob][3][nz][ny][nx] and spectral workspaces [nprob][3 nz + 3 nabs][ny][nx].
+  // Launches cover the whole group; no block straddles two problems.
   int nx, ny, nz, nabs, j0, jev;
-  const T* kx;              // [nx] Bloch-shifted lateral wavenumbers
-  const T* ky;              // [ny]
+  int nprob;
+  int64_t pfield;           // elements of one problem's field
+  int64_t pspec;            // elements of one problem's spectral workspace
+  const T* kx;              // [nprob][nx] Bloch-shifted lateral wavenumbers
+  const T* ky;              // [nprob][ny]
   const T* kz;              // [nz] axial wavenumbers (fftfreq order)
   const cplx<T>* inv_s;     // [nz] 1 / s(z), PML stretch
   const T* zabs;            // [nabs] z of the absorber row centres (z_ml = 0)
-  const cplx<T>* r_te;      // [ny][nx] multilayer reflection, TE
-  const cplx<T>* r_pe;      // [ny][nx] multilayer reflection, TM (tangential E)
-  const cplx<T>* kd;        // [nabs][ny][nx] k0^2 (eps - eps_bg)
+  const cplx<T>* r_te;      // [nprob][ny][nx] multilayer reflection, TE
+  const cplx<T>* r_pe;      // [nprob][ny][nx] multilayer reflection, TM (tangential E)
+  const cplx<T>* kd;        // [nprob][nabs][ny][nx] k0^2 (eps - eps_bg)
   const cplx<T>* tw_x;      // twiddles exp(-2 pi i m / nx)
   const cplx<T>* tw_y;
   const cplx<T>* tw_z;
+  const T* cphi;            // [nprob] incidence-plane basis at kt = 0
+  const T* sphi;
   T kbg2;                   // (k0 sqrt(eps_bg))^2
   T k0;
   T kz_live;                // |kz| below this (absolute) gets no multilayer response
   T dz;
-  T cphi, sphi;             // incidence-plane basis at kt = 0
   // spectral damping multiplier m(k)
   T pc_mmin, pc_kref2, pc_gamma, pc_reg;
   int pc_bf16;              // round m(k) to bfloat16
   int ax_lds;               // 1: always use the LDS-staged axial kernel
-  const int* skip;          // device flag: when non-null and set, operator kernels return at once
+  // per-problem skip flags: when non-null and skip[b * skip_stride] != 0 the
+  // operator kernels return at once for problem b
+  const int* skip;
+  int skip_stride;
 };
+
+template <typename T>
+__host__ __device__ __forceinline__ bool skipped(const OpTables<T>& t, int b) {
+  return t.skip && t.skip[(int64_t)b * t.skip_stride] != 0;
+}
 
 enum AxialMode { AX_A = 0, AX_AM = 1, AX_AH = 2, AX_M = 3 };
 enum CombineMode { CB_PLAIN = 0, CB_FWD = 1, CB_ADJ = 2 };
@@ -143,40 +158,55 @@ struct KState {
   double snorm2, rnorm2, bnorm2, tol2, rh_norm2;
   double red[4];        // generic reduction outputs
   int iter, done, status, half;
+  int itmax, pad;
 };
 
 constexpr int KRED_THREADS = 256;
-int red_blocks(int64_t n);  // grid of the streaming vector kernels
+int red_blocks(int64_t n, int nprob);  // blocks per problem of the streaming vector kernels
+
+// Per-problem scalars set by the host between Krylov runs.
+struct ProbParams {
+  double bnorm2;  // ||b||^2 of the system the run solves
+  double tol2;    // squared relative stopping tolerance; < 0: problem idle (skipped)
+  double scale;   // y += scale * x (refinement update)
+  double iscale;  // y = iscale * x (normalised residual)
+  double itmax;   // iteration budget of the run
+  double pad[3];
+};
 
 enum FinStage { FIN_INIT = 0, FIN_ALPHA, FIN_SNORM, FIN_OMEGA, FIN_RHO, FIN_RED0 };
-// Sum `nblocks` partials and update the scalars for one stage of the recurrence.
-hipError_t launch_finalize(int stage, KState* ks, const double* part, int nblocks, double a0,
-                           double a1, hipStream_t st);
+// One block per problem: sum problem b's `nblocks` partials (they start at
+// part + b * nblocks * KPART) and update ks[b] for one stage of the recurrence.
+hipError_t launch_finalize(int stage, KState* ks, const double* part, int nblocks, int nprob,
+                           const ProbParams* pp, hipStream_t st);
 
+// Streaming vector kernels over a group: n = elements of one problem; problem
+// b's vectors start at b * n; grid = nprob * red_blocks(n) blocks.
 template <typename T>
 hipError_t launch_k_xr_update(cplx<T>* y, cplx<T>* r, const cplx<T>* p, const cplx<T>* s,
-                              const cplx<T>* t, const cplx<T>* rh, int64_t n, const KState* ks,
-                              double* part, hipStream_t st);
+                              const cplx<T>* t, const cplx<T>* rh, int64_t n, int nprob,
+                              const KState* ks, double* part, hipStream_t st);
 template <typename T>
 hipError_t launch_k_p_update(cplx<T>* p, const cplx<T>* r, const cplx<T>* v, int64_t n,
-                             const KState* ks, hipStream_t st);
+                             int nprob, const KState* ks, hipStream_t st);
 // Start a BiCGSTAB run: rh = r, p = v = y = 0, partials ||r||^2 (then FIN_INIT).
 template <typename T>
 hipError_t launch_k_init(cplx<T>* rh, const cplx<T>* r, cplx<T>* p, cplx<T>* v, cplx<T>* y,
-                         int64_t n, double* part, hipStream_t st);
+                         int64_t n, int nprob, double* part, hipStream_t st);
 // out = a - b, partials ||out||^2 (then FIN_RED0)
 template <typename T>
 hipError_t launch_k_residual(cplx<T>* out, const cplx<T>* a, const cplx<T>* b, int64_t n,
-                             double* part, hipStream_t st);
+                             int nprob, double* part, hipStream_t st);
 // partials ||a||^2 (then FIN_RED0)
 template <typename T>
-hipError_t launch_k_norm2(const cplx<T>* a, int64_t n, double* part, hipStream_t st);
-// y += a * x with a a real scalar held on the host
+hipError_t launch_k_norm2(const cplx<T>* a, int64_t n, int nprob, double* part, hipStream_t st);
+// y += scale_b * x for problem b (scale from pp[b].scale)
 template <typename TY, typename TX>
-hipError_t launch_k_axpy(cplx<TY>* y, const cplx<TX>* x, double a, int64_t n, hipStream_t st);
-// y = a * x (precision conversion with scaling)
+hipError_t launch_k_axpy(cplx<TY>* y, const cplx<TX>* x, const ProbParams* pp, int64_t n,
+                         int nprob, hipStream_t st);
+// y = scale_b * x (precision conversion with scaling; pp == nullptr: scale 1)
 template <typename TY, typename TX>
-hipError_t launch_k_scale_copy(cplx<TY>* y, const cplx<TX>* x, double a, int64_t n,
-                               hipStream_t st);
+hipError_t launch_k_scale_copy(cplx<TY>* y, const cplx<TX>* x, const ProbParams* pp, int64_t n,
+                               int nprob, hipStream_t st);
 
 }  // namespace psfd

@@ -65,6 +65,49 @@ def test_batch_matches_individual_solves(psfd, prec):
         assert torch.equal(E_b[i], E_i)
 
 
+@pytest.mark.parametrize("prec", [0, 1])
+def test_group_of_same_shape_problems_matches_individual_solves(psfd, prec):
+    """Six 32x32x(16+16) problems (different angles, polarisations and
+    permittivities, one with a warm start) share one group plan: every launch
+    covers all six, each keeps its own Krylov scalars and stops on its own.
+    Up to 16 problems a group uses the same per-problem block decomposition
+    as a single solve, so the results are bit-identical."""
+    thetas = [0.0, 2.5, 5.0, 7.5, 10.0, 6.0]
+    cfgs = [dict(base_config(32, 32, 16, 30.0, theta_deg=th, phi_deg=15.0 * i, pol=i % 2),
+                 ml_kz_min=0.1) for i, th in enumerate(thetas)]
+    cfgs += [dict(base_config(16, 16, 8, 15.0, theta_deg=4.0, pol=p), ml_kz_min=0.1) for p in (0, 1)]
+    eps = [dev(_eps(c, 40 + i)) for i, c in enumerate(cfgs)]
+    x0 = [None] * len(cfgs)
+    x0[3] = dev(0.02 * random_field((3, 32, 32, 32), np.random.default_rng(3)))
+    batch = psfd.Batch(cfgs, eps, prec=prec)
+    E_b, infos = batch.solve(x0=x0, tol=1e-9)
+    batch.close()
+    iters = set()
+    for i, c in enumerate(cfgs):
+        plan = psfd.Plan(c, eps[i], prec=prec)
+        E_i, info = plan.solve(tol=1e-9, x0=x0[i])
+        plan.close()
+        assert infos[i]["status"] == "OK" and infos[i]["iters"] == info["iters"]
+        assert infos[i]["rrel"] == info["rrel"]
+        assert torch.equal(E_b[i], E_i)
+        iters.add(info["iters"])
+    assert len(iters) > 1  # the members really stopped at different iterations
+
+
+def test_group_budget_per_problem(psfd):
+    """A budget smaller than any member needs stops every member of the group
+    at that budget with NOT_CONVERGED, reported per problem."""
+    cfgs = [dict(base_config(32, 32, 16, 30.0, theta_deg=th, pol=0), ml_kz_min=0.1)
+            for th in (0.0, 5.0, 10.0)]
+    eps = [dev(_eps(c, 60 + i)) for i, c in enumerate(cfgs)]
+    batch = psfd.Batch(cfgs, eps, prec=psfd.PSFD_C128)
+    E_b, infos = batch.solve(tol=1e-12, maxit=7, check=False)
+    batch.close()
+    for inf in infos:
+        assert inf["status"] == "NOT_CONVERGED" and inf["iters"] == 7
+        assert 0 < inf["rrel"] < 1
+
+
 def test_residual_and_eps_grad_match_oracle(psfd):
     cfg = base_config(32, 16, 8, 15.0, theta_deg=6.0, phi_deg=20.0, pol=1, dy=2.5)
     eps = _eps(cfg, 3)
