@@ -193,7 +193,7 @@ def workload_c3(psfd, args):
                                    "{64,128,192,256}^2, Nz 48, x 5 angles (0-10 deg) x TE/TM, "
                                    "mixed precision, tol %g, batched" % args.tol,
                        "solves": len(cfgs), "voxels": vox,
-                       "workers": int(os.environ.get("PSFD_BATCH_WORKERS", "4"))},
+                       "workers": int(os.environ.get("PSFD_BATCH_WORKERS", "2"))},
             "iters_mean": round(sum(i["iters"] for i in infos) / len(infos), 1),
             "iters_max": max(i["iters"] for i in infos),
             "converged": sum(i["status"] == "OK" for i in infos)}
@@ -305,6 +305,8 @@ def main():
     ap.add_argument("--maxit", type=int, default=20000)
     ap.add_argument("--roofline-kernel", default="xinv", choices=["axial", "yfft", "xfwd", "xinv"])
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 leg")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="default kernel schedules instead of the autotuner's (psfd_tune)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-iters", type=int, default=4)
     ap.add_argument("--cpu-leg", type=float, default=None, help=argparse.SUPPRESS)
@@ -325,6 +327,9 @@ def main():
               "Run with --gpus 1.", file=sys.stderr)
         return 2
 
+    if not args.no_tune:
+        # plans pick up the autotuner's schedules (tuned once per shape, before timing)
+        os.environ["PSFD_TUNE"] = "1"
     import torch
     import paper_2607_25330_amd as psfd
     from psfd_synth import config_c2
@@ -355,6 +360,16 @@ def main():
         del src, dst
 
     prec_mixed = psfd.PSFD_C64_REFINE64
+    schedules = {}
+    if not args.no_tune:
+        from psfd_synth import eps_absorber_default
+        eps0 = psfd.psfd_layout_eps(cfgs[0], a_dev[0], eps_absorber_default())
+        for name, prec in (("mixed", prec_mixed), ("fp64", psfd.PSFD_C128)):
+            plan = psfd.Plan(cfgs[0], eps0, prec)
+            schedules[name] = list(plan.tune())
+            plan.close()
+        del eps0
+        torch.cuda.synchronize()
     if W:
         run_steps(psfd, cfgs, a_dev, range(K, K + W), prec_mixed, args.tol, args.maxit)
         if not args.no_fp64:
@@ -401,6 +416,7 @@ def main():
         "iters_mixed": [i["iters"] for i in infos_m],
         "rrel_mixed_max": max(i["rrel"] for i in infos_m),
         "roofline": roofline,
+        "schedules": schedules or "default",
     }
     if "fp64" in res:
         t_fp64, infos_d = res["fp64"]

@@ -194,15 +194,20 @@ psfd_status psfd_eps_grad(psfd_plan_t p, const void* E, const void* u, double sc
  * stay valid until psfd_solve_batch returns.  The returned handle is only
  * usable with psfd_solve_batch and psfd_destroy.  psfd_solve_batch solves
  * every problem (source b = psfd_rhs of that problem, E_i = x0[i] + M y,
- * as psfd_solve) after the work queued on the batch's stream: problems run
- * largest first on a pool of host workers, each with its own non-blocking
- * stream, plan and captured iteration graphs, so that independent solves
- * overlap on the device.  x0 may be NULL (all zero) or hold NULL entries;
+ * as psfd_solve) after the work queued on the batch's stream.  Problems that
+ * share everything but angle, polarisation and permittivity are solved as
+ * one group (largest first, at most 2^26 voxels and 256 problems per group,
+ * PSFD_GROUP_VOXELS / PSFD_GROUP_MAX in the environment): every kernel launch
+ * covers the whole group, each problem keeps its own Krylov scalars and
+ * refinement and stops on its own, and a 16-iteration chunk of the group is
+ * captured once as a HIP graph and replayed.  Each group's kernel schedules
+ * come from the autotuner (psfd_tune; PSFD_TUNE=0 disables).  Groups run on a
+ * pool of PSFD_BATCH_WORKERS host threads (default 2), each with its own
+ * non-blocking stream.  x0 may be NULL (all zero) or hold NULL entries;
  * E[i] are device complex128 fields of problem i's shape; infos is a host
  * array of n entries (required).  Returns PSFD_OK when every problem
  * converged, else the status of the first failing problem (all problems
- * are attempted).  PSFD_BATCH_WORKERS (environment) sets the pool size
- * (default 4). */
+ * are attempted). */
 psfd_status psfd_plan_batch(int32_t n, const psfd_desc* descs, const void* const* eps_abs_dev,
                             void* hip_stream, psfd_plan_t* out);
 psfd_status psfd_solve_batch(psfd_plan_t batch, const void* const* x0, void* const* E, double tol,
@@ -225,6 +230,25 @@ psfd_status psfd_ml_reflection(psfd_plan_t p, void* r_te, void* r_pe);
  * must read and write once, at its element size). */
 psfd_status psfd_profile_enable(psfd_plan_t p, int32_t kernel);
 psfd_status psfd_profile_read(psfd_plan_t p, double* total_ms, int64_t* launches, double* bytes);
+
+/* Autotuner (not part of the method: it selects among equivalent kernel
+ * schedules).  psfd_tune times the plan's working-precision operator with
+ * each candidate schedule of one knob at a time -- radix schedule (radix 8 or
+ * radix 4 first) and rows per block of the forward and of the inverse x pass,
+ * radix schedule and tile width of the y pass, axial kernel variant
+ * (register-resident with L or 2L lanes per column, or LDS-staged) -- and
+ * keeps the fastest; results are cached per (precision, nx, ny, Nz, nz_abs,
+ * group size) for the life of the process.  Synchronises the plan's stream.
+ * Schedules change the rounding of the FFTs, never the operator.  A plan made
+ * by psfd_plan uses the default schedules unless psfd_tune is called or
+ * PSFD_TUNE=1 is set.  psfd_schedule writes the plan's current schedules to
+ * sched[4] (host): forward x pass, inverse x pass, y pass (bit 0: radix-4
+ * schedule, bit 1: half the rows / tile width), axial variant (0, 1, 2).
+ * psfd_set_schedule sets them (both precisions) from sched[4] (host; values
+ * 0..3, axial 0..2, else PSFD_ERR_ARG) after draining the plan's stream. */
+psfd_status psfd_tune(psfd_plan_t p);
+psfd_status psfd_schedule(psfd_plan_t p, int32_t* sched);
+psfd_status psfd_set_schedule(psfd_plan_t p, const int32_t* sched);
 
 /* Total number of complex elements of one field, 3 * Nz * ny * nx. */
 int64_t psfd_field_size(psfd_plan_t p);

@@ -473,21 +473,32 @@ constexpr int ax_lanes() {
   return l;
 }
 
+template <typename T, int NZ, int L>
+static hipError_t axial_reg_launch(const OpTables<T>& t, const cplx<T>* S, cplx<T>* UW, int mode,
+                                   hipStream_t st) {
+  const int64_t cols = (int64_t)t.nx * t.ny;
+  if ((cols * L) % 256) return hipErrorInvalidValue;
+  dim3 g((unsigned)(cols * L / 256 * t.nprob)), b(256);
+  switch (mode) {
+    case AX_A: hipLaunchKernelGGL((k_axial_reg<T, NZ, L, AX_A>), g, b, 0, st, S, UW, t); break;
+    case AX_AM: hipLaunchKernelGGL((k_axial_reg<T, NZ, L, AX_AM>), g, b, 0, st, S, UW, t); break;
+    default: hipLaunchKernelGGL((k_axial_reg<T, NZ, L, AX_M>), g, b, 0, st, S, UW, t); break;
+  }
+  return hipGetLastError();
+}
+
+// sched_ax: 0 register kernel (L lanes per column), 1 register kernel with
+// 2L lanes, 2 LDS-staged kernel.  The adjoint and Nz > 64 always use the LDS
+// kernel; PSFD_AXIAL_LDS forces it everywhere.
 template <typename T, int NZ>
 static hipError_t axial_n(const OpTables<T>& t, const cplx<T>* S, cplx<T>* UW, int mode,
                           hipStream_t st) {
   constexpr int L = ax_lanes<T, NZ>();
   if constexpr (L > 0) {
-    if (!t.ax_lds && mode != AX_AH) {
-      const int64_t cols = (int64_t)t.nx * t.ny;
-      if ((cols * L) % 256) return hipErrorInvalidValue;
-      dim3 g((unsigned)(cols * L / 256 * t.nprob)), b(256);
-      switch (mode) {
-        case AX_A: hipLaunchKernelGGL((k_axial_reg<T, NZ, L, AX_A>), g, b, 0, st, S, UW, t); break;
-        case AX_AM: hipLaunchKernelGGL((k_axial_reg<T, NZ, L, AX_AM>), g, b, 0, st, S, UW, t); break;
-        default: hipLaunchKernelGGL((k_axial_reg<T, NZ, L, AX_M>), g, b, 0, st, S, UW, t); break;
-      }
-      return hipGetLastError();
+    if (!t.ax_lds && mode != AX_AH && t.sched_ax != 2) {
+      constexpr int L2 = (2 * L <= 16 && NZ % (2 * L) == 0) ? 2 * L : L;
+      if (t.sched_ax == 1) return axial_reg_launch<T, NZ, L2>(t, S, UW, mode, st);
+      return axial_reg_launch<T, NZ, L>(t, S, UW, mode, st);
     }
   }
   constexpr int TX = ax_tile<T, NZ>();

@@ -7,6 +7,10 @@
 // writes output q to (j / NS) NS R + k + q NS; after the last pass the data
 // is in natural order (Stockham autosort, no bit reversal).
 //
+// Radix schedule S: 0 prefers radix 8 (fewest passes), 1 prefers radix 4
+// (fewer registers and shorter butterflies, one more LDS pass); factors of 3
+// always take radix-3 passes last.  The autotuner picks S per shape.
+//
 // Work split: every transform is handled by TPR = N / EPT threads, EPT being
 // the lcm of the pass radices, so each thread owns EPT elements in every
 // pass.  A pass loads all of a thread's inputs into registers, synchronises,
@@ -28,14 +32,17 @@ struct RadixPlan {
 constexpr int gcd_c(int a, int b) { return b == 0 ? a : gcd_c(b, a % b); }
 constexpr int lcm_c(int a, int b) { return a / gcd_c(a, b) * b; }
 
-constexpr RadixPlan make_radix_plan(int n) {
+constexpr RadixPlan make_radix_plan(int n, int sched = 0) {
   RadixPlan p{};
   p.n = n;
   int m = n, a = 0, b = 0;
   while (m % 2 == 0) { m /= 2; ++a; }
   while (m % 3 == 0) { m /= 3; ++b; }
   int n8 = a / 3, rem = a % 3, k = 0;
-  if (rem == 1 && n8 > 0) {
+  if (sched == 1) {
+    for (int i = 0; i < a / 2; ++i) p.r[k++] = 4;
+    if (a % 2) p.r[k++] = 2;
+  } else if (rem == 1 && n8 > 0) {
     for (int i = 0; i < n8 - 1; ++i) p.r[k++] = 8;
     p.r[k++] = 4;
     p.r[k++] = 4;
@@ -57,9 +64,9 @@ constexpr RadixPlan make_radix_plan(int n) {
   return p;
 }
 
-template <int N>
+template <int N, int S = 0>
 struct Radices {
-  static constexpr RadixPlan P = make_radix_plan(N);
+  static constexpr RadixPlan P = make_radix_plan(N, S);
   static constexpr int EPT = P.ept;
   static constexpr int TPR = N / P.ept;
 };
@@ -156,11 +163,11 @@ struct AddrVec {  // transform b = (vector, column): [vector][i][column]
 };
 
 // ---------------------------------------------------------------- one pass
-template <typename T, int N, int R, int NS, int NB, int NT, bool INV, bool BFAST, class Addr>
+template <typename T, int N, int R, int NS, int NB, int NT, bool INV, bool BFAST, int S, class Addr>
 __device__ __forceinline__ void stockham_pass(cplx<T>* s, const cplx<T>* __restrict__ tw,
                                               Addr addr, int tid) {
-  constexpr int EPT = Radices<N>::EPT;
-  constexpr int TPR = Radices<N>::TPR;
+  constexpr int EPT = Radices<N, S>::EPT;
+  constexpr int TPR = Radices<N, S>::TPR;
   constexpr int NW = NB * TPR;
   constexpr int WPT = (NW + NT - 1) / NT;
   constexpr int BPI = EPT / R;
@@ -211,14 +218,14 @@ __device__ __forceinline__ void stockham_pass(cplx<T>* s, const cplx<T>* __restr
   __syncthreads();
 }
 
-template <typename T, int N, int I, int NB, int NT, bool INV, bool BFAST, class Addr>
+template <typename T, int N, int I, int NB, int NT, bool INV, bool BFAST, int S, class Addr>
 __device__ __forceinline__ void stockham_passes(cplx<T>* s, const cplx<T>* __restrict__ tw,
                                                 Addr addr, int tid) {
-  if constexpr (I < Radices<N>::P.np) {
-    constexpr int R = Radices<N>::P.r[I];
-    constexpr int NS = Radices<N>::P.ns[I];
-    stockham_pass<T, N, R, NS, NB, NT, INV, BFAST>(s, tw, addr, tid);
-    stockham_passes<T, N, I + 1, NB, NT, INV, BFAST>(s, tw, addr, tid);
+  if constexpr (I < Radices<N, S>::P.np) {
+    constexpr int R = Radices<N, S>::P.r[I];
+    constexpr int NS = Radices<N, S>::P.ns[I];
+    stockham_pass<T, N, R, NS, NB, NT, INV, BFAST, S>(s, tw, addr, tid);
+    stockham_passes<T, N, I + 1, NB, NT, INV, BFAST, S>(s, tw, addr, tid);
   }
 }
 
@@ -227,10 +234,10 @@ __device__ __forceinline__ void stockham_passes(cplx<T>* s, const cplx<T>* __res
 // threads of the block (it synchronises).  BFAST: consecutive threads take
 // consecutive transforms (strided layouts) rather than consecutive
 // elements of one transform (contiguous rows).
-template <typename T, int N, int NB, int NT, bool INV, bool BFAST, class Addr>
+template <typename T, int N, int NB, int NT, bool INV, bool BFAST, int S = 0, class Addr>
 __device__ __forceinline__ void lds_fft(cplx<T>* s, const cplx<T>* __restrict__ tw, Addr addr,
                                         int tid) {
-  stockham_passes<T, N, 0, NB, NT, INV, BFAST>(s, tw, addr, tid);
+  stockham_passes<T, N, 0, NB, NT, INV, BFAST, S>(s, tw, addr, tid);
 }
 
 }  // namespace psfd

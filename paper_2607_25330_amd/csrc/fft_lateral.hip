@@ -23,24 +23,30 @@ bool lateral_size_ok(int n) {
 template <typename T>
 constexpr int x_elems() { return sizeof(T) == 8 ? 2048 : 4096; }
 
-template <typename T, int N>
+// Schedules (chosen per shape by the autotuner, default 0):
+//   x passes: bit 0 = radix schedule S, bit 1 = half the rows per block;
+//   y pass:   bit 0 = radix schedule S, bit 1 = half the tile width.
+template <typename T, int N, int HALF = 0, int S = 0>
 constexpr int x_rows() {
   int b = 1;
   while (2 * b * N <= x_elems<T>()) b *= 2;
-  return b;
+  return (HALF && b > 1 && (b / 2) * Radices<N, S>::TPR >= 64) ? b / 2 : b;
 }
 
 // rows per block of the inverse x pass: the combine needs a second buffer (W rows)
-template <typename T, int N, int CM>
+template <typename T, int N, int CM, int S = 0, int HALF = 0>
 constexpr int xinv_rows() {
-  constexpr int b = x_rows<T, N>();
-  return (CM == CB_FWD && b > 1 && (b / 2) * Radices<N>::TPR >= 64) ? b / 2 : b;
+  constexpr int b = x_rows<T, N, HALF, S>();
+  return (CM == CB_FWD && b > 1 && (b / 2) * Radices<N, S>::TPR >= 64) ? b / 2 : b;
 }
 
-template <typename T, int N>
+template <typename T, int N, int S = 0, int HALF = 0>
 constexpr int y_tile() {
   int tx = 65536 / (N * (int)sizeof(cplx<T>));
-  return tx > 16 ? 16 : tx;
+  if (tx > 16) tx = 16;
+  while (tx > 1 && tx * Radices<N, S>::TPR > 1024) tx /= 2;
+  if (HALF && tx > 1 && (tx / 2) * Radices<N, S>::TPR >= 64) tx /= 2;
+  return tx;
 }
 
 // ------------------------------------------------------------------ kernels
@@ -63,14 +69,14 @@ struct RowGroup {
 template <typename T>
 __device__ __forceinline__ cplx<double> ldks(const double* a) { return {a[0], a[1]}; }
 
-template <typename T, int N, int B, int PRE>
-__global__ void __launch_bounds__(B * Radices<N>::TPR)
+template <typename T, int N, int B, int PRE, int S>
+__global__ void __launch_bounds__((B * Radices<N, S>::TPR))
 k_xfft_fwd(const cplx<T>* __restrict__ in_all, cplx<T>* __restrict__ out_all,
            const cplx<T>* __restrict__ tw, const RowGroup g, int ny, int nz, int j0, int nabs,
            const cplx<T>* __restrict__ kd_all, const PreOp<T> pre) {
   const int pb = blockIdx.x / g.bpp;
   if (g.skip && g.skip[(int64_t)pb * g.skip_stride]) return;
-  constexpr int NT = B * Radices<N>::TPR;
+  constexpr int NT = B * Radices<N, S>::TPR;
   using Addr = AddrRowPad<N, lds_pad_period<T>()>;
   __shared__ cplx<T> s[B * Addr::PITCH];
   __shared__ cplx<T> tws[N];
@@ -147,7 +153,7 @@ k_xfft_fwd(const cplx<T>* __restrict__ in_all, cplx<T>* __restrict__ out_all,
   }
   if constexpr (PRE == PRE_S) block_partials<1, NT>(acc, pre.part);
   __syncthreads();
-  lds_fft<T, N, B, NT, false, false>(s, tws, Addr{}, tid);
+  lds_fft<T, N, B, NT, false, false, S>(s, tws, Addr{}, tid);
   for (int e = tid; e < B * N; e += NT) {
     const int rr = e / N;
     const int64_t row = row0 + rr;
@@ -155,15 +161,15 @@ k_xfft_fwd(const cplx<T>* __restrict__ in_all, cplx<T>* __restrict__ out_all,
   }
 }
 
-template <typename T, int N, int B, int CM, int POST>
-__global__ void __launch_bounds__(B * Radices<N>::TPR)
+template <typename T, int N, int B, int CM, int POST, int S>
+__global__ void __launch_bounds__((B * Radices<N, S>::TPR))
 k_xfft_inv(const cplx<T>* __restrict__ UW_all, cplx<T>* __restrict__ y_all,
            const cplx<T>* __restrict__ tw, const RowGroup g, int ny, int nz, int j0, int nabs,
            T scale, const cplx<T>* __restrict__ kd_all, const cplx<T>* __restrict__ x_all,
            const PostOp<T> post) {
   const int pb = blockIdx.x / g.bpp;
   if (g.skip && g.skip[(int64_t)pb * g.skip_stride]) return;
-  constexpr int NT = B * Radices<N>::TPR;
+  constexpr int NT = B * Radices<N, S>::TPR;
   constexpr int NBUF = (CM == CB_FWD) ? 2 : 1;
   using Addr = AddrRowPad<N, lds_pad_period<T>()>;
   __shared__ cplx<T> s[NBUF * B * Addr::PITCH];
@@ -235,7 +241,7 @@ k_xfft_inv(const cplx<T>* __restrict__ UW_all, cplx<T>* __restrict__ y_all,
     if (CM == CB_FWD) s[Addr{}(B + rr, xi)] = rwv[k];
   }
   __syncthreads();
-  lds_fft<T, N, NBUF * B, NT, true, false>(s, tws, Addr{}, tid);
+  lds_fft<T, N, NBUF * B, NT, true, false, S>(s, tws, Addr{}, tid);
   double acc[3] = {0.0, 0.0, 0.0};
 #pragma unroll
   for (int k = 0; k < EPT; ++k) {
@@ -263,13 +269,13 @@ k_xfft_inv(const cplx<T>* __restrict__ UW_all, cplx<T>* __restrict__ y_all,
 }
 
 // y pass: problem pb's planes start at pb * stride; grid.y = nprob * nplanes.
-template <typename T, int N, int TX, bool INV>
-__global__ void __launch_bounds__(TX * Radices<N>::TPR)
+template <typename T, int N, int TX, bool INV, int S>
+__global__ void __launch_bounds__((TX * Radices<N, S>::TPR))
 k_yfft(cplx<T>* __restrict__ buf, const cplx<T>* __restrict__ tw, int nx, int nplanes,
        int64_t stride, const int* __restrict__ skip, int skip_stride) {
   const int pb = blockIdx.y / nplanes;
   if (skip && skip[(int64_t)pb * skip_stride]) return;
-  constexpr int NT = TX * Radices<N>::TPR;
+  constexpr int NT = TX * Radices<N, S>::TPR;
   __shared__ cplx<T> s[N * TX];
   __shared__ cplx<T> tws[N];
   const int tid = threadIdx.x;
@@ -287,7 +293,7 @@ k_yfft(cplx<T>* __restrict__ buf, const cplx<T>* __restrict__ tw, int nx, int np
 #pragma unroll
   for (int k = 0; k < EPT; ++k) s[tid + k * NT] = v[k];
   __syncthreads();
-  lds_fft<T, N, TX, NT, INV, true>(s, tws, AddrCol<TX>{}, tid);
+  lds_fft<T, N, TX, NT, INV, true, S>(s, tws, AddrCol<TX>{}, tid);
 #pragma unroll
   for (int k = 0; k < EPT; ++k) {
     const int e = tid + k * NT;
@@ -313,75 +319,113 @@ static RowGroup group_of(const OpTables<T>& t, int64_t nmain, int64_t ntot, int6
   return g;
 }
 
-template <typename T, int N>
-static hipError_t xfwd_n(const OpTables<T>& t, const cplx<T>* in, cplx<T>* out, int64_t nmain,
+template <typename T, int N, int S, int HALF>
+static hipError_t xfwd_v(const OpTables<T>& t, const cplx<T>* in, cplx<T>* out, int64_t nmain,
                          int64_t ntot, int64_t in_stride, int64_t out_stride, const PreOp<T>& pre,
                          int* nblk_out, hipStream_t st) {
-  constexpr int B = x_rows<T, N>();
-  constexpr int NT = B * Radices<N>::TPR;
+  constexpr int B = x_rows<T, N, HALF, S>();
+  constexpr int NT = B * Radices<N, S>::TPR;
+  static_assert(NT <= 1024, "block too large");
   const RowGroup g = group_of(t, nmain, ntot, in_stride, out_stride, B);
   if (nblk_out) *nblk_out = g.bpp;
   dim3 grid((unsigned)((int64_t)g.bpp * g.nprob)), b(NT);
   switch (pre.mode) {
     case PRE_P:
-      hipLaunchKernelGGL((k_xfft_fwd<T, N, B, PRE_P>), grid, b, 0, st, in, out, t.tw_x, g, t.ny,
+      hipLaunchKernelGGL((k_xfft_fwd<T, N, B, PRE_P, S>), grid, b, 0, st, in, out, t.tw_x, g, t.ny,
                          t.nz, t.j0, t.nabs, t.kd, pre);
       break;
     case PRE_S:
-      hipLaunchKernelGGL((k_xfft_fwd<T, N, B, PRE_S>), grid, b, 0, st, in, out, t.tw_x, g, t.ny,
+      hipLaunchKernelGGL((k_xfft_fwd<T, N, B, PRE_S, S>), grid, b, 0, st, in, out, t.tw_x, g, t.ny,
                          t.nz, t.j0, t.nabs, t.kd, pre);
       break;
     default:
-      hipLaunchKernelGGL((k_xfft_fwd<T, N, B, PRE_NONE>), grid, b, 0, st, in, out, t.tw_x, g,
+      hipLaunchKernelGGL((k_xfft_fwd<T, N, B, PRE_NONE, S>), grid, b, 0, st, in, out, t.tw_x, g,
                          t.ny, t.nz, t.j0, t.nabs, t.kd, pre);
       break;
   }
   return hipGetLastError();
 }
 
-template <typename T, int N, int CM>
+template <typename T, int N>
+static hipError_t xfwd_n(const OpTables<T>& t, const cplx<T>* in, cplx<T>* out, int64_t nmain,
+                         int64_t ntot, int64_t in_stride, int64_t out_stride, const PreOp<T>& pre,
+                         int* nblk_out, hipStream_t st) {
+  switch (t.sched_xf & 3) {
+    case 1: return xfwd_v<T, N, 1, 0>(t, in, out, nmain, ntot, in_stride, out_stride, pre, nblk_out, st);
+    case 2: return xfwd_v<T, N, 0, 1>(t, in, out, nmain, ntot, in_stride, out_stride, pre, nblk_out, st);
+    case 3: return xfwd_v<T, N, 1, 1>(t, in, out, nmain, ntot, in_stride, out_stride, pre, nblk_out, st);
+    default: return xfwd_v<T, N, 0, 0>(t, in, out, nmain, ntot, in_stride, out_stride, pre, nblk_out, st);
+  }
+}
+
+template <typename T, int N, int CM, int S, int HALF>
 static void xinv_launch(const OpTables<T>& t, const cplx<T>* UW, cplx<T>* y, int64_t nrows,
                         int64_t in_stride, int64_t out_stride, const cplx<T>* x, T scale,
                         const PostOp<T>& post, int* nblk_out, hipStream_t st) {
-  constexpr int B = xinv_rows<T, N, CM>();
-  constexpr int NT = B * Radices<N>::TPR;
+  constexpr int B = xinv_rows<T, N, CM, S, HALF>();
+  constexpr int NT = B * Radices<N, S>::TPR;
+  static_assert(NT <= 1024, "block too large");
   const RowGroup g = group_of(t, nrows, nrows, in_stride, out_stride, B);
   if (nblk_out) *nblk_out = g.bpp;
   dim3 grid((unsigned)((int64_t)g.bpp * g.nprob)), b(NT);
   if (post.mode == POST_DOT)
-    hipLaunchKernelGGL((k_xfft_inv<T, N, B, CM, POST_DOT>), grid, b, 0, st, UW, y, t.tw_x, g,
+    hipLaunchKernelGGL((k_xfft_inv<T, N, B, CM, POST_DOT, S>), grid, b, 0, st, UW, y, t.tw_x, g,
                        t.ny, t.nz, t.j0, t.nabs, scale, t.kd, x, post);
   else
-    hipLaunchKernelGGL((k_xfft_inv<T, N, B, CM, POST_NONE>), grid, b, 0, st, UW, y, t.tw_x, g,
+    hipLaunchKernelGGL((k_xfft_inv<T, N, B, CM, POST_NONE, S>), grid, b, 0, st, UW, y, t.tw_x, g,
                        t.ny, t.nz, t.j0, t.nabs, scale, t.kd, x, post);
+}
+
+template <typename T, int N, int S, int HALF>
+static void xinv_v(const OpTables<T>& t, const cplx<T>* UW, cplx<T>* y, int64_t nrows,
+                   int64_t in_stride, int64_t out_stride, int cmode, const cplx<T>* x, T scale,
+                   const PostOp<T>& post, int* nblk_out, hipStream_t st) {
+  switch (cmode) {
+    case CB_PLAIN: xinv_launch<T, N, CB_PLAIN, S, HALF>(t, UW, y, nrows, in_stride, out_stride, x, scale, post, nblk_out, st); break;
+    case CB_FWD: xinv_launch<T, N, CB_FWD, S, HALF>(t, UW, y, nrows, in_stride, out_stride, x, scale, post, nblk_out, st); break;
+    default: xinv_launch<T, N, CB_ADJ, S, HALF>(t, UW, y, nrows, in_stride, out_stride, x, scale, post, nblk_out, st); break;
+  }
 }
 
 template <typename T, int N>
 static hipError_t xinv_n(const OpTables<T>& t, const cplx<T>* UW, cplx<T>* y, int64_t nrows,
                          int64_t in_stride, int64_t out_stride, int cmode, const cplx<T>* x,
                          T scale, const PostOp<T>& post, int* nblk_out, hipStream_t st) {
-  switch (cmode) {
-    case CB_PLAIN: xinv_launch<T, N, CB_PLAIN>(t, UW, y, nrows, in_stride, out_stride, x, scale, post, nblk_out, st); break;
-    case CB_FWD: xinv_launch<T, N, CB_FWD>(t, UW, y, nrows, in_stride, out_stride, x, scale, post, nblk_out, st); break;
-    default: xinv_launch<T, N, CB_ADJ>(t, UW, y, nrows, in_stride, out_stride, x, scale, post, nblk_out, st); break;
+  switch (t.sched_xi & 3) {
+    case 1: xinv_v<T, N, 1, 0>(t, UW, y, nrows, in_stride, out_stride, cmode, x, scale, post, nblk_out, st); break;
+    case 2: xinv_v<T, N, 0, 1>(t, UW, y, nrows, in_stride, out_stride, cmode, x, scale, post, nblk_out, st); break;
+    case 3: xinv_v<T, N, 1, 1>(t, UW, y, nrows, in_stride, out_stride, cmode, x, scale, post, nblk_out, st); break;
+    default: xinv_v<T, N, 0, 0>(t, UW, y, nrows, in_stride, out_stride, cmode, x, scale, post, nblk_out, st); break;
   }
+  return hipGetLastError();
+}
+
+template <typename T, int N, int S, int HALF>
+static hipError_t y_v(const OpTables<T>& t, cplx<T>* buf, int nplanes, int64_t stride, bool inv,
+                      hipStream_t st) {
+  constexpr int TX = y_tile<T, N, S, HALF>();
+  constexpr int NT = TX * Radices<N, S>::TPR;
+  static_assert(NT <= 1024, "block too large");
+  if (t.nx % TX) return hipErrorInvalidValue;
+  dim3 g(t.nx / TX, (unsigned)(nplanes * t.nprob));
+  if (inv)
+    hipLaunchKernelGGL((k_yfft<T, N, TX, true, S>), g, dim3(NT), 0, st, buf, t.tw_y, t.nx, nplanes,
+                       stride, t.skip, t.skip_stride);
+  else
+    hipLaunchKernelGGL((k_yfft<T, N, TX, false, S>), g, dim3(NT), 0, st, buf, t.tw_y, t.nx, nplanes,
+                       stride, t.skip, t.skip_stride);
   return hipGetLastError();
 }
 
 template <typename T, int N>
 static hipError_t y_n(const OpTables<T>& t, cplx<T>* buf, int nplanes, int64_t stride, bool inv,
                       hipStream_t st) {
-  constexpr int TX = y_tile<T, N>();
-  constexpr int NT = TX * Radices<N>::TPR;
-  if (t.nx % TX) return hipErrorInvalidValue;
-  dim3 g(t.nx / TX, (unsigned)(nplanes * t.nprob));
-  if (inv)
-    hipLaunchKernelGGL((k_yfft<T, N, TX, true>), g, dim3(NT), 0, st, buf, t.tw_y, t.nx, nplanes,
-                       stride, t.skip, t.skip_stride);
-  else
-    hipLaunchKernelGGL((k_yfft<T, N, TX, false>), g, dim3(NT), 0, st, buf, t.tw_y, t.nx, nplanes,
-                       stride, t.skip, t.skip_stride);
-  return hipGetLastError();
+  switch (t.sched_y & 3) {
+    case 1: return y_v<T, N, 1, 0>(t, buf, nplanes, stride, inv, st);
+    case 2: return y_v<T, N, 0, 1>(t, buf, nplanes, stride, inv, st);
+    case 3: return y_v<T, N, 1, 1>(t, buf, nplanes, stride, inv, st);
+    default: return y_v<T, N, 0, 0>(t, buf, nplanes, stride, inv, st);
+  }
 }
 
 #define PSFD_LATERAL_SWITCH(N, CALL)              \

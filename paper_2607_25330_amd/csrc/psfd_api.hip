@@ -11,6 +11,9 @@
 
 #include <algorithm>
 #include <atomic>
+#include <map>
+#include <mutex>
+#include <tuple>
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
@@ -566,6 +569,113 @@ psfd_status rhs_group(struct psfd_plan* P, cplx<double>* b) {
   return PSFD_OK;
 }
 
+
+// ---------------------------------------------------------------- autotuner
+// Kernel schedules (radix schedule and rows per block of the x passes, radix
+// schedule and tile width of the y pass, axial kernel variant) are chosen per
+// (precision, nx, ny, Nz, N_abs, group size rounded up to a power of two) by
+// timing the working-precision operator of the solve on the plan itself,
+// one knob at a time; the result is kept for the life of the process.
+struct TuneKey {
+  int elem, nx, ny, nz, nabs, gb;
+  bool operator<(const TuneKey& o) const {
+    return std::tie(elem, nx, ny, nz, nabs, gb) < std::tie(o.elem, o.nx, o.ny, o.nz, o.nabs, o.gb);
+  }
+};
+struct TuneVal {
+  int v[4] = {0, 0, 0, 0};  // sched_xf, sched_xi, sched_y, sched_ax
+};
+std::mutex g_tune_mu;
+std::map<TuneKey, TuneVal> g_tune;
+
+template <typename T>
+void set_sched(OpTables<T>& t, const TuneVal& v) {
+  t.sched_xf = v.v[0];
+  t.sched_xi = v.v[1];
+  t.sched_y = v.v[2];
+  t.sched_ax = v.v[3];
+}
+
+template <typename T>
+psfd_status autotune(struct psfd_plan* P) {
+  int gb = 1;
+  while (gb < P->G) gb *= 2;
+  const TuneKey key{(int)sizeof(T), P->nx, P->ny, P->nz, P->nabs, gb};
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune.find(key);
+    if (it != g_tune.end()) {
+      set_sched(tab<T>(P), it->second);
+      return PSFD_OK;
+    }
+  }
+  CHKS(ensure_solver_common(P));
+  if (sizeof(T) == 4) CHKS(ensure_fp32(P));
+  hipStream_t st = P->st;
+  // an FP64 field holds two working-precision fields of the same element count
+  cplx<T>* x = reinterpret_cast<cplx<T>*>(P->b64);
+  cplx<T>* y = reinterpret_cast<cplx<T>*>(P->tmp64);
+  CHK(hipMemsetAsync(x, 0, sizeof(cplx<T>) * (size_t)(P->nfield * P->G), st));
+  const int op = P->use_pc ? OP_AM : OP_A;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  CHK(hipEventCreate(&e0));
+  CHK(hipEventCreate(&e1));
+  struct Ev {
+    hipEvent_t a, b;
+    ~Ev() { (void)hipEventDestroy(a); (void)hipEventDestroy(b); }
+  } ev{e0, e1};
+  auto measure = [&](const TuneVal& v, float* ms) -> psfd_status {
+    set_sched(tab<T>(P), v);
+    CHK(op_apply<T>(P, x, y, op, nullptr, 0));
+    float best = 1e30f;
+    for (int rep = 0; rep < 3; ++rep) {
+      CHK(hipEventRecord(e0, st));
+      for (int i = 0; i < 4; ++i) CHK(op_apply<T>(P, x, y, op, nullptr, 0));
+      CHK(hipEventRecord(e1, st));
+      CHK(hipEventSynchronize(e1));
+      float t = 0.f;
+      CHK(hipEventElapsedTime(&t, e0, e1));
+      best = std::min(best, t);
+    }
+    *ms = best;
+    return PSFD_OK;
+  };
+  TuneVal cur;
+  float cur_ms = 0.f;
+  CHKS(measure(cur, &cur_ms));
+  const int order[4] = {3, 0, 1, 2};
+  const int nval[4] = {4, 4, 4, 3};
+  for (int k : order) {
+    for (int val = 0; val < nval[k]; ++val) {
+      if (val == cur.v[k]) continue;
+      TuneVal cand = cur;
+      cand.v[k] = val;
+      float ms = 0.f;
+      CHKS(measure(cand, &ms));
+      if (ms < 0.98f * cur_ms) {
+        cur = cand;
+        cur_ms = ms;
+      }
+    }
+  }
+  set_sched(tab<T>(P), cur);
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tune[key] = cur;
+  return PSFD_OK;
+}
+
+psfd_status tune_plan(struct psfd_plan* P) {
+  if (P->prec == PSFD_C128) return autotune<double>(P);
+  return autotune<float>(P);
+}
+
+// PSFD_TUNE=1 / 0 forces tuning on / off; otherwise `dflt`.
+bool tune_wanted(bool dflt) {
+  const char* s = std::getenv("PSFD_TUNE");
+  if (!s || !*s) return dflt;
+  return std::atoi(s) != 0;
+}
+
 psfd_status solve_body(struct psfd_plan* P, const cplx<double>* b_in, const cplx<double>* x0,
                        cplx<double>* E, double tol, int maxit, bool adjoint, psfd_info* infos);
 
@@ -915,6 +1025,7 @@ psfd_status plan_group_impl(int G, const psfd_desc* descs, const void* const* ep
   CHK(hipEventCreateWithFlags(&P->join_ev, hipEventDisableTiming));
   P->use_graphs = std::getenv("PSFD_NO_GRAPH") == nullptr;
   CHKS(set_eps_impl(P, eps));
+  if (tune_wanted(G > 1)) CHKS(tune_plan(P));
   CHK(hipStreamSynchronize(P->st));
   guard.p = nullptr;
   *out = P;
@@ -1072,6 +1183,7 @@ psfd_status solve_batch_impl(struct psfd_plan* B, const void* const* x0, void* c
       std::vector<psfd_info> inf(G);
       struct psfd_plan* p = nullptr;
       psfd_status st = guarded([&] { return plan_group_impl(G, ds.data(), es.data(), ws, &p); });
+      if (st == PSFD_OK && G == 1 && tune_wanted(true)) st = guarded([&] { return tune_plan(p); });
       if (st == PSFD_OK) {
         st = guarded([&]() -> psfd_status {
           CHKS(dalloc(p, &p->E64, (size_t)(p->nfield * G)));
@@ -1253,6 +1365,51 @@ psfd_status psfd_profile_read(psfd_plan_t p, double* total_ms, int64_t* launches
     *bytes = p->prof_bytes;
     return PSFD_OK;
   });
+}
+
+psfd_status psfd_tune(psfd_plan_t p) {
+  if (!p || p->is_batch) return fail(PSFD_ERR_ARG, "NULL argument or batch handle");
+  return guarded([&]() -> psfd_status {
+    for (auto& row : p->gexec)  // captured chunks hold the old schedules
+      for (auto& g : row)
+        if (g) {
+          (void)hipGraphExecDestroy(g);
+          g = nullptr;
+        }
+    CHKS(tune_plan(p));
+    CHK(hipStreamSynchronize(p->st));
+    return PSFD_OK;
+  });
+}
+
+psfd_status psfd_set_schedule(psfd_plan_t p, const int32_t* sched) {
+  if (!p || p->is_batch || !sched) return fail(PSFD_ERR_ARG, "NULL argument or batch handle");
+  for (int k = 0; k < 4; ++k)
+    if (sched[k] < 0 || sched[k] > (k == 3 ? 2 : 3)) return fail(PSFD_ERR_ARG, "schedule out of range");
+  return guarded([&]() -> psfd_status {
+    CHK(p->st ? hipStreamSynchronize(p->st) : hipDeviceSynchronize());
+    for (auto& row : p->gexec)
+      for (auto& g : row)
+        if (g) {
+          (void)hipGraphExecDestroy(g);
+          g = nullptr;
+        }
+    TuneVal v;
+    for (int k = 0; k < 4; ++k) v.v[k] = sched[k];
+    set_sched(p->t64, v);
+    set_sched(p->t32, v);
+    return PSFD_OK;
+  });
+}
+
+psfd_status psfd_schedule(psfd_plan_t p, int32_t* sched) {
+  if (!p || p->is_batch || !sched) return fail(PSFD_ERR_ARG, "NULL argument or batch handle");
+  const bool f = p->prec != PSFD_C128;
+  sched[0] = f ? p->t32.sched_xf : p->t64.sched_xf;
+  sched[1] = f ? p->t32.sched_xi : p->t64.sched_xi;
+  sched[2] = f ? p->t32.sched_y : p->t64.sched_y;
+  sched[3] = f ? p->t32.sched_ax : p->t64.sched_ax;
+  return PSFD_OK;
 }
 
 int64_t psfd_field_size(psfd_plan_t p) { return p ? p->nfield : 0; }

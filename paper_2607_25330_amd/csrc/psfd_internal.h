@@ -44,6 +44,11 @@ struct OpTables {
   T pc_mmin, pc_kref2, pc_gamma, pc_reg;
   int pc_bf16;              // round m(k) to bfloat16
   int ax_lds;               // 1: always use the LDS-staged axial kernel
+  // kernel schedules chosen by the autotuner (0 = default): forward x pass,
+  // inverse x pass, y pass (bit 0 radix schedule, bit 1 half rows / tile);
+  // axial kernel (0 register kernel, 1 register kernel with twice the lanes,
+  // 2 LDS-staged kernel)
+  int sched_xf, sched_xi, sched_y, sched_ax;
   // per-problem skip flags: when non-null and skip[b * skip_stride] != 0 the
   // operator kernels return at once for problem b
   const int* skip;

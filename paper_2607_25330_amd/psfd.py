@@ -79,6 +79,9 @@ _SIGS = {
                          c_int32, ctypes.POINTER(Info)],
     "psfd_profile_enable": [c_void_p, c_int32],
     "psfd_profile_read": [c_void_p, c_dp, ctypes.POINTER(c_int64), c_dp],
+    "psfd_tune": [c_void_p],
+    "psfd_schedule": [c_void_p, ctypes.POINTER(c_int32)],
+    "psfd_set_schedule": [c_void_p, ctypes.POINTER(c_int32)],
 }
 
 # kernel ids for Plan.profile_enable
@@ -260,6 +263,21 @@ class Plan:
     @property
     def k0(self):
         return 2.0 * 3.141592653589793 / self.cfg["lam"]
+
+    def tune(self):
+        """psfd_tune: pick the fastest kernel schedules for this shape (cached per process)."""
+        _call("psfd_tune", self._h)
+        return self.schedule()
+
+    def schedule(self):
+        """psfd_schedule: (forward x, inverse x, y, axial) schedule indices."""
+        out = (c_int32 * 4)()
+        _call("psfd_schedule", self._h, out)
+        return tuple(out)
+
+    def set_schedule(self, sched):
+        """psfd_set_schedule: (forward x, inverse x, y, axial) schedule indices."""
+        _call("psfd_set_schedule", self._h, (c_int32 * 4)(*[int(v) for v in sched]))
 
     def profile_enable(self, kernel):
         """Time every launch of one kernel class with HIP events (see PROFILE_KERNELS)."""

@@ -45,7 +45,8 @@ def _eps(cfg, seed):
 
 
 @pytest.mark.parametrize("prec", [0, 1])
-def test_batch_matches_individual_solves(psfd, prec):
+def test_batch_matches_individual_solves(psfd, prec, monkeypatch):
+    monkeypatch.setenv("PSFD_TUNE", "0")
     cfgs = [base_config(32, 32, 16, 30.0, theta_deg=0.0, pol=0),
             base_config(64, 32, 8, 15.0, theta_deg=5.0, pol=1, dy=2.5),
             base_config(16, 16, 8, 15.0, theta_deg=10.0, phi_deg=30.0, pol=0),
@@ -66,12 +67,14 @@ def test_batch_matches_individual_solves(psfd, prec):
 
 
 @pytest.mark.parametrize("prec", [0, 1])
-def test_group_of_same_shape_problems_matches_individual_solves(psfd, prec):
+def test_group_of_same_shape_problems_matches_individual_solves(psfd, prec, monkeypatch):
     """Six 32x32x(16+16) problems (different angles, polarisations and
     permittivities, one with a warm start) share one group plan: every launch
     covers all six, each keeps its own Krylov scalars and stops on its own.
     Up to 16 problems a group uses the same per-problem block decomposition
-    as a single solve, so the results are bit-identical."""
+    as a single solve, so the results are bit-identical (with the default
+    kernel schedules: the autotuner is switched off here)."""
+    monkeypatch.setenv("PSFD_TUNE", "0")
     thetas = [0.0, 2.5, 5.0, 7.5, 10.0, 6.0]
     cfgs = [dict(base_config(32, 32, 16, 30.0, theta_deg=th, phi_deg=15.0 * i, pol=i % 2),
                  ml_kz_min=0.1) for i, th in enumerate(thetas)]

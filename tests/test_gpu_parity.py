@@ -104,6 +104,51 @@ def test_operator_pieces_c64(psfd, name):
     plan.close()
 
 
+# every value of every schedule knob (others at their default), against the oracle
+SCHEDULES = [(v, 0, 0, 0) for v in (1, 2, 3)] + [(0, v, 0, 0) for v in (1, 2, 3)] + \
+    [(0, 0, v, 0) for v in (1, 2, 3)] + [(0, 0, 0, v) for v in (1, 2)]
+
+
+@pytest.mark.parametrize("name", ["c1", "nonsq_tm_phi", "radix3_lateral", "tall_1024", "wide_512"])
+def test_operator_all_schedules(psfd, name):
+    cfg = APPLY_CASES[name]
+    a, eps = case(cfg, seed=7)
+    P = R.Problem(cfg, eps)
+    x = random_field(P.g.shape, np.random.default_rng(12))
+    refA, refM = R.apply_A(P, x), R.apply_M(P, x)
+    p64 = psfd.Plan(cfg, dev(eps))
+    p32 = psfd.Plan(cfg, dev(eps), prec=psfd.PSFD_C64_REFINE64)
+    xd = dev(x)
+    x32 = xd.to(torch.complex64)
+    for sc in SCHEDULES:
+        for p in (p64, p32):
+            p.set_schedule(sc)
+            assert p.schedule() == sc
+        assert relmax(host(p64.apply(xd)), refA) < 1e-12, sc
+        assert relmax(host(p64.precond(xd)), refM) < 1e-12, sc
+        assert relmax(host(p32.apply_c64(x32)).astype(np.complex128), refA) < 3e-5, sc
+    p64.close()
+    p32.close()
+
+
+def test_tuned_solve_matches_oracle(psfd, small_ref):
+    """psfd_tune picks schedules by timing; the solve with them still meets the bar."""
+    cfg, eps, P, E_ref = small_ref[1]
+    for prec, tol, bound in ((psfd.PSFD_C128, 1e-12, 1e-10), (psfd.PSFD_C64_REFINE64, 1e-9, 1e-6)):
+        plan = psfd.Plan(cfg, dev(eps), prec=prec)
+        sc = plan.tune()
+        assert len(sc) == 4 and plan.schedule() == sc
+        E, info = plan.solve(tol=tol)
+        assert np.linalg.norm(host(E) - E_ref) / np.linalg.norm(E_ref) <= bound
+        plan.close()
+    with pytest.raises(psfd.PsfdError):
+        plan = psfd.Plan(cfg, dev(eps))
+        try:
+            plan.set_schedule((0, 0, 0, 3))
+        finally:
+            plan.close()
+
+
 @pytest.mark.parametrize("nx,ny", [(32, 32), (64, 16), (192, 16)])
 def test_layout_eps(psfd, nx, ny):
     cfg = _cfg(nx, ny, 4, 8.0, dy=1.5)
