@@ -10,7 +10,12 @@
 //   done = 0 running, 1 converged, 2 pending half step (y += alpha p only),
 //   3 breakdown or divergence (the host restarts from the current field),
 //   4 idle (the problem is not part of this run),
-//   5 iteration budget of the run used up.
+//   5 iteration budget of the run used up,
+//   6 reliable update due: the recursive residual fell by the factor delta
+//     since the last true residual; the host folds the iterate into the
+//     high-precision solution, recomputes the true residual, replaces r with
+//     it (FIN_REPLACE: rho = <rh, r>) and the recurrence continues with its
+//     search direction p and shadow residual rh kept.
 // A plan may hold a group of problems: every kernel here covers all of them,
 // each block working for one problem (its index from the block index), and
 // the finalize kernel runs one block per problem.
@@ -27,7 +32,6 @@
 
 namespace psfd {
 
-enum { KS_RUN = 0, KS_CONV = 1, KS_HALF = 2, KS_BREAK = 3, KS_IDLE = 4, KS_MAXIT = 5 };
 constexpr double kOmegaLimit = 0.7;
 
 int red_blocks(int64_t n, int nprob) {
@@ -54,9 +58,10 @@ k_finalize(KState* ks_all, const double* __restrict__ part_all, int nblocks,
   bool run;
   if (STAGE == FIN_INIT || STAGE == FIN_RED0) run = true;
   else if (STAGE == FIN_RHO) run = (d == KS_RUN || d == KS_HALF);
+  else if (STAGE == FIN_REPLACE) run = (d == KS_UPDATE);
   else run = (d == KS_RUN);
   if (!run) return;
-  constexpr int NV = (STAGE == FIN_SNORM || STAGE == FIN_INIT || STAGE == FIN_RED0) ? 1 : 3;
+  constexpr int NV = (STAGE == FIN_SNORM || STAGE == FIN_INIT || STAGE == FIN_RED0) ? 1 : 3;  // FIN_REPLACE: 3
   double acc[NV];
 #pragma unroll
   for (int k = 0; k < NV; ++k) acc[k] = 0.0;
@@ -92,6 +97,8 @@ k_finalize(KState* ks_all, const double* __restrict__ part_all, int nblocks,
     ks->bnorm2 = q.bnorm2;
     ks->tol2 = q.tol2;
     ks->itmax = (int)q.itmax;
+    ks->delta2 = q.delta2;
+    ks->rmax2 = acc[0];
     ks->done = (q.tol2 < 0.0) ? KS_IDLE : (ks->itmax <= 0 ? KS_MAXIT : KS_RUN);
     ks->half = 0;
     ks->status = 0;
@@ -157,8 +164,17 @@ k_finalize(KState* ks_all, const double* __restrict__ part_all, int nblocks,
           !(sqrt(norm2(rho_new)) > 1e-30 * sqrt(ks->rh_norm2 * acc[0]))) {
         ks->status = 1;
         ks->done = KS_BREAK;
+      } else if (ks->delta2 > 0.0 && acc[0] <= ks->delta2 * ks->rmax2) {
+        ks->done = KS_UPDATE;
       }
     }
+    if (acc[0] > ks->rmax2) ks->rmax2 = acc[0];
+  } else if constexpr (STAGE == FIN_REPLACE) {
+    // r was replaced by the true residual (host): partials ||r||^2, <rh, r>
+    ks->rnorm2 = acc[0];
+    ks->rmax2 = acc[0];
+    st2(ks->rho, cplx<double>{acc[1], acc[2]});
+    ks->done = (acc[0] <= ks->tol2 * ks->bnorm2) ? KS_CONV : KS_RUN;
   }
 }
 
@@ -171,6 +187,7 @@ hipError_t launch_finalize(int stage, KState* ks, const double* part, int nblock
     case FIN_SNORM: hipLaunchKernelGGL(k_finalize<FIN_SNORM>, g, b, 0, st, ks, part, nblocks, pp); break;
     case FIN_OMEGA: hipLaunchKernelGGL(k_finalize<FIN_OMEGA>, g, b, 0, st, ks, part, nblocks, pp); break;
     case FIN_RHO: hipLaunchKernelGGL(k_finalize<FIN_RHO>, g, b, 0, st, ks, part, nblocks, pp); break;
+    case FIN_REPLACE: hipLaunchKernelGGL(k_finalize<FIN_REPLACE>, g, b, 0, st, ks, part, nblocks, pp); break;
     default: hipLaunchKernelGGL(k_finalize<FIN_RED0>, g, b, 0, st, ks, part, nblocks, pp); break;
   }
   return hipGetLastError();
@@ -264,6 +281,20 @@ k_residual(cplx<T>* __restrict__ out, const cplx<T>* __restrict__ a, const cplx<
 
 template <typename T>
 __global__ void __launch_bounds__(KRED_THREADS)
+k_dot_rr(const cplx<T>* __restrict__ rh, const cplx<T>* __restrict__ r, int64_t n, int nprob,
+         double* __restrict__ part) {
+  double acc[3] = {0.0, 0.0, 0.0};
+  PSFD_GROUP_LOOP(i) {
+    const cplx<double> a = cast<double>(rh[i]), b = cast<double>(r[i]);
+    acc[0] += norm2(b);
+    acc[1] += a.re * b.re + a.im * b.im;
+    acc[2] += a.re * b.im - a.im * b.re;
+  }
+  block_partials<3, KRED_THREADS>(acc, part);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(KRED_THREADS)
 k_norm2(const cplx<T>* __restrict__ a, int64_t n, int nprob, double* __restrict__ part) {
   double acc[1] = {0.0};
   PSFD_GROUP_LOOP(i) acc[0] += norm2(cast<double>(a[i]));
@@ -286,7 +317,12 @@ template <typename TY, typename TX>
 __global__ void __launch_bounds__(KRED_THREADS)
 k_scale_copy(cplx<TY>* __restrict__ y, const cplx<TX>* __restrict__ x,
              const ProbParams* __restrict__ pp, int64_t n, int nprob) {
-  const double a = pp ? pp[blockIdx.x / (gridDim.x / nprob)].iscale : 1.0;
+  double a = 1.0;
+  if (pp) {
+    const ProbParams& q = pp[blockIdx.x / (gridDim.x / nprob)];
+    if (q.mask == 0.0) return;
+    a = q.iscale;
+  }
   PSFD_GROUP_LOOP(i) {
     const cplx<double> xv = cast<double>(x[i]);
     y[i] = cast<TY>(a * xv);
@@ -322,6 +358,12 @@ hipError_t launch_k_residual(cplx<T>* out, const cplx<T>* a, const cplx<T>* b, i
   return hipGetLastError();
 }
 template <typename T>
+hipError_t launch_k_dot_rr(const cplx<T>* rh, const cplx<T>* r, int64_t n, int nprob,
+                           double* part, hipStream_t st) {
+  hipLaunchKernelGGL((k_dot_rr<T>), KGRID, rh, r, n, nprob, part);
+  return hipGetLastError();
+}
+template <typename T>
 hipError_t launch_k_norm2(const cplx<T>* a, int64_t n, int nprob, double* part, hipStream_t st) {
   hipLaunchKernelGGL((k_norm2<T>), KGRID, a, n, nprob, part);
   return hipGetLastError();
@@ -349,7 +391,9 @@ hipError_t launch_k_scale_copy(cplx<TY>* y, const cplx<TX>* x, const ProbParams*
                                        cplx<T>*, int64_t, int, double*, hipStream_t);         \
   template hipError_t launch_k_residual<T>(cplx<T>*, const cplx<T>*, const cplx<T>*, int64_t, \
                                            int, double*, hipStream_t);                        \
-  template hipError_t launch_k_norm2<T>(const cplx<T>*, int64_t, int, double*, hipStream_t);
+  template hipError_t launch_k_norm2<T>(const cplx<T>*, int64_t, int, double*, hipStream_t);   \
+  template hipError_t launch_k_dot_rr<T>(const cplx<T>*, const cplx<T>*, int64_t, int, double*, \
+                                         hipStream_t);
 
 PSFD_INST_K(double)
 PSFD_INST_K(float)
@@ -362,5 +406,6 @@ PSFD_INST_K(float)
 PSFD_INST_AX(double, double)
 PSFD_INST_AX(double, float)
 PSFD_INST_AX(float, double)
+PSFD_INST_AX(float, float)
 
 }  // namespace psfd

@@ -428,9 +428,11 @@ psfd_status norm2_group(struct psfd_plan* P, const cplx<double>* a) {
 //   ... [x-IFFT -> t, <t, s>, ||t||]  fin: omega
 //   [y += alpha p + omega s, r = s - omega t, ||r||, <rh, r>]  fin: rho, beta, stop test
 // Returns when every problem of the group has stopped (converged, budget
-// used, breakdown or idle) or after `maxit` launched iterations.
-template <typename T>
-psfd_status run_bicgstab(struct psfd_plan* P, bool adjoint, int maxit) {
+// used, breakdown or idle) or after `maxit` launched iterations.  Problems
+// that request a reliable update (KS_UPDATE) are served by `on_update`
+// between chunks while the others keep iterating.
+template <typename T, typename U>
+psfd_status run_bicgstab(struct psfd_plan* P, bool adjoint, int maxit, U&& on_update) {
   cplx<T>** V = vecs<T>(P);
   const int64_t n = P->nfield;
   const int G = P->G;
@@ -529,12 +531,17 @@ psfd_status run_bicgstab(struct psfd_plan* P, bool adjoint, int maxit) {
       launched += chunk;
     }
     CHKS(read_state(P));
+    bool upd = false;
+    for (int b = 0; b < G; ++b) upd = upd || P->ks_host[b].done == KS_UPDATE;
+    if (upd) CHKS(on_update());
     bool all = true;
-    for (int b = 0; b < G && all; ++b) all = P->ks_host[b].done != 0;
+    for (int b = 0; b < G && all; ++b) all = P->ks_host[b].done != 0 && P->ks_host[b].done != KS_UPDATE;
     if (all) break;
   }
   return PSFD_OK;
 }
+
+psfd_status no_update() { return PSFD_OK; }
 
 // r = b - op(E) in FP64 (op = A or A^H, no preconditioner) for every problem
 // not marked idle; ||r_b||^2 lands in ks_host[b].red[0].
@@ -764,6 +771,58 @@ psfd_status solve_body(struct psfd_plan* P, const cplx<double>* b_in, const cplx
         rn[i] = std::sqrt(bn2[i]);
       }
   }
+  // Reliable updates (mixed plans): the complex64 residual is replaced by the
+  // true FP64 residual each time it has fallen by kDelta since the last
+  // replacement, so one run reaches the final tolerance with the Krylov
+  // recurrence intact.  PSFD_RELIABLE=0 restores the plain restart form
+  // (inner runs to a loose relative tolerance, then a fresh start).
+  constexpr double kDelta = 0.1;
+  const bool reliable = mixed && [] {
+    const char* e = std::getenv("PSFD_RELIABLE");
+    return !(e && *e && std::atoi(e) == 0);
+  }();
+  std::vector<double> rn0(G, 0.0);  // normalisation of the current complex64 run
+  auto on_update = [&]() -> psfd_status {
+    std::vector<int> upd(G, 0);
+    for (int i = 0; i < G; ++i) upd[i] = P->ks_host[i].done == KS_UPDATE;
+    for (int i = 0; i < G; ++i) {
+      ProbParams& q = P->pp_host[i];
+      q.mask = upd[i];
+      q.scale = upd[i] ? rn0[i] : 0.0;  // E += rn0 M y
+      q.iscale = 0.0;                   // then y = 0
+      P->idle_host[i] = !upd[i];
+    }
+    CHKS(push_params(P));
+    cplx<float>* y = P->v32[V_Y];
+    if (P->use_pc) {
+      CHK(op_apply<float>(P, y, P->v32[V_W], OP_M, P->idle, 1));
+      CHK(launch_k_axpy<double, float>(E, P->v32[V_W], P->pp, n, G, st));
+    } else {
+      CHK(launch_k_axpy<double, float>(E, y, P->pp, n, G, st));
+    }
+    CHK(launch_k_scale_copy<float, float>(y, y, P->pp, n, G, st));
+    CHKS(true_residual(P, b, E, r64, adjoint));
+    for (int i = 0; i < G; ++i) {
+      if (!upd[i]) continue;
+      loc[i].applies += 2;
+      const double rr2 = P->ks_host[i].red[0];
+      rrel[i] = std::sqrt(rr2 / bn2[i]);
+      P->pp_host[i].iscale = std::isfinite(rr2) ? 1.0 / rn0[i] : 0.0;  // r = r_true / rn0
+    }
+    CHKS(push_params(P));
+    CHK(launch_k_scale_copy<float, double>(P->v32[V_R], r64, P->pp, n, G, st));
+    CHK(launch_k_dot_rr<float>(P->v32[V_RH], P->v32[V_R], n, G, P->part, st));
+    CHK(launch_finalize(FIN_REPLACE, P->ks, P->part, red_blocks(n, G), G, P->pp, st));
+    for (int i = 0; i < G; ++i) {  // back to the run's parameters (the final fold uses them)
+      ProbParams& q = P->pp_host[i];
+      P->idle_host[i] = fin[i];
+      q.mask = 1.0;
+      q.scale = fin[i] ? 0.0 : rn0[i];
+      q.iscale = fin[i] ? 0.0 : 1.0 / rn0[i];
+    }
+    CHKS(push_params(P));
+    return read_state(P);
+  };
   for (;;) {
     int active = 0, budget = 0;
     for (int i = 0; i < G; ++i) {
@@ -788,12 +847,16 @@ psfd_status solve_body(struct psfd_plan* P, const cplx<double>* b_in, const cplx
         continue;
       }
       q.itmax = (double)(maxit - total[i]);
+      q.mask = 1.0;
       if (mixed) {
-        const double it = inner_tolerance(tol, rrel[i]);
-        q.bnorm2 = 1.0;  // the run solves for the normalised residual
+        // the run solves for the normalised residual r / rn (norm 1 at its start)
+        const double it = reliable ? 0.5 * tol / rrel[i] : inner_tolerance(tol, rrel[i]);
+        q.bnorm2 = 1.0;
         q.tol2 = it * it;
         q.iscale = 1.0 / rn[i];
         q.scale = rn[i];
+        q.delta2 = reliable ? kDelta * kDelta : 0.0;
+        rn0[i] = rn[i];
       } else {
         q.bnorm2 = bn2[i];
         q.tol2 = tol * tol;
@@ -803,7 +866,7 @@ psfd_status solve_body(struct psfd_plan* P, const cplx<double>* b_in, const cplx
     CHKS(push_params(P));
     if (mixed) {
       CHK(launch_k_scale_copy<float, double>(P->v32[V_R], r64, P->pp, n, G, st));
-      CHKS(run_bicgstab<float>(P, adjoint, budget));
+      CHKS(run_bicgstab<float>(P, adjoint, budget, on_update));
       cplx<float>* y = P->v32[V_Y];
       if (P->use_pc) {
         CHK(op_apply<float>(P, y, P->v32[V_W], OP_M, P->idle, 1));
@@ -812,7 +875,7 @@ psfd_status solve_body(struct psfd_plan* P, const cplx<double>* b_in, const cplx
         CHK(launch_k_axpy<double, float>(E, y, P->pp, n, G, st));
       }
     } else {
-      CHKS(run_bicgstab<double>(P, adjoint, budget));
+      CHKS(run_bicgstab<double>(P, adjoint, budget, no_update));
       cplx<double>* y = P->v64[V_Y];
       if (P->use_pc) {
         CHK(op_apply<double>(P, y, P->tmp64, OP_M, P->idle, 1));

@@ -162,6 +162,7 @@ struct KState {
   double rv[2], ts[2], tt;
   double snorm2, rnorm2, bnorm2, tol2, rh_norm2;
   double red[4];        // generic reduction outputs
+  double rmax2, delta2;  // reliable updates: max ||r||^2 since the last one, trigger factor
   int iter, done, status, half;
   int itmax, pad;
 };
@@ -176,10 +177,14 @@ struct ProbParams {
   double scale;   // y += scale * x (refinement update)
   double iscale;  // y = iscale * x (normalised residual)
   double itmax;   // iteration budget of the run
-  double pad[3];
+  double delta2;  // reliable update when ||r||^2 <= delta2 * (max ||r||^2 since the last one); 0: never
+  double mask;    // 0: the host-driven vector kernels leave this problem untouched
+  double pad;
 };
 
-enum FinStage { FIN_INIT = 0, FIN_ALPHA, FIN_SNORM, FIN_OMEGA, FIN_RHO, FIN_RED0 };
+enum FinStage { FIN_INIT = 0, FIN_ALPHA, FIN_SNORM, FIN_OMEGA, FIN_RHO, FIN_RED0, FIN_REPLACE };
+// Krylov state of a problem (KState::done)
+enum { KS_RUN = 0, KS_CONV = 1, KS_HALF = 2, KS_BREAK = 3, KS_IDLE = 4, KS_MAXIT = 5, KS_UPDATE = 6 };
 // One block per problem: sum problem b's `nblocks` partials (they start at
 // part + b * nblocks * KPART) and update ks[b] for one stage of the recurrence.
 hipError_t launch_finalize(int stage, KState* ks, const double* part, int nblocks, int nprob,
@@ -202,6 +207,10 @@ hipError_t launch_k_init(cplx<T>* rh, const cplx<T>* r, cplx<T>* p, cplx<T>* v, 
 template <typename T>
 hipError_t launch_k_residual(cplx<T>* out, const cplx<T>* a, const cplx<T>* b, int64_t n,
                              int nprob, double* part, hipStream_t st);
+// partials ||r||^2, sum conj(rh) r of a replaced residual (then FIN_REPLACE)
+template <typename T>
+hipError_t launch_k_dot_rr(const cplx<T>* rh, const cplx<T>* r, int64_t n, int nprob,
+                           double* part, hipStream_t st);
 // partials ||a||^2 (then FIN_RED0)
 template <typename T>
 hipError_t launch_k_norm2(const cplx<T>* a, int64_t n, int nprob, double* part, hipStream_t st);
