@@ -47,7 +47,7 @@ def layouts(n, nx, ny, dx):
     return out
 
 
-def run_steps(psfd, cfgs, a_dev, idx, prec, tol, maxit, profile=None):
+def run_steps(psfd, cfgs, a_dev, idx, prec, tol, maxit, profile=None, sched=None):
     """Solve every (layout, polarisation); returns list of infos and profile sums."""
     from psfd_synth import eps_absorber_default
     eps_abs = eps_absorber_default()
@@ -57,6 +57,8 @@ def run_steps(psfd, cfgs, a_dev, idx, prec, tol, maxit, profile=None):
         for cfg in cfgs:
             eps = psfd.psfd_layout_eps(cfg, a_dev[i], eps_abs)
             plan = psfd.Plan(cfg, eps, prec)
+            if sched is not None:
+                plan.set_schedule(sched)
             if profile:
                 plan.profile_enable(profile)
             _, info = plan.solve(tol=tol, maxit=maxit, check=False)
@@ -112,10 +114,11 @@ def _sources_hash():
     return h.hexdigest()
 
 
-def measured_traffic(kernel):
-    """HBM bytes per launch of `kernel` from the committed counter summary
-    (2 x FETCH_SIZE + WRITE_SIZE, calibrated on a device copy), or None when
-    there is none or the kernel sources changed since the counters were taken."""
+def measured_traffic(kernel, sched):
+    """HBM bytes per launch of `kernel` (run with schedule index `sched`) from
+    the committed counter summary (2 x FETCH_SIZE + WRITE_SIZE, calibrated on a
+    device copy), or None when there is none for that schedule or the kernel
+    sources changed since the counters were taken."""
     import re
     path = os.path.join(ROOT, "profiles", "traffic_256x256x48_mixed.md")
     if not os.path.exists(path):
@@ -123,7 +126,8 @@ def measured_traffic(kernel):
     with open(path) as f:
         text = f.read()
     sha = re.search(r"^sources_sha256: ([0-9a-f]{64})$", text, re.M)
-    row = re.search(r"^traffic_bytes_per_launch %s: ([0-9.eE+]+)$" % re.escape(kernel), text, re.M)
+    row = re.search(r"^traffic_bytes_per_launch %s sched %d: ([0-9.eE+]+)$" % (re.escape(kernel), sched),
+                    text, re.M)
     if not sha or not row or sha.group(1) != _sources_hash():
         return None
     return float(row.group(1))
@@ -307,6 +311,8 @@ def main():
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 leg")
     ap.add_argument("--no-tune", action="store_true",
                     help="default kernel schedules instead of the autotuner's (psfd_tune)")
+    ap.add_argument("--schedule", default=None,
+                    help="fixed kernel schedule of the mixed leg, 'xf,xi,y,ax' (no tuning)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-iters", type=int, default=4)
     ap.add_argument("--cpu-leg", type=float, default=None, help=argparse.SUPPRESS)
@@ -327,7 +333,8 @@ def main():
               "Run with --gpus 1.", file=sys.stderr)
         return 2
 
-    if not args.no_tune:
+    forced = tuple(int(v) for v in args.schedule.split(",")) if args.schedule else None
+    if not args.no_tune and forced is None:
         # plans pick up the autotuner's schedules (tuned once per shape, before timing)
         os.environ["PSFD_TUNE"] = "1"
     import torch
@@ -361,7 +368,9 @@ def main():
 
     prec_mixed = psfd.PSFD_C64_REFINE64
     schedules = {}
-    if not args.no_tune:
+    if forced is not None:
+        schedules["mixed"] = list(forced)
+    elif not args.no_tune:
         from psfd_synth import eps_absorber_default
         eps0 = psfd.psfd_layout_eps(cfgs[0], a_dev[0], eps_absorber_default())
         for name, prec in (("mixed", prec_mixed), ("fp64", psfd.PSFD_C128)):
@@ -371,7 +380,7 @@ def main():
         del eps0
         torch.cuda.synchronize()
     if W:
-        run_steps(psfd, cfgs, a_dev, range(K, K + W), prec_mixed, args.tol, args.maxit)
+        run_steps(psfd, cfgs, a_dev, range(K, K + W), prec_mixed, args.tol, args.maxit, sched=forced)
         if not args.no_fp64:
             run_steps(psfd, cfgs, a_dev, range(K, K + W), psfd.PSFD_C128, args.tol, args.maxit)
     torch.cuda.synchronize()
@@ -379,7 +388,7 @@ def main():
     # ---- timed: mixed precision (headline)
     t0 = time.perf_counter()
     infos_m, prof = run_steps(psfd, cfgs, a_dev, range(K), prec_mixed, args.tol, args.maxit,
-                              profile=args.roofline_kernel)
+                              profile=args.roofline_kernel, sched=forced)
     torch.cuda.synchronize()
     t_mixed = time.perf_counter() - t0
     print(f"bench: mixed leg {t_mixed:.3f} s", file=sys.stderr, flush=True)
@@ -397,11 +406,13 @@ def main():
     ok_m = all(i["status"] == "OK" and i["rrel"] <= args.tol for i in infos_m)
     value = nsolve / t_mixed
     ms, nl, by = prof
+    knob = {"xfwd": 0, "xinv": 1, "yfft": 2, "axial": 3}[args.roofline_kernel]
+    kernel_sched = schedules["mixed"][knob] if schedules else 0
     achieved = (by / (ms * 1e-3)) / 1e9 if ms > 0 else 0.0
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": measured_traffic(args.roofline_kernel),
-                "kernel": args.roofline_kernel, "launches": nl,
+                "traffic": measured_traffic(args.roofline_kernel, kernel_sched),
+                "kernel": args.roofline_kernel, "sched": kernel_sched, "launches": nl,
                 "avg_launch_us": round(1e3 * ms / max(nl, 1), 2),
                 "bytes_per_launch": by / max(nl, 1)}
     out = {

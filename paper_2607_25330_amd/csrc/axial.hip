@@ -480,9 +480,9 @@ static hipError_t axial_reg_launch(const OpTables<T>& t, const cplx<T>* S, cplx<
   if ((cols * L) % 256) return hipErrorInvalidValue;
   dim3 g((unsigned)(cols * L / 256 * t.nprob)), b(256);
   switch (mode) {
-    case AX_A: hipLaunchKernelGGL((k_axial_reg<T, NZ, L, AX_A>), g, b, 0, st, S, UW, t); break;
-    case AX_AM: hipLaunchKernelGGL((k_axial_reg<T, NZ, L, AX_AM>), g, b, 0, st, S, UW, t); break;
-    default: hipLaunchKernelGGL((k_axial_reg<T, NZ, L, AX_M>), g, b, 0, st, S, UW, t); break;
+    case AX_A: PSFD_LAUNCH(t, (k_axial_reg<T, NZ, L, AX_A>), g, b, st, S, UW, t); break;
+    case AX_AM: PSFD_LAUNCH(t, (k_axial_reg<T, NZ, L, AX_AM>), g, b, st, S, UW, t); break;
+    default: PSFD_LAUNCH(t, (k_axial_reg<T, NZ, L, AX_M>), g, b, st, S, UW, t); break;
   }
   return hipGetLastError();
 }
@@ -505,10 +505,10 @@ static hipError_t axial_n(const OpTables<T>& t, const cplx<T>* S, cplx<T>* UW, i
   if (t.nx % TX) return hipErrorInvalidValue;
   dim3 g(t.nx / TX, t.ny * t.nprob), b(256);
   switch (mode) {
-    case AX_A: hipLaunchKernelGGL((k_axial<T, NZ, TX, AX_A>), g, b, 0, st, S, UW, t); break;
-    case AX_AM: hipLaunchKernelGGL((k_axial<T, NZ, TX, AX_AM>), g, b, 0, st, S, UW, t); break;
-    case AX_AH: hipLaunchKernelGGL((k_axial<T, NZ, TX, AX_AH>), g, b, 0, st, S, UW, t); break;
-    default: hipLaunchKernelGGL((k_axial<T, NZ, TX, AX_M>), g, b, 0, st, S, UW, t); break;
+    case AX_A: PSFD_LAUNCH(t, (k_axial<T, NZ, TX, AX_A>), g, b, st, S, UW, t); break;
+    case AX_AM: PSFD_LAUNCH(t, (k_axial<T, NZ, TX, AX_AM>), g, b, st, S, UW, t); break;
+    case AX_AH: PSFD_LAUNCH(t, (k_axial<T, NZ, TX, AX_AH>), g, b, st, S, UW, t); break;
+    default: PSFD_LAUNCH(t, (k_axial<T, NZ, TX, AX_M>), g, b, st, S, UW, t); break;
   }
   return hipGetLastError();
 }

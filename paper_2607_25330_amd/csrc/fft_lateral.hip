@@ -331,15 +331,15 @@ static hipError_t xfwd_v(const OpTables<T>& t, const cplx<T>* in, cplx<T>* out, 
   dim3 grid((unsigned)((int64_t)g.bpp * g.nprob)), b(NT);
   switch (pre.mode) {
     case PRE_P:
-      hipLaunchKernelGGL((k_xfft_fwd<T, N, B, PRE_P, S>), grid, b, 0, st, in, out, t.tw_x, g, t.ny,
+      PSFD_LAUNCH(t, (k_xfft_fwd<T, N, B, PRE_P, S>), grid, b, st, in, out, t.tw_x, g, t.ny,
                          t.nz, t.j0, t.nabs, t.kd, pre);
       break;
     case PRE_S:
-      hipLaunchKernelGGL((k_xfft_fwd<T, N, B, PRE_S, S>), grid, b, 0, st, in, out, t.tw_x, g, t.ny,
+      PSFD_LAUNCH(t, (k_xfft_fwd<T, N, B, PRE_S, S>), grid, b, st, in, out, t.tw_x, g, t.ny,
                          t.nz, t.j0, t.nabs, t.kd, pre);
       break;
     default:
-      hipLaunchKernelGGL((k_xfft_fwd<T, N, B, PRE_NONE, S>), grid, b, 0, st, in, out, t.tw_x, g,
+      PSFD_LAUNCH(t, (k_xfft_fwd<T, N, B, PRE_NONE, S>), grid, b, st, in, out, t.tw_x, g,
                          t.ny, t.nz, t.j0, t.nabs, t.kd, pre);
       break;
   }
@@ -369,10 +369,10 @@ static void xinv_launch(const OpTables<T>& t, const cplx<T>* UW, cplx<T>* y, int
   if (nblk_out) *nblk_out = g.bpp;
   dim3 grid((unsigned)((int64_t)g.bpp * g.nprob)), b(NT);
   if (post.mode == POST_DOT)
-    hipLaunchKernelGGL((k_xfft_inv<T, N, B, CM, POST_DOT, S>), grid, b, 0, st, UW, y, t.tw_x, g,
+    PSFD_LAUNCH(t, (k_xfft_inv<T, N, B, CM, POST_DOT, S>), grid, b, st, UW, y, t.tw_x, g,
                        t.ny, t.nz, t.j0, t.nabs, scale, t.kd, x, post);
   else
-    hipLaunchKernelGGL((k_xfft_inv<T, N, B, CM, POST_NONE, S>), grid, b, 0, st, UW, y, t.tw_x, g,
+    PSFD_LAUNCH(t, (k_xfft_inv<T, N, B, CM, POST_NONE, S>), grid, b, st, UW, y, t.tw_x, g,
                        t.ny, t.nz, t.j0, t.nabs, scale, t.kd, x, post);
 }
 
@@ -409,10 +409,10 @@ static hipError_t y_v(const OpTables<T>& t, cplx<T>* buf, int nplanes, int64_t s
   if (t.nx % TX) return hipErrorInvalidValue;
   dim3 g(t.nx / TX, (unsigned)(nplanes * t.nprob));
   if (inv)
-    hipLaunchKernelGGL((k_yfft<T, N, TX, true, S>), g, dim3(NT), 0, st, buf, t.tw_y, t.nx, nplanes,
+    PSFD_LAUNCH(t, (k_yfft<T, N, TX, true, S>), g, dim3(NT), st, buf, t.tw_y, t.nx, nplanes,
                        stride, t.skip, t.skip_stride);
   else
-    hipLaunchKernelGGL((k_yfft<T, N, TX, false, S>), g, dim3(NT), 0, st, buf, t.tw_y, t.nx, nplanes,
+    PSFD_LAUNCH(t, (k_yfft<T, N, TX, false, S>), g, dim3(NT), st, buf, t.tw_y, t.nx, nplanes,
                        stride, t.skip, t.skip_stride);
   return hipGetLastError();
 }

@@ -272,18 +272,17 @@ hipEvent_t take_event(struct psfd_plan* P) {
   return e;
 }
 
-// Launch `fn` and, when kernel `which` is being timed, bracket it with events.
-template <typename F>
-hipError_t timed(struct psfd_plan* P, int which, int elem, double bytes, F&& fn) {
-  if (P->prof_kernel != which || P->prof_elem != elem) return fn();
+// When kernel `which` is being timed (psfd_profile_enable), give the tables a
+// pair of events for the next launch: the launch packet records them at the
+// kernel's start and end, so the pair brackets the kernel alone.
+template <typename T>
+hipError_t arm_events(struct psfd_plan* P, OpTables<T>& t, int which, double bytes) {
+  t.prof_start = t.prof_stop = nullptr;
+  if (P->prof_kernel != which || P->prof_elem != (int)sizeof(cplx<T>)) return hipSuccess;
   hipEvent_t a = take_event(P), b = take_event(P);
   if (!a || !b) return hipErrorOutOfMemory;
-  hipError_t e = hipEventRecord(a, P->st);
-  if (e != hipSuccess) return e;
-  e = fn();
-  if (e != hipSuccess) return e;
-  e = hipEventRecord(b, P->st);
-  if (e != hipSuccess) return e;
+  t.prof_start = a;
+  t.prof_stop = b;
   P->ev_open.emplace_back(a, b);
   P->prof_bytes += bytes;
   P->prof_launches += 1;
@@ -339,26 +338,29 @@ hipError_t op_apply(struct psfd_plan* P, const cplx<T>* x, cplx<T>* y, int op, c
   const int npre = fz.pre.mode == PRE_P ? 3 + 1 : (fz.pre.mode == PRE_S ? 2 + 1 : 1);
   int nb_first = 0;
   // x pass (forward): read the field (+ conj(kd) and absorber rows for the adjoint), write nin planes
-  e = timed(P, PROF_XFWD, (int)sizeof(cplx<T>), pl * (p3 * npre + nin + (adj ? pa + P->nabs : 0)),
-            [&] { return launch_xfft_fwd<T>(t, x, S, adj, fz.pre, &nb_first, st); });
+  e = arm_events(P, t, PROF_XFWD, pl * (p3 * npre + nin + (adj ? pa + P->nabs : 0)));
+  if (e == hipSuccess) e = launch_xfft_fwd<T>(t, x, S, adj, fz.pre, &nb_first, st);
   if (e != hipSuccess) return e;
+  t.prof_start = t.prof_stop = nullptr;
   if (fz.fin_first >= 0) {
     e = launch_finalize(fz.fin_first, P->ks, fz.pre.part, nb_first, P->G, P->pp, st);
     if (e != hipSuccess) return e;
   }
-  e = timed(P, PROF_YFFT, (int)sizeof(cplx<T>), 2.0 * pl * nin, [&] { return launch_yfft<T>(t, S, nin, false, st); });
+  e = arm_events(P, t, PROF_YFFT, 2.0 * pl * nin);
+  if (e == hipSuccess) e = launch_yfft<T>(t, S, nin, false, st);
   if (e != hipSuccess) return e;
-  e = timed(P, PROF_AXIAL, (int)sizeof(cplx<T>), pl * (nin + nout),
-            [&] { return launch_axial<T>(t, S, UW, ax_mode, st); });
+  e = arm_events(P, t, PROF_AXIAL, pl * (nin + nout));
+  if (e == hipSuccess) e = launch_axial<T>(t, S, UW, ax_mode, st);
   if (e != hipSuccess) return e;
-  e = timed(P, PROF_YFFT, (int)sizeof(cplx<T>), 2.0 * pl * nout, [&] { return launch_yfft<T>(t, UW, nout, true, st); });
+  e = arm_events(P, t, PROF_YFFT, 2.0 * pl * nout);
+  if (e == hipSuccess) e = launch_yfft<T>(t, UW, nout, true, st);
   if (e != hipSuccess) return e;
   double comb = cmode == CB_FWD ? pl * (nout + P->nabs + p3)
                                 : (cmode == CB_ADJ ? pl * (p3 + pa + P->nabs + p3) : 2.0 * pl * p3);
   if (fz.post.mode == POST_DOT) comb += pl * p3;
-  return timed(P, PROF_XINV, (int)sizeof(cplx<T>), comb, [&] {
-    return launch_xfft_inv<T>(t, UW, y, cmode, adj ? x : nullptr, fz.post, fz.nblk_post, st);
-  });
+  e = arm_events(P, t, PROF_XINV, comb);
+  if (e != hipSuccess) return e;
+  return launch_xfft_inv<T>(t, UW, y, cmode, adj ? x : nullptr, fz.post, fz.nblk_post, st);
 }
 
 psfd_status ensure_fp32(struct psfd_plan* P) {
@@ -624,47 +626,53 @@ psfd_status autotune(struct psfd_plan* P) {
   cplx<T>* y = reinterpret_cast<cplx<T>*>(P->tmp64);
   CHK(hipMemsetAsync(x, 0, sizeof(cplx<T>) * (size_t)(P->nfield * P->G), st));
   const int op = P->use_pc ? OP_AM : OP_A;
-  hipEvent_t e0 = nullptr, e1 = nullptr;
-  CHK(hipEventCreate(&e0));
-  CHK(hipEventCreate(&e1));
-  struct Ev {
-    hipEvent_t a, b;
-    ~Ev() { (void)hipEventDestroy(a); (void)hipEventDestroy(b); }
-  } ev{e0, e1};
-  auto measure = [&](const TuneVal& v, float* ms) -> psfd_status {
+  // Each knob is judged by the duration of the kernel it controls, taken
+  // from the launch packets' own timestamps (the profiling events).
+  const int saved_kernel = P->prof_kernel, saved_elem = P->prof_elem;
+  auto measure = [&](const TuneVal& v, int which, float* us) -> psfd_status {
     set_sched(tab<T>(P), v);
-    CHK(op_apply<T>(P, x, y, op, nullptr, 0));
+    P->prof_kernel = PROF_OFF;
+    CHK(op_apply<T>(P, x, y, op, nullptr, 0));  // first launch of new code objects
     float best = 1e30f;
-    for (int rep = 0; rep < 3; ++rep) {
-      CHK(hipEventRecord(e0, st));
-      for (int i = 0; i < 4; ++i) CHK(op_apply<T>(P, x, y, op, nullptr, 0));
-      CHK(hipEventRecord(e1, st));
-      CHK(hipEventSynchronize(e1));
-      float t = 0.f;
-      CHK(hipEventElapsedTime(&t, e0, e1));
-      best = std::min(best, t);
+    for (int rep = 0; rep < 5; ++rep) {
+      P->prof_kernel = which;
+      P->prof_elem = (int)sizeof(cplx<T>);
+      P->prof_ms = 0.0;
+      P->prof_launches = 0;
+      P->prof_bytes = 0.0;
+      for (int i = 0; i < 3; ++i) CHK(op_apply<T>(P, x, y, op, nullptr, 0));
+      CHK(hipStreamSynchronize(st));
+      collect_events(P);
+      if (P->prof_launches > 0) best = std::min(best, (float)(1e3 * P->prof_ms / P->prof_launches));
     }
-    *ms = best;
+    P->prof_kernel = PROF_OFF;
+    *us = best;
     return PSFD_OK;
   };
   TuneVal cur;
-  float cur_ms = 0.f;
-  CHKS(measure(cur, &cur_ms));
   const int order[4] = {3, 0, 1, 2};
   const int nval[4] = {4, 4, 4, 3};
+  const int kern[4] = {PROF_XFWD, PROF_XINV, PROF_YFFT, PROF_AXIAL};
   for (int k : order) {
+    float cur_us = 0.f;
+    CHKS(measure(cur, kern[k], &cur_us));
     for (int val = 0; val < nval[k]; ++val) {
       if (val == cur.v[k]) continue;
       TuneVal cand = cur;
       cand.v[k] = val;
-      float ms = 0.f;
-      CHKS(measure(cand, &ms));
-      if (ms < 0.98f * cur_ms) {
+      float us = 0.f;
+      CHKS(measure(cand, kern[k], &us));
+      if (us < 0.97f * cur_us) {  // keep the default unless clearly faster
         cur = cand;
-        cur_ms = ms;
+        cur_us = us;
       }
     }
   }
+  P->prof_kernel = saved_kernel;
+  P->prof_elem = saved_elem;
+  P->prof_ms = 0.0;
+  P->prof_launches = 0;
+  P->prof_bytes = 0.0;
   set_sched(tab<T>(P), cur);
   std::lock_guard<std::mutex> lk(g_tune_mu);
   g_tune[key] = cur;

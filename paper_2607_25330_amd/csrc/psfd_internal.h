@@ -1,5 +1,6 @@
 // Internal declarations shared by the host driver and the kernel files.
 #pragma once
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -53,7 +54,21 @@ struct OpTables {
   // operator kernels return at once for problem b
   const int* skip;
   int skip_stride;
+  // host side: when set, the operator kernel launched with these tables
+  // records the events from its own dispatch packet (kernel start / end)
+  hipEvent_t prof_start, prof_stop;
 };
+
+// Launch `kern` (parenthesised template-id) with the tables `t`; the
+// measurement events, when present, are recorded by the launch itself.
+#define PSFD_LAUNCH(t, kern, grid, block, st, ...)                                          \
+  do {                                                                                      \
+    if ((t).prof_start)                                                                     \
+      hipExtLaunchKernelGGL(kern, grid, block, 0, st, (t).prof_start, (t).prof_stop, 0,     \
+                            __VA_ARGS__);                                                   \
+    else                                                                                    \
+      hipLaunchKernelGGL(kern, grid, block, 0, st, __VA_ARGS__);                            \
+  } while (0)
 
 template <typename T>
 __host__ __device__ __forceinline__ bool skipped(const OpTables<T>& t, int b) {
