@@ -393,6 +393,28 @@ def main():
     t_mixed = time.perf_counter() - t0
     print(f"bench: mixed leg {t_mixed:.3f} s", file=sys.stderr, flush=True)
 
+    # whole-apply and whole-iteration roofline (survey 8(d) algorithmic units):
+    # one complex64 operator apply = read x + write y (48 B / voxel);
+    # one BiCGSTAB iteration = 20 field passes x 24 B = 480 B / voxel.
+    vox = 3 * nx * ny * (cfgs[0]["nz_abs"] + 16)  # complex elements of one field
+    eps0 = psfd.psfd_layout_eps(cfgs[0], a_dev[0], __import__("psfd_synth").eps_absorber_default())
+    plan = psfd.Plan(cfgs[0], eps0, prec_mixed)
+    if forced is not None:
+        plan.set_schedule(forced)
+    xa = torch.randn(plan.shape, dtype=torch.complex64, device=dev)
+    ya = torch.empty_like(xa)
+    for _ in range(3):
+        plan.apply_c64(xa, out=ya)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(20):
+        plan.apply_c64(xa, out=ya)
+    ev1.record()
+    torch.cuda.synchronize()
+    apply_us = 1e3 * ev0.elapsed_time(ev1) / 20
+    plan.close()
+    del xa, ya, eps0
+
     res = {}
     if not args.no_fp64:
         t0 = time.perf_counter()
@@ -427,6 +449,16 @@ def main():
         "iters_mixed": [i["iters"] for i in infos_m],
         "rrel_mixed_max": max(i["rrel"] for i in infos_m),
         "roofline": roofline,
+        "apply_roofline": {"unit": "one complex64 operator apply A x", "alg_bytes": 2 * 8 * vox,
+                           "us": round(apply_us, 1),
+                           "achieved_gbs": round(2 * 8 * vox / (apply_us * 1e-6) / 1e9, 1),
+                           "frac": round(2 * 8 * vox / (apply_us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4)},
+        "iteration_roofline": {"unit": "one BiCGSTAB iteration (2 A.M applies + updates)",
+                               "alg_bytes": 20 * 8 * vox,
+                               "us": round(1e6 * t_mixed / max(1, sum(i["iters"] for i in infos_m)), 1),
+                               "achieved_gbs": round(20 * 8 * vox / (t_mixed / max(1, sum(i["iters"] for i in infos_m))) / 1e9, 1),
+                               "frac": round(20 * 8 * vox / (t_mixed / max(1, sum(i["iters"] for i in infos_m))) / 1e9 / HBM_PEAK_GBS, 4),
+                               "note": "time per iteration includes plan, source and the FP64 reliable updates"},
         "schedules": schedules or "default",
     }
     if "fp64" in res:
