@@ -444,6 +444,11 @@ k_axial_reg(const cplx<T>* __restrict__ S_all, cplx<T>* __restrict__ UW_all, con
     const cplx<T> a1 = c.live ? c.rpe * ap : cplx<T>{T(0), T(0)};
 
     const int64_t wb = (int64_t)3 * NZ - t.j0;  // W row of z is wb + (z - j0) + comp * nabs
+    // exp(i kz z_abs) on this lane's absorber rows (z = lt + L m, every L-th
+    // row): evaluated at the first one, then stepped by exp(i kz L dz)
+    const int zf = t.j0 + ((lt - t.j0) % L + L) % L;  // first absorber-side row of the lane
+    cplx<T> ph = up_phase(c, (T(zf - t.j0) + T(0.5)) * t.dz);
+    const cplx<T> step = up_phase(c, T(L) * t.dz);
 #pragma unroll
     for (int m = 0; m < E; ++m) {
       const int z = lt + L * m;
@@ -452,8 +457,8 @@ k_axial_reg(const cplx<T>* __restrict__ S_all, cplx<T>* __restrict__ UW_all, con
       stv(NZ + L * m, (kx * kx - t.kbg2) * py[m] - (kx * ky) * px[m] + dy[m] * is);
       const int ja = z - t.j0;
       if (ja >= 0 && ja < t.nabs) {
-        const cplx<T> ph = up_phase(c, t.zabs[ja]);
         const cplx<T> vs = a0 * ph, vp = a1 * ph;
+        ph = ph * step;
         stv(wb + L * m, px[m] + (c.sx * vs + c.tx * vp));
         stv(wb + t.nabs + L * m, py[m] + (c.sy * vs + c.ty * vp));
         stv(wb + 2 * t.nabs + L * m, pz[m] - (c.ktkz * vp));

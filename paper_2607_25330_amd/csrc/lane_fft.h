@@ -159,9 +159,11 @@ struct LaneFft {
   cplx<T> tw[E];   // w_N^(t k2)
   cplx<T> cw[P];   // stage s (h = 2^s): w_2h^(t mod h) on the lanes with bit s set, else 1
   T sg[P];         // +1 on the lanes with bit s clear, -1 otherwise
+  bool rot;        // span-2 stage twiddle is not 1 (t mod 4 == 3)
 
   // tw_n: table exp(-2 pi i m / N), m = 0..N-1
   __device__ __forceinline__ void init(const cplx<T>* __restrict__ tw_n, int t) {
+    rot = (t & 3) == 3;
 #pragma unroll
     for (int k2 = 0; k2 < E; ++k2) tw[k2] = tw_n[t * k2];
 #pragma unroll
@@ -188,6 +190,14 @@ struct LaneFft {
   }
 
  private:
+  // The span-2 stage's twiddle is 1 or -i (forward) / +i (inverse): a swap
+  // with a sign instead of a complex product.
+  __device__ __forceinline__ cplx<T> rot_fwd(cplx<T> a) const {
+    return rot ? cplx<T>{a.im, -a.re} : a;
+  }
+  __device__ __forceinline__ cplx<T> rot_inv(cplx<T> a) const {
+    return rot ? cplx<T>{-a.im, a.re} : a;
+  }
   template <int S>
   __device__ __forceinline__ void stages_fwd(cplx<T> (&v)[E]) const {
     if constexpr (S >= 0) {
@@ -196,7 +206,8 @@ struct LaneFft {
       for (int k2 = 0; k2 < E; ++k2) {
         const cplx<T> p = lane_xor<H>(v[k2]);
         cplx<T> r = p + sg[S] * v[k2];
-        if constexpr (H > 1) r = r * cw[S];
+        if constexpr (H == 2) r = rot_fwd(r);
+        else if constexpr (H > 2) r = r * cw[S];
         v[k2] = r;
       }
       stages_fwd<S - 1>(v);
@@ -209,7 +220,8 @@ struct LaneFft {
 #pragma unroll
       for (int k2 = 0; k2 < E; ++k2) {
         cplx<T> a = v[k2];
-        if constexpr (H > 1) a = cmulc(cw[S], a);
+        if constexpr (H == 2) a = rot_inv(a);
+        else if constexpr (H > 2) a = cmulc(cw[S], a);
         const cplx<T> p = lane_xor<H>(a);
         v[k2] = p + sg[S] * a;
       }
