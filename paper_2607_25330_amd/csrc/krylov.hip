@@ -48,21 +48,10 @@ __device__ __forceinline__ cplx<double> ld2(const double* a) { return {a[0], a[1
 __device__ __forceinline__ void st2(double* a, cplx<double> v) { a[0] = v.re; a[1] = v.im; }
 
 // ---------------------------------------------------------------- finalize
-template <int STAGE>
-__global__ void __launch_bounds__(1024)
-k_finalize(KState* ks_all, const double* __restrict__ part_all, int nblocks,
-           const ProbParams* __restrict__ pp) {
-  KState* ks = ks_all + blockIdx.x;
-  const double* part = part_all + (size_t)blockIdx.x * nblocks * KPART;
-  const int d = ks->done;
-  bool run;
-  if (STAGE == FIN_INIT || STAGE == FIN_RED0) run = true;
-  else if (STAGE == FIN_RHO) run = (d == KS_RUN || d == KS_HALF);
-  else if (STAGE == FIN_REPLACE) run = (d == KS_UPDATE);
-  else run = (d == KS_RUN);
-  if (!run) return;
-  constexpr int NV = (STAGE == FIN_SNORM || STAGE == FIN_INIT || STAGE == FIN_RED0) ? 1 : 3;  // FIN_REPLACE: 3
-  double acc[NV];
+// Sum of nblocks partials (NV values each) over the block; thread 0 gets the totals.
+template <int NV>
+__device__ __forceinline__ void sum_partials(const double* __restrict__ part, int nblocks,
+                                             double (&acc)[NV]) {
 #pragma unroll
   for (int k = 0; k < NV; ++k) acc[k] = 0.0;
   for (int b = threadIdx.x; b < nblocks; b += 1024) {
@@ -79,13 +68,39 @@ k_finalize(KState* ks_all, const double* __restrict__ part_all, int nblocks,
     if (lane == 0) sm[k][wv] = v;
   }
   __syncthreads();
-  if (threadIdx.x != 0) return;
+  if (threadIdx.x == 0) {
 #pragma unroll
-  for (int k = 0; k < NV; ++k) {
-    double s = 0.0;
-    for (int w = 0; w < 16; ++w) s += sm[k][w];
-    acc[k] = s;
+    for (int k = 0; k < NV; ++k) {
+      double t = 0.0;
+      for (int w = 0; w < 16; ++w) t += sm[k][w];
+      acc[k] = t;
+    }
   }
+}
+
+template <int STAGE>
+__global__ void __launch_bounds__(1024)
+k_finalize(KState* ks_all, const double* __restrict__ part_all, int nblocks,
+           const ProbParams* __restrict__ pp, const double* __restrict__ part2_all,
+           int nblocks2) {
+  KState* ks = ks_all + blockIdx.x;
+  const double* part = part_all + (size_t)blockIdx.x * nblocks * KPART;
+  const int d = ks->done;
+  bool run;
+  if (STAGE == FIN_INIT || STAGE == FIN_RED0) run = true;
+  else if (STAGE == FIN_RHO) run = (d == KS_RUN || d == KS_HALF);
+  else if (STAGE == FIN_REPLACE) run = (d == KS_UPDATE);
+  else run = (d == KS_RUN);
+  if (!run) return;
+  constexpr int NV = (STAGE == FIN_INIT || STAGE == FIN_RED0) ? 1 : 3;
+  double s2[1] = {0.0};
+  if constexpr (STAGE == FIN_OMEGA) {
+    if (part2_all) sum_partials<1>(part2_all + (size_t)blockIdx.x * nblocks2 * KPART, nblocks2, s2);
+    __syncthreads();
+  }
+  double acc[NV];
+  sum_partials<NV>(part, nblocks, acc);
+  if (threadIdx.x != 0) return;
   if constexpr (STAGE == FIN_INIT) {
     const ProbParams q = pp[blockIdx.x];
     ks->rho[0] = acc[0];
@@ -114,16 +129,20 @@ k_finalize(KState* ks_all, const double* __restrict__ part_all, int nblocks,
     } else {
       st2(ks->alpha, cdiv(ld2(ks->rho), rv));
     }
-  } else if constexpr (STAGE == FIN_SNORM) {
-    ks->snorm2 = acc[0];
-    if (acc[0] <= ks->tol2 * ks->bnorm2) {
-      ks->half = 1;
-      ks->done = KS_HALF;
-    } else if (!(acc[0] < 1e24 * ks->bnorm2)) {
-      ks->status = 2;  // diverged (or not finite)
-      ks->done = KS_BREAK;
-    }
   } else if constexpr (STAGE == FIN_OMEGA) {
+    if (part2_all) {  // half-step test on ||s|| (partials of the forward x pass)
+      ks->snorm2 = s2[0];
+      if (s2[0] <= ks->tol2 * ks->bnorm2) {
+        ks->half = 1;
+        ks->done = KS_HALF;
+        return;
+      }
+      if (!(s2[0] < 1e24 * ks->bnorm2)) {
+        ks->status = 2;  // diverged (or not finite)
+        ks->done = KS_BREAK;
+        return;
+      }
+    }
     // partials hold sum conj(s) t; <t, s> is its conjugate
     const cplx<double> ts = {acc[0], -acc[1]};
     const double tt = acc[2];
@@ -179,17 +198,19 @@ k_finalize(KState* ks_all, const double* __restrict__ part_all, int nblocks,
 }
 
 hipError_t launch_finalize(int stage, KState* ks, const double* part, int nblocks, int nprob,
-                           const ProbParams* pp, hipStream_t st) {
+                           const ProbParams* pp, hipStream_t st, const double* part2,
+                           int nblocks2) {
   dim3 g(nprob), b(1024);
+#define PSFD_FIN(S) hipLaunchKernelGGL(k_finalize<S>, g, b, 0, st, ks, part, nblocks, pp, part2, nblocks2)
   switch (stage) {
-    case FIN_INIT: hipLaunchKernelGGL(k_finalize<FIN_INIT>, g, b, 0, st, ks, part, nblocks, pp); break;
-    case FIN_ALPHA: hipLaunchKernelGGL(k_finalize<FIN_ALPHA>, g, b, 0, st, ks, part, nblocks, pp); break;
-    case FIN_SNORM: hipLaunchKernelGGL(k_finalize<FIN_SNORM>, g, b, 0, st, ks, part, nblocks, pp); break;
-    case FIN_OMEGA: hipLaunchKernelGGL(k_finalize<FIN_OMEGA>, g, b, 0, st, ks, part, nblocks, pp); break;
-    case FIN_RHO: hipLaunchKernelGGL(k_finalize<FIN_RHO>, g, b, 0, st, ks, part, nblocks, pp); break;
-    case FIN_REPLACE: hipLaunchKernelGGL(k_finalize<FIN_REPLACE>, g, b, 0, st, ks, part, nblocks, pp); break;
-    default: hipLaunchKernelGGL(k_finalize<FIN_RED0>, g, b, 0, st, ks, part, nblocks, pp); break;
+    case FIN_INIT: PSFD_FIN(FIN_INIT); break;
+    case FIN_ALPHA: PSFD_FIN(FIN_ALPHA); break;
+    case FIN_OMEGA: PSFD_FIN(FIN_OMEGA); break;
+    case FIN_RHO: PSFD_FIN(FIN_RHO); break;
+    case FIN_REPLACE: PSFD_FIN(FIN_REPLACE); break;
+    default: PSFD_FIN(FIN_RED0); break;
   }
+#undef PSFD_FIN
   return hipGetLastError();
 }
 

@@ -117,6 +117,7 @@ struct psfd_plan {
   int* idle = nullptr;  // [G] 1: problem finished (skipped by operator kernels)
   int* idle_host = nullptr;
   double* part = nullptr;
+  double* part2 = nullptr;  // ||s||^2 partials of the forward x pass (read with omega's)
 
   // batch handle (psfd_plan_batch): the recorded problems
   bool is_batch = false;
@@ -301,14 +302,13 @@ void collect_events(struct psfd_plan* P) {
 }
 
 // Fusion hooks of one operator application: a vector update folded into the
-// first x pass (with an optional finalize launched right after it) and inner
-// products folded into the last x pass.
+// first x pass and inner products folded into the last x pass.
 template <typename T>
 struct Fuse {
   PreOp<T> pre;
-  int fin_first = -1;  // finalize stage after the first x pass (partials from pre)
   PostOp<T> post;
   int* nblk_post = nullptr;  // receives the number of partials per problem written by post
+  int* nblk_pre = nullptr;   // receives the number of partials per problem written by pre
 };
 
 constexpr int kKsStride = (int)(sizeof(KState) / sizeof(int));
@@ -341,11 +341,8 @@ hipError_t op_apply(struct psfd_plan* P, const cplx<T>* x, cplx<T>* y, int op, c
   e = arm_events(P, t, PROF_XFWD, pl * (p3 * npre + nin + (adj ? pa + P->nabs : 0)));
   if (e == hipSuccess) e = launch_xfft_fwd<T>(t, x, S, adj, fz.pre, &nb_first, st);
   if (e != hipSuccess) return e;
+  if (fz.nblk_pre) *fz.nblk_pre = nb_first;
   t.prof_start = t.prof_stop = nullptr;
-  if (fz.fin_first >= 0) {
-    e = launch_finalize(fz.fin_first, P->ks, fz.pre.part, nb_first, P->G, P->pp, st);
-    if (e != hipSuccess) return e;
-  }
   e = arm_events(P, t, PROF_YFFT, 2.0 * pl * nin);
   if (e == hipSuccess) e = launch_yfft<T>(t, S, nin, false, st);
   if (e != hipSuccess) return e;
@@ -388,6 +385,7 @@ psfd_status ensure_solver_common(struct psfd_plan* P) {
   // (x pass rows, or the streaming kernels' blocks)
   const int64_t per = (int64_t)(3 * P->nz + 3 * P->nabs) * P->ny + 2048;
   CHKS(dalloc(P, &P->part, (size_t)(per * KPART * G)));
+  CHKS(dalloc(P, &P->part2, (size_t)(per * KPART * G)));
   CHKS(dalloc(P, &P->b64, (size_t)(P->nfield * G)));
   CHKS(dalloc(P, &P->tmp64, (size_t)(P->nfield * G)));
   CHKS(dalloc(P, &P->res64, (size_t)(P->nfield * G)));
@@ -452,7 +450,7 @@ psfd_status run_bicgstab(struct psfd_plan* P, bool adjoint, int maxit, U&& on_up
     if (!pc) return op_apply<T>(P, in, out, OP_AH, skip, kKsStride, fz);
     Fuse<T> f1, f2;
     f1.pre = fz.pre;
-    f1.fin_first = fz.fin_first;
+    f1.nblk_pre = fz.nblk_pre;
     f2.post = fz.post;
     f2.nblk_post = fz.nblk_post;
     hipError_t e = op_apply<T>(P, in, V[V_W], OP_M, skip, kKsStride, f1);
@@ -461,7 +459,7 @@ psfd_status run_bicgstab(struct psfd_plan* P, bool adjoint, int maxit, U&& on_up
   };
   // the unpreconditioned adjoint transforms extra rows of the input: update p separately
   const bool fuse_p = !(adjoint && !pc);
-  int nb_v = 0, nb_t = 0;
+  int nb_v = 0, nb_t = 0, nb_s = 0;
   auto launch_iters = [&](int count) -> psfd_status {
     for (int i = 0; i < count; ++i) {
       Fuse<T> fa;
@@ -487,14 +485,15 @@ psfd_status run_bicgstab(struct psfd_plan* P, bool adjoint, int maxit, U&& on_up
       fb.pre.pv = V[V_S];
       fb.pre.v = V[V_V];
       fb.pre.ks = ks;
-      fb.pre.part = part;
-      fb.fin_first = FIN_SNORM;
+      fb.pre.part = P->part2;
+      fb.nblk_pre = &nb_s;
       fb.post.mode = POST_DOT;
       fb.post.d = V[V_S];
       fb.post.part = part;
       fb.nblk_post = &nb_t;
       CHK(apply(V[V_S], V[V_T], fb));
-      CHK(launch_finalize(FIN_OMEGA, ks, part, nb_t, G, P->pp, st));
+      // omega, with the half-step test on ||s|| from the forward pass's partials
+      CHK(launch_finalize(FIN_OMEGA, ks, part, nb_t, G, P->pp, st, P->part2, nb_s));
 
       CHK(launch_k_xr_update<T>(V[V_Y], V[V_R], V[V_P], V[V_S], V[V_T], V[V_RH], n, G, ks, part,
                                 st));

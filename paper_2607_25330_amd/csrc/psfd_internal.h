@@ -197,13 +197,16 @@ struct ProbParams {
   double pad;
 };
 
-enum FinStage { FIN_INIT = 0, FIN_ALPHA, FIN_SNORM, FIN_OMEGA, FIN_RHO, FIN_RED0, FIN_REPLACE };
+enum FinStage { FIN_INIT = 0, FIN_ALPHA, FIN_OMEGA, FIN_RHO, FIN_RED0, FIN_REPLACE };
 // Krylov state of a problem (KState::done)
 enum { KS_RUN = 0, KS_CONV = 1, KS_HALF = 2, KS_BREAK = 3, KS_IDLE = 4, KS_MAXIT = 5, KS_UPDATE = 6 };
 // One block per problem: sum problem b's `nblocks` partials (they start at
 // part + b * nblocks * KPART) and update ks[b] for one stage of the recurrence.
+// FIN_OMEGA also sums the ||s||^2 partials of the forward x pass (part2,
+// nblocks2 per problem) and takes the half-step decision there.
 hipError_t launch_finalize(int stage, KState* ks, const double* part, int nblocks, int nprob,
-                           const ProbParams* pp, hipStream_t st);
+                           const ProbParams* pp, hipStream_t st, const double* part2 = nullptr,
+                           int nblocks2 = 0);
 
 // Streaming vector kernels over a group: n = elements of one problem; problem
 // b's vectors start at b * n; grid = nprob * red_blocks(n) blocks.

@@ -201,6 +201,23 @@ def test_solve_mixed_matches_oracle(psfd, small_ref, prec):
     plan.close()
 
 
+def test_mixed_reliable_updates_and_restart_form_agree(psfd, small_ref, monkeypatch):
+    """The mixed solve with reliable updates (default) and with plain restarts
+    (PSFD_RELIABLE=0) both reach the FP64 oracle field within the mixed bar,
+    for a tolerance that needs several residual replacements."""
+    cfg, eps, P, E_ref = small_ref[1]
+    out = {}
+    for mode in ("1", "0"):
+        monkeypatch.setenv("PSFD_RELIABLE", mode)
+        plan = psfd.Plan(cfg, dev(eps), prec=psfd.PSFD_C64_REFINE64)
+        E, info = plan.solve(tol=1e-10)
+        plan.close()
+        assert info["status"] == "OK" and info["rrel"] <= 1e-10
+        out[mode] = host(E)
+        assert np.linalg.norm(out[mode] - E_ref) / np.linalg.norm(E_ref) <= 1e-7
+    assert np.linalg.norm(out["1"] - out["0"]) / np.linalg.norm(E_ref) <= 2e-7
+
+
 def test_solve_unpreconditioned_and_warm_start(psfd, small_ref):
     cfg, eps, P, E_ref = small_ref[0]
     plan0 = psfd.Plan(dict(cfg, precond=0), dev(eps))
