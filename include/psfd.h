@@ -236,16 +236,17 @@ psfd_status psfd_profile_read(psfd_plan_t p, double* total_ms, int64_t* launches
  * each candidate schedule of one knob at a time -- radix schedule (radix 8 or
  * radix 4 first) and rows per block of the forward and of the inverse x pass,
  * radix schedule and tile width of the y pass, axial kernel variant
- * (register-resident with L or 2L lanes per column, or LDS-staged) -- and
+ * (register-resident with L, 2L or L/2 lanes per column, or LDS-staged) -- and
  * keeps the fastest; results are cached per (precision, nx, ny, Nz, nz_abs,
  * group size) for the life of the process.  Synchronises the plan's stream.
  * Schedules change the rounding of the FFTs, never the operator.  A plan made
  * by psfd_plan uses the default schedules unless psfd_tune is called or
  * PSFD_TUNE=1 is set.  psfd_schedule writes the plan's current schedules to
  * sched[4] (host): forward x pass, inverse x pass, y pass (bit 0: radix-4
- * schedule, bit 1: half the rows / tile width), axial variant (0, 1, 2).
- * psfd_set_schedule sets them (both precisions) from sched[4] (host; values
- * 0..3, axial 0..2, else PSFD_ERR_ARG) after draining the plan's stream. */
+ * schedule, bit 1: half the rows / tile width), axial variant (0: L lanes,
+ * 1: 2L lanes, 2: LDS-staged, 3: L/2 lanes).  psfd_set_schedule sets them
+ * (both precisions) from sched[4] (host; values 0..3, else PSFD_ERR_ARG)
+ * after draining the plan's stream. */
 psfd_status psfd_tune(psfd_plan_t p);
 psfd_status psfd_schedule(psfd_plan_t p, int32_t* sched);
 psfd_status psfd_set_schedule(psfd_plan_t p, const int32_t* sched);

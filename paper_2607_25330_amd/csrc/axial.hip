@@ -367,6 +367,19 @@ k_axial_reg(const cplx<T>* __restrict__ S_all, cplx<T>* __restrict__ UW_all, con
     }
     return;
   } else {
+    // Column data parked in LDS: each lane stores and reloads only its own
+    // slots ([slot][register][lane], conflict-free), so no barrier is needed.
+    __shared__ cplx<T> park[2 * E * 256];
+    auto park_st = [&](int slot, const cplx<T>(&v)[E]) {
+#pragma unroll
+      for (int k = 0; k < E; ++k) park[(slot * E + k) * 256 + threadIdx.x] = v[k];
+    };
+    auto park_ld = [&](int slot, cplx<T>(&v)[E]) {
+#pragma unroll
+      for (int k = 0; k < E; ++k) v[k] = park[(slot * E + k) * 256 + threadIdx.x];
+    };
+    // P_t at the evaluation row (the multilayer branch reads it there)
+    cplx<T> ex = {T(0), T(0)}, ey = {T(0), T(0)};
     cplx<T> dx[E], dy[E];
     if constexpr (MODE == AX_AM) {
       F.fwd(px);
@@ -379,16 +392,41 @@ k_axial_reg(const cplx<T>* __restrict__ S_all, cplx<T>* __restrict__ UW_all, con
         px[k2] = m * px[k2];
         py[k2] = m * py[k2];
         pz[k2] = m * pz[k2];
-        dx[k2] = kzl * mul_i(px[k2]);
-        dy[k2] = kzl * mul_i(py[k2]);
       }
+      // P(jev) = sum_k P^[k] exp(+2 pi i k jev / NZ): this lane's terms, then the group sum
+#pragma unroll
+      for (int k2 = 0; k2 < E; ++k2) {
+        const cplx<T> w = conj(t.tw_z[((k2 + kofs) * t.jev) % NZ]);
+        ex = ex + px[k2] * w;
+        ey = ey + py[k2] * w;
+      }
+      ex = lane_group_sum<L>(ex);
+      ey = lane_group_sum<L>(ey);
+#pragma unroll
+      for (int k2 = 0; k2 < E; ++k2) dx[k2] = t.kz[k2 + kofs] * mul_i(px[k2]);
+      park_st(0, px);
+#pragma unroll
+      for (int k2 = 0; k2 < E; ++k2) dy[k2] = t.kz[k2 + kofs] * mul_i(py[k2]);
+      park_st(1, py);
       F.inv(pz);
     } else {
+      const int mj = t.jev / L, tj = t.jev % L;
+#pragma unroll
+      for (int m = 0; m < E; ++m) {
+        if (m == mj) {
+          ex = px[m];
+          ey = py[m];
+        }
+      }
+      ex = {__shfl(ex.re, tj, L), __shfl(ex.im, tj, L)};
+      ey = {__shfl(ey.re, tj, L), __shfl(ey.im, tj, L)};
 #pragma unroll
       for (int m = 0; m < E; ++m) {
         dx[m] = px[m];
         dy[m] = py[m];
       }
+      park_st(0, px);
+      park_st(1, py);
       F.fwd(dx);
       F.fwd(dy);
 #pragma unroll
@@ -400,14 +438,38 @@ k_axial_reg(const cplx<T>* __restrict__ S_all, cplx<T>* __restrict__ UW_all, con
     }
     F.inv(dx);
     F.inv(dy);
-    // U_z and the inner curl vectors w = -D P_t + i k_t P_z (z layout)
+
+    // multilayer amplitudes from the tangential P at the evaluation row
+    ColInfo<T> c;
+    column_info(c, t, pb, ix, iy);
+    const cplx<T> as = (c.sx * ex + c.sy * ey) * c.down;
+    const cplx<T> ap = (c.tx * ex + c.ty * ey) * c.down;
+    const cplx<T> a0 = c.live ? c.rte * as : cplx<T>{T(0), T(0)};
+    const cplx<T> a1 = c.live ? c.rpe * ap : cplx<T>{T(0), T(0)};
+    // exp(i kz z_abs) on this lane's absorber rows (z = lt + L m, every L-th
+    // row): evaluated at the first one, then stepped by exp(i kz L dz)
+    const int zf = t.j0 + ((lt - t.j0) % L + L) % L;
+    const cplx<T> ph0 = up_phase(c, (T(zf - t.j0) + T(0.5)) * t.dz);
+    const cplx<T> step = up_phase(c, T(L) * t.dz);
+    const int64_t wb = (int64_t)3 * NZ - t.j0;  // W row of z is wb + (z - j0) + comp * nabs
+
+    // U_z, the inner curl vectors w = -D P_t + i k_t P_z, and the W_z rows
+    {
+      cplx<T> ph = ph0;
 #pragma unroll
-    for (int m = 0; m < E; ++m) {
-      const cplx<T> is = t.inv_s[lt + L * m];
-      const cplx<T> dpx = dx[m] * is, dpy = dy[m] * is;
-      stv(2 * NZ + L * m, kx * mul_i(dpx) + ky * mul_i(dpy) + (kt2 - t.kbg2) * pz[m]);
-      dx[m] = kx * mul_i(pz[m]) - dpx;
-      dy[m] = ky * mul_i(pz[m]) - dpy;
+      for (int m = 0; m < E; ++m) {
+        const int z = lt + L * m;
+        const cplx<T> is = t.inv_s[z];
+        const cplx<T> dpx = dx[m] * is, dpy = dy[m] * is;
+        stv(2 * NZ + L * m, kx * mul_i(dpx) + ky * mul_i(dpy) + (kt2 - t.kbg2) * pz[m]);
+        dx[m] = kx * mul_i(pz[m]) - dpx;
+        dy[m] = ky * mul_i(pz[m]) - dpy;
+        const int ja = z - t.j0;
+        if (ja >= 0 && ja < t.nabs) {
+          stv(wb + 2 * t.nabs + L * m, pz[m] - c.ktkz * (a1 * ph));
+          ph = ph * step;
+        }
+      }
     }
     F.fwd(dx);
     F.fwd(dy);
@@ -419,49 +481,42 @@ k_axial_reg(const cplx<T>* __restrict__ S_all, cplx<T>* __restrict__ UW_all, con
     }
     F.inv(dx);
     F.inv(dy);
-    if constexpr (MODE == AX_AM) {
-      F.inv(px);
-      F.inv(py);
-    }
 
-    // multilayer amplitudes from the tangential P at the evaluation row
-    ColInfo<T> c;
-    column_info(c, t, pb, ix, iy);
-    const int mj = t.jev / L, tj = t.jev % L;
-    cplx<T> ex = {T(0), T(0)}, ey = {T(0), T(0)};
+    // U_x = (ky^2 - kbg^2) P_x - kx ky P_y + D w_x,  U_y = -kx ky P_x + (kx^2 - kbg^2) P_y + D w_y:
+    // P_x first (then its W rows), P_y second
+    const T cxx = ky * ky - t.kbg2, cxy = -(kx * ky), cyy = kx * kx - t.kbg2;
+    {
+      cplx<T>(&q)[E] = pz;  // P_z is no longer needed: reuse its registers
+      park_ld(0, q);
+      if constexpr (MODE == AX_AM) F.inv(q);
+      cplx<T> ph = ph0;
 #pragma unroll
-    for (int m = 0; m < E; ++m) {
-      if (m == mj) {
-        ex = px[m];
-        ey = py[m];
+      for (int m = 0; m < E; ++m) {
+        const int z = lt + L * m;
+        const cplx<T> is = t.inv_s[z];
+        dx[m] = dx[m] * is + cxx * q[m];
+        dy[m] = dy[m] * is + cxy * q[m];
+        const int ja = z - t.j0;
+        if (ja >= 0 && ja < t.nabs) {
+          const cplx<T> vs = a0 * ph, vp = a1 * ph;
+          stv(wb + L * m, q[m] + (c.sx * vs + c.tx * vp));
+          ph = ph * step;
+        }
       }
-    }
-    ex = {__shfl(ex.re, tj, L), __shfl(ex.im, tj, L)};
-    ey = {__shfl(ey.re, tj, L), __shfl(ey.im, tj, L)};
-    const cplx<T> as = (c.sx * ex + c.sy * ey) * c.down;
-    const cplx<T> ap = (c.tx * ex + c.ty * ey) * c.down;
-    const cplx<T> a0 = c.live ? c.rte * as : cplx<T>{T(0), T(0)};
-    const cplx<T> a1 = c.live ? c.rpe * ap : cplx<T>{T(0), T(0)};
-
-    const int64_t wb = (int64_t)3 * NZ - t.j0;  // W row of z is wb + (z - j0) + comp * nabs
-    // exp(i kz z_abs) on this lane's absorber rows (z = lt + L m, every L-th
-    // row): evaluated at the first one, then stepped by exp(i kz L dz)
-    const int zf = t.j0 + ((lt - t.j0) % L + L) % L;  // first absorber-side row of the lane
-    cplx<T> ph = up_phase(c, (T(zf - t.j0) + T(0.5)) * t.dz);
-    const cplx<T> step = up_phase(c, T(L) * t.dz);
+      park_ld(1, q);
+      if constexpr (MODE == AX_AM) F.inv(q);
+      ph = ph0;
 #pragma unroll
-    for (int m = 0; m < E; ++m) {
-      const int z = lt + L * m;
-      const cplx<T> is = t.inv_s[z];
-      stv(L * m, (ky * ky - t.kbg2) * px[m] - (kx * ky) * py[m] + dx[m] * is);
-      stv(NZ + L * m, (kx * kx - t.kbg2) * py[m] - (kx * ky) * px[m] + dy[m] * is);
-      const int ja = z - t.j0;
-      if (ja >= 0 && ja < t.nabs) {
-        const cplx<T> vs = a0 * ph, vp = a1 * ph;
-        ph = ph * step;
-        stv(wb + L * m, px[m] + (c.sx * vs + c.tx * vp));
-        stv(wb + t.nabs + L * m, py[m] + (c.sy * vs + c.ty * vp));
-        stv(wb + 2 * t.nabs + L * m, pz[m] - (c.ktkz * vp));
+      for (int m = 0; m < E; ++m) {
+        const int z = lt + L * m;
+        stv(L * m, dx[m] + cxy * q[m]);
+        stv(NZ + L * m, dy[m] + cyy * q[m]);
+        const int ja = z - t.j0;
+        if (ja >= 0 && ja < t.nabs) {
+          const cplx<T> vs = a0 * ph, vp = a1 * ph;
+          stv(wb + t.nabs + L * m, q[m] + (c.sy * vs + c.ty * vp));
+          ph = ph * step;
+        }
       }
     }
   }
@@ -493,7 +548,7 @@ static hipError_t axial_reg_launch(const OpTables<T>& t, const cplx<T>* S, cplx<
 }
 
 // sched_ax: 0 register kernel (L lanes per column), 1 register kernel with
-// 2L lanes, 2 LDS-staged kernel.  The adjoint and Nz > 64 always use the LDS
+// 2L lanes, 2 LDS-staged kernel, 3 register kernel with L/2 lanes.  The adjoint and Nz > 64 always use the LDS
 // kernel; PSFD_AXIAL_LDS forces it everywhere.
 template <typename T, int NZ>
 static hipError_t axial_n(const OpTables<T>& t, const cplx<T>* S, cplx<T>* UW, int mode,
@@ -502,7 +557,9 @@ static hipError_t axial_n(const OpTables<T>& t, const cplx<T>* S, cplx<T>* UW, i
   if constexpr (L > 0) {
     if (!t.ax_lds && mode != AX_AH && t.sched_ax != 2) {
       constexpr int L2 = (2 * L <= 16 && NZ % (2 * L) == 0) ? 2 * L : L;
+      constexpr int Lh = (L >= 4 && NZ % (L / 2) == 0 && NZ / (L / 2) <= 16) ? L / 2 : L;
       if (t.sched_ax == 1) return axial_reg_launch<T, NZ, L2>(t, S, UW, mode, st);
+      if (t.sched_ax == 3) return axial_reg_launch<T, NZ, Lh>(t, S, UW, mode, st);
       return axial_reg_launch<T, NZ, L>(t, S, UW, mode, st);
     }
   }

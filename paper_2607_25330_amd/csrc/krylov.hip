@@ -35,10 +35,12 @@ namespace psfd {
 constexpr double kOmegaLimit = 0.7;
 
 int red_blocks(int64_t n, int nprob) {
-  // at most 2048 blocks per problem and about 32k blocks per launch
+  // at most 8192 blocks per problem (enough waves in flight to keep the
+  // streaming kernels at the copy rate) and 128k blocks per launch, so that
+  // groups of up to 16 problems use the per-problem grid of a single solve
   int64_t b = (n + KRED_THREADS - 1) / KRED_THREADS;
-  int64_t cap = 32768 / (nprob > 0 ? nprob : 1);
-  if (cap > 2048) cap = 2048;
+  int64_t cap = 131072 / (nprob > 0 ? nprob : 1);
+  if (cap > 8192) cap = 8192;
   if (b > cap) b = cap;
   if (b < 1) b = 1;
   return (int)b;
@@ -241,15 +243,32 @@ k_xr_update(cplx<T>* __restrict__ y, cplx<T>* __restrict__ r, const cplx<T>* __r
     PSFD_GROUP_LOOP(i) y[i] = y[i] + al * p[i];
   } else {
     const cplx<T> om = cast<T>(ld2(ks->omega));
-    PSFD_GROUP_LOOP(i) {
-      const cplx<T> si = s[i];
-      y[i] = y[i] + al * p[i] + om * si;
-      const cplx<T> ri = si - om * t[i];
-      r[i] = ri;
-      const cplx<double> a = cast<double>(rh[i]), b = cast<double>(ri);
-      acc[0] += norm2(b);
-      acc[1] += a.re * b.re + a.im * b.im;
-      acc[2] += a.re * b.im - a.im * b.re;
+    // two elements per trip: all ten loads are issued before the first use
+    const int bpp = gridDim.x / nprob;
+    const int64_t off = (int64_t)(blockIdx.x / bpp) * n;
+    const int64_t step = (int64_t)bpp * blockDim.x;
+    for (int64_t i = (int64_t)(blockIdx.x % bpp) * blockDim.x + threadIdx.x; i < n; i += 2 * step) {
+      const bool two = i + step < n;
+      const int64_t i0 = off + i, i1 = off + (two ? i + step : i);
+      const cplx<T> s0 = s[i0], s1 = s[i1], t0 = t[i0], t1 = t[i1];
+      const cplx<T> y0 = y[i0], y1 = y[i1], p0 = p[i0], p1 = p[i1];
+      const cplx<T> h0 = rh[i0], h1 = rh[i1];
+      const cplx<T> r0 = s0 - om * t0;
+      y[i0] = y0 + al * p0 + om * s0;
+      r[i0] = r0;
+      const cplx<double> a0 = cast<double>(h0), b0 = cast<double>(r0);
+      acc[0] += norm2(b0);
+      acc[1] += a0.re * b0.re + a0.im * b0.im;
+      acc[2] += a0.re * b0.im - a0.im * b0.re;
+      if (two) {
+        const cplx<T> r1 = s1 - om * t1;
+        y[i1] = y1 + al * p1 + om * s1;
+        r[i1] = r1;
+        const cplx<double> a1 = cast<double>(h1), b1 = cast<double>(r1);
+        acc[0] += norm2(b1);
+        acc[1] += a1.re * b1.re + a1.im * b1.im;
+        acc[2] += a1.re * b1.im - a1.im * b1.re;
+      }
     }
   }
   block_partials<3, KRED_THREADS>(acc, part);

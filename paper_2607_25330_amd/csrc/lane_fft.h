@@ -143,6 +143,16 @@ __device__ __forceinline__ cplx<T> lane_xor(cplx<T> v) {
   return {lane_xor<H>(v.re), lane_xor<H>(v.im)};
 }
 
+// Sum of v over the L lanes of a group (every lane gets the sum).
+template <int L, typename T>
+__device__ __forceinline__ cplx<T> lane_group_sum(cplx<T> v) {
+  if constexpr (L >= 2) v = v + lane_xor<1>(v);
+  if constexpr (L >= 4) v = v + lane_xor<2>(v);
+  if constexpr (L >= 8) v = v + lane_xor<4>(v);
+  if constexpr (L >= 16) v = v + lane_xor<8>(v);
+  return v;
+}
+
 template <int L>
 __device__ __forceinline__ int lane_brev(int t) {
   int r = 0;

@@ -383,7 +383,7 @@ psfd_status ensure_solver_common(struct psfd_plan* P) {
   CHKS(dalloc(P, &P->idle, (size_t)G));
   // per problem: one partial set per block of the largest reducing grid
   // (x pass rows, or the streaming kernels' blocks)
-  const int64_t per = (int64_t)(3 * P->nz + 3 * P->nabs) * P->ny + 2048;
+  const int64_t per = (int64_t)(3 * P->nz + 3 * P->nabs) * P->ny + 8192;
   CHKS(dalloc(P, &P->part, (size_t)(per * KPART * G)));
   CHKS(dalloc(P, &P->part2, (size_t)(per * KPART * G)));
   CHKS(dalloc(P, &P->b64, (size_t)(P->nfield * G)));
@@ -662,7 +662,7 @@ psfd_status autotune(struct psfd_plan* P) {
   };
   TuneVal cur;
   const int order[4] = {3, 0, 1, 2};
-  const int nval[4] = {4, 4, 4, 3};
+  const int nval[4] = {4, 4, 4, 4};
   const int kern[4] = {PROF_XFWD, PROF_XINV, PROF_YFFT, PROF_AXIAL};
   for (int k : order) {
     float cur_us = 0.f;
@@ -1467,7 +1467,7 @@ psfd_status psfd_tune(psfd_plan_t p) {
 psfd_status psfd_set_schedule(psfd_plan_t p, const int32_t* sched) {
   if (!p || p->is_batch || !sched) return fail(PSFD_ERR_ARG, "NULL argument or batch handle");
   for (int k = 0; k < 4; ++k)
-    if (sched[k] < 0 || sched[k] > (k == 3 ? 2 : 3)) return fail(PSFD_ERR_ARG, "schedule out of range");
+    if (sched[k] < 0 || sched[k] > 3) return fail(PSFD_ERR_ARG, "schedule out of range");
   return guarded([&]() -> psfd_status {
     CHK(p->st ? hipStreamSynchronize(p->st) : hipDeviceSynchronize());
     for (auto& row : p->gexec)

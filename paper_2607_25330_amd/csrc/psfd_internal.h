@@ -48,7 +48,7 @@ struct OpTables {
   // kernel schedules chosen by the autotuner (0 = default): forward x pass,
   // inverse x pass, y pass (bit 0 radix schedule, bit 1 half rows / tile);
   // axial kernel (0 register kernel, 1 register kernel with twice the lanes,
-  // 2 LDS-staged kernel)
+  // 2 LDS-staged kernel, 3 register kernel with half the lanes)
   int sched_xf, sched_xi, sched_y, sched_ax;
   // per-problem skip flags: when non-null and skip[b * skip_stride] != 0 the
   // operator kernels return at once for problem b
