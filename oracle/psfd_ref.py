@@ -634,6 +634,61 @@ def flux_balance(P, E):
 
 
 # --------------------------------------------------------------------------
+# Standard full-domain PSFD, the comparison case of the paper's Results
+# section ("Background-decomposition" paragraph and its first figure): the
+# multilayer is discretised in eps on the grid and there is no R_ml.  In this
+# module that is a Problem whose configuration has no multilayer (r_TE =
+# r_TM = 0) and whose "absorber" rows hold the stack.
+# --------------------------------------------------------------------------
+
+
+def layered_eps_rows(nz_abs, dz, layers_eps, layers_d, eps_bg):
+    """Permittivity of a planar stack averaged over each absorber row, shape (nz_abs,).
+
+    The stack (layers listed top to bottom) hangs from the top face of the
+    region, z = nz_abs dz; whatever it does not cover is background.  Row j
+    spans [j dz, (j + 1) dz) and takes the thickness-weighted mean of eps
+    over that interval.  The paper does not say how its standard solver
+    samples the stack; the mean is the effective permittivity for fields
+    tangential to the layers (TE)."""
+    top = nz_abs * dz
+    out = np.empty(nz_abs, np.complex128)
+    for j in range(nz_abs):
+        lo, hi = j * dz, (j + 1) * dz
+        acc, covered = 0j, 0.0
+        z_hi = top
+        for e, d in zip(layers_eps, layers_d):
+            z_lo = z_hi - d
+            ov = max(0.0, min(hi, z_hi) - max(lo, z_lo))
+            acc += complex(e) * ov
+            covered += ov
+            z_hi = z_lo
+        out[j] = (acc + eps_bg * (dz - covered)) / dz
+    return out
+
+
+def specular_reflection(P, E):
+    """Specular (0, 0)-order reflection coefficient of the whole structure,
+    referred to the top face of the absorber region, z_t = nz_abs dz.
+
+    The total upgoing (0, 0) amplitude at the observation row per unit
+    incident amplitude (reflected_obs: scattered field, the multilayer
+    response to it and the multilayer reflection of the incident wave) is
+    projected on s_hat (TE) or on t_hat and divided by -cos(theta) (TM, the
+    magnetic-field sign convention of tmm_reflection), then carried from
+    the observation row back to the face, where the incident wave has
+    phase exp(-i kz0 z_t):  r = value * exp(-i kz0 z_obs) * exp(2 i kz0 z_t)."""
+    g, b = P.g, P.basis
+    up = reflected_obs(P, E)[:, 0, 0]
+    if P.cfg["pol"] == 0:
+        val = b.sx[0, 0] * up[0] + b.sy[0, 0] * up[1]
+    else:
+        val = -(b.tx[0, 0] * up[0] + b.ty[0, 0] * up[1]) / np.cos(g.theta)
+    z_t = g.nz_abs * g.dz
+    return complex(val * np.exp(-1j * g.kz0 * g.z[g.j_obs]) * np.exp(2j * g.kz0 * z_t))
+
+
+# --------------------------------------------------------------------------
 # Dense forms for tiny grids
 # --------------------------------------------------------------------------
 

@@ -16,7 +16,11 @@ from .configs import (  # noqa: F401
     config_c3_sizes,
     config_c4,
     config_c5,
+    FULL_DOMAIN_NZ,
+    FULL_DOMAIN_THETAS_DEG,
     eps_absorber_default,
+    full_domain_config,
+    full_domain_stack,
     multilayer_stack,
     nz_total,
 )

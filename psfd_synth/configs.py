@@ -87,3 +87,38 @@ def config_c4(pol=0):
 def config_c5():
     """128 x 128 lateral, 2 nm pitch; 32 absorber cells over 60 nm; 6 deg, TE."""
     return base_config(128, 128, 32, 60.0, pol=0)
+
+
+# Standard full-domain comparison (paper, Results, "Background-decomposition"
+# paragraph): the bare multilayer discretised on the grid.  Axial sizes per
+# grid step: stack rows plus a 12 nm PML on each side and equal gaps, padded
+# to a length the axial transforms take.
+FULL_DOMAIN_NZ = {1.0: 324, 0.5: 648, 0.25: 1296}
+# Incidence angles the paper's 150 nm periodic cell represents below 20 deg:
+# sin(theta_m) = m lambda / 150 nm.
+FULL_DOMAIN_THETAS_DEG = [math.degrees(math.asin(m * LAMBDA_NM / 150.0)) for m in range(4)]
+
+
+def full_domain_config(dz, theta_deg=0.0, pol=0, nx=1, n_bilayers=ML_BILAYERS, nz=None,
+                       pml_nm=12.0):
+    """Configuration of a full-domain solve of the bare stack (no multilayer
+    operator; the stack goes into the absorber rows, see ``full_domain_stack``).
+
+    ``nz`` defaults to FULL_DOMAIN_NZ[dz]; lateral size nx x nx with pitch dz."""
+    _, thick, _ = multilayer_stack(n_bilayers)
+    nz_abs = int(math.ceil(round(sum(thick) / dz, 9)))
+    nz = FULL_DOMAIN_NZ[dz] if nz is None else int(nz)
+    npml = int(round(pml_nm / dz))
+    gaps = nz - nz_abs - 2 * npml
+    if gaps < 2:
+        raise ValueError("axial size too small for the stack and the PML")
+    cfg = base_config(nx, nx, nz_abs, nz_abs * dz, dx=dz, theta_deg=theta_deg, pol=pol,
+                      nz_pml=npml, nz_gap=gaps // 2, multilayer=False)
+    cfg["nz_gap_top"] = gaps - gaps // 2
+    return cfg
+
+
+def full_domain_stack(n_bilayers=ML_BILAYERS):
+    """(layer permittivities, thicknesses) of the bare stack, top to bottom."""
+    eps, thick, _ = multilayer_stack(n_bilayers)
+    return eps, thick
