@@ -70,7 +70,9 @@ typedef enum {
 
 /* Plan descriptor.  Lengths in nm, angles in radians.
  * Supported sizes: nx, ny in {16, 32, 64, 128, 192, 256, 512, 1024};
- * Nz in {24, 32, 48, 64, 96, 128}; nz_abs >= 1; nz_gap_bot >= 1 (the
+ * Nz in {24, 32, 48, 64, 96, 128} (the register-resident and LDS axial
+ * kernels) or {192, 256, 324, 384, 576, 648, 768} (tall columns of the
+ * full-domain comparison, LDS axial kernel only); nz_abs >= 1; nz_gap_bot >= 1 (the
  * evaluation row of the multilayer split is the last bottom-gap row). */
 typedef struct {
   int32_t nx, ny, nz_abs, nz_gap_bot, nz_gap_top, nz_pml;
@@ -212,6 +214,36 @@ psfd_status psfd_plan_batch(int32_t n, const psfd_desc* descs, const void* const
                             void* hip_stream, psfd_plan_t* out);
 psfd_status psfd_solve_batch(psfd_plan_t batch, const void* const* x0, void* const* E, double tol,
                              int32_t maxit, psfd_info* infos);
+
+/* Standard full-domain discretisation of a planar stack (paper, Results,
+ * "Background-decomposition" paragraph and its first figure: the comparison
+ * solver meshes the whole multilayer; with n_ml = 0 and eps_sub = eps_bg the
+ * plan has no multilayer operator and the stack lives in the absorber rows).
+ *   layers_eps    host, [n_layers][2] permittivities (re, im), top to bottom
+ *   layers_thick  host, [n_layers] thicknesses in nm, >= 0
+ *   eps_abs_dev   device, [nz_abs][ny][nx] complex128 output: row j, which
+ *                 spans [j dz, (j+1) dz) above the region's bottom face, holds
+ *                 the thickness-weighted mean permittivity over that interval
+ *                 of a stack whose top face is the region's top face
+ *                 (z = nz_abs dz); the part no layer covers is eps_bg.  Every
+ *                 lateral point of a row gets the same value.
+ * Uses d->nx, ny, nz_abs, dz, eps_bg only.  Returns PSFD_ERR_ARG for a
+ * negative or non-finite thickness; allocates a temporary and synchronises. */
+psfd_status psfd_layered_eps(const psfd_desc* d, int32_t n_layers, const double* layers_eps,
+                             const double* layers_thick, void* eps_abs_dev, void* hip_stream);
+
+/* Specular (0, 0)-order reflection coefficient of the structure (absorber
+ * region plus the multilayer operator) referred to the top face of the
+ * absorber region, z = nz_abs dz (paper, Results, first figure panels c and
+ * d compare it with the transfer-matrix value of the bare stack).
+ *   E   device [3][Nz][ny][nx] complex128 scattered field of this plan's solve
+ *   r   host, out: (re, im).  TE plans: the s-polarised amplitude; TM plans:
+ *       the magnetic-field coefficient (sign convention of the transfer matrix).
+ * The upgoing (0, 0) amplitude at the observation row is the mean of E over
+ * that row plus the multilayer response to E (read at the evaluation row)
+ * plus the multilayer reflection of the incident wave; it is carried back to
+ * the face.  Single-problem plans only; synchronises the plan's stream. */
+psfd_status psfd_specular(psfd_plan_t p, const void* E, double r[2]);
 
 /* Copy the plan's per-mode multilayer reflections (transfer-matrix method,
  * paper section 2.2 step (iii)): r_te, r_pe device [ny][nx] complex128.

@@ -26,7 +26,8 @@ namespace psfd {
 
 bool axial_size_ok(int n) {
   switch (n) {
-    case 24: case 32: case 48: case 64: case 96: case 128: return true;
+    case 24: case 32: case 48: case 64: case 96: case 128:
+    case 192: case 256: case 324: case 384: case 576: case 648: case 768: return true;
     default: return false;
   }
 }
@@ -99,6 +100,13 @@ __device__ void column_info(ColInfo<T>& c, const OpTables<T>& t, int pb, int ix,
   c.rpe = t.r_pe[mode];
 }
 
+// Columns up to 128 rows keep the z tables (twiddles, 1/s, kz) in LDS next
+// to the column tile; taller columns (the full-domain grids that discretise
+// a whole multilayer) read them through the caches so that one or two
+// columns of five vectors still fit the 64 KiB a block may declare.
+template <int NZ>
+constexpr bool ax_tables_in_lds() { return NZ <= 128; }
+
 template <typename T, int NZ>
 constexpr int ax_tile() {
   int tx = sizeof(T) == 8 ? 8 : 16;
@@ -118,11 +126,16 @@ k_axial(const cplx<T>* __restrict__ S_all, cplx<T>* __restrict__ UW_all, const O
   constexpr int VS = NZ * PITCH;
   constexpr int NV = (MODE == AX_M) ? 3 : 5;
   using Addr = AddrVec<TX, PITCH, VS>;
+  constexpr bool TL = ax_tables_in_lds<NZ>();
+  constexpr int NTAB = TL ? NZ : 1;
   __shared__ cplx<T> buf[NV * VS];
   __shared__ ColInfo<T> ci[TX];
-  __shared__ cplx<T> twz[NZ];
-  __shared__ cplx<T> invs[NZ];
-  __shared__ T kzs[NZ];
+  __shared__ cplx<T> twz_s[NTAB];
+  __shared__ cplx<T> invs_s[NTAB];
+  __shared__ T kzs_s[NTAB];
+  const cplx<T>* twz = TL ? twz_s : t.tw_z;
+  const cplx<T>* invs = TL ? invs_s : t.inv_s;
+  const T* kzs = TL ? kzs_s : t.kz;
 
   const int tid = threadIdx.x;
   const int iy = blockIdx.y % t.ny;
@@ -140,10 +153,12 @@ k_axial(const cplx<T>* __restrict__ S_all, cplx<T>* __restrict__ UW_all, const O
     buf[c * VS + z * PITCH + cc] = S[(int64_t)(c * NZ + z) * plane + colbase + cc];
   }
   if (tid < TX) column_info(ci[tid], t, pb, kx0 + tid, iy);
-  for (int i = tid; i < NZ; i += NT) {
-    twz[i] = t.tw_z[i];
-    invs[i] = t.inv_s[i];
-    kzs[i] = t.kz[i];
+  if constexpr (TL) {
+    for (int i = tid; i < NZ; i += NT) {
+      twz_s[i] = t.tw_z[i];
+      invs_s[i] = t.inv_s[i];
+      kzs_s[i] = t.kz[i];
+    }
   }
   __syncthreads();
 
@@ -585,6 +600,13 @@ hipError_t launch_axial(const OpTables<T>& t, const cplx<T>* S, cplx<T>* UW, int
     case 64: return axial_n<T, 64>(t, S, UW, mode, st);
     case 96: return axial_n<T, 96>(t, S, UW, mode, st);
     case 128: return axial_n<T, 128>(t, S, UW, mode, st);
+    case 192: return axial_n<T, 192>(t, S, UW, mode, st);
+    case 256: return axial_n<T, 256>(t, S, UW, mode, st);
+    case 324: return axial_n<T, 324>(t, S, UW, mode, st);
+    case 384: return axial_n<T, 384>(t, S, UW, mode, st);
+    case 576: return axial_n<T, 576>(t, S, UW, mode, st);
+    case 648: return axial_n<T, 648>(t, S, UW, mode, st);
+    case 768: return axial_n<T, 768>(t, S, UW, mode, st);
     default: return hipErrorInvalidValue;
   }
 }

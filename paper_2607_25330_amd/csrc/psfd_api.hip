@@ -15,6 +15,7 @@
 #include <mutex>
 #include <tuple>
 #include <cmath>
+#include <complex>
 #include <cstdlib>
 #include <cstring>
 #include <new>
@@ -196,7 +197,7 @@ psfd_status validate(const psfd_desc* d) {
   if (d->nz_abs < 1 || d->nz_gap_bot < 1 || d->nz_gap_top < 0 || d->nz_pml < 0)
     return fail(PSFD_ERR_ARG, "need nz_abs >= 1, nz_gap_bot >= 1, nz_gap_top >= 0, nz_pml >= 0");
   const int nz = d->nz_abs + d->nz_gap_bot + d->nz_gap_top + 2 * d->nz_pml;
-  if (!axial_size_ok(nz)) return fail(PSFD_ERR_ARG, "Nz must be one of 24, 32, 48, 64, 96, 128");
+  if (!axial_size_ok(nz)) return fail(PSFD_ERR_ARG, "Nz must be one of 24, 32, 48, 64, 96, 128, 192, 256, 324, 384, 576, 648, 768");
   if (!(d->dx > 0) || !(d->dy > 0) || !(d->dz > 0) || !(d->lambda > 0))
     return fail(PSFD_ERR_ARG, "dx, dy, dz, lambda must be positive");
   if (!(d->eps_bg > 0)) return fail(PSFD_ERR_ARG, "eps_bg must be positive");
@@ -1149,6 +1150,123 @@ psfd_status layout_impl(const psfd_desc* d, const double* a_bin, const double ep
   return PSFD_OK;
 }
 
+// Row means of a planar stack over the absorber rows, walked once from the
+// top face z = nz_abs dz downwards: each row [j dz, (j+1) dz) collects the
+// overlap-weighted permittivity of the layers it meets and the background
+// for the part no layer covers.
+psfd_status layered_impl(const psfd_desc* d, int32_t n, const double* leps, const double* ld,
+                         void* eps_out, void* stream) {
+  if (!d || !eps_out || n < 0 || (n > 0 && (!leps || !ld))) return fail(PSFD_ERR_ARG, "NULL argument");
+  if (!lateral_size_ok(d->nx) || !lateral_size_ok(d->ny) || d->nz_abs < 1 || !(d->dz > 0))
+    return fail(PSFD_ERR_ARG, "unsupported lateral size, nz_abs < 1 or dz <= 0");
+  for (int i = 0; i < n; ++i)
+    if (!(ld[i] >= 0) || !std::isfinite(ld[i]) || !std::isfinite(leps[2 * i]) ||
+        !std::isfinite(leps[2 * i + 1]))
+      return fail(PSFD_ERR_ARG, "layer thicknesses must be finite and >= 0");
+  const int na = d->nz_abs;
+  const double dz = d->dz;
+  std::vector<cplx<double>> rows(na);
+  int i = 0;                     // current layer
+  double ltop = na * dz;         // its top face
+  for (int j = na - 1; j >= 0; --j) {
+    const double lo = j * dz, hi = (j + 1) * dz;
+    double re = 0.0, im = 0.0, cov = 0.0;
+    while (i < n) {
+      const double lbot = ltop - ld[i];
+      const double ov = std::min(hi, ltop) - std::max(lo, lbot);
+      if (ov > 0) {
+        re += leps[2 * i] * ov;
+        im += leps[2 * i + 1] * ov;
+        cov += ov;
+      }
+      if (lbot < lo) break;  // the layer continues into the row below
+      ltop = lbot;
+      ++i;
+    }
+    rows[j] = {(re + d->eps_bg * (dz - cov)) / dz, im / dz};
+  }
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  struct psfd_plan tmp;  // owns the temporary
+  tmp.st = st;
+  cplx<double>* rows_d = nullptr;
+  CHKS(upload(&tmp, &rows_d, rows));
+  CHK(launch_fill_rows(rows_d, (int64_t)d->nx * d->ny, na, static_cast<cplx<double>*>(eps_out), st));
+  CHK(hipStreamSynchronize(st));
+  return PSFD_OK;
+}
+
+// Specular (0, 0)-order reflection coefficient referred to the top face of
+// the absorber region.  The plane means of E_x, E_y at the observation row
+// and at the evaluation row come from the device; the rest is scalar:
+// the upgoing (0, 0) amplitude at the observation row is the scattered
+// field plus the multilayer response to the scattered field (evaluation
+// row amplitude carried to z_ml, projected on s/t, times r_TE / r_pE,
+// carried up) plus the multilayer reflection of the incident wave.
+psfd_status specular_impl(struct psfd_plan* P, const void* E, double* r_out) {
+  if (!P || !E || !r_out) return fail(PSFD_ERR_ARG, "NULL argument");
+  if (P->is_batch || P->G != 1) return fail(PSFD_ERR_ARG, "psfd_specular takes a single-problem plan");
+  const int64_t plane = P->plane;
+  const int jobs = P->j0 + P->nabs, jev = P->jev;
+  PlaneSet ps;
+  ps.off[0] = (int64_t)jobs * plane;
+  ps.off[1] = (int64_t)(P->nz + jobs) * plane;
+  ps.off[2] = (int64_t)jev * plane;
+  ps.off[3] = (int64_t)(P->nz + jev) * plane;
+  const int nblk = (int)std::min<int64_t>(64, (plane + 255) / 256);
+  cplx<double>* part = nullptr;
+  struct psfd_plan tmp;  // owns the temporary
+  tmp.st = P->st;
+  CHKS(dalloc(&tmp, &part, (size_t)4 * nblk));
+  CHK(launch_plane_sums(static_cast<const cplx<double>*>(E), ps, plane, nblk, part, P->st));
+  std::vector<cplx<double>> h((size_t)4 * nblk + 2);
+  CHK(hipMemcpyAsync(h.data(), part, sizeof(cplx<double>) * 4 * nblk, hipMemcpyDeviceToHost, P->st));
+  CHK(hipMemcpyAsync(h.data() + 4 * nblk, P->rte64, sizeof(cplx<double>), hipMemcpyDeviceToHost, P->st));
+  CHK(hipMemcpyAsync(h.data() + 4 * nblk + 1, P->rpe64, sizeof(cplx<double>), hipMemcpyDeviceToHost,
+                     P->st));
+  CHK(hipStreamSynchronize(P->st));
+  std::complex<double> m[4];
+  for (int q = 0; q < 4; ++q) {
+    std::complex<double> acc = 0.0;
+    for (int b = 0; b < nblk; ++b) acc += std::complex<double>(h[q * nblk + b].re, h[q * nblk + b].im);
+    m[q] = acc / (double)plane;
+  }
+  const std::complex<double> rte(h[4 * nblk].re, h[4 * nblk].im);
+  const std::complex<double> rpe(h[4 * nblk + 1].re, h[4 * nblk + 1].im);
+  const ProbInfo& q = P->prob[0];
+  const double kt = std::hypot(q.kx0, q.ky0);
+  double sx, sy, tx, ty;
+  if (kt == 0.0) {
+    sx = -std::sin(q.phi); sy = std::cos(q.phi); tx = std::cos(q.phi); ty = std::sin(q.phi);
+  } else {
+    sx = -q.ky0 / kt; sy = q.kx0 / kt; tx = q.kx0 / kt; ty = q.ky0 / kt;
+  }
+  const double dz = P->d.dz;
+  const double z_t = P->nabs * dz, z_obs = z_t + 0.5 * dz;
+  const std::complex<double> I(0.0, 1.0);
+  const double kz = q.kz0;
+  const bool live = std::abs(kz) >= P->t64.kz_live;
+  const std::complex<double> down = std::exp(-I * kz * (0.5 * dz));
+  const std::complex<double> us = live ? rte * (sx * m[2] + sy * m[3]) * down : 0.0;
+  const std::complex<double> up = live ? rpe * (tx * m[2] + ty * m[3]) * down : 0.0;
+  const std::complex<double> ph = std::exp(I * kz * z_obs);
+  std::complex<double> ux = m[0] + (us * sx + up * tx) * ph;
+  std::complex<double> uy = m[1] + (us * sy + up * ty) * ph;
+  // incident wave reflected by the multilayer, tangential part
+  const double ct = std::cos(q.theta);
+  if (q.pol == 0) {
+    ux += rte * (-std::sin(q.phi)) * ph;
+    uy += rte * std::cos(q.phi) * ph;
+  } else {
+    ux += rpe * (ct * std::cos(q.phi)) * ph;
+    uy += rpe * (ct * std::sin(q.phi)) * ph;
+  }
+  const std::complex<double> val = q.pol == 0 ? sx * ux + sy * uy : -(tx * ux + ty * uy) / ct;
+  const std::complex<double> r = val * std::exp(-I * kz * z_obs) * std::exp(2.0 * I * kz * z_t);
+  r_out[0] = r.real();
+  r_out[1] = r.imag();
+  return PSFD_OK;
+}
+
 template <typename T>
 psfd_status apply_entry(struct psfd_plan* P, const void* x, void* y, int op) {
   if (!P || !x || !y) return fail(PSFD_ERR_ARG, "NULL argument");
@@ -1421,6 +1539,15 @@ psfd_status psfd_ml_reflection(psfd_plan_t p, void* r_te, void* r_pe) {
     CHK(hipMemcpyAsync(r_pe, p->rpe64, bytes, hipMemcpyDeviceToDevice, p->st));
     return PSFD_OK;
   });
+}
+
+psfd_status psfd_layered_eps(const psfd_desc* d, int32_t n_layers, const double* layers_eps,
+                             const double* layers_thick, void* eps_abs_dev, void* hip_stream) {
+  return guarded([&] { return layered_impl(d, n_layers, layers_eps, layers_thick, eps_abs_dev, hip_stream); });
+}
+
+psfd_status psfd_specular(psfd_plan_t p, const void* E, double r[2]) {
+  return guarded([&] { return specular_impl(p, E, r); });
 }
 
 psfd_status psfd_profile_enable(psfd_plan_t p, int32_t kernel) {

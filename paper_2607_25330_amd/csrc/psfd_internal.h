@@ -170,6 +170,15 @@ hipError_t launch_fill_eps(const cplx<double>* plane, int nx, int ny, int nabs, 
                            double eps_bg, cplx<double> eps_abs, cplx<double>* eps_out,
                            hipStream_t st);
 hipError_t launch_real_to_cplx(const double* a, int n, cplx<double>* out, hipStream_t st);
+// out[j][i] = rows[j] for j < nrows, i < plane (rows: device)
+hipError_t launch_fill_rows(const cplx<double>* rows, int64_t plane, int nrows,
+                            cplx<double>* out, hipStream_t st);
+// part[q][b], q < 4, b < nblk: partial sums of the plane starting at f + off[q]
+struct PlaneSet {
+  int64_t off[4];
+};
+hipError_t launch_plane_sums(const cplx<double>* f, const PlaneSet& ps, int64_t plane, int nblk,
+                             cplx<double>* part, hipStream_t st);
 
 // ---- Krylov kernels (krylov.hip)
 struct KState {

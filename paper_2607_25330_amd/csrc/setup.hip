@@ -207,4 +207,52 @@ hipError_t launch_real_to_cplx(const double* a, int n, cplx<double>* out, hipStr
   return hipGetLastError();
 }
 
+// Row values broadcast over every lateral point: out[j][i] = rows[j].
+__global__ void k_fill_rows(const cplx<double>* __restrict__ rows, int64_t plane,
+                            cplx<double>* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y;
+  if (i < plane) out[(int64_t)j * plane + i] = rows[j];
+}
+
+hipError_t launch_fill_rows(const cplx<double>* rows, int64_t plane, int nrows,
+                            cplx<double>* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_fill_rows, dim3((unsigned)((plane + 255) / 256), nrows), dim3(256), 0, st,
+                     rows, plane, out);
+  return hipGetLastError();
+}
+
+// Partial sums of up to four planes of a field: block (b, q) adds the
+// elements b * 256 + tid + k * 256 * gridDim.x of plane q and writes one
+// complex partial to part[q * gridDim.x + b].
+__global__ void __launch_bounds__(256)
+k_plane_sums(const cplx<double>* __restrict__ f, PlaneSet ps, int64_t plane,
+             cplx<double>* __restrict__ part) {
+  const int q = blockIdx.y, tid = threadIdx.x;
+  const cplx<double>* p = f + ps.off[q];
+  double re = 0.0, im = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + tid; i < plane; i += (int64_t)gridDim.x * 256) {
+    re += p[i].re;
+    im += p[i].im;
+  }
+  __shared__ double sr[256], si[256];
+  sr[tid] = re;
+  si[tid] = im;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (tid < h) {
+      sr[tid] += sr[tid + h];
+      si[tid] += si[tid + h];
+    }
+    __syncthreads();
+  }
+  if (tid == 0) part[q * gridDim.x + blockIdx.x] = {sr[0], si[0]};
+}
+
+hipError_t launch_plane_sums(const cplx<double>* f, const PlaneSet& ps, int64_t plane, int nblk,
+                             cplx<double>* part, hipStream_t st) {
+  hipLaunchKernelGGL(k_plane_sums, dim3(nblk, 4), dim3(256), 0, st, f, ps, plane, part);
+  return hipGetLastError();
+}
+
 }  // namespace psfd

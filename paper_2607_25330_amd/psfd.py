@@ -79,6 +79,8 @@ _SIGS = {
                          c_int32, ctypes.POINTER(Info)],
     "psfd_profile_enable": [c_void_p, c_int32],
     "psfd_profile_read": [c_void_p, c_dp, ctypes.POINTER(c_int64), c_dp],
+    "psfd_layered_eps": [ctypes.POINTER(Desc), c_int32, c_dp, c_dp, c_void_p, c_void_p],
+    "psfd_specular": [c_void_p, c_void_p, c_dp],
     "psfd_tune": [c_void_p],
     "psfd_schedule": [c_void_p, ctypes.POINTER(c_int32)],
     "psfd_set_schedule": [c_void_p, ctypes.POINTER(c_int32)],
@@ -170,6 +172,21 @@ def psfd_layout_eps(cfg, a_bin, eps_abs, sigma=None):
     return out
 
 
+def psfd_layered_eps(cfg, layers_eps, layers_thick, device):
+    """Row-mean permittivity of a planar stack hanging from the top face of the
+    absorber region (full-domain discretisation), (nz_abs, ny, nx) complex128."""
+    d, keep = make_desc(cfg)
+    n = len(layers_eps)
+    if len(layers_thick) != n:
+        raise ValueError("layers_eps and layers_thick differ in length")
+    le = (c_double * max(1, 2 * n))(*[v for e in layers_eps for v in (complex(e).real, complex(e).imag)])
+    ld = (c_double * max(1, n))(*[float(t) for t in layers_thick])
+    out = torch.empty((cfg["nz_abs"], cfg["ny"], cfg["nx"]), dtype=torch.complex128, device=device)
+    _call("psfd_layered_eps", ctypes.byref(d), c_int32(n), ctypes.cast(le, c_dp),
+          ctypes.cast(ld, c_dp), _ptr(out, torch.complex128), _stream_handle())
+    return out
+
+
 class Plan:
     """A psfd_plan bound to the current torch stream."""
 
@@ -226,6 +243,13 @@ class Plan:
         rpe = torch.empty(n, dtype=torch.complex128, device=self.device)
         _call("psfd_ml_reflection", self._h, _ptr(rte, torch.complex128), _ptr(rpe, torch.complex128))
         return rte, rpe
+
+    def specular(self, E):
+        """Specular (0, 0)-order reflection coefficient at the absorber region's top face."""
+        r = (c_double * 2)()
+        _call("psfd_specular", self._h, _ptr(E, torch.complex128, self.shape, "E"),
+              ctypes.cast(r, c_dp))
+        return complex(r[0], r[1])
 
     def solve(self, b=None, x0=None, tol=1e-6, maxit=20000, adjoint=False, out=None,
               check=True):

@@ -74,5 +74,10 @@ def test_invalid_arguments_return_err_arg(L):
     assert L.psfd_apply(None, None, None) == psfd.PSFD_ERR_ARG
     assert L.psfd_solve(None, None, None, None, ctypes.c_double(1e-6), 10, 0, None) == psfd.PSFD_ERR_ARG
     assert L.psfd_layout_eps(ctypes.byref(d), None, None, ctypes.c_double(1.0), None, None) == psfd.PSFD_ERR_ARG
+    assert L.psfd_layered_eps(ctypes.byref(d), 0, None, None, None, None) == psfd.PSFD_ERR_ARG
+    neg = (ctypes.c_double * 2)(2.0, 0.0)
+    thick = (ctypes.c_double * 1)(-1.0)
+    assert L.psfd_layered_eps(ctypes.byref(d), 1, neg, thick, ctypes.c_void_p(1), None) == psfd.PSFD_ERR_ARG
+    assert L.psfd_specular(None, None, None) == psfd.PSFD_ERR_ARG
     assert L.psfd_field_size(None) == 0
     L.psfd_destroy(None)
