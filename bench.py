@@ -300,6 +300,103 @@ def workload_c5(psfd, args):
                                    "on the observation row)/d eps, mixed, tol %g" % args.tol}}
 
 
+def workload_fd(psfd, args):
+    """Standard full-domain PSFD (the whole 40-bilayer Mo/Si stack discretised on the grid, no
+    multilayer operator) next to the background-decomposed solve.
+    (1) bare stack, 16x16 lateral, 1 and 0.5 nm grids (Nz 324 / 648), TE at the four angles a
+        150 nm periodic cell represents: reflection against the transfer matrix, iterations, time;
+    (2) one seeded absorber layout, 128x128 lateral at 1 nm, 50 nm absorber, TE normal incidence:
+        background-decomposed grid (Nz 96) against the full-domain grid with the stack under the
+        absorber (Nz 384): iterations, solve time, device memory, specular reflection at the
+        absorber's top face, and the tall axial kernel's bandwidth (launch-packet events).  The
+        decomposed grid runs with the grazing cutoff of the other workloads and without it."""
+    import math
+    import numpy as np
+    import torch
+    from psfd_synth import (FULL_DOMAIN_THETAS_DEG, base_config, eps_absorber_default,
+                            full_domain_config, full_domain_stack, rect_layout)
+    dev = torch.device("cuda:0")
+    eps_l, d_l = full_domain_stack()
+    out = {"metric": "full-domain vs background-decomposed PSFD", "unit": "solves/s",
+           "dtype": "f64", "legs": {"bare_stack": [], "absorber": {}},
+           "config": {"workload": "bare 40-bilayer Mo/Si stack, 16x16 lateral, dz 1 and 0.5 nm, TE, "
+                                  "4 angles, tol 1e-8; 128x128x(50 nm absorber) at 1 nm, TE normal "
+                                  "incidence, decomposed (Nz 96, grazing cutoff 0.1 and none) vs "
+                                  "full-domain (Nz 384), tol %g"
+                                  % args.tol}}
+    t_bare = 0.0
+    for dz in (1.0, 0.5):
+        for th in FULL_DOMAIN_THETAS_DEG:
+            cfg = full_domain_config(dz, th, 0, nx=16)
+            eps = psfd.psfd_layered_eps(cfg, eps_l, d_l, dev)
+            plan = psfd.Plan(cfg, eps, psfd.PSFD_C128)
+            plan.solve(tol=1e-8, maxit=args.maxit)
+            (E, info), dt = _sync_time(lambda: plan.solve(tol=1e-8, maxit=args.maxit))
+            r = plan.specular(E)
+            plan.close()
+            r_tmm = _tmm_te(psfd, cfg, eps_l, d_l, dev)
+            t_bare += dt
+            leg = {"dz": dz, "theta_deg": round(th, 2), "nz": plan.nz, "iters": info["iters"],
+                   "ms": round(1e3 * dt, 2), "R": round(abs(r) ** 2, 5),
+                   "arg_r": round(math.atan2(r.imag, r.real), 4), "R_tmm": round(abs(r_tmm) ** 2, 5),
+                   "arg_r_tmm": round(math.atan2(r_tmm.imag, r_tmm.real), 4),
+                   "abs_r_minus_tmm": float(abs(r - r_tmm))}
+            _log(f"fd bare dz {dz} theta {th:.2f}: {leg}")
+            out["legs"]["bare_stack"].append(leg)
+    # (2) absorber layout on the stack
+    a = torch.from_numpy(rect_layout(128, 128, np.random.default_rng(700), wmin=8, wmax=48)).to(dev)
+    cfg_d = base_config(128, 128, 50, 50.0, dx=1.0, theta_deg=0.0, pol=0, nz_pml=12, nz_gap=11)
+    cfg_f = dict(cfg_d, ml_eps=[], ml_thick=[], eps_sub=1.0 + 0j, nz_abs=330, nz_gap_bot=15,
+                 nz_gap_top=15)
+    eps_abs = psfd.psfd_layout_eps(cfg_d, a, eps_absorber_default())
+    cfg_s = dict(cfg_f, nz_abs=280)
+    eps_f = torch.cat([psfd.psfd_layered_eps(cfg_s, eps_l, d_l, dev), eps_abs], dim=0).contiguous()
+    res = {}
+    cfg_dc = dict(cfg_d, ml_kz_min=ML_KZ_MIN)
+    for name, cfg, eps in (("decomposed", cfg_dc, eps_abs), ("decomposed_no_cutoff", cfg_d, eps_abs),
+                           ("full_domain", cfg_f, eps_f)):
+        for prec_name, prec in (("fp64", psfd.PSFD_C128), ("mixed", psfd.PSFD_C64_REFINE64)):
+            torch.cuda.synchronize()
+            free0 = torch.cuda.mem_get_info()[0]
+            plan = psfd.Plan(cfg, eps, prec)
+            (E, info), dt = _sync_time(lambda: plan.solve(tol=args.tol, maxit=args.maxit, check=False))
+            used = (free0 - torch.cuda.mem_get_info()[0]) / 2 ** 30
+            r = plan.specular(E)
+            leg = {"nz": plan.nz, "iters": info["iters"], "status": info["status"],
+                   "s": round(dt, 3), "device_GiB": round(used, 2), "R": round(abs(r) ** 2, 5),
+                   "arg_r": round(math.atan2(r.imag, r.real), 4)}
+            if prec_name == "fp64":
+                plan.profile_enable("axial")
+                for _ in range(10):
+                    plan.apply(E)
+                torch.cuda.synchronize()
+                ms, nl, by = plan.profile_read()
+                plan.profile_enable("off")
+                leg["axial_us"] = round(1e3 * ms / max(nl, 1), 2)
+                leg["axial_GBs"] = round(by / max(ms, 1e-12) / 1e6, 1)
+            _log(f"fd absorber {name} {prec_name}: {leg}")
+            res[f"{name}_{prec_name}"] = leg
+            plan.close()
+            del E
+    out["legs"]["absorber"] = res
+    out["value"] = round(8 / t_bare, 3)
+    return out
+
+
+def _tmm_te(psfd, cfg, eps_l, d_l, dev):
+    """Transfer-matrix reflection of the bare stack between vacuum half-spaces (TE), from the
+    library's own per-mode table of a plan that carries the stack as its multilayer."""
+    import torch
+    c = dict(cfg, ml_eps=list(eps_l), ml_thick=list(d_l), eps_sub=1.0 + 0j, nz_abs=8,
+             nz_gap_bot=2, nz_gap_top=2)
+    c["nz_pml"] = (32 - 12) // 2
+    plan = psfd.Plan(c, torch.ones((8, c["ny"], c["nx"]), dtype=torch.complex128, device=dev))
+    rte, _ = plan.ml_reflection()
+    r = complex(rte[0, 0].item())
+    plan.close()
+    return r
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -318,7 +415,7 @@ def main():
     ap.add_argument("--cpu-leg", type=float, default=None, help=argparse.SUPPRESS)
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run one device copy of this size (for counter calibration)")
-    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5"],
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5", "fd"],
                     help="c2 (default) is the headline line; the others print their own line")
     ap.add_argument("--c3-clips", type=int, default=64)
     args = ap.parse_args()
@@ -342,7 +439,8 @@ def main():
     from psfd_synth import config_c2
 
     if args.workload != "c2":
-        fn = {"c1": workload_c1, "c3": workload_c3, "c4": workload_c4, "c5": workload_c5}[args.workload]
+        fn = {"c1": workload_c1, "c3": workload_c3, "c4": workload_c4, "c5": workload_c5,
+              "fd": workload_fd}[args.workload]
         res = fn(psfd, args)
         res.update({"n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "data": "synthetic",
                     "higher_is_better": True, "vs_baseline": None})

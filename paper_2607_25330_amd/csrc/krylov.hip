@@ -116,6 +116,7 @@ k_finalize(KState* ks_all, const double* __restrict__ part_all, int nblocks,
     ks->itmax = (int)q.itmax;
     ks->delta2 = q.delta2;
     ks->rmax2 = acc[0];
+    ks->rfold2 = acc[0];
     ks->done = (q.tol2 < 0.0) ? KS_IDLE : (ks->itmax <= 0 ? KS_MAXIT : KS_RUN);
     ks->half = 0;
     ks->status = 0;
@@ -176,7 +177,9 @@ k_finalize(KState* ks_all, const double* __restrict__ part_all, int nblocks,
       ks->done = KS_CONV;
     } else if (ks->iter >= ks->itmax) {
       ks->done = KS_MAXIT;
-    } else if (!(acc[0] < 1e24 * ks->bnorm2)) {
+    } else if (!(acc[0] < 1e8 * ks->rfold2)) {
+      // diverging: the residual has grown 1e4-fold since the run's start or
+      // its last replacement (or is not finite)
       ks->status = 2;
       ks->done = KS_BREAK;
     } else {
@@ -194,6 +197,7 @@ k_finalize(KState* ks_all, const double* __restrict__ part_all, int nblocks,
     // r was replaced by the true residual (host): partials ||r||^2, <rh, r>
     ks->rnorm2 = acc[0];
     ks->rmax2 = acc[0];
+    ks->rfold2 = acc[0];
     st2(ks->rho, cplx<double>{acc[1], acc[2]});
     ks->done = (acc[0] <= ks->tol2 * ks->bnorm2) ? KS_CONV : KS_RUN;
   }

@@ -110,6 +110,7 @@ struct psfd_plan {
   cplx<double>* b64 = nullptr;
   cplx<double>* tmp64 = nullptr;
   cplx<double>* res64 = nullptr;
+  cplx<double>* ebak64 = nullptr;  // the solution before a fold E += s M y (restored if it fails)
   cplx<double>* E64 = nullptr;  // stacked solution of a batch group
   KState* ks = nullptr;
   KState* ks_host = nullptr;
@@ -390,6 +391,7 @@ psfd_status ensure_solver_common(struct psfd_plan* P) {
   CHKS(dalloc(P, &P->b64, (size_t)(P->nfield * G)));
   CHKS(dalloc(P, &P->tmp64, (size_t)(P->nfield * G)));
   CHKS(dalloc(P, &P->res64, (size_t)(P->nfield * G)));
+  CHKS(dalloc(P, &P->ebak64, (size_t)(P->nfield * G)));
   CHK(hipMemsetAsync(P->ks, 0, sizeof(KState) * G, P->st));
   CHK(hipMemsetAsync(P->idle, 0, sizeof(int) * G, P->st));
   CHK(hipHostMalloc((void**)&P->ks_host, sizeof(KState) * G, hipHostMallocDefault));
@@ -732,7 +734,7 @@ psfd_status solve_impl(struct psfd_plan* P, const void* b_in, const void* x0, vo
 // A problem that has finished is idle in the group's later runs.
 psfd_status solve_body(struct psfd_plan* P, const cplx<double>* b_in, const cplx<double>* x0,
                        cplx<double>* E, double tol, int maxit, bool adjoint, psfd_info* infos) {
-  const bool mixed = P->prec != PSFD_C128;
+  bool mixed = P->prec != PSFD_C128;
   const int G = P->G;
   CHKS(ensure_solver_common(P));
   if (mixed) {
@@ -802,6 +804,38 @@ psfd_status solve_body(struct psfd_plan* P, const cplx<double>* b_in, const cplx
     return !(e && *e && std::atoi(e) == 0);
   }();
   std::vector<double> rn0(G, 0.0);  // normalisation of the current complex64 run
+  // Every fold E += s M y is checked against the FP64 true residual: a
+  // problem whose residual does not drop below the one at its last accepted
+  // point gets its previous E back (a diverged or drifted Krylov run never
+  // worsens the returned field), and a mixed plan continues in FP64.
+  std::vector<double> rr_acc(G, 0.0);  // ||b - A E||^2 at the last accepted point
+  for (int i = 0; i < G; ++i) rr_acc[i] = rn[i] * rn[i];
+  std::vector<int> rejected(G, 0);
+  const size_t fbytes = sizeof(cplx<double>) * (size_t)n;
+  auto save_E = [&]() -> psfd_status {
+    CHK(hipMemcpyAsync(P->ebak64, E, fbytes * G, hipMemcpyDeviceToDevice, st));
+    return PSFD_OK;
+  };
+  auto keep_or_restore = [&](const std::vector<int>& mask, std::vector<int>& rej) -> psfd_status {
+    bool any = false;
+    for (int i = 0; i < G; ++i) {
+      rej[i] = 0;
+      if (!mask[i] || P->ks_host[i].red[0] < rr_acc[i]) continue;
+      CHK(hipMemcpyAsync(E + i * n, P->ebak64 + i * n, fbytes, hipMemcpyDeviceToDevice, st));
+      rej[i] = 1;
+      any = true;
+    }
+    if (any) CHKS(true_residual(P, b, E, r64, adjoint));
+    for (int i = 0; i < G; ++i)
+      if (mask[i]) {
+        rr_acc[i] = P->ks_host[i].red[0];
+        if (rej[i]) {
+          rejected[i] = 1;
+          loc[i].applies += 1;
+        }
+      }
+    return PSFD_OK;
+  };
   auto on_update = [&]() -> psfd_status {
     std::vector<int> upd(G, 0);
     for (int i = 0; i < G; ++i) upd[i] = P->ks_host[i].done == KS_UPDATE;
@@ -814,6 +848,7 @@ psfd_status solve_body(struct psfd_plan* P, const cplx<double>* b_in, const cplx
     }
     CHKS(push_params(P));
     cplx<float>* y = P->v32[V_Y];
+    CHKS(save_E());
     if (P->use_pc) {
       CHK(op_apply<float>(P, y, P->v32[V_W], OP_M, P->idle, 1));
       CHK(launch_k_axpy<double, float>(E, P->v32[V_W], P->pp, n, G, st));
@@ -822,6 +857,8 @@ psfd_status solve_body(struct psfd_plan* P, const cplx<double>* b_in, const cplx
     }
     CHK(launch_k_scale_copy<float, float>(y, y, P->pp, n, G, st));
     CHKS(true_residual(P, b, E, r64, adjoint));
+    std::vector<int> rej(G, 0);
+    CHKS(keep_or_restore(upd, rej));
     for (int i = 0; i < G; ++i) {
       if (!upd[i]) continue;
       loc[i].applies += 2;
@@ -833,6 +870,17 @@ psfd_status solve_body(struct psfd_plan* P, const cplx<double>* b_in, const cplx
     CHK(launch_k_scale_copy<float, double>(P->v32[V_R], r64, P->pp, n, G, st));
     CHK(launch_k_dot_rr<float>(P->v32[V_RH], P->v32[V_R], n, G, P->part, st));
     CHK(launch_finalize(FIN_REPLACE, P->ks, P->part, red_blocks(n, G), G, P->pp, st));
+    bool stop = false;
+    for (int i = 0; i < G; ++i) stop = stop || rej[i];
+    if (stop) {  // a rejected update ends that problem's complex64 run
+      CHKS(read_state(P));
+      for (int i = 0; i < G; ++i) {
+        if (!rej[i]) continue;
+        P->ks_host[i].done = KS_BREAK;
+        P->ks_host[i].status = 3;
+        CHK(hipMemcpyAsync(P->ks + i, P->ks_host + i, sizeof(KState), hipMemcpyHostToDevice, st));
+      }
+    }
     for (int i = 0; i < G; ++i) {  // back to the run's parameters (the final fold uses them)
       ProbParams& q = P->pp_host[i];
       P->idle_host[i] = fin[i];
@@ -884,10 +932,13 @@ psfd_status solve_body(struct psfd_plan* P, const cplx<double>* b_in, const cplx
       }
     }
     CHKS(push_params(P));
+    std::vector<double> rr_start(rr_acc);
+    for (int i = 0; i < G; ++i) rejected[i] = 0;
     if (mixed) {
       CHK(launch_k_scale_copy<float, double>(P->v32[V_R], r64, P->pp, n, G, st));
       CHKS(run_bicgstab<float>(P, adjoint, budget, on_update));
       cplx<float>* y = P->v32[V_Y];
+      CHKS(save_E());
       if (P->use_pc) {
         CHK(op_apply<float>(P, y, P->v32[V_W], OP_M, P->idle, 1));
         CHK(launch_k_axpy<double, float>(E, P->v32[V_W], P->pp, n, G, st));
@@ -897,6 +948,7 @@ psfd_status solve_body(struct psfd_plan* P, const cplx<double>* b_in, const cplx
     } else {
       CHKS(run_bicgstab<double>(P, adjoint, budget, no_update));
       cplx<double>* y = P->v64[V_Y];
+      CHKS(save_E());
       if (P->use_pc) {
         CHK(op_apply<double>(P, y, P->tmp64, OP_M, P->idle, 1));
         CHK(launch_k_axpy<double, double>(E, P->tmp64, P->pp, n, G, st));
@@ -915,6 +967,12 @@ psfd_status solve_body(struct psfd_plan* P, const cplx<double>* b_in, const cplx
       run_done[i] = k.done;
     }
     CHKS(true_residual(P, b, E, r64, adjoint));
+    {
+      std::vector<int> act(G, 0), rej(G, 0);
+      for (int i = 0; i < G; ++i) act[i] = !fin[i];
+      CHKS(keep_or_restore(act, rej));
+    }
+    bool escalate = false;
     for (int i = 0; i < G; ++i) {
       if (fin[i]) continue;
       const double rr2 = P->ks_host[i].red[0];
@@ -926,8 +984,20 @@ psfd_status solve_body(struct psfd_plan* P, const cplx<double>* b_in, const cplx
       }
       rrel[i] = std::sqrt(rr2 / bn2[i]);
       rn[i] = std::sqrt(rr2);
-      if (run_done[i] == 3 && rrel[i] > tol && outer[i] >= kMaxRestarts) status[i] = PSFD_BREAKDOWN;
+      if (run_done[i] == KS_BREAK && rrel[i] > tol && outer[i] >= kMaxRestarts)
+        status[i] = PSFD_BREAKDOWN;
       outer[i] += 1;
+      // a complex64 run that was rejected, or broke down without a four-fold
+      // drop of the residual, hands the rest of the solve to FP64
+      if (mixed && rrel[i] > tol &&
+          (rejected[i] || (run_done[i] == KS_BREAK && !(rr2 < 0.0625 * rr_start[i]))))
+        escalate = true;
+    }
+    if (escalate) {
+      mixed = false;
+      CHKS(ensure_krylov<double>(P));
+      CHK(hipMemcpyAsync(P->v64[V_R], r64, fbytes * G, hipMemcpyDeviceToDevice, st));
+      r64 = P->v64[V_R];
     }
   }
   for (int i = 0; i < G; ++i) {

@@ -187,6 +187,7 @@ struct KState {
   double snorm2, rnorm2, bnorm2, tol2, rh_norm2;
   double red[4];        // generic reduction outputs
   double rmax2, delta2;  // reliable updates: max ||r||^2 since the last one, trigger factor
+  double rfold2;         // ||r||^2 at the run's start or its last residual replacement
   int iter, done, status, half;
   int itmax, pad;
 };
