@@ -245,6 +245,48 @@ psfd_status psfd_layered_eps(const psfd_desc* d, int32_t n_layers, const double*
  * the face.  Single-problem plans only; synchronises the plan's stream. */
 psfd_status psfd_specular(psfd_plan_t p, const void* E, double r[2]);
 
+/* Threshold-contour widths (paper, Results, "Practical assessment of
+ * scattered-field convergence" paragraph, equation logistic_sigmoid): the
+ * intensity I = |v|^2 of each field plane is mapped through
+ * S(I) = 1 / (1 + exp(-(I - i_th) / w)) (the paper: i_th = 0.15, w = 0.05),
+ * and on nlines horizontal lines (rows floor((l + 1/2) ny / nlines), along
+ * x) and then nlines vertical lines (columns floor((l + 1/2) nx / nlines),
+ * along y) the segments with S > 1/2 between an upward and the next
+ * downward crossing of S = 1/2 are measured.  Lines are periodic; a sample
+ * is above threshold when re*re + im*im > i_th (products rounded
+ * separately); a crossing is placed by linear interpolation of S.
+ *   planes        device, nplanes planes of [ny][nx] complex128 (e.g. E_y on
+ *                 the observation row), plane_stride elements apart
+ *   seg           device out, [nplanes][2 nlines][max_seg][2] doubles: start
+ *                 (from the line's first sample) and width, in nm, in line
+ *                 order from the first upward crossing
+ *   nseg          device out, [nplanes][2 nlines] int32: segments on each line
+ *                 (0: the line never crosses; a count above max_seg means
+ *                 only max_seg were stored; max(nx, ny)/2 always suffices)
+ * 2 <= nx, ny <= 1024.  Asynchronous on hip_stream. */
+psfd_status psfd_contour_segments(const void* planes, int32_t nx, int32_t ny, int32_t nplanes,
+                                  int64_t plane_stride, double dx, double dy, int32_t nlines,
+                                  double i_th, double w, int32_t max_seg, double* seg,
+                                  int32_t* nseg, void* hip_stream);
+
+/* Width deviation against a reference (same paragraph: delta d = d_ref - d,
+ * divided by the 4x demagnification for wafer-scale numbers).  For every
+ * reference segment the segment of the other field on the same line whose
+ * periodic interval holds the reference segment's centre is its
+ * counterpart.  Inputs are two outputs of psfd_contour_segments with the
+ * same sizes (device).
+ *   delta   device out, [nplanes][2 nlines][max_seg]: (d_ref - d) / demag per
+ *           reference segment, NaN where there is no counterpart (unresolved),
+ *           0 in slots beyond the line's segment count
+ *   stats   host out, [5]: sum |delta|, sum delta^2, resolved count,
+ *           unresolved count, count of |delta| > thr
+ * Allocates a temporary and synchronises hip_stream. */
+psfd_status psfd_contour_deviation(const double* seg_ref, const int32_t* nseg_ref,
+                                   const double* seg, const int32_t* nseg, int32_t nx, int32_t ny,
+                                   int32_t nplanes, double dx, double dy, int32_t nlines,
+                                   int32_t max_seg, double demag, double thr, double* delta,
+                                   double* stats, void* hip_stream);
+
 /* Copy the plan's per-mode multilayer reflections (transfer-matrix method,
  * paper section 2.2 step (iii)): r_te, r_pe device [ny][nx] complex128.
  * r_pe is the tangential-electric-field TM coefficient. */

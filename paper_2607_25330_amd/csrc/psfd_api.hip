@@ -1620,6 +1620,59 @@ psfd_status psfd_specular(psfd_plan_t p, const void* E, double r[2]) {
   return guarded([&] { return specular_impl(p, E, r); });
 }
 
+psfd_status psfd_contour_segments(const void* planes, int32_t nx, int32_t ny, int32_t nplanes,
+                                  int64_t plane_stride, double dx, double dy, int32_t nlines,
+                                  double i_th, double w, int32_t max_seg, double* seg,
+                                  int32_t* nseg, void* hip_stream) {
+  if (!planes || !seg || !nseg) return fail(PSFD_ERR_ARG, "NULL argument");
+  if (nx < 2 || ny < 2 || nx > kContourLineMax || ny > kContourLineMax || nplanes < 1 ||
+      nplanes > 65535 || nlines < 1 || 2 * nlines > 65535 || max_seg < 1 ||
+      plane_stride < (int64_t)nx * ny)
+    return fail(PSFD_ERR_ARG, "bad sizes (2 <= nx, ny <= 1024, nplanes >= 1, nlines >= 1, max_seg >= 1)");
+  if (!(dx > 0) || !(dy > 0) || !(w > 0) || !std::isfinite(i_th))
+    return fail(PSFD_ERR_ARG, "need dx, dy, w > 0 and a finite threshold");
+  return guarded([&]() -> psfd_status {
+    ContourArgs a{static_cast<const cplx<double>*>(planes), plane_stride, nx, ny, nlines, max_seg,
+                  dx, dy, i_th, w, seg, nseg};
+    CHK(launch_contour_segments(a, nplanes, static_cast<hipStream_t>(hip_stream)));
+    return PSFD_OK;
+  });
+}
+
+psfd_status psfd_contour_deviation(const double* seg_ref, const int32_t* nseg_ref,
+                                   const double* seg, const int32_t* nseg, int32_t nx, int32_t ny,
+                                   int32_t nplanes, double dx, double dy, int32_t nlines,
+                                   int32_t max_seg, double demag, double thr, double* delta,
+                                   double* stats, void* hip_stream) {
+  if (!seg_ref || !nseg_ref || !seg || !nseg || !delta || !stats)
+    return fail(PSFD_ERR_ARG, "NULL argument");
+  if (nx < 2 || ny < 2 || nplanes < 1 || nlines < 1 || max_seg < 1)
+    return fail(PSFD_ERR_ARG, "bad sizes");
+  if (!(dx > 0) || !(dy > 0) || !(demag > 0) || !std::isfinite(thr))
+    return fail(PSFD_ERR_ARG, "need dx, dy, demag > 0");
+  return guarded([&]() -> psfd_status {
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    const int64_t items = (int64_t)nplanes * 2 * nlines * max_seg;
+    const int nb = (int)std::max<int64_t>(1, std::min<int64_t>(1024, (items + 255) / 256));
+    struct psfd_plan tmp;  // owns the temporary
+    tmp.st = st;
+    double* part = nullptr;
+    CHKS(dalloc(&tmp, &part, (size_t)nb * 5));
+    DeviationArgs a{seg_ref, nseg_ref, seg, nseg, nplanes, nlines, max_seg, nx * dx, ny * dy,
+                    demag, thr, delta, part};
+    CHK(launch_contour_deviation(a, nb, st));
+    std::vector<double> h((size_t)nb * 5);
+    CHK(hipMemcpyAsync(h.data(), part, sizeof(double) * nb * 5, hipMemcpyDeviceToHost, st));
+    CHK(hipStreamSynchronize(st));
+    for (int k = 0; k < 5; ++k) {
+      double s = 0.0;
+      for (int b = 0; b < nb; ++b) s += h[(size_t)b * 5 + k];
+      stats[k] = s;
+    }
+    return PSFD_OK;
+  });
+}
+
 psfd_status psfd_profile_enable(psfd_plan_t p, int32_t kernel) {
   if (!p || p->is_batch || kernel < PROF_OFF || kernel > PROF_XINV) return fail(PSFD_ERR_ARG, "bad argument");
   return guarded([&]() -> psfd_status {

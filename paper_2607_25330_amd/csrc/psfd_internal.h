@@ -173,6 +173,29 @@ hipError_t launch_real_to_cplx(const double* a, int n, cplx<double>* out, hipStr
 // out[j][i] = rows[j] for j < nrows, i < plane (rows: device)
 hipError_t launch_fill_rows(const cplx<double>* rows, int64_t plane, int nrows,
                             cplx<double>* out, hipStream_t st);
+// ---- threshold-contour width metric (contour.hip)
+constexpr int kContourLineMax = 1024;  // longest scan line
+struct ContourArgs {
+  const cplx<double>* f;   // planes [nplanes] of [ny][nx], plane stride pstride elements
+  int64_t pstride;
+  int nx, ny, nlines, max_seg;
+  double dx, dy, i_th, w;
+  double* seg;             // [nplanes][2 nlines][max_seg][2]: start, width
+  int32_t* nseg;           // [nplanes][2 nlines]
+};
+struct DeviationArgs {
+  const double* sref;
+  const int32_t* nref;
+  const double* sk;
+  const int32_t* nk;
+  int nplanes, nlines, max_seg;
+  double len_h, len_v, demag, thr;
+  double* delta;           // [nplanes][2 nlines][max_seg]
+  double* part;            // [blocks][5]
+};
+hipError_t launch_contour_segments(const ContourArgs& a, int nplanes, hipStream_t st);
+hipError_t launch_contour_deviation(const DeviationArgs& a, int nblocks, hipStream_t st);
+
 // part[q][b], q < 4, b < nblk: partial sums of the plane starting at f + off[q]
 struct PlaneSet {
   int64_t off[4];

@@ -81,6 +81,11 @@ _SIGS = {
     "psfd_profile_read": [c_void_p, c_dp, ctypes.POINTER(c_int64), c_dp],
     "psfd_layered_eps": [ctypes.POINTER(Desc), c_int32, c_dp, c_dp, c_void_p, c_void_p],
     "psfd_specular": [c_void_p, c_void_p, c_dp],
+    "psfd_contour_segments": [c_void_p, c_int32, c_int32, c_int32, c_int64, c_double, c_double,
+                              c_int32, c_double, c_double, c_int32, c_void_p, c_void_p, c_void_p],
+    "psfd_contour_deviation": [c_void_p, c_void_p, c_void_p, c_void_p, c_int32, c_int32, c_int32,
+                               c_double, c_double, c_int32, c_int32, c_double, c_double, c_void_p,
+                               c_dp, c_void_p],
     "psfd_tune": [c_void_p],
     "psfd_schedule": [c_void_p, ctypes.POINTER(c_int32)],
     "psfd_set_schedule": [c_void_p, ctypes.POINTER(c_int32)],
@@ -185,6 +190,49 @@ def psfd_layered_eps(cfg, layers_eps, layers_thick, device):
     _call("psfd_layered_eps", ctypes.byref(d), c_int32(n), ctypes.cast(le, c_dp),
           ctypes.cast(ld, c_dp), _ptr(out, torch.complex128), _stream_handle())
     return out
+
+
+def contour_segments(planes, dx, dy, nlines=100, i_th=0.15, w=0.05, max_seg=None):
+    """Threshold-contour segments of [ny][nx] or [B][ny][nx] complex128 planes.
+
+    Returns (seg [B][2 nlines][max_seg][2] (start, width) float64, nseg [B][2 nlines] int32);
+    horizontal lines first."""
+    p = planes if planes.dim() == 3 else planes.unsqueeze(0)
+    if p.dtype != torch.complex128 or not p.is_cuda:
+        raise TypeError("planes must be a complex128 CUDA tensor")
+    if p.stride(2) != 1 or p.stride(1) != p.shape[2]:
+        raise ValueError("each plane must be contiguous")
+    B, ny, nx = p.shape
+    ms = max(nx, ny) // 2 if max_seg is None else int(max_seg)
+    seg = torch.zeros((B, 2 * nlines, ms, 2), dtype=torch.float64, device=p.device)
+    nseg = torch.zeros((B, 2 * nlines), dtype=torch.int32, device=p.device)
+    _call("psfd_contour_segments", c_void_p(p.data_ptr()), c_int32(nx), c_int32(ny), c_int32(B),
+          c_int64(p.stride(0)), c_double(dx), c_double(dy), c_int32(nlines), c_double(i_th),
+          c_double(w), c_int32(ms), c_void_p(seg.data_ptr()), c_void_p(nseg.data_ptr()),
+          _stream_handle())
+    return seg, nseg
+
+
+def contour_deviation(ref, other, nx, ny, dx, dy, demag=4.0, thr=1.0):
+    """(d_ref - d) / demag per reference segment and the statistics, from two
+    contour_segments results of the same sizes.  Returns (delta, stats dict)."""
+    sr, nr = ref
+    sk, nk = other
+    if sr.shape != sk.shape or nr.shape != nk.shape:
+        raise ValueError("reference and field segments differ in shape")
+    B, nl2, ms, _ = sr.shape
+    delta = torch.empty((B, nl2, ms), dtype=torch.float64, device=sr.device)
+    st = (c_double * 5)()
+    _call("psfd_contour_deviation", c_void_p(sr.data_ptr()), c_void_p(nr.data_ptr()),
+          c_void_p(sk.data_ptr()), c_void_p(nk.data_ptr()), c_int32(nx), c_int32(ny), c_int32(B),
+          c_double(dx), c_double(dy), c_int32(nl2 // 2), c_int32(ms), c_double(demag),
+          c_double(thr), c_void_p(delta.data_ptr()), ctypes.cast(st, c_dp), _stream_handle())
+    n = st[2]
+    mean = st[0] / n if n else float("nan")
+    var = st[1] / n - mean * mean if n else float("nan")
+    return delta, {"sum_abs": st[0], "sum_sq": st[1], "resolved": int(st[2]),
+                   "unresolved": int(st[3]), "above_thr": int(st[4]), "mean_abs": mean,
+                   "std_abs": (max(var, 0.0)) ** 0.5 if n else float("nan")}
 
 
 class Plan:

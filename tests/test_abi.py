@@ -79,5 +79,15 @@ def test_invalid_arguments_return_err_arg(L):
     thick = (ctypes.c_double * 1)(-1.0)
     assert L.psfd_layered_eps(ctypes.byref(d), 1, neg, thick, ctypes.c_void_p(1), None) == psfd.PSFD_ERR_ARG
     assert L.psfd_specular(None, None, None) == psfd.PSFD_ERR_ARG
+    one = ctypes.c_void_p(1)
+    assert L.psfd_contour_segments(None, 64, 64, 1, 4096, 1.0, 1.0, 10, 0.15, 0.05, 8, one, one,
+                                   None) == psfd.PSFD_ERR_ARG
+    assert L.psfd_contour_segments(one, 2048, 64, 1, 2048 * 64, 1.0, 1.0, 10, 0.15, 0.05, 8, one,
+                                   one, None) == psfd.PSFD_ERR_ARG
+    assert L.psfd_contour_segments(one, 64, 64, 1, 100, 1.0, 1.0, 10, 0.15, 0.05, 8, one, one,
+                                   None) == psfd.PSFD_ERR_ARG
+    st5 = (ctypes.c_double * 5)()
+    assert L.psfd_contour_deviation(one, one, one, one, 64, 64, 1, 1.0, 1.0, 10, 8, 0.0, 1.0, one,
+                                    st5, None) == psfd.PSFD_ERR_ARG
     assert L.psfd_field_size(None) == 0
     L.psfd_destroy(None)
