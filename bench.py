@@ -383,6 +383,66 @@ def workload_fd(psfd, args):
     return out
 
 
+def workload_contour(psfd, args):
+    """Practical convergence by threshold-contour widths: 8 seeded 256x256x48 clips (line/space
+    and contacts alternating), TE 6 deg, grazing cutoff 0.1.  Reference: FP64 solve to r_rel 1e-7.
+    Mixed solves stopped after k iterations (k = 50 ... 1600) and run to 1e-6: |delta d| at wafer
+    scale (/4) over 100 horizontal + 100 vertical scan lines of |E_y|^2 on the observation row
+    (S(I) with I_th 0.15, w 0.05), and the metric kernels' own time for the 8 planes."""
+    import numpy as np
+    import torch
+    from psfd_synth import config_c2, eps_absorber_default
+    dev = torch.device("cuda:0")
+    cfg = dict(config_c2(0), ml_kz_min=ML_KZ_MIN)
+    nx, ny, dx = cfg["nx"], cfg["ny"], cfg["dx"]
+    jobs = cfg["nz_pml"] + cfg["nz_gap_bot"] + cfg["nz_abs"]
+    lays = [torch.from_numpy(a).to(dev) for a in layouts(8, nx, ny, dx)]
+    eps = [psfd.psfd_layout_eps(cfg, a, eps_absorber_default()) for a in lays]
+    refs = []
+    for e in eps:
+        plan = psfd.Plan(cfg, e, psfd.PSFD_C128)
+        E, info = plan.solve(tol=1e-7, maxit=args.maxit)
+        refs.append(E[1, jobs].clone())
+        plan.close()
+    ref_planes = torch.stack(refs)
+    seg_ref = psfd.contour_segments(ref_planes, dx, dx)
+    checkpoints = [50, 100, 200, 400, 800, 1600, None]
+    legs = []
+    for k in checkpoints:
+        planes, iters, rrel = [], [], []
+        for e in eps:
+            plan = psfd.Plan(cfg, e, psfd.PSFD_C64_REFINE64)
+            E, info = plan.solve(tol=1e-6 if k is None else 1e-12, maxit=args.maxit if k is None else k,
+                                 check=False)
+            planes.append(E[1, jobs].clone())
+            iters.append(info["iters"])
+            rrel.append(info["rrel"])
+            plan.close()
+        seg_k = psfd.contour_segments(torch.stack(planes), dx, dx)
+        _, st = psfd.contour_deviation(seg_ref, seg_k, nx, ny, dx, dx, demag=4.0, thr=1.0)
+        leg = {"iters": "to 1e-6" if k is None else k, "mean_iters": float(np.mean(iters)),
+               "median_rrel": float(np.median(rrel)), "mean_abs_dd_nm": st["mean_abs"],
+               "std_abs_dd_nm": st["std_abs"], "resolved": st["resolved"],
+               "unresolved": st["unresolved"], "above_1nm": st["above_thr"]}
+        _log(f"contour k={k}: {leg}")
+        legs.append(leg)
+    # metric kernels alone (8 planes, 200 lines each)
+    for _ in range(3):
+        psfd.contour_deviation(seg_ref, psfd.contour_segments(ref_planes, dx, dx), nx, ny, dx, dx)
+    (_, dt) = _sync_time(lambda: [psfd.contour_segments(ref_planes, dx, dx) for _ in range(20)])
+    seg_t = dt / 20
+    (_, dt2) = _sync_time(lambda: [psfd.contour_deviation(seg_ref, seg_ref, nx, ny, dx, dx)
+                                   for _ in range(20)])
+    return {"metric": "threshold-contour width deviation vs iterations", "unit": "planes/s",
+            "value": round(8 / seg_t, 1), "dtype": "f64", "legs": legs,
+            "segments_ms_8_planes": round(1e3 * seg_t, 4),
+            "deviation_ms_8_planes": round(1e3 * dt2 / 20, 4),
+            "segments_per_ref_plane": float(seg_ref[1].sum().item()) / 8,
+            "config": {"workload": "8 seeded 256x256x(32+16) clips, TE 6 deg, cutoff 0.1; reference "
+                                   "FP64 1e-7; mixed stopped at k iterations; 100+100 scan lines, "
+                                   "I_th 0.15, w 0.05, /4 demag"}}
+
+
 def _tmm_te(psfd, cfg, eps_l, d_l, dev):
     """Transfer-matrix reflection of the bare stack between vacuum half-spaces (TE), from the
     library's own per-mode table of a plan that carries the stack as its multilayer."""
@@ -415,7 +475,7 @@ def main():
     ap.add_argument("--cpu-leg", type=float, default=None, help=argparse.SUPPRESS)
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run one device copy of this size (for counter calibration)")
-    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5", "fd"],
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5", "fd", "contour"],
                     help="c2 (default) is the headline line; the others print their own line")
     ap.add_argument("--c3-clips", type=int, default=64)
     args = ap.parse_args()
@@ -440,7 +500,7 @@ def main():
 
     if args.workload != "c2":
         fn = {"c1": workload_c1, "c3": workload_c3, "c4": workload_c4, "c5": workload_c5,
-              "fd": workload_fd}[args.workload]
+              "fd": workload_fd, "contour": workload_contour}[args.workload]
         res = fn(psfd, args)
         res.update({"n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "data": "synthetic",
                     "higher_is_better": True, "vs_baseline": None})
