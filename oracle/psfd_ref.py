@@ -580,6 +580,58 @@ def residual_loss(P, E):
     return float(np.vdot(r, r).real) / (P.g.nx * P.g.ny * P.g.nz)
 
 
+def hf_weight(P, w0, eta):
+    """w(nu) = w0 + eta |nu| on the bins of the 3-D DFT of a field, shape (nz, ny, nx).
+
+    |nu| = |k| / (2 pi) with k the physical wavenumber of each bin: the
+    Bloch-shifted lateral wavenumbers of the grid and the axial ones (the
+    paper names the spatial frequency without saying how the Bloch phase
+    enters; the damping preconditioner uses the same wavenumbers)."""
+    g = P.g
+    K2 = g.kz[:, None, None] ** 2 + g.ky[None, :, None] ** 2 + g.kx[None, None, :] ** 2
+    return w0 + eta * np.sqrt(K2) / (2.0 * np.pi)
+
+
+def hf_penalty(P, r, w0, eta, lam):
+    """(lam / N) sum_alpha ||w(nu) F3[r_alpha]||^2, F3 the unnormalised 3-D DFT
+    (paper, equation loss, second term)."""
+    g = P.g
+    n = g.nx * g.ny * g.nz
+    R3 = np.fft.fftn(r, axes=(1, 2, 3))
+    w = hf_weight(P, w0, eta)
+    return lam * float(np.sum(np.abs(w[None] * R3) ** 2)) / n
+
+
+def pino_loss(P, E, w0, eta, lam):
+    """The whole physics loss (paper, equation loss) at E: (J, residual term,
+    penalty term) with r = A E - b."""
+    g = P.g
+    n = g.nx * g.ny * g.nz
+    r = apply_A(P, E) - rhs(P)
+    t1 = float(np.vdot(r, r).real) / n
+    t2 = hf_penalty(P, r, w0, eta, lam)
+    return t1 + t2, t1, t2
+
+
+def pino_loss_field(P, E, w0, eta, lam):
+    """u = dJ/d conj(r) = (1/N) r + (lam/N) F3^H w^2 F3 r, r = A E - b (F3^H = N F3^-1)."""
+    g = P.g
+    n = g.nx * g.ny * g.nz
+    r = apply_A(P, E) - rhs(P)
+    w2 = hf_weight(P, w0, eta) ** 2
+    FH = n * np.fft.ifftn(w2[None] * np.fft.fftn(r, axes=(1, 2, 3)), axes=(1, 2, 3))
+    return r / n + (lam / n) * FH
+
+
+def pino_loss_grad(P, E, w0, eta, lam):
+    """Gradients of the physics loss in PyTorch's convention (dJ/dRe + i dJ/dIm):
+    with respect to E, 2 A^H u; with respect to eps on absorber voxels,
+    -2 k0^2 sum_alpha u_alpha conj(Psi_alpha) (A E - b depends on eps through
+    -k0^2 d_eps Psi(E)); u = pino_loss_field."""
+    u = pino_loss_field(P, E, w0, eta, lam)
+    return 2.0 * apply_AH(P, u), eps_gradient(P, E, u, -2.0 * P.g.k0 ** 2)
+
+
 # --------------------------------------------------------------------------
 # Outputs and diagnostics
 # --------------------------------------------------------------------------
