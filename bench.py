@@ -443,6 +443,60 @@ def workload_contour(psfd, args):
                                    "I_th 0.15, w 0.05, /4 demag"}}
 
 
+def workload_pino(psfd, args):
+    """The paper's physics loss with the high-frequency penalty, as PINO training evaluates it:
+    16 seeded 128x128x(32+16) clips, TE 6 deg, one field per clip (a solve's output plus smooth
+    noise, standing in for a network prediction); loss + gradients with respect to the field and
+    the permittivity through the autograd wrapper (w0 1, eta_hf 10 nm, lambda_hf 0.01).  Also
+    the loss kernels' own time: residual, weighted spectral pass, gradient combine, adjoint."""
+    import numpy as np
+    import torch
+    from paper_2607_25330_amd.autograd import pino_loss
+    from psfd_synth import config_c5, eps_absorber_default, rect_layout
+    dev = torch.device("cuda:0")
+    cfg = dict(config_c5(), ml_kz_min=ML_KZ_MIN)
+    w0, eta, lam = 1.0, 10.0, 0.01
+    eps = [psfd.psfd_layout_eps(cfg, torch.from_numpy(rect_layout(128, 128, np.random.default_rng(900 + c))).to(dev),
+                                eps_absorber_default()) for c in range(16)]
+    fields = []
+    for c, e in enumerate(eps):
+        plan = psfd.Plan(cfg, e, psfd.PSFD_C64_REFINE64)
+        E, _ = plan.solve(tol=1e-6, maxit=args.maxit)
+        plan.close()
+        fields.append((E + 0.05 * _smooth_noise(E.shape, 950 + c, dev, sigma_cells=4.0)).contiguous())
+
+    def step():
+        out = []
+        for E, e in zip(fields, eps):
+            Et = E.clone().requires_grad_(True)
+            et = e.clone().requires_grad_(True)
+            J = pino_loss(Et, et, cfg, w0, eta, lam)
+            J.backward()
+            out.append((float(J), Et.grad, et.grad))
+        return out
+    step()
+    res, dt = _sync_time(step)
+    # the library calls alone on one plan (no plan setup, no autograd bookkeeping)
+    plan = psfd.Plan(cfg, eps[0], psfd.PSFD_C128)
+    E = fields[0]
+    for _ in range(3):
+        _, g = plan.pino_loss(E, w0, eta, lam)
+        plan.adjoint(g)
+    (_, dt_loss) = _sync_time(lambda: [plan.pino_loss(E, w0, eta, lam) for _ in range(20)])
+    (_, dt_adj) = _sync_time(lambda: [plan.adjoint(g) for _ in range(20)])
+    (_, dt_apply) = _sync_time(lambda: [plan.apply(E) for _ in range(20)])
+    plan.close()
+    vox = 3 * 128 * 128 * 48
+    return {"metric": "physics-loss evaluations/s (loss + field and permittivity gradients)",
+            "value": round(16 / dt, 2), "unit": "evaluations/s", "dtype": "f64",
+            "loss_ms": round(1e3 * dt_loss / 20, 3), "adjoint_ms": round(1e3 * dt_adj / 20, 3),
+            "apply_ms": round(1e3 * dt_apply / 20, 3),
+            "loss_terms_clip0": {"J": res[0][0]}, "voxels": vox,
+            "config": {"workload": "16 seeded rectangle clips 128x128x(32+16), TE 6 deg, field = "
+                                   "mixed solve + smooth noise; J = (1/N)||r||^2 + (lambda/N)"
+                                   "||w F3 r||^2, w0 1, eta 10 nm, lambda 0.01; autograd"}}
+
+
 def _tmm_te(psfd, cfg, eps_l, d_l, dev):
     """Transfer-matrix reflection of the bare stack between vacuum half-spaces (TE), from the
     library's own per-mode table of a plan that carries the stack as its multilayer."""
@@ -475,7 +529,7 @@ def main():
     ap.add_argument("--cpu-leg", type=float, default=None, help=argparse.SUPPRESS)
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run one device copy of this size (for counter calibration)")
-    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5", "fd", "contour"],
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5", "fd", "contour", "pino"],
                     help="c2 (default) is the headline line; the others print their own line")
     ap.add_argument("--c3-clips", type=int, default=64)
     args = ap.parse_args()
@@ -500,7 +554,7 @@ def main():
 
     if args.workload != "c2":
         fn = {"c1": workload_c1, "c3": workload_c3, "c4": workload_c4, "c5": workload_c5,
-              "fd": workload_fd, "contour": workload_contour}[args.workload]
+              "fd": workload_fd, "contour": workload_contour, "pino": workload_pino}[args.workload]
         res = fn(psfd, args)
         res.update({"n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "data": "synthetic",
                     "higher_is_better": True, "vs_baseline": None})

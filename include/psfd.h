@@ -189,6 +189,25 @@ psfd_status psfd_residual(psfd_plan_t p, const void* b, const void* E, void* r, 
  * complex128 (overwritten). */
 psfd_status psfd_eps_grad(psfd_plan_t p, const void* E, const void* u, double scale, void* grad);
 
+/* The physics loss of the paper's PINO (section 2.2, equation loss, with its
+ * frequency weight w(nu) = w0 + eta_hf |nu|) at a field E:
+ *   J = (1/N) sum_alpha ||r_alpha||^2
+ *     + (lambda_hf/N) sum_alpha ||w(nu) F3[r_alpha]||^2,   r = A E - b,
+ * N = nx ny Nz, F3 the unnormalised 3-D DFT, |nu| = |k| / (2 pi) with k the
+ * plan's (Bloch-shifted lateral, axial) wavenumber of each DFT bin, in 1/nm.
+ * The paper does not give w0, eta_hf, lambda_hf: they are arguments.
+ *   E     device [3][Nz][ny][nx] complex128
+ *   loss  host out, [3]: J, the residual term, the penalty term
+ *   g     device out or NULL: the field g = (1/N) r' + lambda_hf H r' with
+ *         r' = b - A E and H = F3^-1 w^2 F3; the gradients then follow as
+ *         dJ/dE = -2 A^H g (psfd_adjoint) and dJ/d eps = psfd_eps_grad(E, g,
+ *         2 k0^2) (PyTorch convention grad = dJ/dRe + i dJ/dIm).
+ * The penalty is evaluated as lambda_hf <r', H r'> (Parseval), one spectral
+ * pass with w^2 as its multiplier whose inner product rides on the last
+ * lateral pass.  Single-problem plans; g must not overlap E; synchronises. */
+psfd_status psfd_pino_loss(psfd_plan_t p, const void* E, double w0, double eta_hf,
+                           double lambda_hf, double loss[3], void* g);
+
 /* Batched solves of independent problems (mask clips x incidence angles x
  * polarisations, uneven sizes allowed).  psfd_plan_batch validates and
  * records n problems: the descriptors and multilayer tables are copied; the

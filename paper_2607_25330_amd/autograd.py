@@ -12,6 +12,10 @@ applied here.  Complex gradients follow the PyTorch convention
 * ``residual_loss(E, eps, cfg)`` -> (1/N) ||A E - b||^2, N = nx ny nz (the
   residual term of the paper's physics loss).  Backward: dJ/dE = -(2/N) A^H r,
   dJ/d eps = (2 k0^2/N) sum_alpha r_alpha conj(Psi_alpha(E)), r = b - A E.
+* ``pino_loss(E, eps, cfg, w0, eta_hf, lambda_hf)`` -> the whole physics loss
+  with the high-frequency penalty (psfd_pino_loss).  Backward: with
+  g = (1/N) r + lambda_hf H r (H = F3^-1 w^2 F3, r = b - A E),
+  dJ/dE = -2 A^H g and dJ/d eps = 2 k0^2 sum_alpha g_alpha conj(Psi_alpha(E)).
 """
 
 import torch
@@ -67,3 +71,30 @@ class _ResidualLoss(torch.autograd.Function):
 def residual_loss(E, eps, cfg):
     """(1/N) ||A(eps) E - b(eps)||^2 (differentiable in E and eps)."""
     return _ResidualLoss.apply(E, eps, cfg)
+
+
+class _PinoLoss(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, E, eps, cfg, w0, eta, lam):
+        plan = Plan(cfg, eps.detach().contiguous())
+        Ed = E.detach().contiguous()
+        (J, _, _), g = plan.pino_loss(Ed, w0, eta, lam, grad=True)
+        ctx.plan = plan
+        ctx.save_for_backward(Ed, g)
+        return torch.tensor(J, dtype=torch.float64, device=E.device)
+
+    @staticmethod
+    def backward(ctx, gJ):
+        E, g = ctx.saved_tensors
+        plan = ctx.plan
+        s = float(gJ)
+        grad_E = plan.adjoint(g).mul_(-2.0 * s)
+        grad_eps = plan.eps_grad(E, g, 2.0 * plan.k0 ** 2 * s)
+        plan.close()
+        return grad_E, grad_eps, None, None, None, None
+
+
+def pino_loss(E, eps, cfg, w0=1.0, eta_hf=0.0, lambda_hf=0.0):
+    """The paper's physics loss (equation loss): (1/N) ||r||^2 + (lambda_hf/N) ||w F3 r||^2,
+    r = A(eps) E - b(eps), w = w0 + eta_hf |nu| (differentiable in E and eps)."""
+    return _PinoLoss.apply(E, eps, cfg, w0, eta_hf, lambda_hf)

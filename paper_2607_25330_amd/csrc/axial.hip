@@ -61,6 +61,17 @@ __device__ __forceinline__ T damping(T k2, const OpTables<T>& t) {
   return m;
 }
 
+// Multiplier of the M mode: the damping m(k), or for the physics loss's
+// high-frequency penalty the squared weight w(nu)^2 = (w0 + eta |k| / 2 pi)^2.
+template <typename T>
+__device__ __forceinline__ T spec_mult(T k2, const OpTables<T>& t) {
+  if (t.hf_mode) {
+    const T wgt = t.hf_w0 + t.hf_eta * sqrt(k2) * T(0.15915494309189533577);
+    return wgt * wgt;
+  }
+  return damping(k2, t);
+}
+
 // exp(i kz z) for kz = kzr + i kzi
 template <typename T>
 __device__ __forceinline__ cplx<T> up_phase(const ColInfo<T>& c, T z) {
@@ -167,7 +178,7 @@ k_axial(const cplx<T>* __restrict__ S_all, cplx<T>* __restrict__ UW_all, const O
     const T kt2 = ci[cc].kt2;
     for (int l = z0; l < NZ; l += ZS) {
       const T kzl = kzs[l];
-      const T m = damping(kt2 + kzl * kzl, t) * inz;
+      const T m = (MODE == AX_M ? spec_mult(kt2 + kzl * kzl, t) : damping(kt2 + kzl * kzl, t)) * inz;
       cplx<T>* b0 = &buf[l * PITCH + cc];
       const cplx<T> p0 = m * b0[0], p1 = m * b0[VS], p2 = m * b0[2 * VS];
       b0[0] = p0;
@@ -366,7 +377,7 @@ k_axial_reg(const cplx<T>* __restrict__ S_all, cplx<T>* __restrict__ UW_all, con
 #pragma unroll
     for (int k2 = 0; k2 < E; ++k2) {
       const T kzl = t.kz[k2 + kofs];
-      const T m = damping(kt2 + kzl * kzl, t) * inz;
+      const T m = spec_mult(kt2 + kzl * kzl, t) * inz;
       px[k2] = m * px[k2];
       py[k2] = m * py[k2];
       pz[k2] = m * pz[k2];

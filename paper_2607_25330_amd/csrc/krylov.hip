@@ -89,7 +89,7 @@ k_finalize(KState* ks_all, const double* __restrict__ part_all, int nblocks,
   const double* part = part_all + (size_t)blockIdx.x * nblocks * KPART;
   const int d = ks->done;
   bool run;
-  if (STAGE == FIN_INIT || STAGE == FIN_RED0) run = true;
+  if (STAGE == FIN_INIT || STAGE == FIN_RED0 || STAGE == FIN_RED3) run = true;
   else if (STAGE == FIN_RHO) run = (d == KS_RUN || d == KS_HALF);
   else if (STAGE == FIN_REPLACE) run = (d == KS_UPDATE);
   else run = (d == KS_RUN);
@@ -123,6 +123,10 @@ k_finalize(KState* ks_all, const double* __restrict__ part_all, int nblocks,
     ks->iter = 0;
   } else if constexpr (STAGE == FIN_RED0) {
     ks->red[0] = acc[0];
+  } else if constexpr (STAGE == FIN_RED3) {
+    ks->red[0] = acc[0];
+    ks->red[1] = acc[1];
+    ks->red[2] = acc[2];
   } else if constexpr (STAGE == FIN_ALPHA) {
     const cplx<double> rv = {acc[0], acc[1]};
     st2(ks->rv, rv);
@@ -214,6 +218,7 @@ hipError_t launch_finalize(int stage, KState* ks, const double* part, int nblock
     case FIN_OMEGA: PSFD_FIN(FIN_OMEGA); break;
     case FIN_RHO: PSFD_FIN(FIN_RHO); break;
     case FIN_REPLACE: PSFD_FIN(FIN_REPLACE); break;
+    case FIN_RED3: PSFD_FIN(FIN_RED3); break;
     default: PSFD_FIN(FIN_RED0); break;
   }
 #undef PSFD_FIN

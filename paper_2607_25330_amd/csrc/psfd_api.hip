@@ -56,7 +56,7 @@ constexpr double kTwoPi = 6.283185307179586476925286766559;
 constexpr int kChunk = 16;         // BiCGSTAB iterations queued between convergence checks
 constexpr int kMaxRestarts = 10;   // residual replacements (FP64) / refinement steps (mixed)
 
-enum { OP_A = 0, OP_AM = 1, OP_AH = 2, OP_M = 3 };
+enum { OP_A = 0, OP_AM = 1, OP_AH = 2, OP_M = 3, OP_HF = 4 };  // OP_HF: F3^-1 w^2 F3
 enum { V_R = 0, V_RH, V_P, V_V, V_S, V_T, V_Y, V_W, V_COUNT };
 
 int fftfreq(int m, int n) { return (m < (n + 1) / 2) ? m : m - n; }
@@ -111,6 +111,7 @@ struct psfd_plan {
   cplx<double>* tmp64 = nullptr;
   cplx<double>* res64 = nullptr;
   cplx<double>* ebak64 = nullptr;  // the solution before a fold E += s M y (restored if it fails)
+  double hf_w0 = 1.0, hf_eta = 0.0;  // weight of the physics loss's high-frequency penalty
   cplx<double>* E64 = nullptr;  // stacked solution of a batch group
   KState* ks = nullptr;
   KState* ks_host = nullptr;
@@ -326,6 +327,11 @@ hipError_t op_apply(struct psfd_plan* P, const cplx<T>* x, cplx<T>* y, int op, c
   OpTables<T> t = tab<T>(P);
   t.skip = skip;
   t.skip_stride = skip_stride;
+  if (op == OP_HF) {
+    t.hf_mode = 1;
+    t.hf_w0 = (T)P->hf_w0;
+    t.hf_eta = (T)P->hf_eta;
+  }
   cplx<T>* S = wsS<T>(P);
   cplx<T>* UW = wsUW<T>(P);
   hipStream_t st = P->st;
@@ -1220,6 +1226,59 @@ psfd_status layout_impl(const psfd_desc* d, const double* a_bin, const double ep
   return PSFD_OK;
 }
 
+// The physics loss of the paper's PINO (equation loss) at a field E:
+//   J = (1/N) ||r||^2 + (lambda/N) sum_alpha ||w(nu) F3 r_alpha||^2,  r = A E - b,
+// with F3 unnormalised, so the penalty equals lambda <r, H r>, H = F3^-1 w^2 F3
+// (Parseval).  H is the M-mode spectral pass with w(nu)^2 as its multiplier;
+// <r, H r> rides on its inverse x pass.  The gradient field
+//   g = (1/N) r' + lambda H r',  r' = b - A E = -r,
+// gives dJ/dE = -2 A^H g and dJ/d eps = 2 k0^2 sum_alpha g_alpha conj(Psi_alpha)
+// (PyTorch's convention grad = dJ/dRe + i dJ/dIm).
+psfd_status pino_loss_impl(struct psfd_plan* P, const void* E_in, double w0, double eta,
+                           double lam, double* out, void* g_out) {
+  if (!P || !E_in || !out) return fail(PSFD_ERR_ARG, "NULL argument");
+  if (P->is_batch || P->G != 1) return fail(PSFD_ERR_ARG, "psfd_pino_loss takes a single-problem plan");
+  if (!std::isfinite(w0) || !std::isfinite(eta) || !(lam >= 0) || !std::isfinite(lam))
+    return fail(PSFD_ERR_ARG, "need finite w0, eta and lambda >= 0");
+  if (g_out == E_in) return fail(PSFD_ERR_ARG, "g must not overlap E");
+  CHKS(ensure_solver_common(P));
+  const auto* E = static_cast<const cplx<double>*>(E_in);
+  const int64_t n = P->nfield;
+  hipStream_t st = P->st;
+  P->idle_host[0] = 0;
+  P->pp_host[0] = ProbParams{};
+  P->pp_host[0].mask = 1.0;
+  CHKS(push_params(P));
+  CHKS(rhs_group(P, P->b64));
+  CHKS(true_residual(P, P->b64, E, P->res64, false));  // r' = b - A E
+  const double rr = P->ks_host[0].red[0];
+  P->hf_w0 = w0;
+  P->hf_eta = eta;
+  Fuse<double> fz;
+  int nb = 0;
+  fz.post.mode = POST_DOT;
+  fz.post.d = P->res64;
+  fz.post.part = P->part;
+  fz.nblk_post = &nb;
+  CHK(op_apply<double>(P, P->res64, P->tmp64, OP_HF, P->idle, 1, fz));  // H r'
+  CHK(launch_finalize(FIN_RED3, P->ks, P->part, nb, 1, P->pp, st));
+  CHKS(read_state(P));
+  const double rh = P->ks_host[0].red[0];  // Re <r', H r'>
+  const double N = (double)P->nx * P->ny * P->nz;
+  out[0] = rr / N + lam * rh;
+  out[1] = rr / N;
+  out[2] = lam * rh;
+  if (g_out) {
+    auto* g = static_cast<cplx<double>*>(g_out);
+    P->pp_host[0].iscale = 1.0 / N;
+    P->pp_host[0].scale = lam;
+    CHKS(push_params(P));
+    CHK(launch_k_scale_copy<double, double>(g, P->res64, P->pp, n, 1, st));
+    CHK(launch_k_axpy<double, double>(g, P->tmp64, P->pp, n, 1, st));
+  }
+  return PSFD_OK;
+}
+
 // Row means of a planar stack over the absorber rows, walked once from the
 // top face z = nz_abs dz downwards: each row [j dz, (j+1) dz) collects the
 // overlap-weighted permittivity of the layers it meets and the background
@@ -1609,6 +1668,11 @@ psfd_status psfd_ml_reflection(psfd_plan_t p, void* r_te, void* r_pe) {
     CHK(hipMemcpyAsync(r_pe, p->rpe64, bytes, hipMemcpyDeviceToDevice, p->st));
     return PSFD_OK;
   });
+}
+
+psfd_status psfd_pino_loss(psfd_plan_t p, const void* E, double w0, double eta_hf,
+                           double lambda_hf, double loss[3], void* g) {
+  return guarded([&] { return pino_loss_impl(p, E, w0, eta_hf, lambda_hf, loss, g); });
 }
 
 psfd_status psfd_layered_eps(const psfd_desc* d, int32_t n_layers, const double* layers_eps,

@@ -44,6 +44,8 @@ struct OpTables {
   // spectral damping multiplier m(k)
   T pc_mmin, pc_kref2, pc_gamma, pc_reg;
   int pc_bf16;              // round m(k) to bfloat16
+  int hf_mode;              // 1: the M-mode multiplier is the loss weight w(nu)^2 instead of m(k)
+  T hf_w0, hf_eta;          // w(nu) = hf_w0 + hf_eta |nu|,  |nu| = |k| / (2 pi)
   int ax_lds;               // 1: always use the LDS-staged axial kernel
   // kernel schedules chosen by the autotuner (0 = default): forward x pass,
   // inverse x pass, y pass (bit 0 radix schedule, bit 1 half rows / tile);
@@ -230,7 +232,7 @@ struct ProbParams {
   double pad;
 };
 
-enum FinStage { FIN_INIT = 0, FIN_ALPHA, FIN_OMEGA, FIN_RHO, FIN_RED0, FIN_REPLACE };
+enum FinStage { FIN_INIT = 0, FIN_ALPHA, FIN_OMEGA, FIN_RHO, FIN_RED0, FIN_REPLACE, FIN_RED3 };
 // Krylov state of a problem (KState::done)
 enum { KS_RUN = 0, KS_CONV = 1, KS_HALF = 2, KS_BREAK = 3, KS_IDLE = 4, KS_MAXIT = 5, KS_UPDATE = 6 };
 // One block per problem: sum problem b's `nblocks` partials (they start at

@@ -86,6 +86,7 @@ _SIGS = {
     "psfd_contour_deviation": [c_void_p, c_void_p, c_void_p, c_void_p, c_int32, c_int32, c_int32,
                                c_double, c_double, c_int32, c_int32, c_double, c_double, c_void_p,
                                c_dp, c_void_p],
+    "psfd_pino_loss": [c_void_p, c_void_p, c_double, c_double, c_double, c_dp, c_void_p],
     "psfd_tune": [c_void_p],
     "psfd_schedule": [c_void_p, ctypes.POINTER(c_int32)],
     "psfd_set_schedule": [c_void_p, ctypes.POINTER(c_int32)],
@@ -291,6 +292,16 @@ class Plan:
         rpe = torch.empty(n, dtype=torch.complex128, device=self.device)
         _call("psfd_ml_reflection", self._h, _ptr(rte, torch.complex128), _ptr(rpe, torch.complex128))
         return rte, rpe
+
+    def pino_loss(self, E, w0=1.0, eta=0.0, lam=0.0, grad=True):
+        """(J, residual term, penalty term) of the physics loss and, with grad=True, the field
+        g = (1/N) (b - A E) + lam H (b - A E) its gradients are built from."""
+        out = (c_double * 3)()
+        g = self._field() if grad else None
+        _call("psfd_pino_loss", self._h, _ptr(E, torch.complex128, self.shape, "E"), c_double(w0),
+              c_double(eta), c_double(lam), ctypes.cast(out, c_dp),
+              c_void_p(None) if g is None else _ptr(g, torch.complex128, self.shape, "g"))
+        return (out[0], out[1], out[2]), g
 
     def specular(self, E):
         """Specular (0, 0)-order reflection coefficient at the absorber region's top face."""
