@@ -19,6 +19,9 @@ from .configs import (  # noqa: F401
     FULL_DOMAIN_NZ,
     FULL_DOMAIN_THETAS_DEG,
     eps_absorber_default,
+    ffno_desc,
+    ffno_weight_blocks,
+    ffno_weights,
     full_domain_config,
     full_domain_stack,
     multilayer_stack,

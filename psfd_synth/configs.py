@@ -122,3 +122,33 @@ def full_domain_stack(n_bilayers=ML_BILAYERS):
     """(layer permittivities, thicknesses) of the bare stack, top to bottom."""
     eps, thick, _ = multilayer_stack(n_bilayers)
     return eps, thick
+
+
+# Factorised Fourier neural operator (paper, section 2.1): sizes and seeded
+# random weights (no trained weights exist here).  The flat weight layout is
+# documented with psfd_ffno_forward in include/psfd.h.
+def ffno_desc(nx, ny, nz, d_v=32, d_h=64, n_layers=4, kx_max=12, ky_max=12, kz_max=8):
+    return {"nx": int(nx), "ny": int(ny), "nz": int(nz), "d_v": int(d_v), "d_h": int(d_h),
+            "n_layers": int(n_layers), "kx_max": int(kx_max), "ky_max": int(ky_max),
+            "kz_max": int(kz_max)}
+
+
+def ffno_weight_blocks(desc):
+    """(name, element count, init scale) of every weight block, in storage order."""
+    dv, dh = desc["d_v"], desc["d_h"]
+    my, mx, mz = 2 * desc["ky_max"] + 1, desc["kx_max"] + 1, desc["kz_max"] + 1
+    blocks = [("P", dv * 4, 0.5), ("p", dv, 0.1)]
+    for _ in range(desc["n_layers"]):
+        blocks += [("Kxy", dv * dv * my * mx * 2, 1.0 / dv), ("Kz", dv * dv * mz * 2, 1.0 / dv),
+                   ("W1", dh * dv, 1.0 / math.sqrt(dv)), ("b1", dh, 0.1),
+                   ("W2", dv * dh, 1.0 / math.sqrt(dh)), ("b2", dv, 0.1)]
+    blocks += [("Q", 6 * dv, 1.0 / math.sqrt(dv)), ("q", 6, 0.0)]
+    return blocks
+
+
+def ffno_weights(desc, seed):
+    """Seeded Gaussian weights, each block scaled by its init scale (float32 values)."""
+    import numpy as np
+    rng = np.random.default_rng(seed)
+    parts = [rng.standard_normal(n) * s for _, n, s in ffno_weight_blocks(desc)]
+    return np.concatenate(parts).astype(np.float32)
