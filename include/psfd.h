@@ -306,6 +306,45 @@ psfd_status psfd_contour_deviation(const double* seg_ref, const int32_t* nseg_re
                                    int32_t max_seg, double demag, double thr, double* delta,
                                    double* stats, void* hip_stream);
 
+/* Factorised Fourier neural operator of the paper's PINO (section 2.1: the
+ * lateral and axial Fourier layers, the pointwise MLP with its residual
+ * connection, the lifting and decoding layers), forward pass only (a field
+ * prediction for the solver's warm start x0).  The paper does not give d_v,
+ * d_h, the layer count or the retained modes; they are fields here. */
+typedef struct {
+  int32_t nx, ny, nz;        /* grid of the prediction, each in 4 .. 8192 (nz <= 4096)      */
+  int32_t d_v, d_h;          /* feature / MLP hidden channels: (32, 64), (16, 32) or (8, 16) */
+  int32_t n_layers;          /* 1 .. 16                                                    */
+  int32_t kx_max, ky_max, kz_max; /* retained modes: kx 0..kx_max of the real-input half
+                                     spectrum, |ky| <= ky_max, kz 0..kz_max; 2 k_max < n,
+                                     kz_max <= 15                                         */
+} psfd_ffno_desc;
+
+/* Number of FP32 weights and workspace bytes of a network (host outputs,
+ * either may be NULL).  Weight layout, row-major blocks in this order:
+ *   P [d_v][4], p [d_v]                       lifting of (a, x/nx, y/ny, z/nz)
+ *   per layer: K_xy [d_v][d_v][2 ky_max + 1][kx_max + 1] complex (re, im pairs;
+ *              ky index m = ky + ky_max), K_z [d_v][d_v][kz_max + 1] complex,
+ *              W1 [d_h][d_v], b1 [d_h], W2 [d_v][d_h], b2 [d_v]
+ *   Q [6][d_v], q [6]                          decoding to Ex.re, Ex.im, Ey.re, ... */
+psfd_status psfd_ffno_sizes(const psfd_ffno_desc* d, int64_t* n_weights, int64_t* workspace_bytes);
+
+/* Forward pass.  Per layer l:
+ *   u_xy = F2^-1[K_xy . F2 v]  on every z slice (truncated real-input DFT;
+ *          the half-spectrum inverse drops the imaginary part of kx = 0),
+ *   u_z  = F1^-1[K_z . F1 u_xy] along z,
+ *   v   <- v + act(W2 gelu(W1 (u_xy + u_z) + b1) + b2), act = gelu (erf form)
+ *          except in the last layer,
+ * with v0 = P (a, x/nx, y/ny, z/nz) + p and E = Q v + q.
+ *   weights    device FP32, layout above
+ *   a_in       device FP32 [nz][ny][nx]: the smoothed material indicator
+ *   E          device out, [3][nz][ny][nx] complex128 (the solver's field layout)
+ *   workspace  device, psfd_ffno_sizes bytes, 256-byte aligned; contents
+ *              are overwritten (no allocation happens in this call)
+ * Asynchronous on hip_stream. */
+psfd_status psfd_ffno_forward(const psfd_ffno_desc* d, const float* weights, const float* a_in,
+                              void* E, void* workspace, void* hip_stream);
+
 /* Copy the plan's per-mode multilayer reflections (transfer-matrix method,
  * paper section 2.2 step (iii)): r_te, r_pe device [ny][nx] complex128.
  * r_pe is the tangential-electric-field TM coefficient. */

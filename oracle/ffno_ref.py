@@ -33,9 +33,10 @@ Weights: one flat float array, blocks in this order (row-major):
   Q [6][d_v], q [6]  (outputs Ex.re, Ex.im, Ey.re, Ey.im, Ez.re, Ez.im).
 """
 
-from math import erf, sqrt
+from math import sqrt
 
 import numpy as np
+from scipy.special import erf
 
 
 def block_sizes(desc):
@@ -72,7 +73,7 @@ def unpack(desc, w):
 
 
 def gelu(x):
-    return 0.5 * x * (1.0 + np.vectorize(erf)(x / sqrt(2.0)))
+    return 0.5 * x * (1.0 + erf(x / sqrt(2.0)))
 
 
 def _cplx(K):

@@ -12,7 +12,7 @@ INCLUDE = os.path.join(ROOT, "include")
 OBJDIR = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libpsfd.so")
 
-SOURCES = ["fft_lateral.hip", "axial.hip", "setup.hip", "krylov.hip", "contour.hip", "psfd_api.hip"]
+SOURCES = ["fft_lateral.hip", "axial.hip", "setup.hip", "krylov.hip", "contour.hip", "ffno.hip", "psfd_api.hip"]
 ARCH = "gfx950"
 FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",

@@ -1,0 +1,342 @@
+// Inference of the factorised Fourier neural operator of the paper's PINO
+// (section 2.1): lifting, L layers of [lateral truncated spectral conv on
+// every z slice -> axial truncated spectral conv -> pointwise MLP with a
+// residual connection], decoding to the three complex field components.
+//
+// Hidden state: d_v real channels, FP32, channel planes [d_v][nz][ny][nx].
+// The retained spectra are small (kx = 0..kx_max of the real-input half
+// spectrum, |ky| <= ky_max, kz = 0..kz_max), so the transforms are direct
+// truncated DFT sums with FP32 twiddle tables (built on the device in FP64):
+// any grid size works and no full-size spectrum is ever stored.
+//   x DFT:  T[c][z][y][kx]  = sum_x v e^{-2 pi i kx x / nx}   (rows staged in LDS)
+//   y DFT:  G[c][z][m][kx]  = sum_y T e^{-2 pi i ky y / ny},   ky = m - ky_max
+//   mix:    U[o][z][m][kx]  = sum_i K_xy[o][i][m][kx] G[i][z][m][kx]
+//   y iDFT: T2[o][z][y][kx] = sum_m U e^{+2 pi i ky y / ny}
+//   x iDFT: u[o][z][y][x]   = (Re T2[..][0] + 2 sum_{kx>0} Re(T2 e^{+2 pi i kx x/nx})) / (nx ny)
+// The axial branch, the sum u_xy + u_z, the MLP and the residual update run
+// in one kernel per tile of TX columns: forward z DFT of every channel into
+// LDS, channel mixing per kz, inverse z DFT added to u_xy into LDS (same
+// buffer), then one thread per voxel runs the MLP from LDS with the weights
+// read as wave-uniform values.
+#include <hip/hip_runtime.h>
+
+#include "psfd_internal.h"
+
+namespace psfd {
+
+namespace {
+
+__device__ __forceinline__ float gelu(float x) {
+  return 0.5f * x * (1.0f + erff(x * 0.70710678118654752f));
+}
+
+__global__ void k_ffno_twiddles(float2* tw, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double s, c;
+  sincospi(2.0 * (double)i / (double)n, &s, &c);
+  tw[i] = make_float2((float)c, (float)s);  // e^{+2 pi i i / n}
+}
+
+__global__ void k_ffno_lift(const FfnoArgs a, const float* __restrict__ P, const float* __restrict__ p,
+                            const float* __restrict__ in, float* __restrict__ v) {
+  const int64_t vox = (int64_t)a.nz * a.ny * a.nx;
+  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < vox;
+       q += (int64_t)gridDim.x * blockDim.x) {
+    const int x = (int)(q % a.nx);
+    const int y = (int)((q / a.nx) % a.ny);
+    const int z = (int)(q / ((int64_t)a.nx * a.ny));
+    const float f0 = in[q], f1 = (float)x / a.nx, f2 = (float)y / a.ny, f3 = (float)z / a.nz;
+    for (int c = 0; c < a.dv; ++c)
+      v[(int64_t)c * vox + q] = P[4 * c] * f0 + P[4 * c + 1] * f1 + P[4 * c + 2] * f2 +
+                                P[4 * c + 3] * f3 + p[c];
+  }
+}
+
+// T[row][kx] for rows of v (row = (c, z, y)); R rows per block staged in LDS.
+__global__ void __launch_bounds__(256) k_ffno_xdft(const FfnoArgs a, const float* __restrict__ v,
+                                                   const float2* __restrict__ twx,
+                                                   float2* __restrict__ T, int64_t nrows, int R) {
+  extern __shared__ float rows_s[];
+  const int64_t r0 = (int64_t)blockIdx.x * R;
+  const int nx = a.nx, mx = a.mx;
+  const int nr = (int)min((int64_t)R, nrows - r0);
+  for (int e = threadIdx.x; e < nr * nx; e += blockDim.x) rows_s[e] = v[r0 * nx + e];
+  __syncthreads();
+  for (int it = threadIdx.x; it < nr * mx; it += blockDim.x) {
+    const int rr = it / mx, kx = it % mx;
+    const float* row = rows_s + rr * nx;
+    float re = 0.f, im = 0.f;
+    int ph = 0;  // kx x mod nx
+    for (int x = 0; x < nx; ++x) {
+      const float2 w = twx[ph];
+      re += row[x] * w.x;
+      im -= row[x] * w.y;
+      ph += kx;
+      if (ph >= nx) ph -= nx;
+    }
+    T[(r0 + rr) * mx + kx] = make_float2(re, im);
+  }
+}
+
+// G[c][z][m][kx] = sum_y T[c][z][y][kx] e^{-2 pi i ky y / ny}
+__global__ void k_ffno_ydft(const FfnoArgs a, const float2* __restrict__ T,
+                            const float2* __restrict__ twy, float2* __restrict__ G) {
+  const int mx = a.mx, my = a.my, ny = a.ny;
+  const int64_t items = (int64_t)a.dv * a.nz * my * mx;
+  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < items;
+       q += (int64_t)gridDim.x * blockDim.x) {
+    const int kx = (int)(q % mx);
+    const int m = (int)((q / mx) % my);
+    const int64_t cz = q / ((int64_t)mx * my);
+    const int ky = m - a.ky_max;
+    const int step = ((ky % ny) + ny) % ny;
+    const float2* t = T + cz * ny * mx + kx;
+    float re = 0.f, im = 0.f;
+    int ph = 0;
+    for (int y = 0; y < ny; ++y) {
+      const float2 w = twy[ph];  // e^{+i theta}; the forward sum takes its conjugate
+      const float2 s = t[(int64_t)y * mx];
+      re += s.x * w.x + s.y * w.y;
+      im += s.y * w.x - s.x * w.y;
+      ph += step;
+      if (ph >= ny) ph -= ny;
+    }
+    G[q] = make_float2(re, im);
+  }
+}
+
+// U[o][z][m][kx] = sum_i K[o][i][m][kx] G[i][z][m][kx]
+__global__ void k_ffno_mix_xy(const FfnoArgs a, const float2* __restrict__ K,
+                              const float2* __restrict__ G, float2* __restrict__ U) {
+  const int modes = a.my * a.mx;
+  const int64_t per_c = (int64_t)a.nz * modes;
+  const int64_t items = (int64_t)a.dv * per_c;
+  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < items;
+       q += (int64_t)gridDim.x * blockDim.x) {
+    const int md = (int)(q % modes);
+    const int64_t zq = (q / modes) % a.nz;
+    const int o = (int)(q / per_c);
+    float re = 0.f, im = 0.f;
+    for (int i = 0; i < a.dv; ++i) {
+      const float2 k = K[((int64_t)o * a.dv + i) * modes + md];
+      const float2 g = G[(int64_t)i * per_c + zq * modes + md];
+      re += k.x * g.x - k.y * g.y;
+      im += k.x * g.y + k.y * g.x;
+    }
+    U[q] = make_float2(re, im);
+  }
+}
+
+// T2[o][z][y][kx] = sum_m U[o][z][m][kx] e^{+2 pi i ky y / ny}
+__global__ void k_ffno_yidft(const FfnoArgs a, const float2* __restrict__ U,
+                             const float2* __restrict__ twy, float2* __restrict__ T2) {
+  const int mx = a.mx, my = a.my, ny = a.ny;
+  const int64_t items = (int64_t)a.dv * a.nz * ny * mx;
+  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < items;
+       q += (int64_t)gridDim.x * blockDim.x) {
+    const int kx = (int)(q % mx);
+    const int y = (int)((q / mx) % ny);
+    const int64_t cz = q / ((int64_t)mx * ny);
+    const float2* u = U + cz * my * mx + kx;
+    float re = 0.f, im = 0.f;
+    for (int m = 0; m < my; ++m) {
+      const int ky = m - a.ky_max;
+      const int64_t ph = (((int64_t)ky * y) % ny + ny) % ny;
+      const float2 w = twy[ph];
+      const float2 s = u[(int64_t)m * mx];
+      re += s.x * w.x - s.y * w.y;
+      im += s.x * w.y + s.y * w.x;
+    }
+    T2[q] = make_float2(re, im);
+  }
+}
+
+// u[o][z][y][x] = (Re T2[..][0] + 2 sum_{kx>0} Re(T2[..][kx] e^{+2 pi i kx x / nx})) / (nx ny)
+__global__ void k_ffno_xidft(const FfnoArgs a, const float2* __restrict__ T2,
+                             const float2* __restrict__ twx, float* __restrict__ u) {
+  const int mx = a.mx, nx = a.nx;
+  const int64_t items = (int64_t)a.dv * a.nz * a.ny * nx;
+  const float norm = 1.0f / ((float)nx * (float)a.ny);
+  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < items;
+       q += (int64_t)gridDim.x * blockDim.x) {
+    const int x = (int)(q % nx);
+    const float2* t = T2 + (q / nx) * mx;
+    float acc = t[0].x;
+    int ph = x;
+    for (int kx = 1; kx < mx; ++kx) {
+      const float2 w = twx[ph];
+      const float2 s = t[kx];
+      acc += 2.0f * (s.x * w.x - s.y * w.y);
+      ph += x;
+      if (ph >= nx) ph -= nx;
+    }
+    u[q] = acc * norm;
+  }
+}
+
+// Axial branch + MLP + residual for TX columns (consecutive x at one (y)).
+// Block: dv * TX threads.  LDS: one buffer, first holding the z spectra
+// W[i][kz][col] (complex), then the sums s[i][z][col] = u_xy + u_z.
+template <int DV, int DH>
+__global__ void __launch_bounds__(256)
+k_ffno_axial_mlp(const FfnoArgs a, const float* __restrict__ u, float* __restrict__ v,
+                 const float2* __restrict__ Kz, const float* __restrict__ W1,
+                 const float* __restrict__ b1, const float* __restrict__ W2,
+                 const float* __restrict__ b2, const float2* __restrict__ twz, int TX, int last) {
+  extern __shared__ float lds[];
+  const int nz = a.nz, mz = a.mz, nx = a.nx;
+  const int64_t plane = (int64_t)a.ny * nx;
+  const int64_t vox = plane * nz;
+  const int tiles_x = nx / TX;
+  const int y = blockIdx.x / tiles_x;
+  const int x0 = (blockIdx.x % tiles_x) * TX;
+  const int64_t col0 = (int64_t)y * nx + x0;
+  const int t = threadIdx.x;
+  const int ch = t / TX, col = t % TX;  // phases A-C: one (channel, column) per thread
+  float2* Ws = reinterpret_cast<float2*>(lds);
+  // A: forward z DFT of channel ch
+  {
+    const float* src = u + (int64_t)ch * vox + col0 + col;
+    for (int kz = 0; kz < mz; ++kz) {
+      float re = 0.f, im = 0.f;
+      int ph = 0;
+      for (int z = 0; z < nz; ++z) {
+        const float val = src[(int64_t)z * plane];
+        const float2 w = twz[ph];
+        re += val * w.x;
+        im -= val * w.y;
+        ph += kz;
+        if (ph >= nz) ph -= nz;
+      }
+      Ws[(ch * mz + kz) * TX + col] = make_float2(re, im);
+    }
+  }
+  __syncthreads();
+  // B: channel mixing per kz (output channel ch), kept in registers
+  float2 zk[16];
+#pragma unroll
+  for (int kz = 0; kz < 16; ++kz) {
+    if (kz < mz) {
+      float re = 0.f, im = 0.f;
+      for (int i = 0; i < DV; ++i) {
+        const float2 k = Kz[((int64_t)ch * DV + i) * mz + kz];
+        const float2 w = Ws[(i * mz + kz) * TX + col];
+        re += k.x * w.x - k.y * w.y;
+        im += k.x * w.y + k.y * w.x;
+      }
+      zk[kz] = make_float2(re, im);
+    }
+  }
+  __syncthreads();
+  // C: inverse z DFT + u_xy -> s in LDS
+  {
+    float* S = lds;
+    const float* src = u + (int64_t)ch * vox + col0 + col;
+    const float inz = 1.0f / nz;
+    for (int z = 0; z < nz; ++z) {
+      float acc = zk[0].x;
+#pragma unroll
+      for (int kz = 1; kz < 16; ++kz) {
+        if (kz < mz) {
+          const float2 w = twz[(int)(((int64_t)kz * z) % nz)];
+          acc += 2.0f * (zk[kz].x * w.x - zk[kz].y * w.y);
+        }
+      }
+      S[(ch * nz + z) * TX + col] = src[(int64_t)z * plane] + acc * inz;
+    }
+  }
+  __syncthreads();
+  // D: MLP per voxel (z, column) + residual
+  const float* S = lds;
+  for (int e = t; e < nz * TX; e += blockDim.x) {
+    const int z = e / TX, c2 = e % TX;
+    float s[DV], o[DV];
+#pragma unroll
+    for (int i = 0; i < DV; ++i) {
+      s[i] = S[(i * nz + z) * TX + c2];
+      o[i] = b2[i];
+    }
+    for (int j = 0; j < DH; ++j) {
+      float h = b1[j];
+#pragma unroll
+      for (int i = 0; i < DV; ++i) h += W1[j * DV + i] * s[i];
+      h = gelu(h);
+#pragma unroll
+      for (int i = 0; i < DV; ++i) o[i] += W2[i * DH + j] * h;
+    }
+    const int64_t q = (int64_t)z * plane + col0 + c2;
+#pragma unroll
+    for (int i = 0; i < DV; ++i) {
+      const float add = last ? o[i] : gelu(o[i]);
+      v[(int64_t)i * vox + q] += add;
+    }
+  }
+}
+
+__global__ void k_ffno_decode(const FfnoArgs a, const float* __restrict__ Q,
+                              const float* __restrict__ qb, const float* __restrict__ v,
+                              cplx<double>* __restrict__ E) {
+  const int64_t vox = (int64_t)a.nz * a.ny * a.nx;
+  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < vox;
+       q += (int64_t)gridDim.x * blockDim.x) {
+    float acc[6];
+    for (int k = 0; k < 6; ++k) acc[k] = qb[k];
+    for (int c = 0; c < a.dv; ++c) {
+      const float val = v[(int64_t)c * vox + q];
+      for (int k = 0; k < 6; ++k) acc[k] += Q[k * a.dv + c] * val;
+    }
+    for (int k = 0; k < 3; ++k) E[(int64_t)k * vox + q] = {(double)acc[2 * k], (double)acc[2 * k + 1]};
+  }
+}
+
+unsigned grid_for(int64_t items) {
+  return (unsigned)std::max<int64_t>(1, std::min<int64_t>((items + 255) / 256, 8192));
+}
+
+template <int DV, int DH>
+hipError_t axial_mlp_launch(const FfnoArgs& a, const FfnoPtrs& w, int layer, int last, hipStream_t st) {
+  const int tx = a.tx;
+  const size_t shm = sizeof(float) * (size_t)std::max(DV * a.nz * tx, 2 * DV * a.mz * tx);
+  hipLaunchKernelGGL((k_ffno_axial_mlp<DV, DH>), dim3((unsigned)(a.ny * (a.nx / tx))),
+                     dim3(DV * tx), shm, st, a, w.u, w.v, w.Kz[layer], w.W1[layer], w.b1[layer],
+                     w.W2[layer], w.b2[layer], w.twz, tx, last);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t ffno_forward(const FfnoArgs& a, const FfnoPtrs& w, const float* in, cplx<double>* E,
+                        hipStream_t st) {
+  hipLaunchKernelGGL(k_ffno_twiddles, dim3((a.nx + 255) / 256), dim3(256), 0, st, w.twx, a.nx);
+  hipLaunchKernelGGL(k_ffno_twiddles, dim3((a.ny + 255) / 256), dim3(256), 0, st, w.twy, a.ny);
+  hipLaunchKernelGGL(k_ffno_twiddles, dim3((a.nz + 255) / 256), dim3(256), 0, st, w.twz, a.nz);
+  const int64_t vox = (int64_t)a.nz * a.ny * a.nx;
+  hipLaunchKernelGGL(k_ffno_lift, dim3(grid_for(vox)), dim3(256), 0, st, a, w.P, w.p, in, w.v);
+  const int64_t nrows = (int64_t)a.dv * a.nz * a.ny;
+  const int R = std::max(1, std::min(256 / a.mx, 12288 / a.nx));
+  for (int l = 0; l < a.nl; ++l) {
+    hipLaunchKernelGGL(k_ffno_xdft, dim3((unsigned)((nrows + R - 1) / R)), dim3(256),
+                       sizeof(float) * (size_t)R * a.nx, st, a, w.v, w.twx, w.T, nrows, R);
+    hipLaunchKernelGGL(k_ffno_ydft, dim3(grid_for((int64_t)a.dv * a.nz * a.my * a.mx)), dim3(256),
+                       0, st, a, w.T, w.twy, w.G);
+    hipLaunchKernelGGL(k_ffno_mix_xy, dim3(grid_for((int64_t)a.dv * a.nz * a.my * a.mx)),
+                       dim3(256), 0, st, a, w.Kxy[l], w.G, w.U);
+    hipLaunchKernelGGL(k_ffno_yidft, dim3(grid_for((int64_t)a.dv * a.nz * a.ny * a.mx)), dim3(256),
+                       0, st, a, w.U, w.twy, w.T);
+    hipLaunchKernelGGL(k_ffno_xidft, dim3(grid_for(vox * a.dv)), dim3(256), 0, st, a, w.T, w.twx,
+                       w.u);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int last = l == a.nl - 1;
+    if (a.dv == 32 && a.dh == 64) e = axial_mlp_launch<32, 64>(a, w, l, last, st);
+    else if (a.dv == 16 && a.dh == 32) e = axial_mlp_launch<16, 32>(a, w, l, last, st);
+    else if (a.dv == 8 && a.dh == 16) e = axial_mlp_launch<8, 16>(a, w, l, last, st);
+    else e = hipErrorInvalidValue;
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(k_ffno_decode, dim3(grid_for(vox)), dim3(256), 0, st, a, w.Q, w.q, w.v, E);
+  return hipGetLastError();
+}
+
+}  // namespace psfd

@@ -1670,6 +1670,104 @@ psfd_status psfd_ml_reflection(psfd_plan_t p, void* r_te, void* r_pe) {
   });
 }
 
+}  // extern "C"
+
+namespace {
+
+struct FfnoLayout {
+  FfnoArgs a{};
+  int64_t n_weights = 0;
+  size_t off_v = 0, off_u = 0, off_T = 0, off_G = 0, off_U = 0, off_tx = 0, off_ty = 0, off_tz = 0;
+  size_t bytes = 0;
+};
+
+size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+
+psfd_status ffno_layout(const psfd_ffno_desc* d, FfnoLayout* L) {
+  if (!d) return fail(PSFD_ERR_ARG, "desc is NULL");
+  const bool dims = (d->d_v == 32 && d->d_h == 64) || (d->d_v == 16 && d->d_h == 32) ||
+                    (d->d_v == 8 && d->d_h == 16);
+  if (!dims) return fail(PSFD_ERR_ARG, "(d_v, d_h) must be (32, 64), (16, 32) or (8, 16)");
+  if (d->nx < 4 || d->ny < 4 || d->nz < 4 || d->nx > 8192 || d->ny > 8192 || d->nz > 4096)
+    return fail(PSFD_ERR_ARG, "need 4 <= nx, ny <= 8192 and 4 <= nz <= 4096");
+  if (d->n_layers < 1 || d->n_layers > kFfnoMaxLayers) return fail(PSFD_ERR_ARG, "1 <= n_layers <= 16");
+  if (d->kx_max < 0 || d->ky_max < 0 || d->kz_max < 0 || 2 * d->kx_max >= d->nx ||
+      2 * d->ky_max >= d->ny || 2 * d->kz_max >= d->nz || d->kz_max > 15)
+    return fail(PSFD_ERR_ARG, "need 0 <= 2 k_max < n for every axis and kz_max <= 15");
+  FfnoArgs& a = L->a;
+  a.nx = d->nx; a.ny = d->ny; a.nz = d->nz; a.dv = d->d_v; a.dh = d->d_h; a.nl = d->n_layers;
+  a.mx = d->kx_max + 1; a.my = 2 * d->ky_max + 1; a.mz = d->kz_max + 1; a.ky_max = d->ky_max;
+  a.tx = 0;
+  for (int tx = 256 / a.dv; tx >= 1; tx /= 2) {
+    const size_t shm = sizeof(float) * (size_t)std::max(a.dv * a.nz * tx, 2 * a.dv * a.mz * tx);
+    if (a.nx % tx == 0 && shm <= 65536) { a.tx = tx; break; }
+  }
+  if (!a.tx) return fail(PSFD_ERR_ARG, "nz too large for the axial kernel's LDS tile");
+  const int64_t dv = a.dv, dh = a.dh;
+  L->n_weights = dv * 4 + dv + a.nl * (dv * dv * a.my * a.mx * 2 + dv * dv * a.mz * 2 + dh * dv +
+                                       dh + dv * dh + dv) + 6 * dv + 6;
+  const size_t vox = (size_t)a.nz * a.ny * a.nx;
+  size_t o = 0;
+  L->off_v = o; o = align256(o + sizeof(float) * dv * vox);
+  L->off_u = o; o = align256(o + sizeof(float) * dv * vox);
+  L->off_T = o; o = align256(o + sizeof(float2) * dv * a.nz * a.ny * a.mx);
+  L->off_G = o; o = align256(o + sizeof(float2) * dv * a.nz * a.my * a.mx);
+  L->off_U = o; o = align256(o + sizeof(float2) * dv * a.nz * a.my * a.mx);
+  L->off_tx = o; o = align256(o + sizeof(float2) * a.nx);
+  L->off_ty = o; o = align256(o + sizeof(float2) * a.ny);
+  L->off_tz = o; o = align256(o + sizeof(float2) * a.nz);
+  L->bytes = o;
+  return PSFD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+psfd_status psfd_ffno_sizes(const psfd_ffno_desc* d, int64_t* n_weights, int64_t* workspace_bytes) {
+  FfnoLayout L;
+  CHKS(ffno_layout(d, &L));
+  if (n_weights) *n_weights = L.n_weights;
+  if (workspace_bytes) *workspace_bytes = (int64_t)L.bytes;
+  return PSFD_OK;
+}
+
+psfd_status psfd_ffno_forward(const psfd_ffno_desc* d, const float* weights, const float* a_in,
+                              void* E, void* workspace, void* hip_stream) {
+  FfnoLayout L;
+  CHKS(ffno_layout(d, &L));
+  if (!weights || !a_in || !E || !workspace) return fail(PSFD_ERR_ARG, "NULL argument");
+  return guarded([&]() -> psfd_status {
+    const FfnoArgs& a = L.a;
+    FfnoPtrs w{};
+    const float* q = weights;
+    const int64_t dv = a.dv, dh = a.dh;
+    w.P = q; q += dv * 4;
+    w.p = q; q += dv;
+    for (int l = 0; l < a.nl; ++l) {
+      w.Kxy[l] = reinterpret_cast<const float2*>(q); q += dv * dv * a.my * a.mx * 2;
+      w.Kz[l] = reinterpret_cast<const float2*>(q); q += dv * dv * a.mz * 2;
+      w.W1[l] = q; q += dh * dv;
+      w.b1[l] = q; q += dh;
+      w.W2[l] = q; q += dv * dh;
+      w.b2[l] = q; q += dv;
+    }
+    w.Q = q; q += 6 * dv;
+    w.q = q;
+    char* ws = static_cast<char*>(workspace);
+    w.v = reinterpret_cast<float*>(ws + L.off_v);
+    w.u = reinterpret_cast<float*>(ws + L.off_u);
+    w.T = reinterpret_cast<float2*>(ws + L.off_T);
+    w.G = reinterpret_cast<float2*>(ws + L.off_G);
+    w.U = reinterpret_cast<float2*>(ws + L.off_U);
+    w.twx = reinterpret_cast<float2*>(ws + L.off_tx);
+    w.twy = reinterpret_cast<float2*>(ws + L.off_ty);
+    w.twz = reinterpret_cast<float2*>(ws + L.off_tz);
+    CHK(ffno_forward(a, w, a_in, static_cast<cplx<double>*>(E), static_cast<hipStream_t>(hip_stream)));
+    return PSFD_OK;
+  });
+}
+
 psfd_status psfd_pino_loss(psfd_plan_t p, const void* E, double w0, double eta_hf,
                            double lambda_hf, double loss[3], void* g) {
   return guarded([&] { return pino_loss_impl(p, E, w0, eta_hf, lambda_hf, loss, g); });

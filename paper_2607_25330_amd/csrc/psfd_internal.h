@@ -198,6 +198,25 @@ struct DeviationArgs {
 hipError_t launch_contour_segments(const ContourArgs& a, int nplanes, hipStream_t st);
 hipError_t launch_contour_deviation(const DeviationArgs& a, int nblocks, hipStream_t st);
 
+// ---- factorised Fourier neural operator inference (ffno.hip)
+constexpr int kFfnoMaxLayers = 16;
+struct FfnoArgs {
+  int nx, ny, nz, dv, dh, nl;
+  int mx, my, mz, ky_max;  // retained modes: kx 0..mx-1, ky -ky_max..ky_max (my), kz 0..mz-1
+  int tx;                  // columns per block of the axial + MLP kernel
+};
+struct FfnoPtrs {
+  const float *P, *p, *Q, *q;
+  const float2* Kxy[kFfnoMaxLayers];
+  const float2* Kz[kFfnoMaxLayers];
+  const float *W1[kFfnoMaxLayers], *b1[kFfnoMaxLayers], *W2[kFfnoMaxLayers], *b2[kFfnoMaxLayers];
+  float *v, *u;            // hidden state and lateral-branch output, [dv][nz][ny][nx]
+  float2 *T, *G, *U;       // [dv][nz][ny][mx], [dv][nz][my][mx] x 2
+  float2 *twx, *twy, *twz; // e^{+2 pi i k / n}
+};
+hipError_t ffno_forward(const FfnoArgs& a, const FfnoPtrs& w, const float* in, cplx<double>* E,
+                        hipStream_t st);
+
 // part[q][b], q < 4, b < nblk: partial sums of the plane starting at f + off[q]
 struct PlaneSet {
   int64_t off[4];

@@ -57,6 +57,11 @@ class Info(ctypes.Structure):
                 ("applies", c_int32), ("rrel_true", c_double), ("rrel_hist_last", c_double)]
 
 
+class FfnoDesc(ctypes.Structure):
+    _fields_ = [(n, c_int32) for n in ("nx", "ny", "nz", "d_v", "d_h", "n_layers", "kx_max",
+                                         "ky_max", "kz_max")]
+
+
 _SIGS = {
     "psfd_layout_eps": [ctypes.POINTER(Desc), c_void_p, c_dp, c_double, c_void_p, c_void_p],
     "psfd_plan": [ctypes.POINTER(Desc), c_void_p, c_void_p, ctypes.POINTER(c_void_p)],
@@ -87,6 +92,8 @@ _SIGS = {
                                c_double, c_double, c_int32, c_int32, c_double, c_double, c_void_p,
                                c_dp, c_void_p],
     "psfd_pino_loss": [c_void_p, c_void_p, c_double, c_double, c_double, c_dp, c_void_p],
+    "psfd_ffno_sizes": [ctypes.POINTER(FfnoDesc), ctypes.POINTER(c_int64), ctypes.POINTER(c_int64)],
+    "psfd_ffno_forward": [ctypes.POINTER(FfnoDesc), c_void_p, c_void_p, c_void_p, c_void_p, c_void_p],
     "psfd_tune": [c_void_p],
     "psfd_schedule": [c_void_p, ctypes.POINTER(c_int32)],
     "psfd_set_schedule": [c_void_p, ctypes.POINTER(c_int32)],
@@ -234,6 +241,31 @@ def contour_deviation(ref, other, nx, ny, dx, dy, demag=4.0, thr=1.0):
     return delta, {"sum_abs": st[0], "sum_sq": st[1], "resolved": int(st[2]),
                    "unresolved": int(st[3]), "above_thr": int(st[4]), "mean_abs": mean,
                    "std_abs": (max(var, 0.0)) ** 0.5 if n else float("nan")}
+
+
+class Ffno:
+    """Factorised Fourier neural operator forward pass (psfd_ffno_forward) with its own
+    workspace; `weights` is a flat float32 CUDA tensor in the documented layout."""
+
+    def __init__(self, desc, weights):
+        self.desc = FfnoDesc(**{k: int(desc[k]) for k, _ in FfnoDesc._fields_})
+        nw, nb = c_int64(), c_int64()
+        _call("psfd_ffno_sizes", ctypes.byref(self.desc), ctypes.byref(nw), ctypes.byref(nb))
+        if weights.dtype != torch.float32 or not weights.is_cuda or weights.numel() != nw.value:
+            raise ValueError(f"weights must be a float32 CUDA tensor of {nw.value} elements")
+        self.weights = weights.contiguous()
+        self.workspace = torch.empty(nb.value, dtype=torch.uint8, device=weights.device)
+        self.shape = (3, desc["nz"], desc["ny"], desc["nx"])
+
+    def __call__(self, a, out=None):
+        a = a.to(torch.float32).contiguous()
+        if tuple(a.shape) != self.shape[1:]:
+            raise ValueError(f"a must have shape {self.shape[1:]}")
+        E = torch.empty(self.shape, dtype=torch.complex128, device=a.device) if out is None else out
+        _call("psfd_ffno_forward", ctypes.byref(self.desc), c_void_p(self.weights.data_ptr()),
+              c_void_p(a.data_ptr()), _ptr(E, torch.complex128, self.shape, "E"),
+              c_void_p(self.workspace.data_ptr()), _stream_handle())
+        return E
 
 
 class Plan:
