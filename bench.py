@@ -497,6 +497,47 @@ def workload_pino(psfd, args):
                                    "||w F3 r||^2, w0 1, eta 10 nm, lambda 0.01; autograd"}}
 
 
+def workload_ffno(psfd, args):
+    """Factorised Fourier neural operator forward pass (seeded random weights; no trained
+    weights exist): d_v 32, d_h 64, 4 layers, modes kx 12, |ky| 12, kz 8, on the 256x256x48
+    solver grid and on the paper's 1200x1200x100 inference grid.  The dominant kernel is the
+    fused axial branch + MLP (2 d_v d_h multiply-adds per voxel for the MLP); it is timed with
+    torch events around the whole forward pass and reported against the FP32 vector peak."""
+    import numpy as np
+    import torch
+    from psfd_synth import ffno_desc, ffno_weights
+    dev = torch.device("cuda:0")
+    out = {"metric": "F-FNO forward passes/s", "unit": "forwards/s", "dtype": "f32", "legs": {}}
+    grids = {"256x256x48": (256, 256, 48), "1200x1200x100": (1200, 1200, 100)}
+    for name in args.ffno_grids.split(","):
+        nx, ny, nz = grids[name]
+        d = ffno_desc(nx, ny, nz, d_v=32, d_h=64, n_layers=4, kx_max=12, ky_max=12, kz_max=8)
+        w = torch.from_numpy(ffno_weights(d, 1234)).to(dev)
+        net = psfd.Ffno(d, w)
+        g = torch.Generator(device=dev).manual_seed(5)
+        a = torch.rand((nz, ny, nx), generator=g, device=dev, dtype=torch.float32)
+        E = net(a)
+        for _ in range(2):
+            net(a, out=E)
+        reps = 5 if nx < 1000 else 2
+        _, dt = _sync_time(lambda: [net(a, out=E) for _ in range(reps)])
+        vox = nx * ny * nz
+        mlp_flop = 4 * vox * 2 * 2 * 32 * 64
+        leg = {"ms": round(1e3 * dt / reps, 3), "voxels": vox, "mlp_tflop": round(mlp_flop / 1e12, 3),
+               "mlp_tflops_if_all_time": round(mlp_flop / (dt / reps) / 1e12, 2),
+               "workspace_GiB": round(net.workspace.numel() / 2 ** 30, 2),
+               "finite": bool(torch.isfinite(E.real).all().item())}
+        _log(f"ffno {name}: {leg}")
+        out["legs"][name] = leg
+        del net, E, a
+        torch.cuda.empty_cache()
+    last = out["legs"].get("1200x1200x100") or next(iter(out["legs"].values()))
+    out["value"] = round(1e3 / last["ms"], 3)
+    out["config"] = {"workload": "F-FNO d_v 32, d_h 64, 4 layers, modes (12, 12, 8), random "
+                                 "weights; 256x256x48 and 1200x1200x100 (value: the latter)"}
+    return out
+
+
 def _tmm_te(psfd, cfg, eps_l, d_l, dev):
     """Transfer-matrix reflection of the bare stack between vacuum half-spaces (TE), from the
     library's own per-mode table of a plan that carries the stack as its multilayer."""
@@ -529,9 +570,11 @@ def main():
     ap.add_argument("--cpu-leg", type=float, default=None, help=argparse.SUPPRESS)
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run one device copy of this size (for counter calibration)")
-    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5", "fd", "contour", "pino"],
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5", "fd", "contour", "pino", "ffno"],
                     help="c2 (default) is the headline line; the others print their own line")
     ap.add_argument("--c3-clips", type=int, default=64)
+    ap.add_argument("--ffno-grids", default="256x256x48,1200x1200x100",
+                    help="grids of the ffno workload (comma-separated)")
     args = ap.parse_args()
 
     if args.cpu_leg is not None:
@@ -554,7 +597,8 @@ def main():
 
     if args.workload != "c2":
         fn = {"c1": workload_c1, "c3": workload_c3, "c4": workload_c4, "c5": workload_c5,
-              "fd": workload_fd, "contour": workload_contour, "pino": workload_pino}[args.workload]
+              "fd": workload_fd, "contour": workload_contour, "pino": workload_pino,
+              "ffno": workload_ffno}[args.workload]
         res = fn(psfd, args)
         res.update({"n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "data": "synthetic",
                     "higher_is_better": True, "vs_baseline": None})

@@ -13,11 +13,11 @@
 //   mix:    U[o][z][m][kx]  = sum_i K_xy[o][i][m][kx] G[i][z][m][kx]
 //   y iDFT: T2[o][z][y][kx] = sum_m U e^{+2 pi i ky y / ny}
 //   x iDFT: u[o][z][y][x]   = (Re T2[..][0] + 2 sum_{kx>0} Re(T2 e^{+2 pi i kx x/nx})) / (nx ny)
-// The axial branch, the sum u_xy + u_z, the MLP and the residual update run
-// in one kernel per tile of TX columns: forward z DFT of every channel into
-// LDS, channel mixing per kz, inverse z DFT added to u_xy into LDS (same
-// buffer), then one thread per voxel runs the MLP from LDS with the weights
-// read as wave-uniform values.
+// The axial branch runs per tile of TX columns (forward z DFT of every
+// channel into LDS, channel mixing per kz, inverse z DFT added in place to
+// u_xy); the MLP and the residual update then run one voxel per thread with
+// the weights in LDS (W2 is transposed once per call into the workspace so
+// that both products read contiguous rows).
 #include <hip/hip_runtime.h>
 
 #include "psfd_internal.h"
@@ -61,15 +61,21 @@ __global__ void __launch_bounds__(256) k_ffno_xdft(const FfnoArgs a, const float
   const int64_t r0 = (int64_t)blockIdx.x * R;
   const int nx = a.nx, mx = a.mx;
   const int nr = (int)min((int64_t)R, nrows - r0);
+  // twiddles after the rows in LDS when they fit (nx <= 2048), else from memory
+  float2* tw_s = reinterpret_cast<float2*>(rows_s + ((R * nx + 1) & ~1));
+  const bool tl = nx <= 2048;
   for (int e = threadIdx.x; e < nr * nx; e += blockDim.x) rows_s[e] = v[r0 * nx + e];
+  if (tl)
+    for (int e = threadIdx.x; e < nx; e += blockDim.x) tw_s[e] = twx[e];
   __syncthreads();
+  const float2* tw = tl ? tw_s : twx;
   for (int it = threadIdx.x; it < nr * mx; it += blockDim.x) {
     const int rr = it / mx, kx = it % mx;
     const float* row = rows_s + rr * nx;
     float re = 0.f, im = 0.f;
     int ph = 0;  // kx x mod nx
     for (int x = 0; x < nx; ++x) {
-      const float2 w = twx[ph];
+      const float2 w = tw[ph];
       re += row[x] * w.x;
       im -= row[x] * w.y;
       ph += kx;
@@ -153,37 +159,47 @@ __global__ void k_ffno_yidft(const FfnoArgs a, const float2* __restrict__ U,
 }
 
 // u[o][z][y][x] = (Re T2[..][0] + 2 sum_{kx>0} Re(T2[..][kx] e^{+2 pi i kx x / nx})) / (nx ny)
-__global__ void k_ffno_xidft(const FfnoArgs a, const float2* __restrict__ T2,
-                             const float2* __restrict__ twx, float* __restrict__ u) {
+// One block per group of R rows (row = (o, z, y)): the rows' spectra and the
+// twiddles (nx <= 2048) are staged in LDS, threads walk x.
+__global__ void __launch_bounds__(256) k_ffno_xidft(const FfnoArgs a, const float2* __restrict__ T2,
+                                                    const float2* __restrict__ twx,
+                                                    float* __restrict__ u, int64_t nrows, int R) {
+  extern __shared__ float2 xi_s[];
   const int mx = a.mx, nx = a.nx;
-  const int64_t items = (int64_t)a.dv * a.nz * a.ny * nx;
+  const int64_t r0 = (int64_t)blockIdx.x * R;
+  const int nr = (int)min((int64_t)R, nrows - r0);
+  float2* tw_s = xi_s + R * mx;
+  const bool tl = nx <= 2048;
+  for (int e = threadIdx.x; e < nr * mx; e += blockDim.x) xi_s[e] = T2[r0 * mx + e];
+  if (tl)
+    for (int e = threadIdx.x; e < nx; e += blockDim.x) tw_s[e] = twx[e];
+  __syncthreads();
+  const float2* tw = tl ? tw_s : twx;
   const float norm = 1.0f / ((float)nx * (float)a.ny);
-  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < items;
-       q += (int64_t)gridDim.x * blockDim.x) {
-    const int x = (int)(q % nx);
-    const float2* t = T2 + (q / nx) * mx;
+  for (int e = threadIdx.x; e < nr * nx; e += blockDim.x) {
+    const int rr = e / nx, x = e % nx;
+    const float2* t = xi_s + rr * mx;
     float acc = t[0].x;
     int ph = x;
     for (int kx = 1; kx < mx; ++kx) {
-      const float2 w = twx[ph];
-      const float2 s = t[kx];
-      acc += 2.0f * (s.x * w.x - s.y * w.y);
+      const float2 w = tw[ph];
+      const float2 sv = t[kx];
+      acc += 2.0f * (sv.x * w.x - sv.y * w.y);
       ph += x;
       if (ph >= nx) ph -= nx;
     }
-    u[q] = acc * norm;
+    u[(r0 + rr) * nx + x] = acc * norm;
   }
 }
 
-// Axial branch + MLP + residual for TX columns (consecutive x at one (y)).
-// Block: dv * TX threads.  LDS: one buffer, first holding the z spectra
-// W[i][kz][col] (complex), then the sums s[i][z][col] = u_xy + u_z.
-template <int DV, int DH>
+// Axial branch for TX columns (consecutive x at one y): forward z DFT of
+// every channel into LDS, channel mixing per kz in registers, inverse z DFT
+// added in place to u_xy, so that u holds s = u_xy + u_z afterwards.
+// Block: dv * TX threads, one (channel, column) each.
+template <int DV>
 __global__ void __launch_bounds__(256)
-k_ffno_axial_mlp(const FfnoArgs a, const float* __restrict__ u, float* __restrict__ v,
-                 const float2* __restrict__ Kz, const float* __restrict__ W1,
-                 const float* __restrict__ b1, const float* __restrict__ W2,
-                 const float* __restrict__ b2, const float2* __restrict__ twz, int TX, int last) {
+k_ffno_axial(const FfnoArgs a, float* __restrict__ u, const float2* __restrict__ Kz,
+             const float2* __restrict__ twz, int TX) {
   extern __shared__ float lds[];
   const int nz = a.nz, mz = a.mz, nx = a.nx;
   const int64_t plane = (int64_t)a.ny * nx;
@@ -193,27 +209,34 @@ k_ffno_axial_mlp(const FfnoArgs a, const float* __restrict__ u, float* __restric
   const int x0 = (blockIdx.x % tiles_x) * TX;
   const int64_t col0 = (int64_t)y * nx + x0;
   const int t = threadIdx.x;
-  const int ch = t / TX, col = t % TX;  // phases A-C: one (channel, column) per thread
+  const int ch = t / TX, col = t % TX;
   float2* Ws = reinterpret_cast<float2*>(lds);
-  // A: forward z DFT of channel ch
+  float* col_u = u + (int64_t)ch * vox + col0 + col;
+  // forward z DFT of channel ch (each element read once, all kz accumulated)
   {
-    const float* src = u + (int64_t)ch * vox + col0 + col;
-    for (int kz = 0; kz < mz; ++kz) {
-      float re = 0.f, im = 0.f;
-      int ph = 0;
-      for (int z = 0; z < nz; ++z) {
-        const float val = src[(int64_t)z * plane];
-        const float2 w = twz[ph];
-        re += val * w.x;
-        im -= val * w.y;
-        ph += kz;
-        if (ph >= nz) ph -= nz;
+    float2 acc[16];
+#pragma unroll
+    for (int kz = 0; kz < 16; ++kz) acc[kz] = make_float2(0.f, 0.f);
+    for (int z = 0; z < nz; ++z) {
+      const float val = col_u[(int64_t)z * plane];
+      int ph = 0;  // kz z mod nz
+#pragma unroll
+      for (int kz = 0; kz < 16; ++kz) {
+        if (kz < mz) {
+          const float2 w = twz[ph];
+          acc[kz].x += val * w.x;
+          acc[kz].y -= val * w.y;
+          ph += z;
+          if (ph >= nz) ph -= nz;
+        }
       }
-      Ws[(ch * mz + kz) * TX + col] = make_float2(re, im);
     }
+#pragma unroll
+    for (int kz = 0; kz < 16; ++kz)
+      if (kz < mz) Ws[(ch * mz + kz) * TX + col] = acc[kz];
   }
   __syncthreads();
-  // B: channel mixing per kz (output channel ch), kept in registers
+  // channel mixing per kz for output channel ch
   float2 zk[16];
 #pragma unroll
   for (int kz = 0; kz < 16; ++kz) {
@@ -228,50 +251,71 @@ k_ffno_axial_mlp(const FfnoArgs a, const float* __restrict__ u, float* __restric
       zk[kz] = make_float2(re, im);
     }
   }
-  __syncthreads();
-  // C: inverse z DFT + u_xy -> s in LDS
-  {
-    float* S = lds;
-    const float* src = u + (int64_t)ch * vox + col0 + col;
-    const float inz = 1.0f / nz;
-    for (int z = 0; z < nz; ++z) {
-      float acc = zk[0].x;
+  // inverse z DFT added to u_xy (this thread's own column and channel)
+  const float inz = 1.0f / nz;
+  for (int z = 0; z < nz; ++z) {
+    float acc = zk[0].x;
+    int ph = z;  // kz z mod nz, from kz = 1
 #pragma unroll
-      for (int kz = 1; kz < 16; ++kz) {
-        if (kz < mz) {
-          const float2 w = twz[(int)(((int64_t)kz * z) % nz)];
-          acc += 2.0f * (zk[kz].x * w.x - zk[kz].y * w.y);
-        }
+    for (int kz = 1; kz < 16; ++kz) {
+      if (kz < mz) {
+        const float2 w = twz[ph];
+        acc += 2.0f * (zk[kz].x * w.x - zk[kz].y * w.y);
+        ph += z;
+        if (ph >= nz) ph -= nz;
       }
-      S[(ch * nz + z) * TX + col] = src[(int64_t)z * plane] + acc * inz;
     }
+    col_u[(int64_t)z * plane] += acc * inz;
   }
+}
+
+// Pointwise MLP with residual: v <- v + act(W2 gelu(W1 s + b1) + b2), one
+// voxel per thread (channel planes, coalesced), weights staged in LDS and
+// read as broadcasts; W2 is used transposed ([d_h][d_v]) so that both
+// products walk contiguous rows while only s, o and one hidden unit are live.
+template <int DV, int DH>
+__global__ void __launch_bounds__(256)
+k_ffno_mlp(const FfnoArgs a, const float* __restrict__ s_in, float* __restrict__ v,
+           const float* __restrict__ W1, const float* __restrict__ b1,
+           const float* __restrict__ W2T, const float* __restrict__ b2, int last) {
+  __shared__ float w1s[DH * DV], w2s[DH * DV], b1s[DH], b2s[DV];
+  for (int e = threadIdx.x; e < DH * DV; e += blockDim.x) {
+    w1s[e] = W1[e];
+    w2s[e] = W2T[e];
+  }
+  for (int e = threadIdx.x; e < DH; e += blockDim.x) b1s[e] = b1[e];
+  for (int e = threadIdx.x; e < DV; e += blockDim.x) b2s[e] = b2[e];
   __syncthreads();
-  // D: MLP per voxel (z, column) + residual
-  const float* S = lds;
-  for (int e = t; e < nz * TX; e += blockDim.x) {
-    const int z = e / TX, c2 = e % TX;
+  const int64_t vox = (int64_t)a.nz * a.ny * a.nx;
+  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < vox;
+       q += (int64_t)gridDim.x * blockDim.x) {
     float s[DV], o[DV];
 #pragma unroll
     for (int i = 0; i < DV; ++i) {
-      s[i] = S[(i * nz + z) * TX + c2];
-      o[i] = b2[i];
+      s[i] = s_in[(int64_t)i * vox + q];
+      o[i] = b2s[i];
     }
+#pragma unroll 1
     for (int j = 0; j < DH; ++j) {
-      float h = b1[j];
+      float acc = b1s[j];
 #pragma unroll
-      for (int i = 0; i < DV; ++i) h += W1[j * DV + i] * s[i];
-      h = gelu(h);
+      for (int i = 0; i < DV; ++i) acc += w1s[j * DV + i] * s[i];
+      const float h = gelu(acc);
 #pragma unroll
-      for (int i = 0; i < DV; ++i) o[i] += W2[i * DH + j] * h;
+      for (int i = 0; i < DV; ++i) o[i] += w2s[j * DV + i] * h;
     }
-    const int64_t q = (int64_t)z * plane + col0 + c2;
 #pragma unroll
-    for (int i = 0; i < DV; ++i) {
-      const float add = last ? o[i] : gelu(o[i]);
-      v[(int64_t)i * vox + q] += add;
-    }
+    for (int i = 0; i < DV; ++i) v[(int64_t)i * vox + q] += last ? o[i] : gelu(o[i]);
   }
+}
+
+// out[j][i] = in[i][j] for an [rows][cols] matrix
+__global__ void k_ffno_transpose(const float* __restrict__ in, int rows, int cols,
+                                 float* __restrict__ out) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= rows * cols) return;
+  const int i = e / cols, j = e % cols;
+  out[j * rows + i] = in[e];
 }
 
 __global__ void k_ffno_decode(const FfnoArgs a, const float* __restrict__ Q,
@@ -297,10 +341,12 @@ unsigned grid_for(int64_t items) {
 template <int DV, int DH>
 hipError_t axial_mlp_launch(const FfnoArgs& a, const FfnoPtrs& w, int layer, int last, hipStream_t st) {
   const int tx = a.tx;
-  const size_t shm = sizeof(float) * (size_t)std::max(DV * a.nz * tx, 2 * DV * a.mz * tx);
-  hipLaunchKernelGGL((k_ffno_axial_mlp<DV, DH>), dim3((unsigned)(a.ny * (a.nx / tx))),
-                     dim3(DV * tx), shm, st, a, w.u, w.v, w.Kz[layer], w.W1[layer], w.b1[layer],
-                     w.W2[layer], w.b2[layer], w.twz, tx, last);
+  const size_t shm = sizeof(float2) * (size_t)DV * a.mz * tx;
+  hipLaunchKernelGGL((k_ffno_axial<DV>), dim3((unsigned)(a.ny * (a.nx / tx))), dim3(DV * tx), shm,
+                     st, a, w.u, w.Kz[layer], w.twz, tx);
+  const int64_t vox = (int64_t)a.nz * a.ny * a.nx;
+  hipLaunchKernelGGL((k_ffno_mlp<DV, DH>), dim3(grid_for(vox)), dim3(256), 0, st, a, w.u, w.v,
+                     w.W1[layer], w.b1[layer], w.W2T + (size_t)layer * DV * DH, w.b2[layer], last);
   return hipGetLastError();
 }
 
@@ -311,21 +357,28 @@ hipError_t ffno_forward(const FfnoArgs& a, const FfnoPtrs& w, const float* in, c
   hipLaunchKernelGGL(k_ffno_twiddles, dim3((a.nx + 255) / 256), dim3(256), 0, st, w.twx, a.nx);
   hipLaunchKernelGGL(k_ffno_twiddles, dim3((a.ny + 255) / 256), dim3(256), 0, st, w.twy, a.ny);
   hipLaunchKernelGGL(k_ffno_twiddles, dim3((a.nz + 255) / 256), dim3(256), 0, st, w.twz, a.nz);
+  for (int l = 0; l < a.nl; ++l)
+    hipLaunchKernelGGL(k_ffno_transpose, dim3((a.dv * a.dh + 255) / 256), dim3(256), 0, st,
+                       w.W2[l], a.dv, a.dh, w.W2T + (size_t)l * a.dv * a.dh);
   const int64_t vox = (int64_t)a.nz * a.ny * a.nx;
   hipLaunchKernelGGL(k_ffno_lift, dim3(grid_for(vox)), dim3(256), 0, st, a, w.P, w.p, in, w.v);
   const int64_t nrows = (int64_t)a.dv * a.nz * a.ny;
-  const int R = std::max(1, std::min(256 / a.mx, 12288 / a.nx));
+  const int R = std::max(1, std::min(256 / a.mx, 10240 / a.nx));
+  const int Ri = std::max(1, 2048 / a.nx);  // rows per block of the inverse x pass
+  const size_t xidft_shm = sizeof(float2) * ((size_t)Ri * a.mx + (a.nx <= 2048 ? a.nx : 0));
+  const size_t xdft_shm =
+      sizeof(float) * (size_t)((R * a.nx + 1) & ~1) + (a.nx <= 2048 ? sizeof(float2) * a.nx : 0);
   for (int l = 0; l < a.nl; ++l) {
-    hipLaunchKernelGGL(k_ffno_xdft, dim3((unsigned)((nrows + R - 1) / R)), dim3(256),
-                       sizeof(float) * (size_t)R * a.nx, st, a, w.v, w.twx, w.T, nrows, R);
+    hipLaunchKernelGGL(k_ffno_xdft, dim3((unsigned)((nrows + R - 1) / R)), dim3(256), xdft_shm, st,
+                       a, w.v, w.twx, w.T, nrows, R);
     hipLaunchKernelGGL(k_ffno_ydft, dim3(grid_for((int64_t)a.dv * a.nz * a.my * a.mx)), dim3(256),
                        0, st, a, w.T, w.twy, w.G);
     hipLaunchKernelGGL(k_ffno_mix_xy, dim3(grid_for((int64_t)a.dv * a.nz * a.my * a.mx)),
                        dim3(256), 0, st, a, w.Kxy[l], w.G, w.U);
     hipLaunchKernelGGL(k_ffno_yidft, dim3(grid_for((int64_t)a.dv * a.nz * a.ny * a.mx)), dim3(256),
                        0, st, a, w.U, w.twy, w.T);
-    hipLaunchKernelGGL(k_ffno_xidft, dim3(grid_for(vox * a.dv)), dim3(256), 0, st, a, w.T, w.twx,
-                       w.u);
+    hipLaunchKernelGGL(k_ffno_xidft, dim3((unsigned)((nrows + Ri - 1) / Ri)), dim3(256), xidft_shm,
+                       st, a, w.T, w.twx, w.u, nrows, Ri);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const int last = l == a.nl - 1;

@@ -1678,6 +1678,7 @@ struct FfnoLayout {
   FfnoArgs a{};
   int64_t n_weights = 0;
   size_t off_v = 0, off_u = 0, off_T = 0, off_G = 0, off_U = 0, off_tx = 0, off_ty = 0, off_tz = 0;
+  size_t off_w2t = 0;
   size_t bytes = 0;
 };
 
@@ -1698,11 +1699,8 @@ psfd_status ffno_layout(const psfd_ffno_desc* d, FfnoLayout* L) {
   a.nx = d->nx; a.ny = d->ny; a.nz = d->nz; a.dv = d->d_v; a.dh = d->d_h; a.nl = d->n_layers;
   a.mx = d->kx_max + 1; a.my = 2 * d->ky_max + 1; a.mz = d->kz_max + 1; a.ky_max = d->ky_max;
   a.tx = 0;
-  for (int tx = 256 / a.dv; tx >= 1; tx /= 2) {
-    const size_t shm = sizeof(float) * (size_t)std::max(a.dv * a.nz * tx, 2 * a.dv * a.mz * tx);
-    if (a.nx % tx == 0 && shm <= 65536) { a.tx = tx; break; }
-  }
-  if (!a.tx) return fail(PSFD_ERR_ARG, "nz too large for the axial kernel's LDS tile");
+  for (int tx = 256 / a.dv; tx >= 1; tx /= 2)
+    if (a.nx % tx == 0) { a.tx = tx; break; }
   const int64_t dv = a.dv, dh = a.dh;
   L->n_weights = dv * 4 + dv + a.nl * (dv * dv * a.my * a.mx * 2 + dv * dv * a.mz * 2 + dh * dv +
                                        dh + dv * dh + dv) + 6 * dv + 6;
@@ -1716,6 +1714,7 @@ psfd_status ffno_layout(const psfd_ffno_desc* d, FfnoLayout* L) {
   L->off_tx = o; o = align256(o + sizeof(float2) * a.nx);
   L->off_ty = o; o = align256(o + sizeof(float2) * a.ny);
   L->off_tz = o; o = align256(o + sizeof(float2) * a.nz);
+  L->off_w2t = o; o = align256(o + sizeof(float) * a.nl * dv * dh);
   L->bytes = o;
   return PSFD_OK;
 }
@@ -1763,6 +1762,7 @@ psfd_status psfd_ffno_forward(const psfd_ffno_desc* d, const float* weights, con
     w.twx = reinterpret_cast<float2*>(ws + L.off_tx);
     w.twy = reinterpret_cast<float2*>(ws + L.off_ty);
     w.twz = reinterpret_cast<float2*>(ws + L.off_tz);
+    w.W2T = reinterpret_cast<float*>(ws + L.off_w2t);
     CHK(ffno_forward(a, w, a_in, static_cast<cplx<double>*>(E), static_cast<hipStream_t>(hip_stream)));
     return PSFD_OK;
   });
