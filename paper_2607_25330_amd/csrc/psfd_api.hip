@@ -817,6 +817,7 @@ psfd_status solve_body(struct psfd_plan* P, const cplx<double>* b_in, const cplx
   std::vector<double> rr_acc(G, 0.0);  // ||b - A E||^2 at the last accepted point
   for (int i = 0; i < G; ++i) rr_acc[i] = rn[i] * rn[i];
   std::vector<int> rejected(G, 0);
+  std::vector<int> stall(G, 0);  // complex64 runs in a row without progress
   const size_t fbytes = sizeof(cplx<double>) * (size_t)n;
   auto save_E = [&]() -> psfd_status {
     CHK(hipMemcpyAsync(P->ebak64, E, fbytes * G, hipMemcpyDeviceToDevice, st));
@@ -993,11 +994,15 @@ psfd_status solve_body(struct psfd_plan* P, const cplx<double>* b_in, const cplx
       if (run_done[i] == KS_BREAK && rrel[i] > tol && outer[i] >= kMaxRestarts)
         status[i] = PSFD_BREAKDOWN;
       outer[i] += 1;
-      // a complex64 run that was rejected, or broke down without a four-fold
-      // drop of the residual, hands the rest of the solve to FP64
-      if (mixed && rrel[i] > tol &&
-          (rejected[i] || (run_done[i] == KS_BREAK && !(rr2 < 0.0625 * rr_start[i]))))
-        escalate = true;
+      // A complex64 run that ended in a rejected fold or a breakdown without
+      // its residual falling fourfold is a stall; after two stalls in a row
+      // the rest of the solve runs on FP64 Krylov vectors.  A run that made
+      // progress and then met its precision floor (a rejected update) is
+      // followed by a fresh complex64 run normalised to the new residual.
+      const bool progressed = rr2 < 0.0625 * rr_start[i];
+      const bool failed = rejected[i] || run_done[i] == KS_BREAK;
+      stall[i] = (failed && !progressed) ? stall[i] + 1 : 0;
+      if (mixed && rrel[i] > tol && stall[i] >= 2) escalate = true;
     }
     if (escalate) {
       mixed = false;
