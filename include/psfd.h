@@ -317,7 +317,7 @@ typedef struct {
   int32_t n_layers;          /* 1 .. 16                                                    */
   int32_t kx_max, ky_max, kz_max; /* retained modes: kx 0..kx_max of the real-input half
                                      spectrum, |ky| <= ky_max, kz 0..kz_max; 2 k_max < n,
-                                     kz_max <= 15                                         */
+                                     kx_max <= 31, kz_max <= 15                           */
 } psfd_ffno_desc;
 
 /* Number of FP32 weights and workspace bytes of a network (host outputs,

@@ -6,9 +6,10 @@
 // Hidden state: d_v real channels, FP32, channel planes [d_v][nz][ny][nx].
 // The retained spectra are small (kx = 0..kx_max of the real-input half
 // spectrum, |ky| <= ky_max, kz = 0..kz_max), so the transforms are direct
-// truncated DFT sums with FP32 twiddle tables (built on the device in FP64):
+// truncated DFT sums (one FP32 table value e^{2 pi i j / n} per sample, built
+// on the device in FP64, its powers by repeated multiplication):
 // any grid size works and no full-size spectrum is ever stored.
-//   x DFT:  T[c][z][y][kx]  = sum_x v e^{-2 pi i kx x / nx}   (rows staged in LDS)
+//   x DFT:  T[c][z][y][kx]  = sum_x v e^{-2 pi i kx x / nx}   (one row per thread)
 //   y DFT:  G[c][z][m][kx]  = sum_y T e^{-2 pi i ky y / ny},   ky = m - ky_max
 //   mix:    U[o][z][m][kx]  = sum_i K_xy[o][i][m][kx] G[i][z][m][kx]
 //   y iDFT: T2[o][z][y][kx] = sum_m U e^{+2 pi i ky y / ny}
@@ -53,35 +54,55 @@ __global__ void k_ffno_lift(const FfnoArgs a, const float* __restrict__ P, const
   }
 }
 
-// T[row][kx] for rows of v (row = (c, z, y)); R rows per block staged in LDS.
+__device__ __forceinline__ float2 cmul2(float2 a, float2 b) {
+  return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+
+// T[row][kx] for rows of v (row = (c, z, y)): one thread per row, the block's
+// 256 rows staged in LDS 32 samples at a time (pitch 33 floats: the lanes of
+// a wave read distinct banks).  Per sample x the powers w^(kx x),
+// kx = 0..mx-1, come from one table value w^x by repeated multiplication,
+// and every kx is accumulated in registers.
+template <int MXM>
 __global__ void __launch_bounds__(256) k_ffno_xdft(const FfnoArgs a, const float* __restrict__ v,
                                                    const float2* __restrict__ twx,
-                                                   float2* __restrict__ T, int64_t nrows, int R) {
-  extern __shared__ float rows_s[];
-  const int64_t r0 = (int64_t)blockIdx.x * R;
-  const int nx = a.nx, mx = a.mx;
-  const int nr = (int)min((int64_t)R, nrows - r0);
-  // twiddles after the rows in LDS when they fit (nx <= 2048), else from memory
-  float2* tw_s = reinterpret_cast<float2*>(rows_s + ((R * nx + 1) & ~1));
-  const bool tl = nx <= 2048;
-  for (int e = threadIdx.x; e < nr * nx; e += blockDim.x) rows_s[e] = v[r0 * nx + e];
-  if (tl)
-    for (int e = threadIdx.x; e < nx; e += blockDim.x) tw_s[e] = twx[e];
-  __syncthreads();
-  const float2* tw = tl ? tw_s : twx;
-  for (int it = threadIdx.x; it < nr * mx; it += blockDim.x) {
-    const int rr = it / mx, kx = it % mx;
-    const float* row = rows_s + rr * nx;
-    float re = 0.f, im = 0.f;
-    int ph = 0;  // kx x mod nx
-    for (int x = 0; x < nx; ++x) {
-      const float2 w = tw[ph];
-      re += row[x] * w.x;
-      im -= row[x] * w.y;
-      ph += kx;
-      if (ph >= nx) ph -= nx;
+                                                   float2* __restrict__ T, int64_t nrows) {
+  constexpr int ROWS = 256, CH = 32, PITCH = CH + 1;
+  __shared__ float tile[ROWS * PITCH];
+  const int64_t r0 = (int64_t)blockIdx.x * ROWS;
+  const int nr = (int)min((int64_t)ROWS, nrows - r0);
+  const int nx = a.nx, mx = a.mx, t = threadIdx.x;
+  float re[MXM], im[MXM];
+#pragma unroll
+  for (int k = 0; k < MXM; ++k) re[k] = im[k] = 0.f;
+  for (int x0 = 0; x0 < nx; x0 += CH) {
+    const int nc = min(CH, nx - x0);
+    __syncthreads();
+    for (int e = t; e < nr * nc; e += ROWS) {
+      const int r = e / nc, c = e % nc;
+      tile[r * PITCH + c] = v[(r0 + r) * nx + x0 + c];
     }
-    T[(r0 + rr) * mx + kx] = make_float2(re, im);
+    __syncthreads();
+    if (t < nr) {
+      for (int c = 0; c < nc; ++c) {
+        const float val = tile[t * PITCH + c];
+        const float2 w1 = twx[x0 + c];  // e^{+i 2 pi x / nx}
+        float2 p = make_float2(1.f, 0.f);
+#pragma unroll
+        for (int k = 0; k < MXM; ++k) {
+          if (k < mx) {
+            re[k] += val * p.x;  // the forward sum takes the conjugate power
+            im[k] -= val * p.y;
+            p = cmul2(p, w1);
+          }
+        }
+      }
+    }
+  }
+  if (t < nr) {
+#pragma unroll
+    for (int k = 0; k < MXM; ++k)
+      if (k < mx) T[(r0 + t) * mx + k] = make_float2(re[k], im[k]);
   }
 }
 
@@ -180,13 +201,12 @@ __global__ void __launch_bounds__(256) k_ffno_xidft(const FfnoArgs a, const floa
     const int rr = e / nx, x = e % nx;
     const float2* t = xi_s + rr * mx;
     float acc = t[0].x;
-    int ph = x;
+    const float2 w1 = tw[x];  // e^{+i 2 pi x / nx}; its powers by repeated multiplication
+    float2 p = w1;
     for (int kx = 1; kx < mx; ++kx) {
-      const float2 w = tw[ph];
       const float2 sv = t[kx];
-      acc += 2.0f * (sv.x * w.x - sv.y * w.y);
-      ph += x;
-      if (ph >= nx) ph -= nx;
+      acc += 2.0f * (sv.x * p.x - sv.y * p.y);
+      p = cmul2(p, w1);
     }
     u[(r0 + rr) * nx + x] = acc * norm;
   }
@@ -194,8 +214,9 @@ __global__ void __launch_bounds__(256) k_ffno_xidft(const FfnoArgs a, const floa
 
 // Axial branch for TX columns (consecutive x at one y): forward z DFT of
 // every channel into LDS, channel mixing per kz in registers, inverse z DFT
-// added in place to u_xy, so that u holds s = u_xy + u_z afterwards.
-// Block: dv * TX threads, one (channel, column) each.
+// added in place to u_xy, so that u holds s = u_xy + u_z afterwards.  A block
+// of G x TX threads (G channel groups) walks the channels g, g + G, ...; the
+// TX consecutive columns of a channel make one contiguous load per z.
 template <int DV>
 __global__ void __launch_bounds__(256)
 k_ffno_axial(const FfnoArgs a, float* __restrict__ u, const float2* __restrict__ Kz,
@@ -209,25 +230,25 @@ k_ffno_axial(const FfnoArgs a, float* __restrict__ u, const float2* __restrict__
   const int x0 = (blockIdx.x % tiles_x) * TX;
   const int64_t col0 = (int64_t)y * nx + x0;
   const int t = threadIdx.x;
-  const int ch = t / TX, col = t % TX;
+  const int col = t % TX, g = t / TX, G = blockDim.x / TX;
   float2* Ws = reinterpret_cast<float2*>(lds);
-  float* col_u = u + (int64_t)ch * vox + col0 + col;
-  // forward z DFT of channel ch (each element read once, all kz accumulated)
-  {
+  // forward z DFT of each of this thread's channels (each element read once)
+#pragma unroll 1
+  for (int ch = g; ch < DV; ch += G) {
+    const float* col_u = u + (int64_t)ch * vox + col0 + col;
     float2 acc[16];
 #pragma unroll
     for (int kz = 0; kz < 16; ++kz) acc[kz] = make_float2(0.f, 0.f);
     for (int z = 0; z < nz; ++z) {
       const float val = col_u[(int64_t)z * plane];
-      int ph = 0;  // kz z mod nz
+      const float2 w1 = twz[z];
+      float2 p = make_float2(1.f, 0.f);  // w^(kz z)
 #pragma unroll
       for (int kz = 0; kz < 16; ++kz) {
         if (kz < mz) {
-          const float2 w = twz[ph];
-          acc[kz].x += val * w.x;
-          acc[kz].y -= val * w.y;
-          ph += z;
-          if (ph >= nz) ph -= nz;
+          acc[kz].x += val * p.x;
+          acc[kz].y -= val * p.y;
+          p = cmul2(p, w1);
         }
       }
     }
@@ -236,36 +257,40 @@ k_ffno_axial(const FfnoArgs a, float* __restrict__ u, const float2* __restrict__
       if (kz < mz) Ws[(ch * mz + kz) * TX + col] = acc[kz];
   }
   __syncthreads();
-  // channel mixing per kz for output channel ch
-  float2 zk[16];
-#pragma unroll
-  for (int kz = 0; kz < 16; ++kz) {
-    if (kz < mz) {
-      float re = 0.f, im = 0.f;
-      for (int i = 0; i < DV; ++i) {
-        const float2 k = Kz[((int64_t)ch * DV + i) * mz + kz];
-        const float2 w = Ws[(i * mz + kz) * TX + col];
-        re += k.x * w.x - k.y * w.y;
-        im += k.x * w.y + k.y * w.x;
-      }
-      zk[kz] = make_float2(re, im);
-    }
-  }
-  // inverse z DFT added to u_xy (this thread's own column and channel)
   const float inz = 1.0f / nz;
-  for (int z = 0; z < nz; ++z) {
-    float acc = zk[0].x;
-    int ph = z;  // kz z mod nz, from kz = 1
+#pragma unroll 1
+  for (int o = g; o < DV; o += G) {
+    // channel mixing per kz for output channel o
+    float2 zk[16];
 #pragma unroll
-    for (int kz = 1; kz < 16; ++kz) {
+    for (int kz = 0; kz < 16; ++kz) {
       if (kz < mz) {
-        const float2 w = twz[ph];
-        acc += 2.0f * (zk[kz].x * w.x - zk[kz].y * w.y);
-        ph += z;
-        if (ph >= nz) ph -= nz;
+        float re = 0.f, im = 0.f;
+#pragma unroll 4
+        for (int i = 0; i < DV; ++i) {
+          const float2 k = Kz[((int64_t)o * DV + i) * mz + kz];
+          const float2 w = Ws[(i * mz + kz) * TX + col];
+          re += k.x * w.x - k.y * w.y;
+          im += k.x * w.y + k.y * w.x;
+        }
+        zk[kz] = make_float2(re, im);
       }
     }
-    col_u[(int64_t)z * plane] += acc * inz;
+    // inverse z DFT added to u_xy (this thread's own column of channel o)
+    float* col_u = u + (int64_t)o * vox + col0 + col;
+    for (int z = 0; z < nz; ++z) {
+      float acc = zk[0].x;
+      const float2 w1 = twz[z];
+      float2 p = w1;  // w^(kz z), from kz = 1
+#pragma unroll
+      for (int kz = 1; kz < 16; ++kz) {
+        if (kz < mz) {
+          acc += 2.0f * (zk[kz].x * p.x - zk[kz].y * p.y);
+          p = cmul2(p, w1);
+        }
+      }
+      col_u[(int64_t)z * plane] += acc * inz;
+    }
   }
 }
 
@@ -342,7 +367,8 @@ template <int DV, int DH>
 hipError_t axial_mlp_launch(const FfnoArgs& a, const FfnoPtrs& w, int layer, int last, hipStream_t st) {
   const int tx = a.tx;
   const size_t shm = sizeof(float2) * (size_t)DV * a.mz * tx;
-  hipLaunchKernelGGL((k_ffno_axial<DV>), dim3((unsigned)(a.ny * (a.nx / tx))), dim3(DV * tx), shm,
+  const int threads = std::min(256, DV * tx);
+  hipLaunchKernelGGL((k_ffno_axial<DV>), dim3((unsigned)(a.ny * (a.nx / tx))), dim3(threads), shm,
                      st, a, w.u, w.Kz[layer], w.twz, tx);
   const int64_t vox = (int64_t)a.nz * a.ny * a.nx;
   hipLaunchKernelGGL((k_ffno_mlp<DV, DH>), dim3(grid_for(vox)), dim3(256), 0, st, a, w.u, w.v,
@@ -363,14 +389,14 @@ hipError_t ffno_forward(const FfnoArgs& a, const FfnoPtrs& w, const float* in, c
   const int64_t vox = (int64_t)a.nz * a.ny * a.nx;
   hipLaunchKernelGGL(k_ffno_lift, dim3(grid_for(vox)), dim3(256), 0, st, a, w.P, w.p, in, w.v);
   const int64_t nrows = (int64_t)a.dv * a.nz * a.ny;
-  const int R = std::max(1, std::min(256 / a.mx, 10240 / a.nx));
   const int Ri = std::max(1, 2048 / a.nx);  // rows per block of the inverse x pass
   const size_t xidft_shm = sizeof(float2) * ((size_t)Ri * a.mx + (a.nx <= 2048 ? a.nx : 0));
-  const size_t xdft_shm =
-      sizeof(float) * (size_t)((R * a.nx + 1) & ~1) + (a.nx <= 2048 ? sizeof(float2) * a.nx : 0);
   for (int l = 0; l < a.nl; ++l) {
-    hipLaunchKernelGGL(k_ffno_xdft, dim3((unsigned)((nrows + R - 1) / R)), dim3(256), xdft_shm, st,
-                       a, w.v, w.twx, w.T, nrows, R);
+    const dim3 gx((unsigned)((nrows + 255) / 256));
+    if (a.mx <= 16)
+      hipLaunchKernelGGL(k_ffno_xdft<16>, gx, dim3(256), 0, st, a, w.v, w.twx, w.T, nrows);
+    else
+      hipLaunchKernelGGL(k_ffno_xdft<32>, gx, dim3(256), 0, st, a, w.v, w.twx, w.T, nrows);
     hipLaunchKernelGGL(k_ffno_ydft, dim3(grid_for((int64_t)a.dv * a.nz * a.my * a.mx)), dim3(256),
                        0, st, a, w.T, w.twy, w.G);
     hipLaunchKernelGGL(k_ffno_mix_xy, dim3(grid_for((int64_t)a.dv * a.nz * a.my * a.mx)),

@@ -1698,14 +1698,14 @@ psfd_status ffno_layout(const psfd_ffno_desc* d, FfnoLayout* L) {
     return fail(PSFD_ERR_ARG, "need 4 <= nx, ny <= 8192 and 4 <= nz <= 4096");
   if (d->n_layers < 1 || d->n_layers > kFfnoMaxLayers) return fail(PSFD_ERR_ARG, "1 <= n_layers <= 16");
   if (d->kx_max < 0 || d->ky_max < 0 || d->kz_max < 0 || 2 * d->kx_max >= d->nx ||
-      2 * d->ky_max >= d->ny || 2 * d->kz_max >= d->nz || d->kz_max > 15)
-    return fail(PSFD_ERR_ARG, "need 0 <= 2 k_max < n for every axis and kz_max <= 15");
+      2 * d->ky_max >= d->ny || 2 * d->kz_max >= d->nz || d->kz_max > 15 || d->kx_max > 31)
+    return fail(PSFD_ERR_ARG, "need 0 <= 2 k_max < n for every axis, kx_max <= 31, kz_max <= 15");
   FfnoArgs& a = L->a;
   a.nx = d->nx; a.ny = d->ny; a.nz = d->nz; a.dv = d->d_v; a.dh = d->d_h; a.nl = d->n_layers;
   a.mx = d->kx_max + 1; a.my = 2 * d->ky_max + 1; a.mz = d->kz_max + 1; a.ky_max = d->ky_max;
-  a.tx = 0;
-  for (int tx = 256 / a.dv; tx >= 1; tx /= 2)
-    if (a.nx % tx == 0) { a.tx = tx; break; }
+  a.tx = 1;  // columns per block of the axial branch: contiguous loads, spectra within 64 KiB
+  for (int tx = 16; tx >= 1; tx /= 2)
+    if (a.nx % tx == 0 && (size_t)a.dv * a.mz * tx * sizeof(float2) <= 65536) { a.tx = tx; break; }
   const int64_t dv = a.dv, dh = a.dh;
   L->n_weights = dv * 4 + dv + a.nl * (dv * dv * a.my * a.mx * 2 + dv * dv * a.mz * 2 + dh * dv +
                                        dh + dv * dh + dv) + 6 * dv + 6;
