@@ -14,9 +14,8 @@
 //   mix:    U[o][z][m][kx]  = sum_i K_xy[o][i][m][kx] G[i][z][m][kx]
 //   y iDFT: T2[o][z][y][kx] = sum_m U e^{+2 pi i ky y / ny}
 //   x iDFT: u[o][z][y][x]   = (Re T2[..][0] + 2 sum_{kx>0} Re(T2 e^{+2 pi i kx x/nx})) / (nx ny)
-// The axial branch runs per tile of TX columns (forward z DFT of every
-// channel into LDS, channel mixing per kz, inverse z DFT added in place to
-// u_xy); the MLP and the residual update then run one voxel per thread with
+// The axial branch runs as three coalesced passes over the columns (forward
+// z DFT, channel mixing per kz, inverse z DFT added in place to u_xy); the MLP and the residual update then run one voxel per thread with
 // the weights in LDS (W2 is transposed once per call into the workspace so
 // that both products read contiguous rows).
 #include <hip/hip_runtime.h>
@@ -212,37 +211,30 @@ __global__ void __launch_bounds__(256) k_ffno_xidft(const FfnoArgs a, const floa
   }
 }
 
-// Axial branch for TX columns (consecutive x at one y): forward z DFT of
-// every channel into LDS, channel mixing per kz in registers, inverse z DFT
-// added in place to u_xy, so that u holds s = u_xy + u_z afterwards.  A block
-// of G x TX threads (G channel groups) walks the channels g, g + G, ...; the
-// TX consecutive columns of a channel make one contiguous load per z.
-template <int DV>
+// Axial branch in three coalesced passes over the columns (col = y nx + x,
+// consecutive threads on consecutive columns):
+//   forward:  W[c][kz][col] = sum_z u[c][z][col] w^(-kz z)
+//   mixing:   Z[o][kz][col] = sum_i K_z[o][i][kz] W[i][kz][col]   (one thread per (kz, col),
+//             the d_v inputs in registers, the weights wave-uniform)
+//   inverse:  u[o][z][col] += (Re Z[o][0] + 2 sum_{kz>0} Re(Z[o][kz] w^(kz z))) / nz
+// so that u holds s = u_xy + u_z afterwards; powers of w by repeated multiplication.
 __global__ void __launch_bounds__(256)
-k_ffno_axial(const FfnoArgs a, float* __restrict__ u, const float2* __restrict__ Kz,
-             const float2* __restrict__ twz, int TX) {
-  extern __shared__ float lds[];
-  const int nz = a.nz, mz = a.mz, nx = a.nx;
-  const int64_t plane = (int64_t)a.ny * nx;
-  const int64_t vox = plane * nz;
-  const int tiles_x = nx / TX;
-  const int y = blockIdx.x / tiles_x;
-  const int x0 = (blockIdx.x % tiles_x) * TX;
-  const int64_t col0 = (int64_t)y * nx + x0;
-  const int t = threadIdx.x;
-  const int col = t % TX, g = t / TX, G = blockDim.x / TX;
-  float2* Ws = reinterpret_cast<float2*>(lds);
-  // forward z DFT of each of this thread's channels (each element read once)
-#pragma unroll 1
-  for (int ch = g; ch < DV; ch += G) {
-    const float* col_u = u + (int64_t)ch * vox + col0 + col;
+k_ffno_zdft(const FfnoArgs a, const float* __restrict__ u, const float2* __restrict__ twz,
+            float2* __restrict__ W) {
+  const int64_t plane = (int64_t)a.ny * a.nx;
+  const int64_t items = (int64_t)a.dv * plane;
+  const int nz = a.nz, mz = a.mz;
+  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < items;
+       q += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t c = q / plane, col = q % plane;
+    const float* src = u + c * plane * nz + col;
     float2 acc[16];
 #pragma unroll
     for (int kz = 0; kz < 16; ++kz) acc[kz] = make_float2(0.f, 0.f);
     for (int z = 0; z < nz; ++z) {
-      const float val = col_u[(int64_t)z * plane];
+      const float val = src[(int64_t)z * plane];
       const float2 w1 = twz[z];
-      float2 p = make_float2(1.f, 0.f);  // w^(kz z)
+      float2 p = make_float2(1.f, 0.f);
 #pragma unroll
       for (int kz = 0; kz < 16; ++kz) {
         if (kz < mz) {
@@ -252,36 +244,60 @@ k_ffno_axial(const FfnoArgs a, float* __restrict__ u, const float2* __restrict__
         }
       }
     }
+    float2* dst = W + c * mz * plane + col;
 #pragma unroll
     for (int kz = 0; kz < 16; ++kz)
-      if (kz < mz) Ws[(ch * mz + kz) * TX + col] = acc[kz];
+      if (kz < mz) dst[(int64_t)kz * plane] = acc[kz];
   }
-  __syncthreads();
-  const float inz = 1.0f / nz;
+}
+
+template <int DV>
+__global__ void __launch_bounds__(256)
+k_ffno_zmix(const FfnoArgs a, const float2* __restrict__ Kz, const float2* __restrict__ W,
+            float2* __restrict__ Z) {
+  const int64_t plane = (int64_t)a.ny * a.nx;
+  const int mz = a.mz;
+  const int64_t items = (int64_t)mz * plane;
+  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < items;
+       q += (int64_t)gridDim.x * blockDim.x) {
+    const int kz = (int)(q / plane);
+    const int64_t col = q % plane;
+    float2 w[DV];
+#pragma unroll
+    for (int i = 0; i < DV; ++i) w[i] = W[((int64_t)i * mz + kz) * plane + col];
 #pragma unroll 1
-  for (int o = g; o < DV; o += G) {
-    // channel mixing per kz for output channel o
+    for (int o = 0; o < DV; ++o) {
+      float re = 0.f, im = 0.f;
+#pragma unroll
+      for (int i = 0; i < DV; ++i) {
+        const float2 k = Kz[((int64_t)o * DV + i) * mz + kz];
+        re += k.x * w[i].x - k.y * w[i].y;
+        im += k.x * w[i].y + k.y * w[i].x;
+      }
+      Z[((int64_t)o * mz + kz) * plane + col] = make_float2(re, im);
+    }
+  }
+}
+
+__global__ void __launch_bounds__(256)
+k_ffno_zidft(const FfnoArgs a, const float2* __restrict__ Z, const float2* __restrict__ twz,
+             float* __restrict__ u) {
+  const int64_t plane = (int64_t)a.ny * a.nx;
+  const int64_t items = (int64_t)a.dv * plane;
+  const int nz = a.nz, mz = a.mz;
+  const float inz = 1.0f / nz;
+  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < items;
+       q += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t o = q / plane, col = q % plane;
+    const float2* zs = Z + o * mz * plane + col;
     float2 zk[16];
 #pragma unroll
-    for (int kz = 0; kz < 16; ++kz) {
-      if (kz < mz) {
-        float re = 0.f, im = 0.f;
-#pragma unroll 4
-        for (int i = 0; i < DV; ++i) {
-          const float2 k = Kz[((int64_t)o * DV + i) * mz + kz];
-          const float2 w = Ws[(i * mz + kz) * TX + col];
-          re += k.x * w.x - k.y * w.y;
-          im += k.x * w.y + k.y * w.x;
-        }
-        zk[kz] = make_float2(re, im);
-      }
-    }
-    // inverse z DFT added to u_xy (this thread's own column of channel o)
-    float* col_u = u + (int64_t)o * vox + col0 + col;
+    for (int kz = 0; kz < 16; ++kz) zk[kz] = kz < mz ? zs[(int64_t)kz * plane] : make_float2(0.f, 0.f);
+    float* dst = u + o * plane * nz + col;
     for (int z = 0; z < nz; ++z) {
       float acc = zk[0].x;
       const float2 w1 = twz[z];
-      float2 p = w1;  // w^(kz z), from kz = 1
+      float2 p = w1;
 #pragma unroll
       for (int kz = 1; kz < 16; ++kz) {
         if (kz < mz) {
@@ -289,7 +305,7 @@ k_ffno_axial(const FfnoArgs a, float* __restrict__ u, const float2* __restrict__
           p = cmul2(p, w1);
         }
       }
-      col_u[(int64_t)z * plane] += acc * inz;
+      dst[(int64_t)z * plane] += acc * inz;
     }
   }
 }
@@ -365,12 +381,14 @@ unsigned grid_for(int64_t items) {
 
 template <int DV, int DH>
 hipError_t axial_mlp_launch(const FfnoArgs& a, const FfnoPtrs& w, int layer, int last, hipStream_t st) {
-  const int tx = a.tx;
-  const size_t shm = sizeof(float2) * (size_t)DV * a.mz * tx;
-  const int threads = std::min(256, DV * tx);
-  hipLaunchKernelGGL((k_ffno_axial<DV>), dim3((unsigned)(a.ny * (a.nx / tx))), dim3(threads), shm,
-                     st, a, w.u, w.Kz[layer], w.twz, tx);
-  const int64_t vox = (int64_t)a.nz * a.ny * a.nx;
+  const int64_t plane = (int64_t)a.ny * a.nx;
+  const int64_t vox = plane * a.nz;
+  hipLaunchKernelGGL(k_ffno_zdft, dim3(grid_for((int64_t)DV * plane)), dim3(256), 0, st, a, w.u,
+                     w.twz, w.W);
+  hipLaunchKernelGGL((k_ffno_zmix<DV>), dim3(grid_for((int64_t)a.mz * plane)), dim3(256), 0, st, a,
+                     w.Kz[layer], w.W, w.Z);
+  hipLaunchKernelGGL(k_ffno_zidft, dim3(grid_for((int64_t)DV * plane)), dim3(256), 0, st, a, w.Z,
+                     w.twz, w.u);
   hipLaunchKernelGGL((k_ffno_mlp<DV, DH>), dim3(grid_for(vox)), dim3(256), 0, st, a, w.u, w.v,
                      w.W1[layer], w.b1[layer], w.W2T + (size_t)layer * DV * DH, w.b2[layer], last);
   return hipGetLastError();

@@ -1683,7 +1683,7 @@ struct FfnoLayout {
   FfnoArgs a{};
   int64_t n_weights = 0;
   size_t off_v = 0, off_u = 0, off_T = 0, off_G = 0, off_U = 0, off_tx = 0, off_ty = 0, off_tz = 0;
-  size_t off_w2t = 0;
+  size_t off_w2t = 0, off_W = 0, off_Z = 0;
   size_t bytes = 0;
 };
 
@@ -1703,9 +1703,6 @@ psfd_status ffno_layout(const psfd_ffno_desc* d, FfnoLayout* L) {
   FfnoArgs& a = L->a;
   a.nx = d->nx; a.ny = d->ny; a.nz = d->nz; a.dv = d->d_v; a.dh = d->d_h; a.nl = d->n_layers;
   a.mx = d->kx_max + 1; a.my = 2 * d->ky_max + 1; a.mz = d->kz_max + 1; a.ky_max = d->ky_max;
-  a.tx = 1;  // columns per block of the axial branch: contiguous loads, spectra within 64 KiB
-  for (int tx = 16; tx >= 1; tx /= 2)
-    if (a.nx % tx == 0 && (size_t)a.dv * a.mz * tx * sizeof(float2) <= 65536) { a.tx = tx; break; }
   const int64_t dv = a.dv, dh = a.dh;
   L->n_weights = dv * 4 + dv + a.nl * (dv * dv * a.my * a.mx * 2 + dv * dv * a.mz * 2 + dh * dv +
                                        dh + dv * dh + dv) + 6 * dv + 6;
@@ -1720,6 +1717,8 @@ psfd_status ffno_layout(const psfd_ffno_desc* d, FfnoLayout* L) {
   L->off_ty = o; o = align256(o + sizeof(float2) * a.ny);
   L->off_tz = o; o = align256(o + sizeof(float2) * a.nz);
   L->off_w2t = o; o = align256(o + sizeof(float) * a.nl * dv * dh);
+  L->off_W = o; o = align256(o + sizeof(float2) * dv * a.mz * (size_t)a.ny * a.nx);
+  L->off_Z = o; o = align256(o + sizeof(float2) * dv * a.mz * (size_t)a.ny * a.nx);
   L->bytes = o;
   return PSFD_OK;
 }
@@ -1768,6 +1767,8 @@ psfd_status psfd_ffno_forward(const psfd_ffno_desc* d, const float* weights, con
     w.twy = reinterpret_cast<float2*>(ws + L.off_ty);
     w.twz = reinterpret_cast<float2*>(ws + L.off_tz);
     w.W2T = reinterpret_cast<float*>(ws + L.off_w2t);
+    w.W = reinterpret_cast<float2*>(ws + L.off_W);
+    w.Z = reinterpret_cast<float2*>(ws + L.off_Z);
     CHK(ffno_forward(a, w, a_in, static_cast<cplx<double>*>(E), static_cast<hipStream_t>(hip_stream)));
     return PSFD_OK;
   });

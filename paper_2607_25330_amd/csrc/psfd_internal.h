@@ -203,7 +203,6 @@ constexpr int kFfnoMaxLayers = 16;
 struct FfnoArgs {
   int nx, ny, nz, dv, dh, nl;
   int mx, my, mz, ky_max;  // retained modes: kx 0..mx-1, ky -ky_max..ky_max (my), kz 0..mz-1
-  int tx;                  // columns per block of the axial + MLP kernel
 };
 struct FfnoPtrs {
   const float *P, *p, *Q, *q;
@@ -213,6 +212,7 @@ struct FfnoPtrs {
   float *v, *u;            // hidden state and lateral-branch output, [dv][nz][ny][nx]
   float* W2T;              // [nl][dh][dv] transposed MLP output weights
   float2 *T, *G, *U;       // [dv][nz][ny][mx], [dv][nz][my][mx] x 2
+  float2 *W, *Z;           // axial spectra before / after mixing, [dv][mz][ny][nx] each
   float2 *twx, *twy, *twz; // e^{+2 pi i k / n}
 };
 hipError_t ffno_forward(const FfnoArgs& a, const FfnoPtrs& w, const float* in, cplx<double>* E,
