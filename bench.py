@@ -688,7 +688,7 @@ def main():
     t_mixed = time.perf_counter() - t0
     print(f"bench: mixed leg {t_mixed:.3f} s", file=sys.stderr, flush=True)
 
-    # whole-apply and whole-iteration roofline (survey 8(d) algorithmic units):
+    # whole-apply and whole-iteration roofline (algorithmic bytes per voxel):
     # one complex64 operator apply = read x + write y (48 B / voxel);
     # one BiCGSTAB iteration = 20 field passes x 24 B = 480 B / voxel.
     vox = 3 * nx * ny * (cfgs[0]["nz_abs"] + 16)  # complex elements of one field
