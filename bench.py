@@ -380,6 +380,12 @@ def workload_fd(psfd, args):
             del E
     out["legs"]["absorber"] = res
     out["value"] = round(8 / t_bare, 3)
+    fl = res.get("full_domain_fp64", {})
+    if "axial_GBs" in fl:
+        out["roofline"] = {"bound": "hbm", "achieved": fl["axial_GBs"], "peak": HBM_PEAK_GBS,
+                           "unit": "GB/s", "frac": round(fl["axial_GBs"] / HBM_PEAK_GBS, 4),
+                           "traffic": None, "kernel": "axial (LDS-staged, Nz 384, FP64 A apply)",
+                           "avg_launch_us": fl["axial_us"]}
     return out
 
 
@@ -436,6 +442,11 @@ def workload_contour(psfd, args):
     return {"metric": "threshold-contour width deviation vs iterations", "unit": "planes/s",
             "value": round(8 / seg_t, 1), "dtype": "f64", "legs": legs,
             "segments_ms_8_planes": round(1e3 * seg_t, 4),
+            "roofline": {"bound": "hbm", "unit": "GB/s", "peak": HBM_PEAK_GBS, "traffic": None,
+                         "kernel": "contour segments (8 planes, 200 lines of 256 samples each)",
+                         "achieved": round(8 * 200 * 256 * 16 / seg_t / 1e9, 1),
+                         "frac": round(8 * 200 * 256 * 16 / seg_t / 1e9 / HBM_PEAK_GBS, 5),
+                         "note": "one launch per call: latency-bound, not bandwidth-bound"},
             "deviation_ms_8_planes": round(1e3 * dt2 / 20, 4),
             "segments_per_ref_plane": float(seg_ref[1].sum().item()) / 8,
             "config": {"workload": "8 seeded 256x256x(32+16) clips, TE 6 deg, cutoff 0.1; reference "
@@ -492,6 +503,11 @@ def workload_pino(psfd, args):
             "loss_ms": round(1e3 * dt_loss / 20, 3), "adjoint_ms": round(1e3 * dt_adj / 20, 3),
             "apply_ms": round(1e3 * dt_apply / 20, 3),
             "loss_terms_clip0": {"J": res[0][0]}, "voxels": vox,
+            "roofline": {"bound": "hbm", "unit": "GB/s", "peak": HBM_PEAK_GBS, "traffic": None,
+                         "kernel": "one psfd_pino_loss call (FP64), counted as its 8 field passes "
+                                   "(read E, b; write r; read r, write H r; read r, H r, write g)",
+                         "achieved": round(8 * 16 * vox / (dt_loss / 20) / 1e9, 1),
+                         "frac": round(8 * 16 * vox / (dt_loss / 20) / 1e9 / HBM_PEAK_GBS, 4)},
             "config": {"workload": "16 seeded rectangle clips 128x128x(32+16), TE 6 deg, field = "
                                    "mixed solve + smooth noise; J = (1/N)||r||^2 + (lambda/N)"
                                    "||w F3 r||^2, w0 1, eta 10 nm, lambda 0.01; autograd"}}
@@ -533,6 +549,11 @@ def workload_ffno(psfd, args):
         torch.cuda.empty_cache()
     last = out["legs"].get("1200x1200x100") or next(iter(out["legs"].values()))
     out["value"] = round(1e3 / last["ms"], 3)
+    mlp = last["mlp_tflop"] / (last["ms"] / 1e3)
+    out["roofline"] = {"bound": "alu", "unit": "TFLOP/s", "peak": 157.3, "traffic": None,
+                       "kernel": "whole forward pass, counted as its MLP flops only",
+                       "achieved": round(mlp, 2), "frac": round(mlp / 157.3, 4),
+                       "note": "per-kernel figures in the rocprofv3 summary"}
     out["config"] = {"workload": "F-FNO d_v 32, d_h 64, 4 layers, modes (12, 12, 8), random "
                                  "weights; 256x256x48 and 1200x1200x100 (value: the latter)"}
     return out
