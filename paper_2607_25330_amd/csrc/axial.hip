@@ -150,7 +150,12 @@ k_axial(const cplx<T>* __restrict__ S_all, cplx<T>* __restrict__ UW_all, const O
 
   const int tid = threadIdx.x;
   const int iy = blockIdx.y % t.ny;
-  const int kx0 = blockIdx.x * TX;
+  // Workgroups go to the 8 XCDs round-robin by linear id; with gridDim.x a
+  // multiple of 8 the tiles of one XCD are made neighbours along x, so that
+  // the narrow column tiles of neighbouring blocks share that XCD's L2 lines.
+  const int bx = (gridDim.x % 8 == 0) ? (blockIdx.x % 8) * (gridDim.x / 8) + blockIdx.x / 8
+                                      : blockIdx.x;
+  const int kx0 = bx * TX;
   const int64_t plane = (int64_t)t.nx * t.ny;
   const int64_t colbase = (int64_t)iy * t.nx + kx0;
   const T inz = T(1) / T(NZ);
