@@ -386,7 +386,15 @@ psfd_status psfd_set_schedule(psfd_plan_t p, const int32_t* sched);
 /* Total number of complex elements of one field, 3 * Nz * ny * nx. */
 int64_t psfd_field_size(psfd_plan_t p);
 
+/* Destroy a plan: waits for its stream, then gives its device blocks to the
+ * library's memory cache (blocks are reused by later plans asking for the
+ * same sizes, at most 32 GiB are kept; a failed allocation empties the cache
+ * first).  PSFD_CACHE=0 in the environment frees the blocks instead. */
 void psfd_destroy(psfd_plan_t p);
+
+/* Free every device block held by the library's memory cache (the caller
+ * wants the memory back; no plan needs to be destroyed for this). */
+void psfd_trim_cache(void);
 
 /* Message of the last error on this thread ("" if none). */
 const char* psfd_last_error(void);

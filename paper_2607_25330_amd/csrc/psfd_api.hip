@@ -52,6 +52,50 @@ psfd_status fail(psfd_status s, const std::string& msg) {
     if (s_ != PSFD_OK) return s_;           \
   } while (0)
 
+// Device memory cache: blocks given back by a destroyed plan are kept per
+// (device, size) and handed to the next plan asking for that size (plans of
+// one shape are typically made and destroyed in a loop), at most kCacheMax
+// bytes in all.  A failed allocation empties the cache and tries again;
+// psfd_trim_cache() empties it on request, PSFD_CACHE=0 disables it.
+std::mutex g_cache_mu;
+std::multimap<std::pair<int, size_t>, void*> g_cache;
+size_t g_cache_bytes = 0;
+constexpr size_t kCacheMax = size_t(32) << 30;
+
+bool cache_on() {
+  static const bool on = [] {
+    const char* e = std::getenv("PSFD_CACHE");
+    return !(e && *e && std::atoi(e) == 0);
+  }();
+  return on;
+}
+
+void* cache_take(int dev, size_t bytes) {
+  std::lock_guard<std::mutex> lk(g_cache_mu);
+  auto it = g_cache.find({dev, bytes});
+  if (it == g_cache.end()) return nullptr;
+  void* p = it->second;
+  g_cache.erase(it);
+  g_cache_bytes -= bytes;
+  return p;
+}
+
+bool cache_put(int dev, size_t bytes, void* p) {
+  if (!cache_on()) return false;
+  std::lock_guard<std::mutex> lk(g_cache_mu);
+  if (g_cache_bytes + bytes > kCacheMax) return false;
+  g_cache.emplace(std::make_pair(dev, bytes), p);
+  g_cache_bytes += bytes;
+  return true;
+}
+
+void cache_trim() {
+  std::lock_guard<std::mutex> lk(g_cache_mu);
+  for (auto& kv : g_cache) (void)hipFree(kv.second);
+  g_cache.clear();
+  g_cache_bytes = 0;
+}
+
 constexpr double kTwoPi = 6.283185307179586476925286766559;
 constexpr int kChunk = 16;         // BiCGSTAB iterations queued between convergence checks
 constexpr int kMaxRestarts = 10;   // residual replacements (FP64) / refinement steps (mixed)
@@ -90,7 +134,8 @@ struct psfd_plan {
   hipStream_t st = nullptr;
   int prec = PSFD_C128;
   bool use_pc = true;
-  std::vector<void*> allocs;
+  std::vector<std::pair<void*, size_t>> allocs;  // device blocks and their sizes
+  int alloc_dev = 0;
 
   OpTables<double> t64{};
   OpTables<float> t32{};
@@ -143,6 +188,12 @@ struct psfd_plan {
   int64_t prof_launches = 0;
 
   ~psfd_plan() {
+    // nothing may still run on the blocks that go back to the cache
+    if (!allocs.empty()) {
+      if (st) (void)hipStreamSynchronize(st);
+      else (void)hipDeviceSynchronize();
+      if (own_st) (void)hipStreamSynchronize(own_st);
+    }
     for (auto& row : gexec)
       for (auto& g : row)
         if (g) (void)hipGraphExecDestroy(g);
@@ -150,7 +201,8 @@ struct psfd_plan {
     if (join_ev) (void)hipEventDestroy(join_ev);
     for (auto& pr : ev_open) { ev_pool.push_back(pr.first); ev_pool.push_back(pr.second); }
     for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
-    for (void* p : allocs) (void)hipFree(p);
+    for (auto& a : allocs)
+      if (!cache_put(alloc_dev, a.second, a.first)) (void)hipFree(a.first);
     if (ks_host) (void)hipHostFree(ks_host);
     if (pp_host) (void)hipHostFree(pp_host);
     if (idle_host) (void)hipHostFree(idle_host);
@@ -161,15 +213,25 @@ namespace {
 
 template <typename T>
 psfd_status dalloc(struct psfd_plan* P, T** out, size_t count) {
-  void* q = nullptr;
   const size_t bytes = std::max<size_t>(count, 1) * sizeof(T);
-  hipError_t e = hipMalloc(&q, bytes);
-  if (e != hipSuccess) {
-    (void)hipGetLastError();
-    return fail(PSFD_ERR_ALLOC, "hipMalloc of " + std::to_string(bytes) + " bytes failed: " +
-                                    hipGetErrorString(e));
+  int dev = 0;
+  CHK(hipGetDevice(&dev));
+  void* q = cache_take(dev, bytes);
+  if (!q) {
+    hipError_t e = hipMalloc(&q, bytes);
+    if (e != hipSuccess) {  // the cache may hold the memory: give it back and try again
+      (void)hipGetLastError();
+      cache_trim();
+      e = hipMalloc(&q, bytes);
+    }
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(PSFD_ERR_ALLOC, "hipMalloc of " + std::to_string(bytes) + " bytes failed: " +
+                                      hipGetErrorString(e));
+    }
   }
-  P->allocs.push_back(q);
+  P->alloc_dev = dev;
+  P->allocs.push_back({q, bytes});
   *out = static_cast<T*>(q);
   return PSFD_OK;
 }
@@ -1920,6 +1982,8 @@ void psfd_destroy(psfd_plan_t p) {
   else (void)hipDeviceSynchronize();
   delete p;
 }
+
+void psfd_trim_cache(void) { cache_trim(); }
 
 const char* psfd_last_error(void) { return g_err.c_str(); }
 

@@ -120,6 +120,8 @@ def lib():
         L.psfd_field_size.restype = c_int64
         L.psfd_destroy.argtypes = [c_void_p]
         L.psfd_destroy.restype = None
+        L.psfd_trim_cache.argtypes = []
+        L.psfd_trim_cache.restype = None
         L.psfd_last_error.argtypes = []
         L.psfd_last_error.restype = ctypes.c_char_p
         _lib = L
@@ -183,6 +185,11 @@ def psfd_layout_eps(cfg, a_bin, eps_abs, sigma=None):
     _call("psfd_layout_eps", ctypes.byref(d), _ptr(a, torch.float64, (cfg["ny"], cfg["nx"]), "a_bin"),
           ctypes.cast(ea, c_dp), c_double(sig), _ptr(out, torch.complex128), _stream_handle())
     return out
+
+
+def trim_cache():
+    """Free the device blocks the library keeps from destroyed plans."""
+    lib().psfd_trim_cache()
 
 
 def psfd_layered_eps(cfg, layers_eps, layers_thick, device):

@@ -47,3 +47,29 @@ def test_mixed_solve_of_a_hard_system_matches_fp64(psfd):
     assert np.isfinite(i2["rrel"]) and i2["rrel"] <= 1.0
     ref.close()
     mixed.close()
+
+
+def test_plans_reuse_cached_device_memory(psfd):
+    """Blocks of destroyed plans are reused by later plans (and freed by trim_cache):
+    repeated solves on recycled memory give bit-identical fields."""
+    print("robust: memory cache reuse", flush=True)
+    cfg_a = base_config(32, 32, 16, 30.0)
+    cfg_b = base_config(64, 32, 8, 15.0, pol=1)
+    a = torch.from_numpy(rect_layout(32, 32, np.random.default_rng(3), wmin=2, wmax=8)).to(DEV)
+    b = torch.from_numpy(rect_layout(64, 32, np.random.default_rng(4), wmin=2, wmax=8)).to(DEV)
+    eps_a = psfd.psfd_layout_eps(cfg_a, a, eps_absorber_default())
+    eps_b = psfd.psfd_layout_eps(cfg_b, b, eps_absorber_default())
+
+    def solve(cfg, eps, prec):
+        p = psfd.Plan(cfg, eps, prec)
+        E, _ = p.solve(tol=1e-8)
+        p.close()
+        return E.clone()
+
+    ref = {prec: solve(cfg_a, eps_a, prec) for prec in (psfd.PSFD_C128, psfd.PSFD_C64_REFINE64)}
+    for _ in range(2):
+        solve(cfg_b, eps_b, psfd.PSFD_C64_REFINE64)
+        for prec, E0 in ref.items():
+            assert torch.equal(solve(cfg_a, eps_a, prec), E0)
+    psfd.trim_cache()
+    assert torch.equal(solve(cfg_a, eps_a, psfd.PSFD_C128), ref[psfd.PSFD_C128])
