@@ -102,14 +102,17 @@ def cpu_leg(iters_proj, sample_iters):
             "s_per_iteration": per_iter, "setup_s": setup, "projected": True}
 
 
+# the files the inverse x pass (the roofline kernel) is compiled from
+ROOFLINE_KERNEL_SOURCES = ["cplx.h", "fft_core.h", "fft_lateral.hip", "psfd_internal.h", "reduce.h"]
+
+
 def _sources_hash():
-    """SHA-256 over the library's kernel sources (file name + bytes, sorted by name)."""
-    import glob
+    """SHA-256 over the roofline kernel's sources (file name + bytes, sorted by name)."""
     import hashlib
     h = hashlib.sha256()
-    for p in sorted(glob.glob(os.path.join(ROOT, "paper_2607_25330_amd", "csrc", "*"))):
-        h.update(os.path.basename(p).encode())
-        with open(p, "rb") as f:
+    for name in sorted(ROOFLINE_KERNEL_SOURCES):
+        h.update(name.encode())
+        with open(os.path.join(ROOT, "paper_2607_25330_amd", "csrc", name), "rb") as f:
             h.update(f.read())
     return h.hexdigest()
 

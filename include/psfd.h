@@ -336,7 +336,7 @@ psfd_status psfd_ffno_sizes(const psfd_ffno_desc* d, int64_t* n_weights, int64_t
  *   v   <- v + act(W2 gelu(W1 (u_xy + u_z) + b1) + b2), act = gelu (erf form)
  *          except in the last layer,
  * with v0 = P (a, x/nx, y/ny, z/nz) + p and E = Q v + q.
- *   weights    device FP32, layout above
+ *   weights    device FP32, layout above, 8-byte aligned
  *   a_in       device FP32 [nz][ny][nx]: the smoothed material indicator
  *   E          device out, [3][nz][ny][nx] complex128 (the solver's field layout)
  *   workspace  device, psfd_ffno_sizes bytes, 256-byte aligned; contents

@@ -1802,6 +1802,10 @@ psfd_status psfd_ffno_forward(const psfd_ffno_desc* d, const float* weights, con
   FfnoLayout L;
   CHKS(ffno_layout(d, &L));
   if (!weights || !a_in || !E || !workspace) return fail(PSFD_ERR_ARG, "NULL argument");
+  if (reinterpret_cast<uintptr_t>(workspace) % 256 || reinterpret_cast<uintptr_t>(weights) % 8 ||
+      reinterpret_cast<uintptr_t>(a_in) % 4 || reinterpret_cast<uintptr_t>(E) % 16)
+    return fail(PSFD_ERR_ARG, "workspace must be 256-byte, weights 8-byte, a_in 4-byte and E "
+                              "16-byte aligned");
   return guarded([&]() -> psfd_status {
     const FfnoArgs& a = L.a;
     FfnoPtrs w{};
