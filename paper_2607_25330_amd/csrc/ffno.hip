@@ -59,15 +59,17 @@ __device__ __forceinline__ float2 cmul2(float2 a, float2 b) {
 
 // T[row][kx] for rows of v (row = (c, z, y)): one thread per row, the block's
 // 256 rows staged in LDS 32 samples at a time (pitch 33 floats: the lanes of
-// a wave read distinct banks).  Per sample x the powers w^(kx x),
-// kx = 0..mx-1, come from one table value w^x by repeated multiplication,
-// and every kx is accumulated in registers.
+// a wave read distinct banks).  The powers w^(kx x), kx = 0..mx-1, depend on
+// x only: for each chunk of 32 samples one wave forms them once for the
+// whole block (from the table value w^x by repeated multiplication) and every
+// row reads them as LDS broadcasts; every kx is accumulated in registers.
 template <int MXM>
 __global__ void __launch_bounds__(256) k_ffno_xdft(const FfnoArgs a, const float* __restrict__ v,
                                                    const float2* __restrict__ twx,
                                                    float2* __restrict__ T, int64_t nrows) {
   constexpr int ROWS = 256, CH = 32, PITCH = CH + 1;
   __shared__ float tile[ROWS * PITCH];
+  __shared__ float2 pw[CH * MXM];
   const int64_t r0 = (int64_t)blockIdx.x * ROWS;
   const int nr = (int)min((int64_t)ROWS, nrows - r0);
   const int nx = a.nx, mx = a.mx, t = threadIdx.x;
@@ -77,22 +79,36 @@ __global__ void __launch_bounds__(256) k_ffno_xdft(const FfnoArgs a, const float
   for (int x0 = 0; x0 < nx; x0 += CH) {
     const int nc = min(CH, nx - x0);
     __syncthreads();
-    for (int e = t; e < nr * nc; e += ROWS) {
-      const int r = e / nc, c = e % nc;
-      tile[r * PITCH + c] = v[(r0 + r) * nx + x0 + c];
+    if (nc == CH) {
+      for (int e = t; e < nr * CH; e += ROWS) {
+        const int r = e / CH, c = e % CH;
+        tile[r * PITCH + c] = v[(r0 + r) * nx + x0 + c];
+      }
+    } else {
+      for (int e = t; e < nr * nc; e += ROWS) {
+        const int r = e / nc, c = e % nc;
+        tile[r * PITCH + c] = v[(r0 + r) * nx + x0 + c];
+      }
+    }
+    if (t < nc) {
+      const float2 w1 = twx[x0 + t];  // e^{+i 2 pi x / nx}
+      float2 p = make_float2(1.f, 0.f);
+      for (int k = 0; k < mx; ++k) {
+        pw[t * MXM + k] = p;
+        p = cmul2(p, w1);
+      }
     }
     __syncthreads();
     if (t < nr) {
       for (int c = 0; c < nc; ++c) {
         const float val = tile[t * PITCH + c];
-        const float2 w1 = twx[x0 + c];  // e^{+i 2 pi x / nx}
-        float2 p = make_float2(1.f, 0.f);
+        const float2* pc = pw + c * MXM;
 #pragma unroll
         for (int k = 0; k < MXM; ++k) {
           if (k < mx) {
+            const float2 p = pc[k];
             re[k] += val * p.x;  // the forward sum takes the conjugate power
             im[k] -= val * p.y;
-            p = cmul2(p, w1);
           }
         }
       }
@@ -179,47 +195,88 @@ __global__ void k_ffno_yidft(const FfnoArgs a, const float2* __restrict__ U,
 }
 
 // u[o][z][y][x] = (Re T2[..][0] + 2 sum_{kx>0} Re(T2[..][kx] e^{+2 pi i kx x / nx})) / (nx ny)
-// One block per group of R rows (row = (o, z, y)): the rows' spectra and the
-// twiddles (nx <= 2048) are staged in LDS, threads walk x.
+// One block per XR rows (row = (o, z, y)), their spectra staged in LDS; a
+// thread takes columns x, forms the powers w^(kx x) once in registers
+// (repeated multiplication of the table value w^x) and applies them to every
+// row of the block, reading the spectra as LDS broadcasts; stores are
+// coalesced along x.
+constexpr int kXidftRows = 32;
+template <int MXM>
 __global__ void __launch_bounds__(256) k_ffno_xidft(const FfnoArgs a, const float2* __restrict__ T2,
                                                     const float2* __restrict__ twx,
-                                                    float* __restrict__ u, int64_t nrows, int R) {
-  extern __shared__ float2 xi_s[];
+                                                    float* __restrict__ u, int64_t nrows) {
+  __shared__ float2 sp[kXidftRows * MXM];
   const int mx = a.mx, nx = a.nx;
-  const int64_t r0 = (int64_t)blockIdx.x * R;
-  const int nr = (int)min((int64_t)R, nrows - r0);
-  float2* tw_s = xi_s + R * mx;
-  const bool tl = nx <= 2048;
-  for (int e = threadIdx.x; e < nr * mx; e += blockDim.x) xi_s[e] = T2[r0 * mx + e];
-  if (tl)
-    for (int e = threadIdx.x; e < nx; e += blockDim.x) tw_s[e] = twx[e];
+  const int64_t r0 = (int64_t)blockIdx.x * kXidftRows;
+  const int nr = (int)min((int64_t)kXidftRows, nrows - r0);
+  for (int e = threadIdx.x; e < nr * mx; e += blockDim.x) {
+    const int rr = e / mx, k = e % mx;
+    sp[rr * MXM + k] = T2[(r0 + rr) * mx + k];
+  }
   __syncthreads();
-  const float2* tw = tl ? tw_s : twx;
   const float norm = 1.0f / ((float)nx * (float)a.ny);
-  for (int e = threadIdx.x; e < nr * nx; e += blockDim.x) {
-    const int rr = e / nx, x = e % nx;
-    const float2* t = xi_s + rr * mx;
-    float acc = t[0].x;
-    const float2 w1 = tw[x];  // e^{+i 2 pi x / nx}; its powers by repeated multiplication
+  for (int x = threadIdx.x; x < nx; x += blockDim.x) {
+    const float2 w1 = twx[x];  // e^{+i 2 pi x / nx}
+    float2 pk[MXM];
     float2 p = w1;
-    for (int kx = 1; kx < mx; ++kx) {
-      const float2 sv = t[kx];
-      acc += 2.0f * (sv.x * p.x - sv.y * p.y);
-      p = cmul2(p, w1);
+#pragma unroll
+    for (int k = 1; k < MXM; ++k) {
+      if (k < mx) {
+        pk[k] = p;
+        p = cmul2(p, w1);
+      }
     }
-    u[(r0 + rr) * nx + x] = acc * norm;
+    for (int rr = 0; rr < nr; ++rr) {
+      const float2* t = sp + rr * MXM;
+      float acc = t[0].x;
+#pragma unroll
+      for (int k = 1; k < MXM; ++k) {
+        if (k < mx) {
+          const float2 sv = t[k];
+          acc += 2.0f * (sv.x * pk[k].x - sv.y * pk[k].y);
+        }
+      }
+      u[(r0 + rr) * nx + x] = acc * norm;
+    }
   }
 }
 
 // Axial branch in three coalesced passes over the columns (col = y nx + x,
 // consecutive threads on consecutive columns):
 //   forward:  W[c][kz][col] = sum_z u[c][z][col] w^(-kz z)
-//   mixing:   Z[o][kz][col] = sum_i K_z[o][i][kz] W[i][kz][col]   (one thread per (kz, col),
-//             the d_v inputs in registers, the weights wave-uniform)
+//   mixing:   Z[o][kz][col] = sum_i K_z[o][i][kz] W[i][kz][col]   (one thread per column,
+//             kz = blockIdx.y, the d_v inputs in registers)
 //   inverse:  u[o][z][col] += (Re Z[o][0] + 2 sum_{kz>0} Re(Z[o][kz] w^(kz z))) / nz
-// so that u holds s = u_xy + u_z afterwards; powers of w by repeated multiplication.
+// so that u holds s = u_xy + u_z afterwards.  The powers w^(kz z) depend on
+// z only: they are tabulated once per forward pass (PZ[z][kz], repeated
+// multiplication of the table value w^z) and, z being the same for every
+// thread of a pass step, read as scalar loads, as are the mixing weights
+// (a kz-major copy KzT[kz][o][i] of K_z).  The column loads of four z rows
+// are issued together.
+constexpr int kZPow = 16;  // row stride of the power table (kz_max <= 15)
+
+__global__ void k_ffno_zpowers(const float2* __restrict__ twz, int nz, int mz,
+                               float2* __restrict__ pz) {
+  const int z = blockIdx.x * blockDim.x + threadIdx.x;
+  if (z >= nz) return;
+  const float2 w1 = twz[z];
+  float2 p = make_float2(1.f, 0.f);
+  for (int kz = 0; kz < kZPow; ++kz) {
+    pz[z * kZPow + kz] = p;
+    if (kz + 1 < mz) p = cmul2(p, w1);
+  }
+}
+
+// KzT[kz][o][i] = Kz[o][i][kz] (one layer)
+__global__ void k_ffno_kz_major(const float2* __restrict__ Kz, int dv, int mz,
+                                float2* __restrict__ KzT) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= dv * dv * mz) return;
+  KzT[(int64_t)(e % mz) * dv * dv + e / mz] = Kz[e];
+}
+
 __global__ void __launch_bounds__(256)
-k_ffno_zdft(const FfnoArgs a, const float* __restrict__ u, const float2* __restrict__ twz,
+k_ffno_zdft(const FfnoArgs a, const float* __restrict__ u, const float2* __restrict__ pz,
             float2* __restrict__ W) {
   const int64_t plane = (int64_t)a.ny * a.nx;
   const int64_t items = (int64_t)a.dv * plane;
@@ -228,40 +285,45 @@ k_ffno_zdft(const FfnoArgs a, const float* __restrict__ u, const float2* __restr
        q += (int64_t)gridDim.x * blockDim.x) {
     const int64_t c = q / plane, col = q % plane;
     const float* src = u + c * plane * nz + col;
-    float2 acc[16];
+    float2 acc[kZPow];
 #pragma unroll
-    for (int kz = 0; kz < 16; ++kz) acc[kz] = make_float2(0.f, 0.f);
-    for (int z = 0; z < nz; ++z) {
-      const float val = src[(int64_t)z * plane];
-      const float2 w1 = twz[z];
-      float2 p = make_float2(1.f, 0.f);
+    for (int kz = 0; kz < kZPow; ++kz) acc[kz] = make_float2(0.f, 0.f);
+    for (int z0 = 0; z0 < nz; z0 += 4) {
+      float val[4];
 #pragma unroll
-      for (int kz = 0; kz < 16; ++kz) {
-        if (kz < mz) {
-          acc[kz].x += val * p.x;
-          acc[kz].y -= val * p.y;
-          p = cmul2(p, w1);
+      for (int j = 0; j < 4; ++j) val[j] = (z0 + j < nz) ? src[(int64_t)(z0 + j) * plane] : 0.f;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        if (z0 + j < nz) {
+          const float2* pw = pz + (z0 + j) * kZPow;
+#pragma unroll
+          for (int kz = 0; kz < kZPow; ++kz) {
+            if (kz < mz) {
+              const float2 p = pw[kz];
+              acc[kz].x += val[j] * p.x;
+              acc[kz].y -= val[j] * p.y;
+            }
+          }
         }
       }
     }
     float2* dst = W + c * mz * plane + col;
 #pragma unroll
-    for (int kz = 0; kz < 16; ++kz)
+    for (int kz = 0; kz < kZPow; ++kz)
       if (kz < mz) dst[(int64_t)kz * plane] = acc[kz];
   }
 }
 
 template <int DV>
 __global__ void __launch_bounds__(256)
-k_ffno_zmix(const FfnoArgs a, const float2* __restrict__ Kz, const float2* __restrict__ W,
+k_ffno_zmix(const FfnoArgs a, const float2* __restrict__ KzT, const float2* __restrict__ W,
             float2* __restrict__ Z) {
   const int64_t plane = (int64_t)a.ny * a.nx;
   const int mz = a.mz;
-  const int64_t items = (int64_t)mz * plane;
-  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < items;
-       q += (int64_t)gridDim.x * blockDim.x) {
-    const int kz = (int)(q / plane);
-    const int64_t col = q % plane;
+  const int kz = blockIdx.y;
+  const float2* K = KzT + (int64_t)kz * DV * DV;
+  for (int64_t col = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; col < plane;
+       col += (int64_t)gridDim.x * blockDim.x) {
     float2 w[DV];
 #pragma unroll
     for (int i = 0; i < DV; ++i) w[i] = W[((int64_t)i * mz + kz) * plane + col];
@@ -270,7 +332,7 @@ k_ffno_zmix(const FfnoArgs a, const float2* __restrict__ Kz, const float2* __res
       float re = 0.f, im = 0.f;
 #pragma unroll
       for (int i = 0; i < DV; ++i) {
-        const float2 k = Kz[((int64_t)o * DV + i) * mz + kz];
+        const float2 k = K[o * DV + i];
         re += k.x * w[i].x - k.y * w[i].y;
         im += k.x * w[i].y + k.y * w[i].x;
       }
@@ -280,7 +342,7 @@ k_ffno_zmix(const FfnoArgs a, const float2* __restrict__ Kz, const float2* __res
 }
 
 __global__ void __launch_bounds__(256)
-k_ffno_zidft(const FfnoArgs a, const float2* __restrict__ Z, const float2* __restrict__ twz,
+k_ffno_zidft(const FfnoArgs a, const float2* __restrict__ Z, const float2* __restrict__ pz,
              float* __restrict__ u) {
   const int64_t plane = (int64_t)a.ny * a.nx;
   const int64_t items = (int64_t)a.dv * plane;
@@ -290,22 +352,29 @@ k_ffno_zidft(const FfnoArgs a, const float2* __restrict__ Z, const float2* __res
        q += (int64_t)gridDim.x * blockDim.x) {
     const int64_t o = q / plane, col = q % plane;
     const float2* zs = Z + o * mz * plane + col;
-    float2 zk[16];
+    float2 zk[kZPow];
 #pragma unroll
-    for (int kz = 0; kz < 16; ++kz) zk[kz] = kz < mz ? zs[(int64_t)kz * plane] : make_float2(0.f, 0.f);
+    for (int kz = 0; kz < kZPow; ++kz) zk[kz] = kz < mz ? zs[(int64_t)kz * plane] : make_float2(0.f, 0.f);
     float* dst = u + o * plane * nz + col;
-    for (int z = 0; z < nz; ++z) {
-      float acc = zk[0].x;
-      const float2 w1 = twz[z];
-      float2 p = w1;
+    for (int z0 = 0; z0 < nz; z0 += 4) {
+      float old[4];
 #pragma unroll
-      for (int kz = 1; kz < 16; ++kz) {
-        if (kz < mz) {
-          acc += 2.0f * (zk[kz].x * p.x - zk[kz].y * p.y);
-          p = cmul2(p, w1);
+      for (int j = 0; j < 4; ++j) old[j] = (z0 + j < nz) ? dst[(int64_t)(z0 + j) * plane] : 0.f;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        if (z0 + j < nz) {
+          const float2* pw = pz + (z0 + j) * kZPow;
+          float acc = zk[0].x;
+#pragma unroll
+          for (int kz = 1; kz < kZPow; ++kz) {
+            if (kz < mz) {
+              const float2 p = pw[kz];
+              acc += 2.0f * (zk[kz].x * p.x - zk[kz].y * p.y);
+            }
+          }
+          dst[(int64_t)(z0 + j) * plane] = old[j] + acc * inz;
         }
       }
-      dst[(int64_t)z * plane] += acc * inz;
     }
   }
 }
@@ -384,11 +453,11 @@ hipError_t axial_mlp_launch(const FfnoArgs& a, const FfnoPtrs& w, int layer, int
   const int64_t plane = (int64_t)a.ny * a.nx;
   const int64_t vox = plane * a.nz;
   hipLaunchKernelGGL(k_ffno_zdft, dim3(grid_for((int64_t)DV * plane)), dim3(256), 0, st, a, w.u,
-                     w.twz, w.W);
-  hipLaunchKernelGGL((k_ffno_zmix<DV>), dim3(grid_for((int64_t)a.mz * plane)), dim3(256), 0, st, a,
-                     w.Kz[layer], w.W, w.Z);
+                     w.pz, w.W);
+  hipLaunchKernelGGL((k_ffno_zmix<DV>), dim3(grid_for(plane), (unsigned)a.mz), dim3(256), 0, st, a,
+                     w.KzT + (size_t)layer * a.mz * DV * DV, w.W, w.Z);
   hipLaunchKernelGGL(k_ffno_zidft, dim3(grid_for((int64_t)DV * plane)), dim3(256), 0, st, a, w.Z,
-                     w.twz, w.u);
+                     w.pz, w.u);
   hipLaunchKernelGGL((k_ffno_mlp<DV, DH>), dim3(grid_for(vox)), dim3(256), 0, st, a, w.u, w.v,
                      w.W1[layer], w.b1[layer], w.W2T + (size_t)layer * DV * DH, w.b2[layer], last);
   return hipGetLastError();
@@ -401,14 +470,17 @@ hipError_t ffno_forward(const FfnoArgs& a, const FfnoPtrs& w, const float* in, c
   hipLaunchKernelGGL(k_ffno_twiddles, dim3((a.nx + 255) / 256), dim3(256), 0, st, w.twx, a.nx);
   hipLaunchKernelGGL(k_ffno_twiddles, dim3((a.ny + 255) / 256), dim3(256), 0, st, w.twy, a.ny);
   hipLaunchKernelGGL(k_ffno_twiddles, dim3((a.nz + 255) / 256), dim3(256), 0, st, w.twz, a.nz);
-  for (int l = 0; l < a.nl; ++l)
+  hipLaunchKernelGGL(k_ffno_zpowers, dim3((a.nz + 255) / 256), dim3(256), 0, st, w.twz, a.nz, a.mz,
+                     w.pz);
+  for (int l = 0; l < a.nl; ++l) {
     hipLaunchKernelGGL(k_ffno_transpose, dim3((a.dv * a.dh + 255) / 256), dim3(256), 0, st,
                        w.W2[l], a.dv, a.dh, w.W2T + (size_t)l * a.dv * a.dh);
+    hipLaunchKernelGGL(k_ffno_kz_major, dim3((a.dv * a.dv * a.mz + 255) / 256), dim3(256), 0, st,
+                       w.Kz[l], a.dv, a.mz, w.KzT + (size_t)l * a.mz * a.dv * a.dv);
+  }
   const int64_t vox = (int64_t)a.nz * a.ny * a.nx;
   hipLaunchKernelGGL(k_ffno_lift, dim3(grid_for(vox)), dim3(256), 0, st, a, w.P, w.p, in, w.v);
   const int64_t nrows = (int64_t)a.dv * a.nz * a.ny;
-  const int Ri = std::max(1, 2048 / a.nx);  // rows per block of the inverse x pass
-  const size_t xidft_shm = sizeof(float2) * ((size_t)Ri * a.mx + (a.nx <= 2048 ? a.nx : 0));
   for (int l = 0; l < a.nl; ++l) {
     const dim3 gx((unsigned)((nrows + 255) / 256));
     if (a.mx <= 16)
@@ -421,8 +493,11 @@ hipError_t ffno_forward(const FfnoArgs& a, const FfnoPtrs& w, const float* in, c
                        dim3(256), 0, st, a, w.Kxy[l], w.G, w.U);
     hipLaunchKernelGGL(k_ffno_yidft, dim3(grid_for((int64_t)a.dv * a.nz * a.ny * a.mx)), dim3(256),
                        0, st, a, w.U, w.twy, w.T);
-    hipLaunchKernelGGL(k_ffno_xidft, dim3((unsigned)((nrows + Ri - 1) / Ri)), dim3(256), xidft_shm,
-                       st, a, w.T, w.twx, w.u, nrows, Ri);
+    const dim3 gi((unsigned)((nrows + kXidftRows - 1) / kXidftRows));
+    if (a.mx <= 16)
+      hipLaunchKernelGGL(k_ffno_xidft<16>, gi, dim3(256), 0, st, a, w.T, w.twx, w.u, nrows);
+    else
+      hipLaunchKernelGGL(k_ffno_xidft<32>, gi, dim3(256), 0, st, a, w.T, w.twx, w.u, nrows);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const int last = l == a.nl - 1;

@@ -211,6 +211,8 @@ struct FfnoPtrs {
   const float *W1[kFfnoMaxLayers], *b1[kFfnoMaxLayers], *W2[kFfnoMaxLayers], *b2[kFfnoMaxLayers];
   float *v, *u;            // hidden state and lateral-branch output, [dv][nz][ny][nx]
   float* W2T;              // [nl][dh][dv] transposed MLP output weights
+  float2* KzT;             // [nl][mz][dv][dv] axial mixing weights, kz-major
+  float2* pz;              // [nz][16] powers w^(kz z) of the axial transforms
   float2 *T, *G, *U;       // [dv][nz][ny][mx], [dv][nz][my][mx] x 2
   float2 *W, *Z;           // axial spectra before / after mixing, [dv][mz][ny][nx] each
   float2 *twx, *twy, *twz; // e^{+2 pi i k / n}

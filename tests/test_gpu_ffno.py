@@ -3,7 +3,8 @@ section 2.1) against the oracle, with seeded random weights (no trained
 weights exist here) shared by both sides as FP32 values.
 
 * grids with non-power-of-two and unequal sizes, all three (d_v, d_h) pairs,
-  one to four layers, asymmetric mode counts;
+  one to four layers, asymmetric mode counts, ragged row blocks and odd nz,
+  kx_max above 15;
 * output E (complex128, the solver's layout) within 2e-5 of max |E| (FP32
   hidden state and transforms, FP64 oracle);
 * the prediction serves as the solver's warm start: a solve from it reaches
@@ -42,6 +43,10 @@ CASES = [
     dict(nx=64, ny=48, nz=32, d_v=16, d_h=32, n_layers=3, kx_max=8, ky_max=6, kz_max=5),
     dict(nx=80, ny=72, nz=48, d_v=32, d_h=64, n_layers=4, kx_max=12, ky_max=12, kz_max=8),
     dict(nx=40, ny=36, nz=100, d_v=32, d_h=64, n_layers=1, kx_max=5, ky_max=7, kz_max=15),
+    # row counts (d_v nz ny) that leave ragged x-pass blocks, odd nz (the axial passes take
+    # four z rows at a time), kx_max > 15 (the wider x kernels)
+    dict(nx=30, ny=18, nz=11, d_v=8, d_h=16, n_layers=2, kx_max=4, ky_max=3, kz_max=2),
+    dict(nx=70, ny=22, nz=13, d_v=16, d_h=32, n_layers=1, kx_max=20, ky_max=5, kz_max=6),
 ]
 
 
