@@ -57,68 +57,95 @@ __device__ __forceinline__ float2 cmul2(float2 a, float2 b) {
   return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
 
-// T[row][kx] for rows of v (row = (c, z, y)): one thread per row, the block's
-// 256 rows staged in LDS 32 samples at a time (pitch 33 floats: the lanes of
-// a wave read distinct banks).  The powers w^(kx x), kx = 0..mx-1, depend on
-// x only: for each chunk of 32 samples one wave forms them once for the
-// whole block (from the table value w^x by repeated multiplication) and every
-// row reads them as LDS broadcasts; every kx is accumulated in registers.
+// T[row][kx] = sum_x v[row][x] w^(-kx x), w = e^{2 pi i / nx}, rows of v
+// (row = (c, z, y)).  kXL lanes share a row (a wave takes 64 / kXL rows and
+// reads each of them front to back) and lane l sums the samples
+// x = l + kXL j.  The power splits as w^(kx x) = w^(kx l) w^(kx kXL j): the
+// second factor is the same for the whole wave and comes from a table
+// (qx[j][kx], exact twiddles) read as scalar loads (whole table rows), so a
+// sample costs two multiply-adds per kx,
+//   S_l[kx] = sum_j v(l + kXL j) conj(qx[j][kx]);
+// each lane then applies its own conj(w^(kx l)) once per row and the kXL
+// lanes are summed by butterflies.  The loads of kXB samples per lane are
+// issued together.  The inner loop carries no bounds tests: the table is
+// padded to whole batches, samples past the row end are loaded in bounds and
+// multiplied by zero, and all MXM modes are summed (the ones at or above mx
+// are not stored).
+constexpr int kXL = 16;
+constexpr int kXB = 4;
+
+__host__ __device__ constexpr int xdft_table_rows(int nx) {
+  return ((nx + kXL - 1) / kXL + kXB - 1) / kXB * kXB;
+}
+
+__global__ void k_ffno_xpowers(const float2* __restrict__ twx, int nx, int mxm,
+                               float2* __restrict__ qx) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= xdft_table_rows(nx) * mxm) return;
+  const int j = e / mxm, kx = e % mxm;
+  qx[e] = twx[(int)(((int64_t)kx * kXL * j) % nx)];
+}
+
 template <int MXM>
 __global__ void __launch_bounds__(256) k_ffno_xdft(const FfnoArgs a, const float* __restrict__ v,
                                                    const float2* __restrict__ twx,
+                                                   const float2* __restrict__ qx,
                                                    float2* __restrict__ T, int64_t nrows) {
-  constexpr int ROWS = 256, CH = 32, PITCH = CH + 1;
-  __shared__ float tile[ROWS * PITCH];
-  __shared__ float2 pw[CH * MXM];
-  const int64_t r0 = (int64_t)blockIdx.x * ROWS;
-  const int nr = (int)min((int64_t)ROWS, nrows - r0);
-  const int nx = a.nx, mx = a.mx, t = threadIdx.x;
-  float re[MXM], im[MXM];
+  constexpr int RPB = 256 / kXL;  // rows per block and step
+  const int nx = a.nx, mx = a.mx;
+  const int l = threadIdx.x % kXL;
+  const int nj = (nx + kXL - 1) / kXL;
+  float2 pl[MXM];  // w^(kx l), the same for every row this thread takes
 #pragma unroll
-  for (int k = 0; k < MXM; ++k) re[k] = im[k] = 0.f;
-  for (int x0 = 0; x0 < nx; x0 += CH) {
-    const int nc = min(CH, nx - x0);
-    __syncthreads();
-    if (nc == CH) {
-      for (int e = t; e < nr * CH; e += ROWS) {
-        const int r = e / CH, c = e % CH;
-        tile[r * PITCH + c] = v[(r0 + r) * nx + x0 + c];
+  for (int k = 0; k < MXM; ++k) pl[k] = k < mx ? twx[(k * l) % nx] : make_float2(1.f, 0.f);
+  for (int64_t base = (int64_t)blockIdx.x * RPB; base < nrows; base += (int64_t)gridDim.x * RPB) {
+    const int64_t row = base + threadIdx.x / kXL;
+    const bool live = row < nrows;
+    const float* src = v + (live ? row : 0) * nx;
+    float sr[MXM], si[MXM];
+#pragma unroll
+    for (int k = 0; k < MXM; ++k) sr[k] = si[k] = 0.f;
+    for (int j0 = 0; j0 < nj; j0 += kXB) {
+      float val[kXB];
+#pragma unroll
+      for (int u = 0; u < kXB; ++u) {  // in-bounds load times a 0/1 mask: no branch
+        const int x = l + kXL * (j0 + u);
+        val[u] = src[min(x, nx - 1)] * ((live && x < nx) ? 1.f : 0.f);
       }
-    } else {
-      for (int e = t; e < nr * nc; e += ROWS) {
-        const int r = e / nc, c = e % nc;
-        tile[r * PITCH + c] = v[(r0 + r) * nx + x0 + c];
-      }
-    }
-    if (t < nc) {
-      const float2 w1 = twx[x0 + t];  // e^{+i 2 pi x / nx}
-      float2 p = make_float2(1.f, 0.f);
-      for (int k = 0; k < mx; ++k) {
-        pw[t * MXM + k] = p;
-        p = cmul2(p, w1);
-      }
-    }
-    __syncthreads();
-    if (t < nr) {
-      for (int c = 0; c < nc; ++c) {
-        const float val = tile[t * PITCH + c];
-        const float2* pc = pw + c * MXM;
+      // the table row is the same for the whole wave: scalar loads
+      const int jq = __builtin_amdgcn_readfirstlane(j0);
+#pragma unroll
+      for (int u = 0; u < kXB; ++u) {
+        const float2* q = qx + (jq + u) * MXM;
 #pragma unroll
         for (int k = 0; k < MXM; ++k) {
-          if (k < mx) {
-            const float2 p = pc[k];
-            re[k] += val * p.x;  // the forward sum takes the conjugate power
-            im[k] -= val * p.y;
-          }
+          const float2 w = q[k];
+          sr[k] += val[u] * w.x;  // the forward sum takes the conjugate power
+          si[k] -= val[u] * w.y;
         }
       }
     }
-  }
-  if (t < nr) {
 #pragma unroll
-    for (int k = 0; k < MXM; ++k)
-      if (k < mx) T[(r0 + t) * mx + k] = make_float2(re[k], im[k]);
+    for (int k = 0; k < MXM; ++k) {
+      if (k < mx) {
+        // conj(w^(kx l)) S_l, then the sum over the kXL lanes of the row
+        float re = pl[k].x * sr[k] + pl[k].y * si[k];
+        float im = pl[k].x * si[k] - pl[k].y * sr[k];
+#pragma unroll
+        for (int off = 1; off < kXL; off <<= 1) {
+          re += __shfl_xor(re, off, kXL);
+          im += __shfl_xor(im, off, kXL);
+        }
+        if (live && (k % kXL) == l) T[row * mx + k] = make_float2(re, im);
+      }
+    }
   }
+}
+
+template <int MXM>
+void xdft_launch(const FfnoArgs& a, const FfnoPtrs& w, int64_t nrows, hipStream_t st) {
+  const dim3 g((unsigned)std::min<int64_t>((nrows + 15) / 16, 16384));
+  hipLaunchKernelGGL((k_ffno_xdft<MXM>), g, dim3(256), 0, st, a, w.v, w.twx, w.qx, w.T, nrows);
 }
 
 // G[c][z][m][kx] = sum_y T[c][z][y][kx] e^{-2 pi i ky y / ny}
@@ -195,48 +222,53 @@ __global__ void k_ffno_yidft(const FfnoArgs a, const float2* __restrict__ U,
 }
 
 // u[o][z][y][x] = (Re T2[..][0] + 2 sum_{kx>0} Re(T2[..][kx] e^{+2 pi i kx x / nx})) / (nx ny)
-// One block per XR rows (row = (o, z, y)), their spectra staged in LDS; a
-// thread takes columns x, forms the powers w^(kx x) once in registers
-// (repeated multiplication of the table value w^x) and applies them to every
-// row of the block, reading the spectra as LDS broadcasts; stores are
-// coalesced along x.
-constexpr int kXidftRows = 32;
+// With the split of the x DFT (kXL lanes per row, lane l writes x = l + kXL j,
+// w^(kx x) = w^(kx l) w^(kx kXL j)), each lane forms R_l[kx] = T2[kx] w^(kx l)
+// (doubled for kx > 0) once per row; an output sample then costs two
+// multiply-adds per kx with the wave-uniform table value qx[j][kx] (scalar
+// loads, the table of the forward pass):
+//   u(l + kXL j) = (Re R_l[0] + sum_{kx>0} Re(R_l[kx] qx[j][kx])) / (nx ny).
+// Modes at and above mx have R = 0; the stores are masked at the row end.
 template <int MXM>
 __global__ void __launch_bounds__(256) k_ffno_xidft(const FfnoArgs a, const float2* __restrict__ T2,
                                                     const float2* __restrict__ twx,
+                                                    const float2* __restrict__ qx,
                                                     float* __restrict__ u, int64_t nrows) {
-  __shared__ float2 sp[kXidftRows * MXM];
-  const int mx = a.mx, nx = a.nx;
-  const int64_t r0 = (int64_t)blockIdx.x * kXidftRows;
-  const int nr = (int)min((int64_t)kXidftRows, nrows - r0);
-  for (int e = threadIdx.x; e < nr * mx; e += blockDim.x) {
-    const int rr = e / mx, k = e % mx;
-    sp[rr * MXM + k] = T2[(r0 + rr) * mx + k];
-  }
-  __syncthreads();
+  constexpr int RPB = 256 / kXL;  // rows per block and step
+  const int nx = a.nx, mx = a.mx;
+  const int l = threadIdx.x % kXL;
+  const int nj = (nx + kXL - 1) / kXL;
   const float norm = 1.0f / ((float)nx * (float)a.ny);
-  for (int x = threadIdx.x; x < nx; x += blockDim.x) {
-    const float2 w1 = twx[x];  // e^{+i 2 pi x / nx}
-    float2 pk[MXM];
-    float2 p = w1;
+  float2 pl[MXM];  // w^(kx l)
 #pragma unroll
-    for (int k = 1; k < MXM; ++k) {
-      if (k < mx) {
-        pk[k] = p;
-        p = cmul2(p, w1);
-      }
+  for (int k = 0; k < MXM; ++k) pl[k] = k < mx ? twx[(k * l) % nx] : make_float2(0.f, 0.f);
+  for (int64_t base = (int64_t)blockIdx.x * RPB; base < nrows; base += (int64_t)gridDim.x * RPB) {
+    const int64_t row = base + threadIdx.x / kXL;
+    const bool live = row < nrows;
+    const float2* t = T2 + (live ? row : 0) * mx;
+    float rr[MXM], ri[MXM];
+#pragma unroll
+    for (int k = 0; k < MXM; ++k) {
+      const float2 tv = k < mx ? t[k] : make_float2(0.f, 0.f);
+      const float f = k == 0 ? 1.f : 2.f;
+      rr[k] = f * (tv.x * pl[k].x - tv.y * pl[k].y);
+      ri[k] = f * (tv.x * pl[k].y + tv.y * pl[k].x);
     }
-    for (int rr = 0; rr < nr; ++rr) {
-      const float2* t = sp + rr * MXM;
-      float acc = t[0].x;
+    float* dst = u + (live ? row : 0) * nx;
+    for (int j0 = 0; j0 < nj; j0 += kXB) {
+      const int jq = __builtin_amdgcn_readfirstlane(j0);  // wave-uniform: scalar table loads
 #pragma unroll
-      for (int k = 1; k < MXM; ++k) {
-        if (k < mx) {
-          const float2 sv = t[k];
-          acc += 2.0f * (sv.x * pk[k].x - sv.y * pk[k].y);
+      for (int uu = 0; uu < kXB; ++uu) {
+        const float2* q = qx + (jq + uu) * MXM;
+        float acc = rr[0];  // qx[j][0] = 1
+#pragma unroll
+        for (int k = 1; k < MXM; ++k) {
+          const float2 w = q[k];
+          acc += rr[k] * w.x - ri[k] * w.y;
         }
+        const int x = l + kXL * (j0 + uu);
+        if (live && x < nx) dst[x] = acc * norm;
       }
-      u[(r0 + rr) * nx + x] = acc * norm;
     }
   }
 }
@@ -255,11 +287,16 @@ __global__ void __launch_bounds__(256) k_ffno_xidft(const FfnoArgs a, const floa
 // are issued together.
 constexpr int kZPow = 16;  // row stride of the power table (kz_max <= 15)
 
+constexpr int kZB = 4;  // z rows per batch of column loads
+__host__ __device__ constexpr int zdft_table_rows(int nz) { return (nz + kZB - 1) / kZB * kZB; }
+
+// pz[z][kz] = w^(kz z) for kz < mz (the last power repeated above), rows up to
+// a whole batch (rows past nz hold finite values that meet zero samples)
 __global__ void k_ffno_zpowers(const float2* __restrict__ twz, int nz, int mz,
                                float2* __restrict__ pz) {
   const int z = blockIdx.x * blockDim.x + threadIdx.x;
-  if (z >= nz) return;
-  const float2 w1 = twz[z];
+  if (z >= zdft_table_rows(nz)) return;
+  const float2 w1 = z < nz ? twz[z] : make_float2(1.f, 0.f);
   float2 p = make_float2(1.f, 0.f);
   for (int kz = 0; kz < kZPow; ++kz) {
     pz[z * kZPow + kz] = p;
@@ -288,22 +325,18 @@ k_ffno_zdft(const FfnoArgs a, const float* __restrict__ u, const float2* __restr
     float2 acc[kZPow];
 #pragma unroll
     for (int kz = 0; kz < kZPow; ++kz) acc[kz] = make_float2(0.f, 0.f);
-    for (int z0 = 0; z0 < nz; z0 += 4) {
-      float val[4];
+    for (int z0 = 0; z0 < nz; z0 += kZB) {
+      float val[kZB];
 #pragma unroll
-      for (int j = 0; j < 4; ++j) val[j] = (z0 + j < nz) ? src[(int64_t)(z0 + j) * plane] : 0.f;
+      for (int j = 0; j < kZB; ++j) val[j] = (z0 + j < nz) ? src[(int64_t)(z0 + j) * plane] : 0.f;
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        if (z0 + j < nz) {
-          const float2* pw = pz + (z0 + j) * kZPow;
+      for (int j = 0; j < kZB; ++j) {
+        const float2* pw = pz + (z0 + j) * kZPow;
 #pragma unroll
-          for (int kz = 0; kz < kZPow; ++kz) {
-            if (kz < mz) {
-              const float2 p = pw[kz];
-              acc[kz].x += val[j] * p.x;
-              acc[kz].y -= val[j] * p.y;
-            }
-          }
+        for (int kz = 0; kz < kZPow; ++kz) {  // every row entry: no bounds tests in the loop
+          const float2 p = pw[kz];
+          acc[kz].x += val[j] * p.x;
+          acc[kz].y -= val[j] * p.y;
         }
       }
     }
@@ -356,24 +389,20 @@ k_ffno_zidft(const FfnoArgs a, const float2* __restrict__ Z, const float2* __res
 #pragma unroll
     for (int kz = 0; kz < kZPow; ++kz) zk[kz] = kz < mz ? zs[(int64_t)kz * plane] : make_float2(0.f, 0.f);
     float* dst = u + o * plane * nz + col;
-    for (int z0 = 0; z0 < nz; z0 += 4) {
-      float old[4];
+    for (int z0 = 0; z0 < nz; z0 += kZB) {
+      float old[kZB];
 #pragma unroll
-      for (int j = 0; j < 4; ++j) old[j] = (z0 + j < nz) ? dst[(int64_t)(z0 + j) * plane] : 0.f;
+      for (int j = 0; j < kZB; ++j) old[j] = (z0 + j < nz) ? dst[(int64_t)(z0 + j) * plane] : 0.f;
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        if (z0 + j < nz) {
-          const float2* pw = pz + (z0 + j) * kZPow;
-          float acc = zk[0].x;
+      for (int j = 0; j < kZB; ++j) {
+        const float2* pw = pz + (z0 + j) * kZPow;
+        float acc = zk[0].x;
 #pragma unroll
-          for (int kz = 1; kz < kZPow; ++kz) {
-            if (kz < mz) {
-              const float2 p = pw[kz];
-              acc += 2.0f * (zk[kz].x * p.x - zk[kz].y * p.y);
-            }
-          }
-          dst[(int64_t)(z0 + j) * plane] = old[j] + acc * inz;
+        for (int kz = 1; kz < kZPow; ++kz) {  // zk is zero at and above mz
+          const float2 p = pw[kz];
+          acc += 2.0f * (zk[kz].x * p.x - zk[kz].y * p.y);
         }
+        if (z0 + j < nz) dst[(int64_t)(z0 + j) * plane] = old[j] + acc * inz;
       }
     }
   }
@@ -470,8 +499,13 @@ hipError_t ffno_forward(const FfnoArgs& a, const FfnoPtrs& w, const float* in, c
   hipLaunchKernelGGL(k_ffno_twiddles, dim3((a.nx + 255) / 256), dim3(256), 0, st, w.twx, a.nx);
   hipLaunchKernelGGL(k_ffno_twiddles, dim3((a.ny + 255) / 256), dim3(256), 0, st, w.twy, a.ny);
   hipLaunchKernelGGL(k_ffno_twiddles, dim3((a.nz + 255) / 256), dim3(256), 0, st, w.twz, a.nz);
-  hipLaunchKernelGGL(k_ffno_zpowers, dim3((a.nz + 255) / 256), dim3(256), 0, st, w.twz, a.nz, a.mz,
-                     w.pz);
+  {
+    const int mxm = a.mx <= 16 ? 16 : 32, nj = xdft_table_rows(a.nx);
+    hipLaunchKernelGGL(k_ffno_xpowers, dim3((nj * mxm + 255) / 256), dim3(256), 0, st, w.twx, a.nx,
+                       mxm, w.qx);
+  }
+  hipLaunchKernelGGL(k_ffno_zpowers, dim3((zdft_table_rows(a.nz) + 255) / 256), dim3(256), 0, st,
+                     w.twz, a.nz, a.mz, w.pz);
   for (int l = 0; l < a.nl; ++l) {
     hipLaunchKernelGGL(k_ffno_transpose, dim3((a.dv * a.dh + 255) / 256), dim3(256), 0, st,
                        w.W2[l], a.dv, a.dh, w.W2T + (size_t)l * a.dv * a.dh);
@@ -482,22 +516,19 @@ hipError_t ffno_forward(const FfnoArgs& a, const FfnoPtrs& w, const float* in, c
   hipLaunchKernelGGL(k_ffno_lift, dim3(grid_for(vox)), dim3(256), 0, st, a, w.P, w.p, in, w.v);
   const int64_t nrows = (int64_t)a.dv * a.nz * a.ny;
   for (int l = 0; l < a.nl; ++l) {
-    const dim3 gx((unsigned)((nrows + 255) / 256));
-    if (a.mx <= 16)
-      hipLaunchKernelGGL(k_ffno_xdft<16>, gx, dim3(256), 0, st, a, w.v, w.twx, w.T, nrows);
-    else
-      hipLaunchKernelGGL(k_ffno_xdft<32>, gx, dim3(256), 0, st, a, w.v, w.twx, w.T, nrows);
+    if (a.mx <= 16) xdft_launch<16>(a, w, nrows, st);
+    else xdft_launch<32>(a, w, nrows, st);
     hipLaunchKernelGGL(k_ffno_ydft, dim3(grid_for((int64_t)a.dv * a.nz * a.my * a.mx)), dim3(256),
                        0, st, a, w.T, w.twy, w.G);
     hipLaunchKernelGGL(k_ffno_mix_xy, dim3(grid_for((int64_t)a.dv * a.nz * a.my * a.mx)),
                        dim3(256), 0, st, a, w.Kxy[l], w.G, w.U);
     hipLaunchKernelGGL(k_ffno_yidft, dim3(grid_for((int64_t)a.dv * a.nz * a.ny * a.mx)), dim3(256),
                        0, st, a, w.U, w.twy, w.T);
-    const dim3 gi((unsigned)((nrows + kXidftRows - 1) / kXidftRows));
+    const dim3 gi((unsigned)std::min<int64_t>((nrows + 15) / 16, 16384));
     if (a.mx <= 16)
-      hipLaunchKernelGGL(k_ffno_xidft<16>, gi, dim3(256), 0, st, a, w.T, w.twx, w.u, nrows);
+      hipLaunchKernelGGL(k_ffno_xidft<16>, gi, dim3(256), 0, st, a, w.T, w.twx, w.qx, w.u, nrows);
     else
-      hipLaunchKernelGGL(k_ffno_xidft<32>, gi, dim3(256), 0, st, a, w.T, w.twx, w.u, nrows);
+      hipLaunchKernelGGL(k_ffno_xidft<32>, gi, dim3(256), 0, st, a, w.T, w.twx, w.qx, w.u, nrows);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const int last = l == a.nl - 1;
