@@ -115,7 +115,6 @@ k_finalize(KState* ks_all, const double* __restrict__ part_all, int nblocks,
     ks->tol2 = q.tol2;
     ks->itmax = (int)q.itmax;
     ks->delta2 = q.delta2;
-    ks->rmax2 = acc[0];
     ks->rfold2 = acc[0];
     ks->done = (q.tol2 < 0.0) ? KS_IDLE : (ks->itmax <= 0 ? KS_MAXIT : KS_RUN);
     ks->half = 0;
@@ -192,15 +191,13 @@ k_finalize(KState* ks_all, const double* __restrict__ part_all, int nblocks,
           !(sqrt(norm2(rho_new)) > 1e-30 * sqrt(ks->rh_norm2 * acc[0]))) {
         ks->status = 1;
         ks->done = KS_BREAK;
-      } else if (ks->delta2 > 0.0 && acc[0] <= ks->delta2 * ks->rmax2) {
+      } else if (ks->delta2 > 0.0 && acc[0] <= ks->delta2 * ks->rfold2) {
         ks->done = KS_UPDATE;
       }
     }
-    if (acc[0] > ks->rmax2) ks->rmax2 = acc[0];
   } else if constexpr (STAGE == FIN_REPLACE) {
     // r was replaced by the true residual (host): partials ||r||^2, <rh, r>
     ks->rnorm2 = acc[0];
-    ks->rmax2 = acc[0];
     ks->rfold2 = acc[0];
     st2(ks->rho, cplx<double>{acc[1], acc[2]});
     ks->done = (acc[0] <= ks->tol2 * ks->bnorm2) ? KS_CONV : KS_RUN;
