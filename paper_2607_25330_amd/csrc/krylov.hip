@@ -33,6 +33,16 @@
 namespace psfd {
 
 constexpr double kOmegaLimit = 0.7;
+// Reliable updates are due when the recursive residual has fallen by the
+// factor delta below its value at the run's start or last replacement, or,
+// after a spike of more than sqrt(kSpike2) over that value, by delta below
+// the spike (the rounding gap between the recursive and the true residual
+// grows with the largest residual seen, so a large spike calls for an
+// earlier replacement).  Measured on the benchmark clips and the batched
+// uneven workload: the spike rule alone (van der Vorst and Ye's running
+// maximum) fires updates that the fold check rejects, the progress rule
+// alone lets the gap grow on the small grids; together they keep both.
+constexpr double kSpike2 = 10.0;
 
 int red_blocks(int64_t n, int nprob) {
   // at most 8192 blocks per problem (enough waves in flight to keep the
@@ -115,6 +125,7 @@ k_finalize(KState* ks_all, const double* __restrict__ part_all, int nblocks,
     ks->tol2 = q.tol2;
     ks->itmax = (int)q.itmax;
     ks->delta2 = q.delta2;
+    ks->rmax2 = acc[0];
     ks->rfold2 = acc[0];
     ks->done = (q.tol2 < 0.0) ? KS_IDLE : (ks->itmax <= 0 ? KS_MAXIT : KS_RUN);
     ks->half = 0;
@@ -191,13 +202,17 @@ k_finalize(KState* ks_all, const double* __restrict__ part_all, int nblocks,
           !(sqrt(norm2(rho_new)) > 1e-30 * sqrt(ks->rh_norm2 * acc[0]))) {
         ks->status = 1;
         ks->done = KS_BREAK;
-      } else if (ks->delta2 > 0.0 && acc[0] <= ks->delta2 * ks->rfold2) {
+      } else if (ks->delta2 > 0.0 &&
+                 (acc[0] <= ks->delta2 * ks->rfold2 ||
+                  (ks->rmax2 >= kSpike2 * ks->rfold2 && acc[0] <= ks->delta2 * ks->rmax2))) {
         ks->done = KS_UPDATE;
       }
     }
+    if (acc[0] > ks->rmax2) ks->rmax2 = acc[0];
   } else if constexpr (STAGE == FIN_REPLACE) {
     // r was replaced by the true residual (host): partials ||r||^2, <rh, r>
     ks->rnorm2 = acc[0];
+    ks->rmax2 = acc[0];
     ks->rfold2 = acc[0];
     st2(ks->rho, cplx<double>{acc[1], acc[2]});
     ks->done = (acc[0] <= ks->tol2 * ks->bnorm2) ? KS_CONV : KS_RUN;

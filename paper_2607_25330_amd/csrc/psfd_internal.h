@@ -234,8 +234,8 @@ struct KState {
   double rv[2], ts[2], tt;
   double snorm2, rnorm2, bnorm2, tol2, rh_norm2;
   double red[4];        // generic reduction outputs
-  double delta2;  // reliable updates: due once ||r||^2 <= delta2 rfold2
-  double rfold2;  // ||r||^2 at the run's start or its last residual replacement
+  double rmax2, delta2;  // reliable updates: max ||r||^2 since the last one, trigger factor
+  double rfold2;         // ||r||^2 at the run's start or its last residual replacement
   int iter, done, status, half;
   int itmax, pad;
 };
