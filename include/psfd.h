@@ -221,7 +221,11 @@ psfd_status psfd_pino_loss(psfd_plan_t p, const void* E, double w0, double eta_h
  * PSFD_GROUP_VOXELS / PSFD_GROUP_MAX in the environment): every kernel launch
  * covers the whole group, each problem keeps its own Krylov scalars and
  * refinement and stops on its own, and a 16-iteration chunk of the group is
- * captured once as a HIP graph and replayed.  Each group's kernel schedules
+ * captured once as a HIP graph and replayed.  Mixed-precision groups of more
+ * than one problem refine by restarts (inner runs to a loose tolerance, then
+ * an FP64 fold and a fresh start) instead of the reliable updates of a
+ * single-problem solve, whose host round trips would stop every member;
+ * PSFD_RELIABLE=0 / 1 selects one form for all plans.  Each group's kernel schedules
  * come from the autotuner (psfd_tune; PSFD_TUNE=0 disables).  Groups run on a
  * pool of PSFD_BATCH_WORKERS host threads (default 2), each with its own
  * non-blocking stream.  x0 may be NULL (all zero) or hold NULL entries;

@@ -66,15 +66,19 @@ def test_batch_matches_individual_solves(psfd, prec, monkeypatch):
         assert torch.equal(E_b[i], E_i)
 
 
-@pytest.mark.parametrize("prec", [0, 1])
-def test_group_of_same_shape_problems_matches_individual_solves(psfd, prec, monkeypatch):
+@pytest.mark.parametrize("prec,form", [(0, None), (1, "0"), (1, "1")])
+def test_group_of_same_shape_problems_matches_individual_solves(psfd, prec, form, monkeypatch):
     """Six 32x32x(16+16) problems (different angles, polarisations and
     permittivities, one with a warm start) share one group plan: every launch
     covers all six, each keeps its own Krylov scalars and stops on its own.
     Up to 16 problems a group uses the same per-problem block decomposition
     as a single solve, so the results are bit-identical (with the default
-    kernel schedules: the autotuner is switched off here)."""
+    kernel schedules: the autotuner is switched off here).  Mixed plans take
+    the restart form in groups and reliable updates alone, so the mixed case
+    pins one form for both sides (PSFD_RELIABLE), each form in turn."""
     monkeypatch.setenv("PSFD_TUNE", "0")
+    if form is not None:
+        monkeypatch.setenv("PSFD_RELIABLE", form)
     thetas = [0.0, 2.5, 5.0, 7.5, 10.0, 6.0]
     cfgs = [dict(base_config(32, 32, 16, 30.0, theta_deg=th, phi_deg=15.0 * i, pol=i % 2),
                  ml_kz_min=0.1) for i, th in enumerate(thetas)]
