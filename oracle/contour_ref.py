@@ -21,7 +21,7 @@ What it computes:
   demagnification of a 0.33-NA EUV system for wafer-scale numbers; a
   reference segment with no counterpart is "unresolved".
 
-Readings where the paper is silent (listed in the design notes):
+Readings where the paper is silent:
 the lines are periodic (the mask cell is periodic); whether a sample is
 above threshold is decided on I > I_th (no rounding of the sigmoid can flip
 it); the crossing between two samples is placed by linear interpolation of

@@ -29,8 +29,7 @@ warm-start" paragraph):
   relative_residual).
 
 Where the paper defers details to its companion PSFD paper (not available),
-the readings used here are listed in the repository's design notes; each is
-named where it is used (grid, PML, basis, TMM convention, ...).
+each reading used here is stated where it is used (grid, PML, basis, TMM convention, ...).
 
 Array layout: fields are complex arrays of shape (3, nz, ny, nx): component,
 axial row (bottom to top), y, x.  The permittivity is given on absorber
