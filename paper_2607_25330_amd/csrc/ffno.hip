@@ -142,10 +142,93 @@ __global__ void __launch_bounds__(256) k_ffno_xdft(const FfnoArgs a, const float
   }
 }
 
+// The same sum with vector loads, for rows whose length is a multiple of 4
+// (16-byte aligned rows): lane l of a row reads the 4 samples
+// x = 64 j + 4 l + c, c = 0..3, in one load, and the power splits as
+// w^(kx x) = w^(4 kx l) w^(kx (64 j + c)); the second factor comes from the
+// table q4[4 j + c][kx] (scalar loads), the first is applied once per row.
+constexpr int kXB4 = 2;  // vector loads per lane issued together
+
+__host__ __device__ constexpr int xdft4_table_rows(int nx) {
+  return 4 * (((nx + 4 * kXL - 1) / (4 * kXL) + kXB4 - 1) / kXB4 * kXB4);
+}
+
+__global__ void k_ffno_xpowers4(const float2* __restrict__ twx, int nx, int mxm,
+                                float2* __restrict__ q4) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= xdft4_table_rows(nx) * mxm) return;
+  const int m = e / mxm, kx = e % mxm;
+  const int64_t x = 4 * (int64_t)kXL * (m / 4) + m % 4;
+  q4[e] = twx[(int)(((int64_t)kx * x) % nx)];
+}
+
+template <int MXM>
+__global__ void __launch_bounds__(256) k_ffno_xdft4(const FfnoArgs a, const float* __restrict__ v,
+                                                    const float2* __restrict__ twx,
+                                                    const float2* __restrict__ q4,
+                                                    float2* __restrict__ T, int64_t nrows) {
+  constexpr int RPB = 256 / kXL;
+  const int nx = a.nx, mx = a.mx;
+  const int l = threadIdx.x % kXL;
+  const int nj = (nx + 4 * kXL - 1) / (4 * kXL);
+  float2 pl[MXM];  // w^(4 kx l)
+#pragma unroll
+  for (int k = 0; k < MXM; ++k) pl[k] = k < mx ? twx[(4 * k * l) % nx] : make_float2(1.f, 0.f);
+  for (int64_t base = (int64_t)blockIdx.x * RPB; base < nrows; base += (int64_t)gridDim.x * RPB) {
+    const int64_t row = base + threadIdx.x / kXL;
+    const bool live = row < nrows;
+    const float* src = v + (live ? row : 0) * nx;
+    float sr[MXM], si[MXM];
+#pragma unroll
+    for (int k = 0; k < MXM; ++k) sr[k] = si[k] = 0.f;
+    for (int j0 = 0; j0 < nj; j0 += kXB4) {
+      float4 val[kXB4];
+#pragma unroll
+      for (int u = 0; u < kXB4; ++u) {  // in-bounds load times a 0/1 mask: no branch
+        const int x0 = 4 * l + 4 * kXL * (j0 + u);
+        const float4 t = *reinterpret_cast<const float4*>(src + min(x0, nx - 4));
+        const float m = (live && x0 < nx) ? 1.f : 0.f;
+        val[u] = make_float4(t.x * m, t.y * m, t.z * m, t.w * m);
+      }
+      const int jq = __builtin_amdgcn_readfirstlane(j0);  // wave-uniform: scalar table loads
+#pragma unroll
+      for (int u = 0; u < kXB4; ++u) {
+        const float vc[4] = {val[u].x, val[u].y, val[u].z, val[u].w};
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          const float2* q = q4 + (4 * (jq + u) + c) * MXM;
+#pragma unroll
+          for (int k = 0; k < MXM; ++k) {
+            const float2 w = q[k];
+            sr[k] += vc[c] * w.x;  // the forward sum takes the conjugate power
+            si[k] -= vc[c] * w.y;
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < MXM; ++k) {
+      if (k < mx) {
+        float re = pl[k].x * sr[k] + pl[k].y * si[k];
+        float im = pl[k].x * si[k] - pl[k].y * sr[k];
+#pragma unroll
+        for (int off = 1; off < kXL; off <<= 1) {
+          re += __shfl_xor(re, off, kXL);
+          im += __shfl_xor(im, off, kXL);
+        }
+        if (live && (k % kXL) == l) T[row * mx + k] = make_float2(re, im);
+      }
+    }
+  }
+}
+
 template <int MXM>
 void xdft_launch(const FfnoArgs& a, const FfnoPtrs& w, int64_t nrows, hipStream_t st) {
   const dim3 g((unsigned)std::min<int64_t>((nrows + 15) / 16, 16384));
-  hipLaunchKernelGGL((k_ffno_xdft<MXM>), g, dim3(256), 0, st, a, w.v, w.twx, w.qx, w.T, nrows);
+  if (a.nx % 4 == 0)
+    hipLaunchKernelGGL((k_ffno_xdft4<MXM>), g, dim3(256), 0, st, a, w.v, w.twx, w.q4, w.T, nrows);
+  else
+    hipLaunchKernelGGL((k_ffno_xdft<MXM>), g, dim3(256), 0, st, a, w.v, w.twx, w.qx, w.T, nrows);
 }
 
 // G[c][z][m][kx] = sum_y T[c][z][y][kx] e^{-2 pi i ky y / ny}
@@ -503,6 +586,11 @@ hipError_t ffno_forward(const FfnoArgs& a, const FfnoPtrs& w, const float* in, c
     const int mxm = a.mx <= 16 ? 16 : 32, nj = xdft_table_rows(a.nx);
     hipLaunchKernelGGL(k_ffno_xpowers, dim3((nj * mxm + 255) / 256), dim3(256), 0, st, w.twx, a.nx,
                        mxm, w.qx);
+    if (a.nx % 4 == 0) {
+      const int n4 = xdft4_table_rows(a.nx);
+      hipLaunchKernelGGL(k_ffno_xpowers4, dim3((n4 * mxm + 255) / 256), dim3(256), 0, st, w.twx,
+                         a.nx, mxm, w.q4);
+    }
   }
   hipLaunchKernelGGL(k_ffno_zpowers, dim3((zdft_table_rows(a.nz) + 255) / 256), dim3(256), 0, st,
                      w.twz, a.nz, a.mz, w.pz);

@@ -1749,7 +1749,7 @@ struct FfnoLayout {
   FfnoArgs a{};
   int64_t n_weights = 0;
   size_t off_v = 0, off_u = 0, off_T = 0, off_G = 0, off_U = 0, off_tx = 0, off_ty = 0, off_tz = 0;
-  size_t off_w2t = 0, off_kzt = 0, off_pz = 0, off_qx = 0, off_W = 0, off_Z = 0;
+  size_t off_w2t = 0, off_kzt = 0, off_pz = 0, off_qx = 0, off_q4 = 0, off_W = 0, off_Z = 0;
   size_t bytes = 0;
 };
 
@@ -1786,6 +1786,7 @@ psfd_status ffno_layout(const psfd_ffno_desc* d, FfnoLayout* L) {
   L->off_kzt = o; o = align256(o + sizeof(float2) * a.nl * a.mz * dv * dv);
   L->off_pz = o; o = align256(o + sizeof(float2) * 16 * (size_t)(a.nz + 3));
   L->off_qx = o; o = align256(o + sizeof(float2) * 32 * (size_t)((a.nx + 15) / 16 + 7));
+  L->off_q4 = o; o = align256(o + sizeof(float2) * 32 * (size_t)(4 * ((a.nx + 63) / 64) + 4));
   L->off_W = o; o = align256(o + sizeof(float2) * dv * a.mz * (size_t)a.ny * a.nx);
   L->off_Z = o; o = align256(o + sizeof(float2) * dv * a.mz * (size_t)a.ny * a.nx);
   L->bytes = o;
@@ -1843,6 +1844,7 @@ psfd_status psfd_ffno_forward(const psfd_ffno_desc* d, const float* weights, con
     w.KzT = reinterpret_cast<float2*>(ws + L.off_kzt);
     w.pz = reinterpret_cast<float2*>(ws + L.off_pz);
     w.qx = reinterpret_cast<float2*>(ws + L.off_qx);
+    w.q4 = reinterpret_cast<float2*>(ws + L.off_q4);
     w.W = reinterpret_cast<float2*>(ws + L.off_W);
     w.Z = reinterpret_cast<float2*>(ws + L.off_Z);
     CHK(ffno_forward(a, w, a_in, static_cast<cplx<double>*>(E), static_cast<hipStream_t>(hip_stream)));

@@ -214,6 +214,7 @@ struct FfnoPtrs {
   float2* KzT;             // [nl][mz][dv][dv] axial mixing weights, kz-major
   float2* pz;              // [nz + 3][16] powers w^(kz z) of the axial transforms
   float2* qx;              // [ceil(nx / 16) + 7][16 or 32] powers w^(16 kx j) of the x DFT
+  float2* q4;              // [4 ceil(nx / 64) + 4][16 or 32] powers w^(kx (64 j + c)) (nx % 4 == 0)
   float2 *T, *G, *U;       // [dv][nz][ny][mx], [dv][nz][my][mx] x 2
   float2 *W, *Z;           // axial spectra before / after mixing, [dv][mz][ny][nx] each
   float2 *twx, *twy, *twz; // e^{+2 pi i k / n}
