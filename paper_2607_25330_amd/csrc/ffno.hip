@@ -356,6 +356,57 @@ __global__ void __launch_bounds__(256) k_ffno_xidft(const FfnoArgs a, const floa
   }
 }
 
+// The inverse x DFT with 16-byte stores for rows whose length is a multiple
+// of 4: lane l writes x = 64 j + 4 l + c, c = 0..3, from R_l[kx] =
+// T2[kx] w^(4 kx l) (doubled for kx > 0) and the table q4[4 j + c][kx] of
+// the forward pass.
+template <int MXM>
+__global__ void __launch_bounds__(256) k_ffno_xidft4(const FfnoArgs a, const float2* __restrict__ T2,
+                                                     const float2* __restrict__ twx,
+                                                     const float2* __restrict__ q4,
+                                                     float* __restrict__ u, int64_t nrows) {
+  constexpr int RPB = 256 / kXL;
+  const int nx = a.nx, mx = a.mx;
+  const int l = threadIdx.x % kXL;
+  const int nj = (nx + 4 * kXL - 1) / (4 * kXL);
+  const float norm = 1.0f / ((float)nx * (float)a.ny);
+  float2 pl[MXM];  // w^(4 kx l)
+#pragma unroll
+  for (int k = 0; k < MXM; ++k) pl[k] = k < mx ? twx[(4 * k * l) % nx] : make_float2(0.f, 0.f);
+  for (int64_t base = (int64_t)blockIdx.x * RPB; base < nrows; base += (int64_t)gridDim.x * RPB) {
+    const int64_t row = base + threadIdx.x / kXL;
+    const bool live = row < nrows;
+    const float2* t = T2 + (live ? row : 0) * mx;
+    float rr[MXM], ri[MXM];
+#pragma unroll
+    for (int k = 0; k < MXM; ++k) {
+      const float2 tv = k < mx ? t[k] : make_float2(0.f, 0.f);
+      const float f = k == 0 ? 1.f : 2.f;
+      rr[k] = f * (tv.x * pl[k].x - tv.y * pl[k].y);
+      ri[k] = f * (tv.x * pl[k].y + tv.y * pl[k].x);
+    }
+    float* dst = u + (live ? row : 0) * nx;
+    for (int j = 0; j < nj; ++j) {
+      const int jq = __builtin_amdgcn_readfirstlane(j);  // wave-uniform: scalar table loads
+      float out[4];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const float2* q = q4 + (4 * jq + c) * MXM;
+        float acc = rr[0] * q[0].x - ri[0] * q[0].y;
+#pragma unroll
+        for (int k = 1; k < MXM; ++k) {
+          const float2 w = q[k];
+          acc += rr[k] * w.x - ri[k] * w.y;
+        }
+        out[c] = acc * norm;
+      }
+      const int x0 = 4 * l + 4 * kXL * j;
+      if (live && x0 < nx)
+        *reinterpret_cast<float4*>(dst + x0) = make_float4(out[0], out[1], out[2], out[3]);
+    }
+  }
+}
+
 // Axial branch in three coalesced passes over the columns (col = y nx + x,
 // consecutive threads on consecutive columns):
 //   forward:  W[c][kz][col] = sum_z u[c][z][col] w^(-kz z)
@@ -613,10 +664,16 @@ hipError_t ffno_forward(const FfnoArgs& a, const FfnoPtrs& w, const float* in, c
     hipLaunchKernelGGL(k_ffno_yidft, dim3(grid_for((int64_t)a.dv * a.nz * a.ny * a.mx)), dim3(256),
                        0, st, a, w.U, w.twy, w.T);
     const dim3 gi((unsigned)std::min<int64_t>((nrows + 15) / 16, 16384));
-    if (a.mx <= 16)
+    if (a.nx % 4 == 0) {
+      if (a.mx <= 16)
+        hipLaunchKernelGGL(k_ffno_xidft4<16>, gi, dim3(256), 0, st, a, w.T, w.twx, w.q4, w.u, nrows);
+      else
+        hipLaunchKernelGGL(k_ffno_xidft4<32>, gi, dim3(256), 0, st, a, w.T, w.twx, w.q4, w.u, nrows);
+    } else if (a.mx <= 16) {
       hipLaunchKernelGGL(k_ffno_xidft<16>, gi, dim3(256), 0, st, a, w.T, w.twx, w.qx, w.u, nrows);
-    else
+    } else {
       hipLaunchKernelGGL(k_ffno_xidft<32>, gi, dim3(256), 0, st, a, w.T, w.twx, w.qx, w.u, nrows);
+    }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const int last = l == a.nl - 1;
