@@ -292,10 +292,12 @@ __global__ void k_ffno_yidft(const FfnoArgs a, const float2* __restrict__ U,
     const int64_t cz = q / ((int64_t)mx * ny);
     const float2* u = U + cz * my * mx + kx;
     float re = 0.f, im = 0.f;
+    // table index of ky y mod ny for ky = -ky_max, then stepped by y per mode
+    int ph = (int)((((int64_t)(-a.ky_max) * y) % ny + ny) % ny);
     for (int m = 0; m < my; ++m) {
-      const int ky = m - a.ky_max;
-      const int64_t ph = (((int64_t)ky * y) % ny + ny) % ny;
       const float2 w = twy[ph];
+      ph += y;
+      if (ph >= ny) ph -= ny;
       const float2 s = u[(int64_t)m * mx];
       re += s.x * w.x - s.y * w.y;
       im += s.x * w.y + s.y * w.x;
