@@ -215,7 +215,17 @@ class Basis:
     s_hat = (-ky, kx, 0)/kt, t_hat = (kx, ky, 0)/kt; at kt = 0 the basis of
     the incidence plane is used.  kz = sqrt(kbg^2 - kt^2) with Im kz >= 0.
     Grazing modes, |kz| < max(ml_kz_min, 1e-9) k0, get no multilayer
-    response (the paper is silent on grazing orders)."""
+    response (the paper is silent on grazing orders).
+
+    The TM amplitude of the downgoing field is read from the whole field
+    vector at the evaluation row: a downgoing TM wave of tangential amplitude
+    a has E_t = a t_hat and E_z = (kt/kz) a, and a is the least-squares fit
+    of that polarisation to (t_hat . E_t, E_z).  For a field that is one
+    downgoing wave this is t_hat . E_t exactly; it differs where the field on
+    the evaluation row also holds other content, which for near-grazing orders
+    a periodic PML box always does (coordinate stretching does not act on a
+    z-constant field).  Read from E_t alone, that content is multiplied by
+    kt/kz when the upgoing TM field's E_z is formed."""
 
     def __init__(self, g):
         KX = np.broadcast_to(g.kx[None, :], (g.ny, g.nx))
@@ -235,21 +245,38 @@ class Basis:
         self.live = np.abs(self.kzb) >= kz_min * g.k0
         kzn = np.where(self.live, self.kzb, 1.0)
         self.ktkz = np.where(self.live, kt / kzn, 0.0)
+        # TM amplitude of the downgoing field: least-squares projection of the
+        # field vector (t_hat . E_t, E_z) on the polarisation (1, kt/kz) of a
+        # downgoing TM wave, a_p = w_t (t_hat . E_t) + w_z E_z.
+        den = 1.0 + np.abs(self.ktkz) ** 2
+        self.w_t = 1.0 / den
+        self.w_z = np.conj(self.ktkz) / den
 
 
-def ml_field_hat(g, basis, r_te, r_pe, Xt_ev, rows):
+def downgoing_amplitudes(g, basis, X_ev):
+    """TE and TM amplitudes at z_ml of the downgoing field, from the lateral
+    Fourier coefficients X_ev (3, ny, nx) of the field on the evaluation row.
+
+    (i) the field there is taken as downgoing, its amplitude at z_ml = 0 is
+    the value times exp(-i kz dz/2); (ii) TE: s_hat . E_t; TM: the
+    least-squares fit w_t (t_hat . E_t) + w_z E_z (see Basis)."""
+    b = basis
+    down = np.exp(-1j * b.kzb * (0.5 * g.dz))
+    a_s = (b.sx * X_ev[0] + b.sy * X_ev[1]) * down
+    a_p = (b.w_t * (b.tx * X_ev[0] + b.ty * X_ev[1]) + b.w_z * X_ev[2]) * down
+    return a_s, a_p
+
+
+def ml_field_hat(g, basis, r_te, r_pe, X_ev, rows):
     """Reflected multilayer field on the given rows, lateral Fourier space.
 
-    Xt_ev: (2, ny, nx) tangential coefficients at the evaluation row.
-    (i) the field there is purely downgoing; its amplitude at z_ml = 0 is
-    Xt_ev * exp(-i kz dz/2); (ii) TE/TM projection on s_hat, t_hat;
+    X_ev: (3, ny, nx) coefficients of the field at the evaluation row.
+    (i)-(ii) downgoing TE/TM amplitudes at z_ml (downgoing_amplitudes);
     (iii) multiply by r_TE, r_pE; (iv) propagate upward:
     E_ML(z) = [a_s s_hat + a_p (t_hat - (kt/kz) z_hat)] exp(i kz z).
     Returns (3, len(rows), ny, nx)."""
     b = basis
-    down = np.exp(-1j * b.kzb * (0.5 * g.dz))
-    a_s = (b.sx * Xt_ev[0] + b.sy * Xt_ev[1]) * down
-    a_p = (b.tx * Xt_ev[0] + b.ty * Xt_ev[1]) * down
+    a_s, a_p = downgoing_amplitudes(g, b, X_ev)
     u_s = np.where(b.live, r_te * a_s, 0.0)
     u_p = np.where(b.live, r_pe * a_p, 0.0)
     out = np.zeros((3, len(rows), g.ny, g.nx), np.complex128)
@@ -262,7 +289,7 @@ def ml_field_hat(g, basis, r_te, r_pe, Xt_ev, rows):
 
 
 def ml_field_hat_adjoint(g, basis, r_te, r_pe, Q, rows):
-    """Adjoint of ml_field_hat (same rows): (3, len(rows), ny, nx) -> (2, ny, nx)."""
+    """Adjoint of ml_field_hat (same rows): (3, len(rows), ny, nx) -> (3, ny, nx)."""
     b = basis
     c_s = np.zeros((g.ny, g.nx), np.complex128)
     c_p = np.zeros((g.ny, g.nx), np.complex128)
@@ -270,10 +297,11 @@ def ml_field_hat_adjoint(g, basis, r_te, r_pe, Q, rows):
         ph = np.conj(np.exp(1j * b.kzb * g.z[j]))
         c_s += ph * (b.sx * Q[0, i] + b.sy * Q[1, i])
         c_p += ph * (b.tx * Q[0, i] + b.ty * Q[1, i] - np.conj(b.ktkz) * Q[2, i])
-    c_s = np.where(b.live, np.conj(r_te) * c_s, 0.0)
-    c_p = np.where(b.live, np.conj(r_pe) * c_p, 0.0)
     down = np.conj(np.exp(-1j * b.kzb * (0.5 * g.dz)))
-    return np.stack([down * (b.sx * c_s + b.tx * c_p), down * (b.sy * c_s + b.ty * c_p)])
+    c_s = down * np.where(b.live, np.conj(r_te) * c_s, 0.0)
+    c_p = down * np.where(b.live, np.conj(r_pe) * c_p, 0.0)
+    wt = np.conj(b.w_t) * c_p
+    return np.stack([b.sx * c_s + b.tx * wt, b.sy * c_s + b.ty * wt, np.conj(b.w_z) * c_p])
 
 
 # --------------------------------------------------------------------------
@@ -379,7 +407,7 @@ def apply_A(P, x):
     Xh = fft2(x)
     U = curlcurl_hat(g, Xh, dz_apply) - (g.kbg ** 2) * Xh
     y = ifft2(U)
-    V = ml_field_hat(g, P.basis, P.r_te, P.r_pe, Xh[0:2, g.j_ev], g.abs_rows)
+    V = ml_field_hat(g, P.basis, P.r_te, P.r_pe, Xh[:, g.j_ev], g.abs_rows)
     e_ml = ifft2(V)
     ra = g.abs_rows
     y[:, ra] -= g.k0 ** 2 * P.deps[None] * (x[:, ra] + e_ml)
@@ -394,7 +422,7 @@ def apply_AH(P, x):
     ra = g.abs_rows
     dconj = g.k0 ** 2 * np.conj(P.deps)[None]
     Q = fft2(dconj * x[:, ra])
-    U[0:2, g.j_ev] -= ml_field_hat_adjoint(g, P.basis, P.r_te, P.r_pe, Q, ra)
+    U[:, g.j_ev] -= ml_field_hat_adjoint(g, P.basis, P.r_te, P.r_pe, Q, ra)
     y = ifft2(U)
     y[:, ra] -= dconj * x[:, ra]
     return y
@@ -557,7 +585,7 @@ def local_field(P, E):
     with R_ml inside A), shape (3, nz_abs, ny, nx)."""
     g = P.g
     Xh = fft2(E)
-    V = ml_field_hat(g, P.basis, P.r_te, P.r_pe, Xh[0:2, g.j_ev], g.abs_rows)
+    V = ml_field_hat(g, P.basis, P.r_te, P.r_pe, Xh[:, g.j_ev], g.abs_rows)
     bg = background_field(g, P.cfg, g.abs_rows)
     return E[:, g.abs_rows] + ifft2(V) + bg[:, :, None, None]
 
@@ -648,7 +676,7 @@ def reflected_obs(P, E):
     incident) at the multilayer interface."""
     g = P.g
     Xh = fft2(E)
-    up = ml_field_hat(g, P.basis, P.r_te, P.r_pe, Xh[0:2, g.j_ev], [g.j_obs])[:, 0]
+    up = ml_field_hat(g, P.basis, P.r_te, P.r_pe, Xh[:, g.j_ev], [g.j_obs])[:, 0]
     tot = (Xh[:, g.j_obs] + up) / (g.nx * g.ny)
     bgr = background_field(g, P.cfg, [g.j_obs])[:, 0]
     e_in, _ = incident_vectors(g, P.cfg["pol"])
@@ -673,12 +701,10 @@ def flux_balance(P, E):
     w_s, w_p = kz, g.kbg ** 2 / kz
     f_up = np.sum(np.where(prop, w_s * np.abs(us) ** 2 + w_p * np.abs(upp) ** 2, 0.0))
     Xh = fft2(E) / (g.nx * g.ny)
-    down = np.exp(-1j * b.kzb * 0.5 * g.dz)
-    ds = (b.sx * Xh[0, g.j_ev] + b.sy * Xh[1, g.j_ev]) * down
-    dp = (b.tx * Xh[0, g.j_ev] + b.ty * Xh[1, g.j_ev]) * down
+    ds, dp = downgoing_amplitudes(g, b, Xh[:, g.j_ev])
     e_in, _ = incident_vectors(g, P.cfg["pol"])
     ds[0, 0] += b.sx[0, 0] * e_in[0] + b.sy[0, 0] * e_in[1]
-    dp[0, 0] += b.tx[0, 0] * e_in[0] + b.ty[0, 0] * e_in[1]
+    dp[0, 0] += b.w_t[0, 0] * (b.tx[0, 0] * e_in[0] + b.ty[0, 0] * e_in[1]) + b.w_z[0, 0] * e_in[2]
     f_ml = np.sum(np.where(prop, (1 - np.abs(P.r_te) ** 2) * w_s * np.abs(ds) ** 2
                            + (1 - np.abs(P.r_pe) ** 2) * w_p * np.abs(dp) ** 2, 0.0))
     return float((f_up + f_ml) / g.kz0)
@@ -769,7 +795,7 @@ def dense_kronecker(P):
     A = T^-1 C T - k0^2 diag(eps) - k0^2 diag(d_eps) T^-1 R T, where T is
     the lateral DFT on every (component, row) plane, C holds the per-mode
     curl-curl blocks with D_z = diag(1/s) Fz^-1 diag(i kz) Fz, and R maps
-    the tangential evaluation-row coefficients to absorber rows."""
+    the evaluation-row coefficients to absorber rows."""
     g, b = P.g, P.basis
     nx, ny, nz = g.nx, g.ny, g.nz
     L = nx * ny
@@ -790,6 +816,7 @@ def dense_kronecker(P):
     r_te, r_pe = P.r_te.ravel(), P.r_pe.ravel()
     sx, sy, tx, ty = b.sx.ravel(), b.sy.ravel(), b.tx.ravel(), b.ty.ravel()
     kzb, ktkz, live = b.kzb.ravel(), b.ktkz.ravel(), b.live.ravel()
+    w_t, w_z = b.w_t.ravel(), b.w_z.ravel()
     DD = Dz @ Dz
     for q in range(L):
         kx, ky = KX[q], KY[q]
@@ -805,13 +832,13 @@ def dense_kronecker(P):
         down = np.exp(-1j * kzb[q] * 0.5 * g.dz)
         ws = [sx[q], sy[q], 0.0]
         wp = [tx[q], ty[q], -ktkz[q]]
-        src_s = [sx[q], sy[q]]
-        src_p = [tx[q], ty[q]]
+        src_s = [sx[q], sy[q], 0.0]
+        src_p = [w_t[q] * tx[q], w_t[q] * ty[q], w_z[q]]
         for j in g.abs_rows:
             ph = np.exp(1j * kzb[q] * g.z[j]) * down
             for c in range(3):
                 row = (c * nz + j) * L + q
-                for c2 in range(2):
+                for c2 in range(3):
                     col = (c2 * nz + g.j_ev) * L + q
                     R[row, col] = ph * (r_te[q] * ws[c] * src_s[c2] + r_pe[q] * wp[c] * src_p[c2])
     T = np.kron(np.eye(3 * nz), F2)
@@ -826,7 +853,7 @@ def dense_kronecker(P):
 def slab_1d_matrix(P):
     """Dense 3nz x 3nz matrix of the (0, 0) lateral mode for a laterally uniform d_eps.
 
-    Explicit D_z matrix and rank-two multilayer coupling; used to pin the
+    Explicit D_z matrix and low-rank multilayer coupling; used to pin the
     3-D solve of a uniform slab against a 1-D solve."""
     g, b = P.g, P.basis
     nz = g.nz
@@ -848,8 +875,10 @@ def slab_1d_matrix(P):
         wp = [b.tx[0, 0], b.ty[0, 0], -b.ktkz[0, 0]]
         for j in g.abs_rows:
             ph = np.exp(1j * b.kzb[0, 0] * g.z[j]) * down
+            src_s = [b.sx[0, 0], b.sy[0, 0], 0.0]
+            src_p = [b.w_t[0, 0] * b.tx[0, 0], b.w_t[0, 0] * b.ty[0, 0], b.w_z[0, 0]]
             for c in range(3):
-                for c2, (ss, tt) in enumerate(zip([b.sx[0, 0], b.sy[0, 0]], [b.tx[0, 0], b.ty[0, 0]])):
+                for c2 in range(3):
                     A[c * nz + j, c2 * nz + g.j_ev] -= g.k0 ** 2 * de[j] * ph * (
-                        P.r_te[0, 0] * ws[c] * ss + P.r_pe[0, 0] * wp[c] * tt)
+                        P.r_te[0, 0] * ws[c] * src_s[c2] + P.r_pe[0, 0] * wp[c] * src_p[c2])
     return A

@@ -100,7 +100,7 @@ def test_discrete_ml_chain_matches_analytic_background(pol):
     e_in, _ = R.incident_vectors(g, pol)
     inc = e_in[:, None] * np.exp(-1j * g.kz0 * g.z)[None, :]
     x = np.broadcast_to(inc[:, :, None, None], g.shape).astype(np.complex128)
-    V = R.ml_field_hat(g, P.basis, P.r_te, P.r_pe, R.fft2(x)[0:2, g.j_ev], g.abs_rows)
+    V = R.ml_field_hat(g, P.basis, P.r_te, P.r_pe, R.fft2(x)[:, g.j_ev], g.abs_rows)
     e_ml = R.ifft2(V)
     expect = R.background_field(g, cfg, g.abs_rows) - inc[:, g.abs_rows]
     np.testing.assert_allclose(e_ml, np.broadcast_to(expect[:, :, None, None], e_ml.shape),
@@ -185,9 +185,78 @@ def test_grazing_cutoff_zeroes_only_grazing_modes(rng):
     g = P0.g
     cut = np.abs(P0.basis.kzb) < 0.5 * g.k0
     assert cut.any() and (~cut).any()
-    Xt = random_field((2, g.ny, g.nx), rng)
+    Xt = random_field((3, g.ny, g.nx), rng)
     V0 = R.ml_field_hat(g, P0.basis, P0.r_te, P0.r_pe, Xt, g.abs_rows)
     V1 = R.ml_field_hat(g, P1.basis, P1.r_te, P1.r_pe, Xt, g.abs_rows)
     assert np.all(V1[:, :, cut] == 0)
     np.testing.assert_array_equal(V1[:, :, ~cut], V0[:, :, ~cut])
     assert np.abs(V0[:, :, cut]).max() > 0
+
+
+def _downgoing_wave_rows(g, b, a_s, a_p, rows):
+    """Lateral coefficients of the downgoing wave sum_k [a_s s_hat + a_p (t_hat +
+    (kt/kz) z_hat)] exp(-i kz z), written out from the plane-wave relations."""
+    out = np.zeros((3, len(rows), g.ny, g.nx), np.complex128)
+    for i, j in enumerate(rows):
+        ph = np.exp(-1j * b.kzb * g.z[j])
+        out[0, i] = (a_s * b.sx + a_p * b.tx) * ph
+        out[1, i] = (a_s * b.sy + a_p * b.ty) * ph
+        out[2, i] = a_p * b.kt / b.kzb * ph
+    return out
+
+
+@pytest.mark.parametrize("pol", [0, 1])
+def test_downgoing_amplitudes_of_plane_waves(rng, pol):
+    """Every lateral order (propagating and evanescent) of a pure downgoing TE + TM
+    wave returns its own amplitudes at z_ml, and R_ml returns r times them."""
+    cfg = small_cfg(nx=16, ny=12, nz_abs=3, dx=4.0, theta_deg=7.0, phi_deg=25.0, pol=pol)
+    P = R.Problem(cfg, np.full((3, 12, 16), 0.9 + 0.05j))
+    g, b = P.g, P.basis
+    assert (b.kzb.imag > 0).any() and (b.kzb.imag == 0).any()
+    a_s = random_field((g.ny, g.nx), rng)
+    a_p = random_field((g.ny, g.nx), rng)
+    X = _downgoing_wave_rows(g, b, a_s, a_p, [g.j_ev])[:, 0]
+    d_s, d_p = R.downgoing_amplitudes(g, b, X)
+    np.testing.assert_allclose(d_s, a_s, rtol=0, atol=1e-12 * np.abs(a_s).max())
+    np.testing.assert_allclose(d_p, a_p, rtol=0, atol=1e-12 * np.abs(a_p).max())
+    V = R.ml_field_hat(g, b, P.r_te, P.r_pe, X, [g.j_obs])[:, 0]
+    ph = np.exp(1j * b.kzb * g.z[g.j_obs])
+    up_s = P.r_te * a_s * ph
+    up_p = P.r_pe * a_p * ph
+    expect = np.stack([up_s * b.sx + up_p * b.tx, up_s * b.sy + up_p * b.ty, -up_p * b.kt / b.kzb])
+    np.testing.assert_allclose(V, expect, rtol=0, atol=1e-11 * np.abs(expect).max())
+
+
+def test_tm_reading_ignores_content_orthogonal_to_tm_polarisation(rng):
+    """The TM amplitude is the least-squares fit of the downgoing TM polarisation
+    (1, kt/kz) in (t_hat . E_t, E_z): content along (-conj(kt/kz), 1) reads as zero,
+    and TE-polarised tangential content does not enter it."""
+    cfg = small_cfg(nx=16, ny=12, nz_abs=3, dx=4.0, theta_deg=7.0, phi_deg=25.0)
+    P = R.Problem(cfg, np.full((3, 12, 16), 0.9 + 0.05j))
+    g, b = P.g, P.basis
+    c = random_field((g.ny, g.nx), rng)
+    q = b.kt / b.kzb
+    X = np.stack([-np.conj(q) * c * b.tx, -np.conj(q) * c * b.ty, c])
+    d_s, d_p = R.downgoing_amplitudes(g, b, X)
+    assert np.abs(d_p).max() <= 1e-13 * np.abs(c).max() * (1 + np.abs(q).max())
+    assert np.abs(d_s).max() <= 1e-13 * np.abs(c).max() * (1 + np.abs(q).max())
+    X2 = np.stack([c * b.sx, c * b.sy, np.zeros_like(c)])
+    _, d_p2 = R.downgoing_amplitudes(g, b, X2)
+    assert np.abs(d_p2).max() <= 1e-14 * np.abs(c).max()
+
+
+@pytest.mark.parametrize("kt_over_k0", [0.99, 0.995, 0.999, 0.9995])
+def test_near_grazing_tm_block_stays_passive(kt_over_k0):
+    """The 1-D operator of a near-grazing lateral order (the incidence order of a
+    laterally uniform slab at theta = asin(kt/k0)), with the lossy mean contrast of
+    a 45 % absorber fill and the multilayer on, keeps every eigenvalue in the lower
+    half plane (exp(-i omega t): loss gives Im < 0) up to 1e-2 k0^2.  Reading the
+    TM amplitude from E_t alone puts eigenvalues up to +0.6 k0^2 there, which stalls
+    BiCGSTAB on layouts that scatter into such orders."""
+    from psfd_synth import base_config, eps_absorber_default
+    theta = float(np.degrees(np.arcsin(kt_over_k0)))
+    cfg = base_config(1, 1, 32, 60.0, theta_deg=theta, pol=1)
+    eps = np.full((32, 1, 1), 1.0 + 0.45 * (eps_absorber_default() - 1.0))
+    P = R.Problem(cfg, eps)
+    w = np.linalg.eigvals(R.slab_1d_matrix(P)) / P.g.k0 ** 2
+    assert w.imag.max() < 1e-2, w.imag.max()
