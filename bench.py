@@ -28,14 +28,15 @@ if ROOT not in sys.path:
 
 METRIC = "PSFD solves/s at rel. residual 1e-6 (mixed/batched vs FP64 plain); HBM GB/s"
 HBM_PEAK_GBS = 8000.0
-# Lateral orders within |kz| < 0.1 k0 of grazing get no multilayer response: the
-# periodic-z PML domain cannot absorb them and BiCGSTAB stalls on 2-D layouts
-# otherwise (orders near |kz| = 0.02 k0 wrap around the z period; with the cut every
-# layout class converges, and the near field moves by at most 5e-3 at peak intensity 0.58).
-ML_KZ_MIN = 0.1
-WORKLOAD = ("256x256 lateral @2nm, 32 absorber cells / 60 nm (Nz=48), seeded line/space + "
-            "contact layouts, TE+TM, 6 deg, grazing cutoff |kz|<0.1k0, tol 1e-6, "
-            "plan+TMM+source+solve")
+# Grazing cutoff of the multilayer response (|kz| < ML_KZ_MIN k0 gets none); 0 is the
+# operator as defined (every order with |kz| >= 1e-9 k0 reflected); --ml-kz-min sets it.
+ML_KZ_MIN = 0.0
+
+
+def workload_name():
+    cut = ("no grazing cutoff" if ML_KZ_MIN == 0.0 else f"grazing cutoff |kz|<{ML_KZ_MIN:g}k0")
+    return ("256x256 lateral @2nm, 32 absorber cells / 60 nm (Nz=48), seeded line/space + "
+            f"contact layouts, TE+TM, 6 deg, {cut}, tol 1e-6, plan+TMM+source+solve")
 
 
 def layouts(n, nx, ny, dx):
@@ -617,6 +618,8 @@ def _tmm_te(psfd, cfg, eps_l, d_l, dev):
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--ml-kz-min", type=float, default=0.0,
+                    help="grazing cutoff of the multilayer response in units of k0 (0: none)")
     ap.add_argument("--steps", type=int, default=4)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--tol", type=float, default=1e-6)
@@ -639,6 +642,8 @@ def main():
     ap.add_argument("--ffno-grids", default="256x256x48,1200x1200x100",
                     help="grids of the ffno workload (comma-separated)")
     args = ap.parse_args()
+    global ML_KZ_MIN
+    ML_KZ_MIN = args.ml_kz_min
 
     if args.cpu_leg is not None:
         print(json.dumps(cpu_leg(args.cpu_leg, args.cpu_sample_iters)))
@@ -762,7 +767,7 @@ def main():
         "steps": K, "warmup": W, "ms_per_step": round(1e3 * t_mixed / K, 2),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32+f64", "data": "synthetic",
-        "config": {"workload": WORKLOAD, "solves_per_step": 2, "grid": [256, 256, 48],
+        "config": {"workload": workload_name(), "solves_per_step": 2, "grid": [256, 256, 48],
                    "ml_kz_min": ML_KZ_MIN,
                    "precision": "complex64 operator/Krylov, FP64 residual + refinement"},
         "converged": ok_m,
@@ -794,7 +799,7 @@ def main():
         env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1",
                    MKL_NUM_THREADS="1", HIP_VISIBLE_DEVICES="", CUDA_VISIBLE_DEVICES="")
         print("bench: cpu baseline (oracle) ...", file=sys.stderr, flush=True)
-        cp = subprocess.run([sys.executable, os.path.abspath(__file__), "--cpu-leg",
+        cp = subprocess.run([sys.executable, os.path.abspath(__file__), "--ml-kz-min", str(ML_KZ_MIN), "--cpu-leg",
                              str(iters_proj), "--cpu-sample-iters", str(args.cpu_sample_iters)],
                             capture_output=True, text=True, env=env, timeout=600)
         if cp.returncode == 0:

@@ -11,9 +11,12 @@
 // curl of curl, four G applications per column), minus kbg^2 P.  P = X for
 // the plain operator and P = M X for the fused operator-times-preconditioner
 // (F_z, multiply by the damping m(k), and the D of P shares that forward
-// transform).  The multilayer branch takes the tangential P at the
-// evaluation row (purely downgoing there), projects it on the TE/TM basis,
-// multiplies by r_TE / r_pE and propagates it up to the absorber rows:
+// transform).  The multilayer branch takes P at the evaluation row (taken as
+// downgoing there) and splits it into TE and TM amplitudes: TE = s . P_t, TM
+// = the least-squares fit of the downgoing TM polarisation (1, kt/kz) to
+// (t . P_t, P_z), i.e. w_t (t . P_t) + w_z P_z with w_t = 1 / (1 + |kt/kz|^2),
+// w_z = conj(kt/kz) w_t; it multiplies them by r_TE / r_pE and propagates
+// them up to the absorber rows:
 //   W = P + E_ML on absorber rows,  so that  y = F2^-1[U] - k0^2 d_eps F2^-1[W].
 // The adjoint replaces D by -D^H = G diag(1/conj(s)) and the multilayer
 // branch by its adjoint applied to F2[conj(k0^2 d_eps) x] (extra input planes),
@@ -37,8 +40,10 @@ struct ColInfo {
   T kx, ky, kt2, sx, sy, tx, ty;
   T kzr, kzi;          // background axial wavenumber kzr + i kzi (one of them is 0)
   cplx<T> ktkz, down;  // kt / kz,  exp(-i kz dz / 2)
+  T wt;                // TM amplitude weights: a_p = wt (t . P_t) + wz P_z
+  cplx<T> wz;
   cplx<T> rte, rpe;
-  cplx<T> a0, a1;      // forward: upgoing (TE, TM) amplitudes; adjoint: evaluation-row terms
+  cplx<T> a0, a1, a2;  // forward: upgoing (TE, TM) amplitudes; adjoint: evaluation-row terms (x, y, z)
   int live;
 };
 
@@ -101,6 +106,8 @@ __device__ void column_info(ColInfo<T>& c, const OpTables<T>& t, int pb, int ix,
   if (!c.live) c.ktkz = {T(0), T(0)};
   else if (c.kzi == T(0)) c.ktkz = {kt / c.kzr, T(0)};
   else c.ktkz = {T(0), -kt / c.kzi};
+  c.wt = T(1) / (T(1) + c.ktkz.re * c.ktkz.re + c.ktkz.im * c.ktkz.im);
+  c.wz = {c.wt * c.ktkz.re, -c.wt * c.ktkz.im};
   const T h = T(0.5) * t.dz;
   T s, co;
   sc(c.kzr * h, &s, &co);
@@ -231,8 +238,9 @@ k_axial(const cplx<T>* __restrict__ S_all, cplx<T>* __restrict__ UW_all, const O
     ColInfo<T>& c = ci[tid];
     if constexpr (MODE != AX_AH) {
       const cplx<T> px = buf[t.jev * PITCH + tid], py = buf[VS + t.jev * PITCH + tid];
+      const cplx<T> pz = buf[2 * VS + t.jev * PITCH + tid];
       const cplx<T> as = (c.sx * px + c.sy * py) * c.down;
-      const cplx<T> ap = (c.tx * px + c.ty * py) * c.down;
+      const cplx<T> ap = (c.wt * (c.tx * px + c.ty * py) + c.wz * pz) * c.down;
       c.a0 = c.live ? c.rte * as : cplx<T>{T(0), T(0)};
       c.a1 = c.live ? c.rpe * ap : cplx<T>{T(0), T(0)};
     } else {
@@ -247,13 +255,15 @@ k_axial(const cplx<T>* __restrict__ S_all, cplx<T>* __restrict__ UW_all, const O
       }
       cs = c.live ? cmulc(c.rte, cs) : cplx<T>{T(0), T(0)};
       cp = c.live ? cmulc(c.rpe, cp) : cplx<T>{T(0), T(0)};
-      c.a0 = cmulc(c.down, c.sx * cs + c.tx * cp);
-      c.a1 = cmulc(c.down, c.sy * cs + c.ty * cp);
+      c.a0 = cmulc(c.down, c.sx * cs + (c.tx * c.wt) * cp);
+      c.a1 = cmulc(c.down, c.sy * cs + (c.ty * c.wt) * cp);
+      c.a2 = cmulc(c.down, cmulc(c.wz, cp));
     }
   }
 
   // Uz and the inner curl vectors w = -D P_t + i k_t P_z.
   const T ckx = ci[cc].kx, cky = ci[cc].ky, ckt2 = ci[cc].kt2;
+  cplx<T> uz_ev = {T(0), T(0)};  // adjoint: U_z of the evaluation row, completed below
   for (int z = z0; z < NZ; z += ZS) {
     const int o = z * PITCH + cc;
     cplx<T> dpx = buf[3 * VS + o], dpy = buf[4 * VS + o];
@@ -265,6 +275,7 @@ k_axial(const cplx<T>* __restrict__ S_all, cplx<T>* __restrict__ UW_all, const O
     const cplx<T> pz = buf[2 * VS + o];
     const cplx<T> uz = ckx * mul_i(dpx) + cky * mul_i(dpy) + (ckt2 - t.kbg2) * pz;
     UW[(int64_t)(2 * NZ + z) * plane + colbase + cc] = uz;
+    if (z == t.jev) uz_ev = uz;
     cplx<T> wx = ckx * mul_i(pz) - dpx;
     cplx<T> wy = cky * mul_i(pz) - dpy;
     if constexpr (MODE == AX_AH) {
@@ -285,7 +296,7 @@ k_axial(const cplx<T>* __restrict__ S_all, cplx<T>* __restrict__ UW_all, const O
   __syncthreads();
   lds_fft<T, NZ, 2 * TX, NT, true, true>(buf + 3 * VS, twz, Addr{}, tid);
 
-  const cplx<T> ca0 = ci[cc].a0, ca1 = ci[cc].a1;
+  const cplx<T> ca0 = ci[cc].a0, ca1 = ci[cc].a1, ca2 = ci[cc].a2;
   for (int z = z0; z < NZ; z += ZS) {
     const int o = z * PITCH + cc;
     cplx<T> dwx = buf[3 * VS + o], dwy = buf[4 * VS + o];
@@ -301,6 +312,8 @@ k_axial(const cplx<T>* __restrict__ S_all, cplx<T>* __restrict__ UW_all, const O
       if (z == t.jev) {
         ux = ux - ca0;
         uy = uy - ca1;
+        // the same thread wrote U_z of this row in the first pass
+        UW[(int64_t)(2 * NZ + z) * plane + colbase + cc] = uz_ev - ca2;
       }
     }
     UW[(int64_t)z * plane + colbase + cc] = ux;
@@ -409,8 +422,8 @@ k_axial_reg(const cplx<T>* __restrict__ S_all, cplx<T>* __restrict__ UW_all, con
 #pragma unroll
       for (int k = 0; k < E; ++k) v[k] = park[(slot * E + k) * 256 + threadIdx.x];
     };
-    // P_t at the evaluation row (the multilayer branch reads it there)
-    cplx<T> ex = {T(0), T(0)}, ey = {T(0), T(0)};
+    // P at the evaluation row (the multilayer branch reads it there)
+    cplx<T> ex = {T(0), T(0)}, ey = {T(0), T(0)}, ez = {T(0), T(0)};
     cplx<T> dx[E], dy[E];
     if constexpr (MODE == AX_AM) {
       F.fwd(px);
@@ -430,9 +443,11 @@ k_axial_reg(const cplx<T>* __restrict__ S_all, cplx<T>* __restrict__ UW_all, con
         const cplx<T> w = conj(t.tw_z[((k2 + kofs) * t.jev) % NZ]);
         ex = ex + px[k2] * w;
         ey = ey + py[k2] * w;
+        ez = ez + pz[k2] * w;
       }
       ex = lane_group_sum<L>(ex);
       ey = lane_group_sum<L>(ey);
+      ez = lane_group_sum<L>(ez);
 #pragma unroll
       for (int k2 = 0; k2 < E; ++k2) dx[k2] = t.kz[k2 + kofs] * mul_i(px[k2]);
       park_st(0, px);
@@ -447,10 +462,12 @@ k_axial_reg(const cplx<T>* __restrict__ S_all, cplx<T>* __restrict__ UW_all, con
         if (m == mj) {
           ex = px[m];
           ey = py[m];
+          ez = pz[m];
         }
       }
       ex = {__shfl(ex.re, tj, L), __shfl(ex.im, tj, L)};
       ey = {__shfl(ey.re, tj, L), __shfl(ey.im, tj, L)};
+      ez = {__shfl(ez.re, tj, L), __shfl(ez.im, tj, L)};
 #pragma unroll
       for (int m = 0; m < E; ++m) {
         dx[m] = px[m];
@@ -470,11 +487,11 @@ k_axial_reg(const cplx<T>* __restrict__ S_all, cplx<T>* __restrict__ UW_all, con
     F.inv(dx);
     F.inv(dy);
 
-    // multilayer amplitudes from the tangential P at the evaluation row
+    // multilayer amplitudes from P at the evaluation row
     ColInfo<T> c;
     column_info(c, t, pb, ix, iy);
     const cplx<T> as = (c.sx * ex + c.sy * ey) * c.down;
-    const cplx<T> ap = (c.tx * ex + c.ty * ey) * c.down;
+    const cplx<T> ap = (c.wt * (c.tx * ex + c.ty * ey) + c.wz * ez) * c.down;
     const cplx<T> a0 = c.live ? c.rte * as : cplx<T>{T(0), T(0)};
     const cplx<T> a1 = c.live ? c.rpe * ap : cplx<T>{T(0), T(0)};
     // exp(i kz z_abs) on this lane's absorber rows (z = lt + L m, every L-th

@@ -1400,8 +1400,9 @@ psfd_status layered_impl(const psfd_desc* d, int32_t n, const double* leps, cons
 // and at the evaluation row come from the device; the rest is scalar:
 // the upgoing (0, 0) amplitude at the observation row is the scattered
 // field plus the multilayer response to the scattered field (evaluation
-// row amplitude carried to z_ml, projected on s/t, times r_TE / r_pE,
-// carried up) plus the multilayer reflection of the incident wave.
+// row amplitude carried to z_ml, split into TE / TM as the operator does,
+// times r_TE / r_pE, carried up) plus the multilayer reflection of the
+// incident wave.
 psfd_status specular_impl(struct psfd_plan* P, const void* E, double* r_out) {
   if (!P || !E || !r_out) return fail(PSFD_ERR_ARG, "NULL argument");
   if (P->is_batch || P->G != 1) return fail(PSFD_ERR_ARG, "psfd_specular takes a single-problem plan");
@@ -1412,26 +1413,27 @@ psfd_status specular_impl(struct psfd_plan* P, const void* E, double* r_out) {
   ps.off[1] = (int64_t)(P->nz + jobs) * plane;
   ps.off[2] = (int64_t)jev * plane;
   ps.off[3] = (int64_t)(P->nz + jev) * plane;
+  ps.off[4] = (int64_t)(2 * P->nz + jev) * plane;
   const int nblk = (int)std::min<int64_t>(64, (plane + 255) / 256);
   cplx<double>* part = nullptr;
   struct psfd_plan tmp;  // owns the temporary
   tmp.st = P->st;
-  CHKS(dalloc(&tmp, &part, (size_t)4 * nblk));
+  CHKS(dalloc(&tmp, &part, (size_t)5 * nblk));
   CHK(launch_plane_sums(static_cast<const cplx<double>*>(E), ps, plane, nblk, part, P->st));
-  std::vector<cplx<double>> h((size_t)4 * nblk + 2);
-  CHK(hipMemcpyAsync(h.data(), part, sizeof(cplx<double>) * 4 * nblk, hipMemcpyDeviceToHost, P->st));
-  CHK(hipMemcpyAsync(h.data() + 4 * nblk, P->rte64, sizeof(cplx<double>), hipMemcpyDeviceToHost, P->st));
-  CHK(hipMemcpyAsync(h.data() + 4 * nblk + 1, P->rpe64, sizeof(cplx<double>), hipMemcpyDeviceToHost,
+  std::vector<cplx<double>> h((size_t)5 * nblk + 2);
+  CHK(hipMemcpyAsync(h.data(), part, sizeof(cplx<double>) * 5 * nblk, hipMemcpyDeviceToHost, P->st));
+  CHK(hipMemcpyAsync(h.data() + 5 * nblk, P->rte64, sizeof(cplx<double>), hipMemcpyDeviceToHost, P->st));
+  CHK(hipMemcpyAsync(h.data() + 5 * nblk + 1, P->rpe64, sizeof(cplx<double>), hipMemcpyDeviceToHost,
                      P->st));
   CHK(hipStreamSynchronize(P->st));
-  std::complex<double> m[4];
-  for (int q = 0; q < 4; ++q) {
+  std::complex<double> m[5];
+  for (int q = 0; q < 5; ++q) {
     std::complex<double> acc = 0.0;
     for (int b = 0; b < nblk; ++b) acc += std::complex<double>(h[q * nblk + b].re, h[q * nblk + b].im);
     m[q] = acc / (double)plane;
   }
-  const std::complex<double> rte(h[4 * nblk].re, h[4 * nblk].im);
-  const std::complex<double> rpe(h[4 * nblk + 1].re, h[4 * nblk + 1].im);
+  const std::complex<double> rte(h[5 * nblk].re, h[5 * nblk].im);
+  const std::complex<double> rpe(h[5 * nblk + 1].re, h[5 * nblk + 1].im);
   const ProbInfo& q = P->prob[0];
   const double kt = std::hypot(q.kx0, q.ky0);
   double sx, sy, tx, ty;
@@ -1447,7 +1449,10 @@ psfd_status specular_impl(struct psfd_plan* P, const void* E, double* r_out) {
   const bool live = std::abs(kz) >= P->t64.kz_live;
   const std::complex<double> down = std::exp(-I * kz * (0.5 * dz));
   const std::complex<double> us = live ? rte * (sx * m[2] + sy * m[3]) * down : 0.0;
-  const std::complex<double> up = live ? rpe * (tx * m[2] + ty * m[3]) * down : 0.0;
+  // TM amplitude: least-squares fit of the downgoing TM polarisation (1, kt/kz)
+  const double q_tz = live ? kt / kz : 0.0;
+  const double w_t = 1.0 / (1.0 + q_tz * q_tz), w_z = q_tz * w_t;
+  const std::complex<double> up = live ? rpe * (w_t * (tx * m[2] + ty * m[3]) + w_z * m[4]) * down : 0.0;
   const std::complex<double> ph = std::exp(I * kz * z_obs);
   std::complex<double> ux = m[0] + (us * sx + up * tx) * ph;
   std::complex<double> uy = m[1] + (us * sy + up * ty) * ph;

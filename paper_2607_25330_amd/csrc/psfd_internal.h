@@ -224,7 +224,7 @@ hipError_t ffno_forward(const FfnoArgs& a, const FfnoPtrs& w, const float* in, c
 
 // part[q][b], q < 4, b < nblk: partial sums of the plane starting at f + off[q]
 struct PlaneSet {
-  int64_t off[4];
+  int64_t off[5];
 };
 hipError_t launch_plane_sums(const cplx<double>* f, const PlaneSet& ps, int64_t plane, int nblk,
                              cplx<double>* part, hipStream_t st);

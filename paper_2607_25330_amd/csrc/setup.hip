@@ -251,7 +251,7 @@ k_plane_sums(const cplx<double>* __restrict__ f, PlaneSet ps, int64_t plane,
 
 hipError_t launch_plane_sums(const cplx<double>* f, const PlaneSet& ps, int64_t plane, int nblk,
                              cplx<double>* part, hipStream_t st) {
-  hipLaunchKernelGGL(k_plane_sums, dim3(nblk, 4), dim3(256), 0, st, f, ps, plane, part);
+  hipLaunchKernelGGL(k_plane_sums, dim3(nblk, 5), dim3(256), 0, st, f, ps, plane, part);
   return hipGetLastError();
 }
 

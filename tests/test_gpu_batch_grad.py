@@ -52,7 +52,7 @@ def test_batch_matches_individual_solves(psfd, prec, monkeypatch):
             base_config(16, 16, 8, 15.0, theta_deg=10.0, phi_deg=30.0, pol=0),
             base_config(64, 64, 32, 60.0, theta_deg=2.5, pol=1)]
     for c in cfgs:
-        c["ml_kz_min"] = 0.1
+        c["ml_kz_min"] = 0.0
     eps = [dev(_eps(c, 10 + i)) for i, c in enumerate(cfgs)]
     x0 = [None, None, dev(0.01 * random_field((3, 24, 16, 16), np.random.default_rng(1))), None]
     batch = psfd.Batch(cfgs, eps, prec=prec)
@@ -81,8 +81,8 @@ def test_group_of_same_shape_problems_matches_individual_solves(psfd, prec, form
         monkeypatch.setenv("PSFD_RELIABLE", form)
     thetas = [0.0, 2.5, 5.0, 7.5, 10.0, 6.0]
     cfgs = [dict(base_config(32, 32, 16, 30.0, theta_deg=th, phi_deg=15.0 * i, pol=i % 2),
-                 ml_kz_min=0.1) for i, th in enumerate(thetas)]
-    cfgs += [dict(base_config(16, 16, 8, 15.0, theta_deg=4.0, pol=p), ml_kz_min=0.1) for p in (0, 1)]
+                 ml_kz_min=0.0) for i, th in enumerate(thetas)]
+    cfgs += [dict(base_config(16, 16, 8, 15.0, theta_deg=4.0, pol=p), ml_kz_min=0.0) for p in (0, 1)]
     eps = [dev(_eps(c, 40 + i)) for i, c in enumerate(cfgs)]
     x0 = [None] * len(cfgs)
     x0[3] = dev(0.02 * random_field((3, 32, 32, 32), np.random.default_rng(3)))
@@ -104,7 +104,7 @@ def test_group_of_same_shape_problems_matches_individual_solves(psfd, prec, form
 def test_group_budget_per_problem(psfd):
     """A budget smaller than any member needs stops every member of the group
     at that budget with NOT_CONVERGED, reported per problem."""
-    cfgs = [dict(base_config(32, 32, 16, 30.0, theta_deg=th, pol=0), ml_kz_min=0.1)
+    cfgs = [dict(base_config(32, 32, 16, 30.0, theta_deg=th, pol=0), ml_kz_min=0.0)
             for th in (0.0, 5.0, 10.0)]
     eps = [dev(_eps(c, 60 + i)) for i, c in enumerate(cfgs)]
     batch = psfd.Batch(cfgs, eps, prec=psfd.PSFD_C128)
@@ -153,7 +153,7 @@ def test_intensity_gradient_matches_oracle_adjoint(psfd):
 
 @pytest.fixture(scope="module")
 def c5_case():
-    cfg = dict(base_config(128, 128, 32, 60.0, theta_deg=6.0, pol=0), ml_kz_min=0.1)
+    cfg = dict(base_config(128, 128, 32, 60.0, theta_deg=6.0, pol=0), ml_kz_min=0.0)
     eps = _eps(cfg, 21)
     rng = np.random.default_rng(22)
     voxels = [(int(rng.integers(0, 32)), int(rng.integers(0, 128)), int(rng.integers(0, 128)))

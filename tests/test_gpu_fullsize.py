@@ -1,5 +1,6 @@
 """GPU parity at the full workload sizes, in the configuration the benchmark
-times (mixed-precision plans, grazing cutoff 0.1, device-built permittivity).
+times (mixed-precision plans, the multilayer operator on every order,
+device-built permittivity).
 
 * 256 x 256 x 48 (line/space layout, TE and TM): permittivity, operator,
   preconditioner and source element by element against the FP64 oracle; the
@@ -28,7 +29,7 @@ pytestmark = pytest.mark.gpu
 
 DEV = torch.device("cuda:0")
 EPS_ABS = eps_absorber_default()
-KZ_CUT = 0.1
+KZ_CUT = 0.0
 
 
 @pytest.fixture(scope="module")
