@@ -171,6 +171,20 @@ psfd_status psfd_precond_c64(psfd_plan_t p, const void* x, void* y);
 psfd_status psfd_solve(psfd_plan_t p, const void* b, const void* x0, void* E, double tol,
                        int32_t maxit, int32_t adjoint, psfd_info* info);
 
+/* psfd_solve with a caller-given shadow residual: BiCGSTAB leaves the choice
+ * of the shadow vector r^ open (any r^ with <r^, r0> != 0); psfd_solve takes
+ * r^ = r0.  shadow: device complex128 field (single-problem plan), the r^ of
+ * the first Krylov run; later runs (restarts from the current field) take
+ * their own starting residual.  A shadow with |<r^, r0>| <= 1e-30 ||r^|| ||r0||
+ * is a breakdown before the first step: that run ends with no iteration, E is
+ * unchanged, and the solve restarts from E with r^ = r (info.restarts counts
+ * the extra run).  Other arguments, results and errors as psfd_solve; an x0
+ * with a non-finite residual returns PSFD_ERR_ARG before E is written (both
+ * entry points). */
+psfd_status psfd_solve_shadow(psfd_plan_t p, const void* b, const void* x0, void* E, double tol,
+                              int32_t maxit, int32_t adjoint, const void* shadow,
+                              psfd_info* info);
+
 /* r = b - A E in FP64 (b = NULL: the analytic source psfd_rhs) and, if
  * norm2 != NULL, ||r||^2 (host, synchronises).  E, r: device complex128
  * fields; r must not overlap E or b.  The residual of equation

@@ -102,6 +102,7 @@ k_finalize(KState* ks_all, const double* __restrict__ part_all, int nblocks,
   if (STAGE == FIN_INIT || STAGE == FIN_RED0 || STAGE == FIN_RED3) run = true;
   else if (STAGE == FIN_RHO) run = (d == KS_RUN || d == KS_HALF);
   else if (STAGE == FIN_REPLACE) run = (d == KS_UPDATE);
+  else if (STAGE == FIN_SHADOW) run = (d == KS_RUN);
   else run = (d == KS_RUN);
   if (!run) return;
   constexpr int NV = (STAGE == FIN_INIT || STAGE == FIN_RED0) ? 1 : 3;
@@ -209,6 +210,17 @@ k_finalize(KState* ks_all, const double* __restrict__ part_all, int nblocks,
       }
     }
     if (acc[0] > ks->rmax2) ks->rmax2 = acc[0];
+  } else if constexpr (STAGE == FIN_SHADOW) {
+    // a caller-given shadow residual replaced rh after FIN_INIT: partials
+    // ||r||^2, sum conj(rh) r; ||rh||^2 is in red[0] (FIN_RED0 before this).
+    // rho = <rh, r> = 0 is a breakdown of the recurrence before its first step.
+    ks->rh_norm2 = ks->red[0];
+    const cplx<double> rho = {acc[1], acc[2]};
+    st2(ks->rho, rho);
+    if (!(sqrt(norm2(rho)) > 1e-30 * sqrt(ks->rh_norm2 * acc[0]))) {
+      ks->status = 1;
+      ks->done = KS_BREAK;
+    }
   } else if constexpr (STAGE == FIN_REPLACE) {
     // r was replaced by the true residual (host): partials ||r||^2, <rh, r>
     ks->rnorm2 = acc[0];
@@ -229,6 +241,7 @@ hipError_t launch_finalize(int stage, KState* ks, const double* part, int nblock
     case FIN_ALPHA: PSFD_FIN(FIN_ALPHA); break;
     case FIN_OMEGA: PSFD_FIN(FIN_OMEGA); break;
     case FIN_RHO: PSFD_FIN(FIN_RHO); break;
+    case FIN_SHADOW: PSFD_FIN(FIN_SHADOW); break;
     case FIN_REPLACE: PSFD_FIN(FIN_REPLACE); break;
     case FIN_RED3: PSFD_FIN(FIN_RED3); break;
     default: PSFD_FIN(FIN_RED0); break;

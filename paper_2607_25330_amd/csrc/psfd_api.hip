@@ -502,8 +502,11 @@ psfd_status norm2_group(struct psfd_plan* P, const cplx<double>* a) {
 // used, breakdown or idle) or after `maxit` launched iterations.  Problems
 // that request a reliable update (KS_UPDATE) are served by `on_update`
 // between chunks while the others keep iterating.
+// shadow (optional, complex128 [G] fields): the shadow residual of this run
+// in place of r (the recurrence then starts with rho = <shadow, r>).
 template <typename T, typename U>
-psfd_status run_bicgstab(struct psfd_plan* P, bool adjoint, int maxit, U&& on_update) {
+psfd_status run_bicgstab(struct psfd_plan* P, bool adjoint, int maxit, U&& on_update,
+                         const cplx<double>* shadow = nullptr) {
   cplx<T>** V = vecs<T>(P);
   const int64_t n = P->nfield;
   const int G = P->G;
@@ -514,6 +517,13 @@ psfd_status run_bicgstab(struct psfd_plan* P, bool adjoint, int maxit, U&& on_up
   const bool pc = P->use_pc;
   CHK(launch_k_init<T>(V[V_RH], V[V_R], V[V_P], V[V_V], V[V_Y], n, G, part, st));
   CHK(launch_finalize(FIN_INIT, ks, part, red_blocks(n, G), G, P->pp, st));
+  if (shadow) {
+    CHK(launch_k_scale_copy<T, double>(V[V_RH], shadow, nullptr, n, G, st));
+    CHK(launch_k_norm2<T>(V[V_RH], n, G, part, st));
+    CHK(launch_finalize(FIN_RED0, ks, part, red_blocks(n, G), G, P->pp, st));
+    CHK(launch_k_dot_rr<T>(V[V_RH], V[V_R], n, G, part, st));
+    CHK(launch_finalize(FIN_SHADOW, ks, part, red_blocks(n, G), G, P->pp, st));
+  }
 
   // The first operator of a composite (M then A^H) carries the update; the last carries the dot.
   auto apply = [&](const cplx<T>* in, cplx<T>* out, Fuse<T>& fz) -> hipError_t {
@@ -774,20 +784,22 @@ bool tune_wanted(bool dflt) {
 }
 
 psfd_status solve_body(struct psfd_plan* P, const cplx<double>* b_in, const cplx<double>* x0,
-                       cplx<double>* E, double tol, int maxit, bool adjoint, psfd_info* infos);
+                       cplx<double>* E, double tol, int maxit, bool adjoint, psfd_info* infos,
+                       const cplx<double>* shadow);
 
 // The solve runs on the plan's private stream, after the work already queued on
 // the caller's stream; it returns with that private stream drained.  b_in, x0,
 // E: stacked [G] fields; infos: [G].
 psfd_status solve_impl(struct psfd_plan* P, const void* b_in, const void* x0, void* E_out,
-                       double tol, int maxit, bool adjoint, psfd_info* infos) {
+                       double tol, int maxit, bool adjoint, psfd_info* infos,
+                       const void* shadow = nullptr) {
   CHK(hipEventRecord(P->join_ev, P->st));
   CHK(hipStreamWaitEvent(P->own_st, P->join_ev, 0));
   hipStream_t user = P->st;
   P->st = P->own_st;
   psfd_status s = solve_body(P, static_cast<const cplx<double>*>(b_in),
                              static_cast<const cplx<double>*>(x0), static_cast<cplx<double>*>(E_out),
-                             tol, maxit, adjoint, infos);
+                             tol, maxit, adjoint, infos, static_cast<const cplx<double>*>(shadow));
   hipError_t e = hipStreamSynchronize(P->own_st);
   P->st = user;
   if (s == PSFD_OK && e != hipSuccess) return fail(PSFD_ERR_HIP, hipGetErrorString(e));
@@ -800,8 +812,11 @@ psfd_status solve_impl(struct psfd_plan* P, const void* b_in, const void* x0, vo
 //   mixed plans: iterative refinement, each step a complex64 BiCGSTAB on the
 //   normalised FP64 residual to a relative tolerance of about 0.3 tol / r_rel.
 // A problem that has finished is idle in the group's later runs.
+// shadow: optional shadow residual of the first Krylov run (later runs take
+// their starting residual).
 psfd_status solve_body(struct psfd_plan* P, const cplx<double>* b_in, const cplx<double>* x0,
-                       cplx<double>* E, double tol, int maxit, bool adjoint, psfd_info* infos) {
+                       cplx<double>* E, double tol, int maxit, bool adjoint, psfd_info* infos,
+                       const cplx<double>* shadow) {
   bool mixed = P->prec != PSFD_C128;
   const int G = P->G;
   CHKS(ensure_solver_common(P));
@@ -828,28 +843,34 @@ psfd_status solve_body(struct psfd_plan* P, const cplx<double>* b_in, const cplx
     bn2[i] = P->ks_host[i].red[0];
     if (!std::isfinite(bn2[i])) return fail(PSFD_ERR_ARG, "right-hand side is not finite");
   }
-  if (x0 && x0 != E)
-    CHK(hipMemcpyAsync(E, x0, sizeof(cplx<double>) * n * G, hipMemcpyDeviceToDevice, st));
-  if (!x0) CHK(hipMemsetAsync(E, 0, sizeof(cplx<double>) * n * G, st));
   for (int i = 0; i < G; ++i) {
     P->idle_host[i] = 0;
     if (bn2[i] == 0.0) {  // zero right-hand side: E = 0
-      CHK(hipMemsetAsync(E + i * n, 0, sizeof(cplx<double>) * n, st));
       fin[i] = 1;
       status[i] = PSFD_OK;
       P->idle_host[i] = 1;
     }
   }
-  CHKS(push_params(P));
+  CHKS(push_params(P));  // idle flags before the first operator apply
 
   cplx<double>* r64 = mixed ? P->res64 : P->v64[V_R];
+  if (x0) {  // the initial residual from x0 itself, so that a bad x0 leaves E untouched
+    CHKS(true_residual(P, b, x0, r64, adjoint));
+    for (int i = 0; i < G; ++i)
+      if (!fin[i] && !std::isfinite(P->ks_host[i].red[0]))
+        return fail(PSFD_ERR_ARG, "initial guess gives a non-finite residual");
+  }
+  if (x0 && x0 != E)
+    CHK(hipMemcpyAsync(E, x0, sizeof(cplx<double>) * n * G, hipMemcpyDeviceToDevice, st));
+  if (!x0) CHK(hipMemsetAsync(E, 0, sizeof(cplx<double>) * n * G, st));
+  for (int i = 0; i < G; ++i)
+    if (bn2[i] == 0.0) CHK(hipMemsetAsync(E + i * n, 0, sizeof(cplx<double>) * n, st));
+
   if (x0) {
-    CHKS(true_residual(P, b, E, r64, adjoint));
     for (int i = 0; i < G; ++i) {
       if (fin[i]) continue;
       loc[i].applies += 1;
       const double rr2 = P->ks_host[i].red[0];
-      if (!std::isfinite(rr2)) return fail(PSFD_ERR_ARG, "initial guess gives a non-finite residual");
       rrel[i] = std::sqrt(rr2 / bn2[i]);
       rn[i] = std::sqrt(rr2);
     }
@@ -1009,7 +1030,7 @@ psfd_status solve_body(struct psfd_plan* P, const cplx<double>* b_in, const cplx
     for (int i = 0; i < G; ++i) rejected[i] = 0;
     if (mixed) {
       CHK(launch_k_scale_copy<float, double>(P->v32[V_R], r64, P->pp, n, G, st));
-      CHKS(run_bicgstab<float>(P, adjoint, budget, on_update));
+      CHKS(run_bicgstab<float>(P, adjoint, budget, on_update, shadow));
       cplx<float>* y = P->v32[V_Y];
       CHKS(save_E());
       if (P->use_pc) {
@@ -1019,7 +1040,7 @@ psfd_status solve_body(struct psfd_plan* P, const cplx<double>* b_in, const cplx
         CHK(launch_k_axpy<double, float>(E, y, P->pp, n, G, st));
       }
     } else {
-      CHKS(run_bicgstab<double>(P, adjoint, budget, no_update));
+      CHKS(run_bicgstab<double>(P, adjoint, budget, no_update, shadow));
       cplx<double>* y = P->v64[V_Y];
       CHKS(save_E());
       if (P->use_pc) {
@@ -1029,6 +1050,7 @@ psfd_status solve_body(struct psfd_plan* P, const cplx<double>* b_in, const cplx
         CHK(launch_k_axpy<double, double>(E, y, P->pp, n, G, st));
       }
     }
+    shadow = nullptr;  // only the first run takes the caller's shadow residual
     std::vector<int> run_done(G, 0);
     for (int i = 0; i < G; ++i) {
       if (fin[i]) continue;
@@ -1681,6 +1703,17 @@ psfd_status psfd_solve(psfd_plan_t p, const void* b, const void* x0, void* E, do
   if (!(tol > 0) || maxit < 0) return fail(PSFD_ERR_ARG, "need tol > 0 and maxit >= 0");
   if (b && b == E) return fail(PSFD_ERR_ARG, "b and E must not overlap");
   return guarded([&] { return solve_impl(p, b, x0, E, tol, maxit, adjoint != 0, info); });
+}
+
+psfd_status psfd_solve_shadow(psfd_plan_t p, const void* b, const void* x0, void* E, double tol,
+                              int32_t maxit, int32_t adjoint, const void* shadow,
+                              psfd_info* info) {
+  if (!p || !E || !shadow || p->is_batch)
+    return fail(PSFD_ERR_ARG, "NULL argument or batch handle");
+  if (!(tol > 0) || maxit < 0) return fail(PSFD_ERR_ARG, "need tol > 0 and maxit >= 0");
+  if (b && b == E) return fail(PSFD_ERR_ARG, "b and E must not overlap");
+  if (shadow == E) return fail(PSFD_ERR_ARG, "shadow and E must not overlap");
+  return guarded([&] { return solve_impl(p, b, x0, E, tol, maxit, adjoint != 0, info, shadow); });
 }
 
 psfd_status psfd_residual(psfd_plan_t p, const void* b, const void* E, void* r, double* norm2) {

@@ -256,7 +256,8 @@ struct ProbParams {
   double pad;
 };
 
-enum FinStage { FIN_INIT = 0, FIN_ALPHA, FIN_OMEGA, FIN_RHO, FIN_RED0, FIN_REPLACE, FIN_RED3 };
+enum FinStage { FIN_INIT = 0, FIN_ALPHA, FIN_OMEGA, FIN_RHO, FIN_RED0, FIN_REPLACE, FIN_RED3,
+                FIN_SHADOW };
 // Krylov state of a problem (KState::done)
 enum { KS_RUN = 0, KS_CONV = 1, KS_HALF = 2, KS_BREAK = 3, KS_IDLE = 4, KS_MAXIT = 5, KS_UPDATE = 6 };
 // One block per problem: sum problem b's `nblocks` partials (they start at

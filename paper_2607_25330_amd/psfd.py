@@ -75,6 +75,8 @@ _SIGS = {
     "psfd_precond_c64": [c_void_p, c_void_p, c_void_p],
     "psfd_solve": [c_void_p, c_void_p, c_void_p, c_void_p, c_double, c_int32, c_int32,
                    ctypes.POINTER(Info)],
+    "psfd_solve_shadow": [c_void_p, c_void_p, c_void_p, c_void_p, c_double, c_int32, c_int32,
+                          c_void_p, ctypes.POINTER(Info)],
     "psfd_ml_reflection": [c_void_p, c_void_p, c_void_p],
     "psfd_residual": [c_void_p, c_void_p, c_void_p, c_void_p, c_dp],
     "psfd_eps_grad": [c_void_p, c_void_p, c_void_p, c_double, c_void_p],
@@ -350,17 +352,25 @@ class Plan:
         return complex(r[0], r[1])
 
     def solve(self, b=None, x0=None, tol=1e-6, maxit=20000, adjoint=False, out=None,
-              check=True):
-        """Returns (E, info dict).  With check=False a non-converged solve returns its status."""
+              check=True, shadow=None):
+        """Returns (E, info dict).  With check=False a non-converged solve returns its status.
+        shadow: the first Krylov run's shadow residual (psfd_solve_shadow)."""
         E = self._field() if out is None else out
         info = Info()
         bp = c_void_p(None) if b is None else _ptr(b, torch.complex128, self.shape, "b")
         xp = c_void_p(None) if x0 is None else _ptr(x0, torch.complex128, self.shape, "x0")
-        st = lib().psfd_solve(self._h, bp, xp, _ptr(E, torch.complex128, self.shape, "E"),
-                              c_double(tol), c_int32(maxit), c_int32(1 if adjoint else 0),
-                              ctypes.byref(info))
+        Ep = _ptr(E, torch.complex128, self.shape, "E")
+        if shadow is None:
+            name = "psfd_solve"
+            st = lib().psfd_solve(self._h, bp, xp, Ep, c_double(tol), c_int32(maxit),
+                                  c_int32(1 if adjoint else 0), ctypes.byref(info))
+        else:
+            name = "psfd_solve_shadow"
+            sp = _ptr(shadow, torch.complex128, self.shape, "shadow")
+            st = lib().psfd_solve_shadow(self._h, bp, xp, Ep, c_double(tol), c_int32(maxit),
+                                         c_int32(1 if adjoint else 0), sp, ctypes.byref(info))
         if check and st != PSFD_OK:
-            raise PsfdError("psfd_solve", st, lib().psfd_last_error().decode())
+            raise PsfdError(name, st, lib().psfd_last_error().decode())
         return E, {"iters": info.iters, "status": STATUS_NAMES.get(st, st),
                    "restarts": info.restarts, "applies": info.applies,
                    "rrel": info.rrel_true, "rrel_rec": info.rrel_hist_last}

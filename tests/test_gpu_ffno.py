@@ -4,7 +4,7 @@ weights exist here) shared by both sides as FP32 values.
 
 * grids with non-power-of-two and unequal sizes, all three (d_v, d_h) pairs,
   one to four layers, asymmetric mode counts, ragged row blocks and odd nz,
-  kx_max above 15;
+  kx_max above 15 on rows taken by the scalar and by the 16-byte x kernels;
 * output E (complex128, the solver's layout) within 2e-5 of max |E| (FP32
   hidden state and transforms, FP64 oracle);
 * the prediction serves as the solver's warm start: a solve from it reaches
@@ -47,6 +47,9 @@ CASES = [
     # four z rows at a time), kx_max > 15 (the wider x kernels)
     dict(nx=30, ny=18, nz=11, d_v=8, d_h=16, n_layers=2, kx_max=4, ky_max=3, kz_max=2),
     dict(nx=70, ny=22, nz=13, d_v=16, d_h=32, n_layers=1, kx_max=20, ky_max=5, kz_max=6),
+    # rows whose length is a multiple of 4 but not of 64 with kx_max > 15: the 16-byte
+    # load / store x kernels with the wider mode count
+    dict(nx=72, ny=20, nz=12, d_v=16, d_h=32, n_layers=2, kx_max=20, ky_max=5, kz_max=4),
 ]
 
 

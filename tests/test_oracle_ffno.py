@@ -128,3 +128,78 @@ def test_shift_equivariance_without_coordinates(axis, shift):
     E = F.forward(d, w, a)
     Es = F.forward(d, w, np.roll(a, shift, axis=axis))
     assert np.abs(Es - np.roll(E, shift, axis=axis + 1)).max() < 1e-11 * np.abs(E).max()
+
+
+def test_lift_channel_order_by_hand():
+    """Lifting P [a, x/nx, y/ny, z/nz] + p at single voxels of a non-square grid,
+    with distinct weights on every input channel."""
+    d = _desc(nx=7, ny=6, nz=5, d_v=2)
+    wts = {"P": np.array([[1.5, 2.0, -3.0, 5.0], [-0.5, 7.0, 11.0, -13.0]]),
+           "p": np.array([0.25, -0.75])}
+    rng = np.random.default_rng(9)
+    a = rng.random((5, 6, 7))
+    v = F.lift(d, wts, a)
+    for (z, y, x) in [(0, 0, 0), (3, 5, 2), (4, 1, 6), (2, 3, 1)]:
+        for c in range(2):
+            P = wts["P"][c]
+            want = P[0] * a[z, y, x] + P[1] * x / 7 + P[2] * y / 6 + P[3] * z / 5 + wts["p"][c]
+            assert abs(v[c, z, y, x] - want) < 1e-14
+
+
+def _inert_layers(wts):
+    """Zero spectral kernels and zero second MLP layer: every layer leaves v unchanged
+    (gelu(0) = 0 and the residual keeps v)."""
+    for lw in wts["layers"]:
+        for k in ("Kxy", "Kz", "W2", "b2"):
+            lw[k][...] = 0.0
+
+
+def test_decode_interleave_by_hand():
+    """With layers that leave the hidden state unchanged, E_c = (Q v + q)[2c] + i (Q v + q)[2c+1]
+    at each voxel, v the lifted input."""
+    d = _desc(nx=7, ny=6, nz=5, d_v=2, d_h=3, n_layers=2)
+    w = ffno_weights(d, 8).astype(np.float64)
+    wts = F.unpack(d, w)
+    _inert_layers(wts)
+    flat = np.concatenate([wts["P"].ravel(), wts["p"]]
+                          + [np.concatenate([lw[k].ravel() for k in ("Kxy", "Kz", "W1", "b1", "W2", "b2")])
+                             for lw in wts["layers"]]
+                          + [wts["Q"].ravel(), wts["q"]])
+    rng = np.random.default_rng(10)
+    a = rng.random((5, 6, 7))
+    E = F.forward(d, flat, a)
+    assert E.shape == (3, 5, 6, 7)
+    Q, q, P, p = wts["Q"], wts["q"], wts["P"], wts["p"]
+    for (z, y, x) in [(0, 0, 0), (3, 5, 2), (4, 1, 6)]:
+        feats = [a[z, y, x], x / 7, y / 6, z / 5]
+        v = [sum(P[c, k] * feats[k] for k in range(4)) + p[c] for c in range(2)]
+        for comp in range(3):
+            re = sum(Q[2 * comp, c] * v[c] for c in range(2)) + q[2 * comp]
+            im = sum(Q[2 * comp + 1, c] * v[c] for c in range(2)) + q[2 * comp + 1]
+            assert abs(E[comp, z, y, x] - complex(re, im)) < 1e-13
+
+
+def test_layer_on_uniform_state_by_hand():
+    """A spatially uniform hidden state only meets the (0, 0) lateral and the 0 axial
+    mode: u_xy = Re K_xy(0,0) v, u_z = Re K_z(0) u_xy, and the layer output is
+    v + gelu(W2 gelu(W1 (u_xy + u_z) + b1) + b2), all written out as sums."""
+    d = _desc(nx=7, ny=6, nz=5, d_v=2, d_h=3, kx_max=2, ky_max=1, kz_max=1)
+    w = ffno_weights(d, 11).astype(np.float64)
+    lw = F.unpack(d, w)["layers"][0]
+    lw["Kxy"] = 20.0 * lw["Kxy"]                      # spectral outputs of order one
+    lw["Kz"] = 20.0 * lw["Kz"]
+    v0 = np.array([0.7, -1.3])
+    v = np.broadcast_to(v0[:, None, None, None], (2, 5, 6, 7)).copy()
+    out = F.layer(d, lw, v, last=False)
+    kxy = lw["Kxy"][:, :, d["ky_max"], 0, 0]          # Re K_xy at kx = ky = 0
+    kz = lw["Kz"][:, :, 0, 0]                          # Re K_z at kz = 0
+    uxy = [sum(kxy[o, i] * v0[i] for i in range(2)) for o in range(2)]
+    uz = [sum(kz[o, i] * uxy[i] for i in range(2)) for o in range(2)]
+    s = [uxy[i] + uz[i] for i in range(2)]
+    gel = lambda t: 0.5 * t * (1 + math.erf(t / math.sqrt(2)))
+    h = [gel(sum(lw["W1"][j, i] * s[i] for i in range(2)) + lw["b1"][j]) for j in range(3)]
+    for o in range(2):
+        t = sum(lw["W2"][o, j] * h[j] for j in range(3)) + lw["b2"][o]
+        want = v0[o] + gel(t)
+        assert np.abs(out[o] - want).max() < 1e-13
+    assert abs(s[0]) > 0.05 and abs(s[1]) > 0.05      # the W1 input is not zero
