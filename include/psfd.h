@@ -116,6 +116,23 @@ typedef struct {
 psfd_status psfd_layout_eps(const psfd_desc* d, const double* a_bin_dev, const double eps_abs[2],
                             double sigma, void* eps_out, void* hip_stream);
 
+/* psfd_layout_eps for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * same arguments and result (equal up to the last bits of the twiddles, which
+ * are generated on the device here).  It calls no hipMalloc / hipFree and
+ * does not synchronise: the work is queued on hip_stream, and eps_out is
+ * ready when the stream reaches that point.  Its workspace is a fixed
+ * library-owned device array of 8 MiB per GPU (two lateral planes and two
+ * twiddle tables), held until the process ends; the caller's current device
+ * must be the stream's device.
+ * Limits: nx * ny <= 512 * 512 (larger layouts return PSFD_ERR_ARG; use
+ * psfd_layout_eps).  Calls on one GPU share the workspace: calls that may
+ * overlap in time on one GPU (different streams without ordering between
+ * them) race and must be serialised by the caller. */
+psfd_status psfd_layout_eps_noalloc(const psfd_desc* d, const double* a_bin_dev,
+                                    const double eps_abs[2], double sigma, void* eps_out,
+                                    void* hip_stream);
+
 /* Build a plan (paper, section 2.2: lateral Bloch wavenumbers, PML stretch,
  * per-mode multilayer reflections r_TE and r_pE by the transfer-matrix
  * method, permittivity contrast).  eps_abs_dev: device, [nz_abs][ny][nx]

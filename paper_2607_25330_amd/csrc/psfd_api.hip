@@ -1284,6 +1284,73 @@ psfd_status plan_group_impl(int G, const psfd_desc* descs, const void* const* ep
   return PSFD_OK;
 }
 
+// ---- allocation-free layout smoothing
+// The workspace of psfd_layout_eps_noalloc: two lateral planes (the complex
+// layout and its spectrum) and the x and y twiddle tables, in one file-scope
+// device array.  Every GPU the library runs on holds its own copy for the
+// life of the process; host code reaches it only through the address
+// hipGetSymbolAddress returns for the current device (kept per device).
+constexpr int64_t kNoAllocPlane = 512 * 512;  // largest nx * ny
+constexpr int kNoAllocTw = 1024;               // largest nx, ny
+constexpr int64_t kNoAllocElems = 2 * kNoAllocPlane + 2 * kNoAllocTw;
+static __device__ __align__(256) cplx<double> scratch[kNoAllocElems];
+
+constexpr int kNoAllocMaxDev = 64;
+std::mutex g_scratch_mu;
+cplx<double>* g_scratch_ptr[kNoAllocMaxDev] = {};
+
+psfd_status scratch_of_current_device(cplx<double>** out) {
+  int dev = -1;
+  CHK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kNoAllocMaxDev) return fail(PSFD_ERR_ARG, "device index out of range");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      return fail(PSFD_ERR_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch_ptr[dev] = static_cast<cplx<double>*>(ptr);
+  }
+  *out = g_scratch_ptr[dev];
+  return PSFD_OK;
+}
+
+// Same arithmetic as layout_impl; the twiddles are generated on the device
+// into the workspace instead of uploaded, and nothing is allocated, freed or
+// synchronised (the launches are queued on the caller's stream).
+psfd_status layout_noalloc_impl(const psfd_desc* d, const double* a_bin, const double eps_abs[2],
+                                double sigma, void* eps_out, void* stream) {
+  if (!d || !a_bin || !eps_abs || !eps_out) return fail(PSFD_ERR_ARG, "NULL argument");
+  if (!lateral_size_ok(d->nx) || !lateral_size_ok(d->ny) || d->nz_abs < 1)
+    return fail(PSFD_ERR_ARG, "unsupported lateral size or nz_abs < 1");
+  if ((int64_t)d->nx * d->ny > kNoAllocPlane || d->nx > kNoAllocTw || d->ny > kNoAllocTw)
+    return fail(PSFD_ERR_ARG, "psfd_layout_eps_noalloc takes nx * ny <= 512 * 512 (its fixed "
+                              "workspace); use psfd_layout_eps for larger layouts");
+  if (!(sigma >= 0) || !(d->dx > 0) || !(d->dy > 0)) return fail(PSFD_ERR_ARG, "bad sigma/dx/dy");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  cplx<double>* ws = nullptr;
+  CHKS(scratch_of_current_device(&ws));
+  const int nx = d->nx, ny = d->ny;
+  cplx<double>* A = ws;
+  cplx<double>* B = ws + kNoAllocPlane;
+  cplx<double>* twx = ws + 2 * kNoAllocPlane;
+  cplx<double>* twy = twx + kNoAllocTw;
+  CHK(launch_twiddles(twx, nx, st));
+  CHK(launch_twiddles(twy, ny, st));
+  OpTables<double> t{};
+  t.nx = nx; t.ny = ny; t.nz = 1; t.nabs = 1; t.j0 = 0;
+  t.tw_x = twx;
+  t.tw_y = twy;
+  CHK(launch_real_to_cplx(a_bin, nx * ny, A, st));
+  CHK(launch_plane_fft<double>(t, A, B, false, st));
+  CHK(launch_smooth_mult(B, nx, ny, d->dx, d->dy, sigma, st));
+  CHK(launch_plane_fft<double>(t, B, A, true, st));
+  CHK(launch_fill_eps(A, nx, ny, d->nz_abs, 1.0 / ((double)nx * ny), d->eps_bg,
+                      cplx<double>{eps_abs[0], eps_abs[1]}, static_cast<cplx<double>*>(eps_out),
+                      st));
+  return PSFD_OK;
+}
+
 psfd_status plan_impl(const psfd_desc* d, const void* eps, void* stream, struct psfd_plan** out) {
   const void* e[1] = {eps};
   return plan_group_impl(1, d, e, stream, out);
@@ -1660,6 +1727,12 @@ extern "C" {
 psfd_status psfd_layout_eps(const psfd_desc* d, const double* a_bin_dev, const double eps_abs[2],
                             double sigma, void* eps_out, void* hip_stream) {
   return guarded([&] { return layout_impl(d, a_bin_dev, eps_abs, sigma, eps_out, hip_stream); });
+}
+
+psfd_status psfd_layout_eps_noalloc(const psfd_desc* d, const double* a_bin_dev,
+                                    const double eps_abs[2], double sigma, void* eps_out,
+                                    void* hip_stream) {
+  return guarded([&] { return layout_noalloc_impl(d, a_bin_dev, eps_abs, sigma, eps_out, hip_stream); });
 }
 
 psfd_status psfd_plan(const psfd_desc* d, const void* eps_abs_dev, void* hip_stream,

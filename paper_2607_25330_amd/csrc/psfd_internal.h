@@ -172,6 +172,8 @@ hipError_t launch_fill_eps(const cplx<double>* plane, int nx, int ny, int nabs, 
                            double eps_bg, cplx<double> eps_abs, cplx<double>* eps_out,
                            hipStream_t st);
 hipError_t launch_real_to_cplx(const double* a, int n, cplx<double>* out, hipStream_t st);
+// w[m] = exp(-2 pi i m / n), m < n (w: device)
+hipError_t launch_twiddles(cplx<double>* w, int n, hipStream_t st);
 // out[j][i] = rows[j] for j < nrows, i < plane (rows: device)
 hipError_t launch_fill_rows(const cplx<double>* rows, int64_t plane, int nrows,
                             cplx<double>* out, hipStream_t st);

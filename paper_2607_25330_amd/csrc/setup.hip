@@ -207,6 +207,20 @@ hipError_t launch_real_to_cplx(const double* a, int n, cplx<double>* out, hipStr
   return hipGetLastError();
 }
 
+// DFT twiddles w[m] = exp(-2 pi i m / n), m < n, in FP64 on the device.
+__global__ void k_twiddles(cplx<double>* __restrict__ w, int n) {
+  const int m = blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= n) return;
+  double s, c;
+  sincospi(-2.0 * (double)m / (double)n, &s, &c);
+  w[m] = {c, s};
+}
+
+hipError_t launch_twiddles(cplx<double>* w, int n, hipStream_t st) {
+  hipLaunchKernelGGL(k_twiddles, dim3((n + 255) / 256), dim3(256), 0, st, w, n);
+  return hipGetLastError();
+}
+
 // Row values broadcast over every lateral point: out[j][i] = rows[j].
 __global__ void k_fill_rows(const cplx<double>* __restrict__ rows, int64_t plane,
                             cplx<double>* __restrict__ out) {

@@ -64,6 +64,7 @@ class FfnoDesc(ctypes.Structure):
 
 _SIGS = {
     "psfd_layout_eps": [ctypes.POINTER(Desc), c_void_p, c_dp, c_double, c_void_p, c_void_p],
+    "psfd_layout_eps_noalloc": [ctypes.POINTER(Desc), c_void_p, c_dp, c_double, c_void_p, c_void_p],
     "psfd_plan": [ctypes.POINTER(Desc), c_void_p, c_void_p, ctypes.POINTER(c_void_p)],
     "psfd_set_eps": [c_void_p, c_void_p],
     "psfd_rhs": [c_void_p, c_void_p],
@@ -186,6 +187,24 @@ def psfd_layout_eps(cfg, a_bin, eps_abs, sigma=None):
     sig = cfg.get("smooth_sigma", 1.0) if sigma is None else sigma
     _call("psfd_layout_eps", ctypes.byref(d), _ptr(a, torch.float64, (cfg["ny"], cfg["nx"]), "a_bin"),
           ctypes.cast(ea, c_dp), c_double(sig), _ptr(out, torch.complex128), _stream_handle())
+    return out
+
+
+def psfd_layout_eps_noalloc(cfg, a_bin, eps_abs, sigma=None, out=None):
+    """psfd_layout_eps through the allocation-free entry point (nx * ny <= 512^2);
+    queued on the current stream, no synchronisation."""
+    d, keep = make_desc(cfg)
+    a = a_bin.to(torch.float64).contiguous()
+    if out is None:
+        out = torch.empty((cfg["nz_abs"], cfg["ny"], cfg["nx"]), dtype=torch.complex128,
+                          device=a.device)
+    e = complex(eps_abs)
+    ea = (c_double * 2)(e.real, e.imag)
+    sig = cfg.get("smooth_sigma", 1.0) if sigma is None else sigma
+    _call("psfd_layout_eps_noalloc", ctypes.byref(d),
+          _ptr(a, torch.float64, (cfg["ny"], cfg["nx"]), "a_bin"), ctypes.cast(ea, c_dp),
+          c_double(sig), _ptr(out, torch.complex128, (cfg["nz_abs"], cfg["ny"], cfg["nx"]), "out"),
+          _stream_handle())
     return out
 
 
