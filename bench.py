@@ -64,6 +64,8 @@ def run_steps(psfd, cfgs, a_dev, idx, prec, tol, maxit, profile=None, sched=None
             if profile:
                 plan.profile_enable(profile)
             _, info = plan.solve(tol=tol, maxit=maxit, check=False)
+            if str(info["status"]).startswith("ERR"):
+                raise RuntimeError(f"solve failed: {info['status']}: {psfd.lib().psfd_last_error().decode()}")
             if profile:
                 ms, n, b = plan.profile_read()
                 prof[0] += ms
@@ -74,16 +76,16 @@ def run_steps(psfd, cfgs, a_dev, idx, prec, tol, maxit, profile=None, sched=None
     return infos, prof
 
 
-def cpu_leg(iters_proj, sample_iters):
-    """Oracle timing on the host: setup + `sample_iters` BiCGSTAB iterations of the
-    same workload (first layout, TE), projected to a full solve with the GPU's
-    FP64 iteration count.  Runs single-threaded (pocketfft is single-threaded;
-    BLAS threads are pinned to 1 by the caller)."""
+def cpu_leg(iters_proj, sample_iters, layout_index=0):
+    """Oracle timing on the host: setup + `sample_iters` BiCGSTAB iterations of one
+    layout of the same workload (TE), projected to a full solve with the GPU's FP64
+    iteration count.  The oracle as it stands: numpy FP64, pocketfft (one thread);
+    the caller pins the BLAS/OpenMP threads to 1."""
     import numpy as np
     from oracle import psfd_ref as R
     from psfd_synth import config_c2, eps_absorber_default
     cfg = dict(config_c2(0), ml_kz_min=ML_KZ_MIN)
-    a = layouts(1, cfg["nx"], cfg["ny"], cfg["dx"])[0]
+    a = layouts(layout_index + 1, cfg["nx"], cfg["ny"], cfg["dx"])[layout_index]
     t0 = time.perf_counter()
     P = R.Problem(cfg, R.eps_from_fill(cfg, R.smooth_layout(cfg, a), eps_absorber_default()))
     b = R.rhs(P)
@@ -92,50 +94,144 @@ def cpu_leg(iters_proj, sample_iters):
     _, iters, _ = R.bicgstab_core(lambda u: R.apply_A(P, u), lambda u: R.apply_M(P, u), b, bnorm,
                                   1e-30, sample_iters)
     t2 = time.perf_counter()
-    info = {"iters": iters}
     per_iter = (t2 - t1) / max(iters, 1)
     setup = t1 - t0
-    solve_s = setup + per_iter * iters_proj
-    return {"value": 1.0 / solve_s, "unit": "solves/s", "cores": 1, "kind": "oracle",
-            "sample": (f"numpy FP64 oracle, first layout TE: setup {setup:.2f} s + "
-                       f"{info['iters']} BiCGSTAB iterations at {per_iter:.2f} s/iteration, "
-                       f"projected to {iters_proj:.0f} iterations (GPU FP64 mean); wall "
-                       f"{t2 - t0:.1f} s"),
-            "s_per_iteration": per_iter, "setup_s": setup, "projected": True}
+    return {"solve_s": setup + per_iter * iters_proj, "s_per_iteration": per_iter,
+            "setup_s": setup, "iters": iters, "wall_s": t2 - t0}
 
 
-# the files the inverse x pass (the roofline kernel) is compiled from
-ROOFLINE_KERNEL_SOURCES = ["cplx.h", "fft_core.h", "fft_lateral.hip", "psfd_internal.h", "reduce.h"]
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
-def _sources_hash():
-    """SHA-256 over the roofline kernel's sources (file name + bytes, sorted by name)."""
+def cpu_baseline(iters_proj, sample_iters, workers):
+    """The oracle on the host, two modes: one process (one core), and `workers`
+    single-threaded processes on different layouts at once (all cores of the
+    share: aggregate solves/s).  Each process projects a full solve from a sample
+    of iterations."""
+    env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1",
+               MKL_NUM_THREADS="1", HIP_VISIBLE_DEVICES="", CUDA_VISIBLE_DEVICES="")
+
+    def spawn(k):
+        return subprocess.Popen([sys.executable, os.path.abspath(__file__), "--ml-kz-min", str(ML_KZ_MIN),
+                                 "--cpu-leg", str(iters_proj), "--cpu-sample-iters", str(sample_iters),
+                                 "--cpu-layout", str(k)], stdout=subprocess.PIPE,
+                                stderr=subprocess.PIPE, text=True, env=env)
+
+    def gather(procs):
+        out = []
+        for p in procs:
+            so, se = p.communicate(timeout=900)
+            if p.returncode != 0:
+                raise RuntimeError(se[-500:])
+            out.append(json.loads(so.strip().splitlines()[-1]))
+        return out
+    t = time.perf_counter()
+    one = gather([spawn(0)])[0]
+    t_one = time.perf_counter() - t
+    t = time.perf_counter()
+    many = gather([spawn(k % 4) for k in range(workers)])
+    t_many = time.perf_counter() - t
+    agg = sum(1.0 / r["solve_s"] for r in many)
+    return {"value": round(agg, 6), "unit": "solves/s", "cores": workers, "kind": "oracle",
+            "sample": (f"numpy FP64 oracle (one thread per process), {workers} processes at once on "
+                       f"the workload's layouts 0-3 (TE): setup + {sample_iters} BiCGSTAB iterations "
+                       f"each, projected to {iters_proj:.0f} iterations (GPU FP64 mean); aggregate of "
+                       f"the {workers} projected solve rates; wall {t_many:.1f} s"),
+            "projected": True,
+            "single_core": {"value": round(1.0 / one["solve_s"], 6), "unit": "solves/s", "cores": 1,
+                            "s_per_iteration": round(one["s_per_iteration"], 3),
+                            "setup_s": round(one["setup_s"], 2), "wall_s": round(t_one, 1)},
+            "all_cores_s_per_iteration_mean": round(sum(r["s_per_iteration"] for r in many) / workers, 3),
+            "host": {"os_cpu_count": os.cpu_count(), "cpu_model": cpu_model(),
+                     "threads_per_process": 1, "fft": "numpy.fft (pocketfft)"}}
+
+
+# the files each timed kernel class is compiled from (the counter summaries record a hash)
+KERNEL_SOURCES = {
+    "xinv": ["cplx.h", "fft_core.h", "fft_lateral.hip", "psfd_internal.h", "reduce.h"],
+    "xfwd": ["cplx.h", "fft_core.h", "fft_lateral.hip", "psfd_internal.h", "reduce.h"],
+    "yfft": ["cplx.h", "fft_core.h", "fft_lateral.hip", "psfd_internal.h"],
+    "axial": ["cplx.h", "fft_core.h", "lane_fft.h", "axial.hip", "psfd_internal.h"],
+}
+KERNEL_NAMES = {"axial": "k_axial_reg / k_axial (axial column kernel)", "xinv": "k_xfft_inv",
+                "xfwd": "k_xfft_fwd", "yfft": "k_yfft"}
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_256x256x48_mixed.md")
+
+
+def _sources_hash(kernel):
+    """SHA-256 over a kernel class's sources (file name + bytes, sorted by name)."""
     import hashlib
     h = hashlib.sha256()
-    for name in sorted(ROOFLINE_KERNEL_SOURCES):
+    for name in sorted(KERNEL_SOURCES[kernel]):
         h.update(name.encode())
         with open(os.path.join(ROOT, "paper_2607_25330_amd", "csrc", name), "rb") as f:
             h.update(f.read())
     return h.hexdigest()
 
 
-def measured_traffic(kernel, sched):
-    """HBM bytes per launch of `kernel` (run with schedule index `sched`) from
-    the committed counter summary (2 x FETCH_SIZE + WRITE_SIZE, calibrated on a
-    device copy), or None when there is none for that schedule or the kernel
-    sources changed since the counters were taken."""
-    import re
-    path = os.path.join(ROOT, "profiles", "traffic_256x256x48_mixed.md")
-    if not os.path.exists(path):
+def _traffic_text():
+    if not os.path.exists(TRAFFIC_FILE):
         return None
-    with open(path) as f:
-        text = f.read()
-    sha = re.search(r"^sources_sha256: ([0-9a-f]{64})$", text, re.M)
+    with open(TRAFFIC_FILE) as f:
+        return f.read()
+
+
+def measured_traffic(kernel, sched):
+    """HBM bytes per launch of `kernel` (schedule index `sched`) from the committed
+    counter summary (FETCH_SIZE and WRITE_SIZE scaled by a device copy's readings),
+    or None when there is none or the kernel's sources changed since."""
+    import re
+    text = _traffic_text()
+    if text is None:
+        return None
+    sha = re.search(r"^sources_sha256 %s: ([0-9a-f]{64})$" % re.escape(kernel), text, re.M)
     row = re.search(r"^traffic_bytes_per_launch %s sched %d: ([0-9.eE+]+)$" % (re.escape(kernel), sched),
                     text, re.M)
-    if not sha or not row or sha.group(1) != _sources_hash():
+    if not sha or not row or sha.group(1) != _sources_hash(kernel):
         return None
     return float(row.group(1))
+
+
+def measured_iteration_traffic():
+    """Counter bytes of one complex64 BiCGSTAB iteration (all its kernels) from the
+    committed summary, or None when any kernel class changed since."""
+    import re
+    text = _traffic_text()
+    if text is None:
+        return None
+    for k in KERNEL_SOURCES:
+        sha = re.search(r"^sources_sha256 %s: ([0-9a-f]{64})$" % re.escape(k), text, re.M)
+        if not sha or sha.group(1) != _sources_hash(k):
+            return None
+    row = re.search(r"^traffic_bytes_per_iteration: ([0-9.eE+]+)$", text, re.M)
+    return float(row.group(1)) if row else None
+
+
+def copy_peak_gbs(dev, mib=1024, reps=5):
+    """Device-to-device copy rate (read + write bytes / time) of a `mib` MiB buffer."""
+    import torch
+    n = mib * 1024 * 1024 // 16
+    src = torch.ones(n, dtype=torch.complex128, device=dev)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    best = 1e30
+    for _ in range(reps):
+        e0.record()
+        dst.copy_(src)
+        e1.record()
+        torch.cuda.synchronize()
+        best = min(best, e0.elapsed_time(e1))
+    del src, dst
+    return 2.0 * mib * 1024 * 1024 / (best * 1e-3) / 1e9
 
 
 def _sync_time(fn):
@@ -624,7 +720,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--tol", type=float, default=1e-6)
     ap.add_argument("--maxit", type=int, default=20000)
-    ap.add_argument("--roofline-kernel", default="xinv", choices=["axial", "yfft", "xfwd", "xinv"])
+    ap.add_argument("--roofline-kernel", default="axial", choices=["axial", "yfft", "xfwd", "xinv"],
+                    help="kernel class timed for the roofline object (the dominant one by rocprof)")
+    ap.add_argument("--no-profile", action="store_true",
+                    help="skip the untimed kernel-timing leg (no roofline object)")
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 leg")
     ap.add_argument("--no-tune", action="store_true",
                     help="default kernel schedules instead of the autotuner's (psfd_tune)")
@@ -633,6 +732,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-iters", type=int, default=4)
     ap.add_argument("--cpu-leg", type=float, default=None, help=argparse.SUPPRESS)
+    ap.add_argument("--cpu-layout", type=int, default=0, help=argparse.SUPPRESS)
+    ap.add_argument("--cpu-workers", type=int, default=16,
+                    help="oracle processes of the all-core CPU baseline (the box's CPU share)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run one device copy of this size (for counter calibration)")
     ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5", "fd", "contour", "pino", "ffno",
@@ -646,7 +748,7 @@ def main():
     ML_KZ_MIN = args.ml_kz_min
 
     if args.cpu_leg is not None:
-        print(json.dumps(cpu_leg(args.cpu_leg, args.cpu_sample_iters)))
+        print(json.dumps(cpu_leg(args.cpu_leg, args.cpu_sample_iters, args.cpu_layout)))
         return 0
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -710,22 +812,43 @@ def main():
             run_steps(psfd, cfgs, a_dev, range(K, K + W), psfd.PSFD_C128, args.tol, args.maxit)
     torch.cuda.synchronize()
 
-    # ---- timed: mixed precision (headline)
+    # ---- timed: mixed precision (headline); both timed legs replay graph-captured chunks
     t0 = time.perf_counter()
-    infos_m, prof = run_steps(psfd, cfgs, a_dev, range(K), prec_mixed, args.tol, args.maxit,
-                              profile=args.roofline_kernel, sched=forced)
+    infos_m, _ = run_steps(psfd, cfgs, a_dev, range(K), prec_mixed, args.tol, args.maxit,
+                           sched=forced)
     torch.cuda.synchronize()
     t_mixed = time.perf_counter() - t0
     print(f"bench: mixed leg {t_mixed:.3f} s", file=sys.stderr, flush=True)
 
-    # whole-apply and whole-iteration roofline (algorithmic bytes per voxel):
-    # one complex64 operator apply = read x + write y (48 B / voxel);
-    # one BiCGSTAB iteration = 20 field passes x 24 B = 480 B / voxel.
-    vox = 3 * nx * ny * (cfgs[0]["nz_abs"] + 16)  # complex elements of one field
+    res = {}
+    if not args.no_fp64:
+        t0 = time.perf_counter()
+        infos_d, _ = run_steps(psfd, cfgs, a_dev, range(K), psfd.PSFD_C128, args.tol, args.maxit)
+        torch.cuda.synchronize()
+        t_fp64 = time.perf_counter() - t0
+        print(f"bench: fp64 leg {t_fp64:.3f} s", file=sys.stderr, flush=True)
+        res["fp64"] = (t_fp64, infos_d)
+
+    # ---- untimed: the same mixed solves again with the roofline kernel's launches timed
+    # by HIP events that its launch packets record on the solver's stream (the chunks
+    # then run without graph replay; the kernels are the same)
+    prof_kernel = None if args.no_profile else args.roofline_kernel
+    prof = (0.0, 0, 0.0)
+    if prof_kernel is not None:
+        infos_p, prof = run_steps(psfd, cfgs, a_dev, range(K), prec_mixed, args.tol, args.maxit,
+                                  profile=prof_kernel, sched=forced)
+        torch.cuda.synchronize()
+        print(f"bench: profiled leg: {prof[1]} launches of {prof_kernel}", file=sys.stderr, flush=True)
+
+    # ---- untimed: one complex64 operator apply, the device copy rate
+    nz = cfgs[0]["nz_abs"] + 16
+    vox = nx * ny * nz                      # voxels of one problem
     eps0 = psfd.psfd_layout_eps(cfgs[0], a_dev[0], __import__("psfd_synth").eps_absorber_default())
     plan = psfd.Plan(cfgs[0], eps0, prec_mixed)
     if forced is not None:
         plan.set_schedule(forced)
+    elif schedules:
+        plan.set_schedule(schedules["mixed"])
     xa = torch.randn(plan.shape, dtype=torch.complex64, device=dev)
     ya = torch.empty_like(xa)
     for _ in range(3):
@@ -739,52 +862,62 @@ def main():
     apply_us = 1e3 * ev0.elapsed_time(ev1) / 20
     plan.close()
     del xa, ya, eps0
-
-    res = {}
-    if not args.no_fp64:
-        t0 = time.perf_counter()
-        infos_d, _ = run_steps(psfd, cfgs, a_dev, range(K), psfd.PSFD_C128, args.tol, args.maxit)
-        torch.cuda.synchronize()
-        t_fp64 = time.perf_counter() - t0
-        print(f"bench: fp64 leg {t_fp64:.3f} s", file=sys.stderr, flush=True)
-        res["fp64"] = (t_fp64, infos_d)
+    copy_gbs = copy_peak_gbs(dev)
 
     nsolve = 2 * K
     ok_m = all(i["status"] == "OK" and i["rrel"] <= args.tol for i in infos_m)
     value = nsolve / t_mixed
-    ms, nl, by = prof
-    knob = {"xfwd": 0, "xinv": 1, "yfft": 2, "axial": 3}[args.roofline_kernel]
-    kernel_sched = schedules["mixed"][knob] if schedules else 0
-    achieved = (by / (ms * 1e-3)) / 1e9 if ms > 0 else 0.0
-    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": measured_traffic(args.roofline_kernel, kernel_sched),
-                "kernel": args.roofline_kernel, "sched": kernel_sched, "launches": nl,
-                "avg_launch_us": round(1e3 * ms / max(nl, 1), 2),
-                "bytes_per_launch": by / max(nl, 1)}
+    it_m = max(1, sum(i["iters"] for i in infos_m))
+    # SURVEY-defined algorithmic bytes: one complex64 A.M apply moves 48 B per voxel
+    # (read x, write y: 3 components x 8 B each way); one BiCGSTAB iteration 480 B.
+    alg_apply = 48.0 * vox
+    alg_iter = 480.0 * vox
+    roofline = None
+    if prof_kernel is not None:
+        ms, nl, by = prof
+        knob = {"xfwd": 0, "xinv": 1, "yfft": 2, "axial": 3}[prof_kernel]
+        kernel_sched = schedules["mixed"][knob] if schedules else (forced[knob] if forced else 0)
+        avg_s = 1e-3 * ms / max(nl, 1)
+        achieved = alg_apply / avg_s / 1e9 if ms > 0 else 0.0
+        traffic = measured_traffic(prof_kernel, kernel_sched)
+        roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                    "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                    "traffic": traffic,
+                    "kernel": KERNEL_NAMES[prof_kernel], "kernel_class": prof_kernel,
+                    "sched": kernel_sched, "launches": nl, "avg_launch_us": round(1e6 * avg_s, 2),
+                    "alg_bytes_per_launch": alg_apply,
+                    "alg_basis": f"48 B/voxel (one complex64 A.M apply) x {vox} voxels per launch",
+                    "own_bytes_per_launch": round(by / max(nl, 1)),
+                    "own_gbs": round(by / max(nl, 1) / avg_s / 1e9, 1) if ms > 0 else None,
+                    "traffic_gbs": round(traffic / avg_s / 1e9, 1) if traffic and ms > 0 else None,
+                    "copy_peak_gbs": round(copy_gbs, 1),
+                    "frac_of_copy_peak": round(achieved / copy_gbs, 4) if copy_gbs else None}
+    it_traffic = measured_iteration_traffic()
     out = {
         "metric": METRIC, "value": round(value, 4), "unit": "solves/s", "n_gpus": 1,
         "steps": K, "warmup": W, "ms_per_step": round(1e3 * t_mixed / K, 2),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32+f64", "data": "synthetic",
-        "config": {"workload": workload_name(), "solves_per_step": 2, "grid": [256, 256, 48],
+        "config": {"workload": workload_name(), "solves_per_step": 2, "grid": [nx, ny, nz],
                    "ml_kz_min": ML_KZ_MIN,
                    "precision": "complex64 operator/Krylov, FP64 residual + refinement"},
         "converged": ok_m,
         "iters_mixed": [i["iters"] for i in infos_m],
         "rrel_mixed_max": max(i["rrel"] for i in infos_m),
         "roofline": roofline,
-        "apply_roofline": {"unit": "one complex64 operator apply A x", "alg_bytes": 2 * 8 * vox,
+        "apply_roofline": {"unit": "one complex64 operator apply A x", "alg_bytes": alg_apply,
                            "us": round(apply_us, 1),
-                           "achieved_gbs": round(2 * 8 * vox / (apply_us * 1e-6) / 1e9, 1),
-                           "frac": round(2 * 8 * vox / (apply_us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4)},
+                           "achieved_gbs": round(alg_apply / (apply_us * 1e-6) / 1e9, 1),
+                           "frac": round(alg_apply / (apply_us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4)},
         "iteration_roofline": {"unit": "one BiCGSTAB iteration (2 A.M applies + updates)",
-                               "alg_bytes": 20 * 8 * vox,
-                               "us": round(1e6 * t_mixed / max(1, sum(i["iters"] for i in infos_m)), 1),
-                               "achieved_gbs": round(20 * 8 * vox / (t_mixed / max(1, sum(i["iters"] for i in infos_m))) / 1e9, 1),
-                               "frac": round(20 * 8 * vox / (t_mixed / max(1, sum(i["iters"] for i in infos_m))) / 1e9 / HBM_PEAK_GBS, 4),
+                               "alg_bytes": alg_iter,
+                               "us": round(1e6 * t_mixed / it_m, 1),
+                               "achieved_gbs": round(alg_iter / (t_mixed / it_m) / 1e9, 1),
+                               "frac": round(alg_iter / (t_mixed / it_m) / 1e9 / HBM_PEAK_GBS, 4),
+                               "counter_bytes": it_traffic,
+                               "counter_over_alg": round(it_traffic / alg_iter, 3) if it_traffic else None,
                                "note": "time per iteration includes plan, source and the FP64 reliable updates"},
-        "schedules": schedules or "default",
+        "schedules": schedules or ("forced" if forced else "default"),
     }
     if "fp64" in res:
         t_fp64, infos_d = res["fp64"]
@@ -796,16 +929,11 @@ def main():
     if not args.no_cpu_baseline:
         iters_proj = (sum(i["iters"] for i in res["fp64"][1]) / nsolve if "fp64" in res
                       else sum(i["iters"] for i in infos_m) / nsolve)
-        env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1",
-                   MKL_NUM_THREADS="1", HIP_VISIBLE_DEVICES="", CUDA_VISIBLE_DEVICES="")
         print("bench: cpu baseline (oracle) ...", file=sys.stderr, flush=True)
-        cp = subprocess.run([sys.executable, os.path.abspath(__file__), "--ml-kz-min", str(ML_KZ_MIN), "--cpu-leg",
-                             str(iters_proj), "--cpu-sample-iters", str(args.cpu_sample_iters)],
-                            capture_output=True, text=True, env=env, timeout=600)
-        if cp.returncode == 0:
-            out["cpu_baseline"] = json.loads(cp.stdout.strip().splitlines()[-1])
-        else:
-            out["cpu_baseline"] = {"error": cp.stderr[-500:]}
+        try:
+            out["cpu_baseline"] = cpu_baseline(iters_proj, args.cpu_sample_iters, args.cpu_workers)
+        except Exception as exc:  # noqa: BLE001 - report, do not lose the GPU line
+            out["cpu_baseline"] = {"error": str(exc)[-500:]}
     print(json.dumps(out), flush=True)
     return 0
 

@@ -390,8 +390,12 @@ psfd_status psfd_ml_reflection(psfd_plan_t p, void* r_te, void* r_pe);
  * stream: 0 = off, 1 = axial column kernel, 2 = y-pass FFT, 3 = forward
  * x-pass FFT, 4 = inverse x-pass FFT with the combine epilogue.  Only
  * launches in the plan's working precision are timed (complex64 for the
- * PSFD_C64_* plans, whose FP64 residual applies are not counted).  Enabling
- * resets the counters.  psfd_profile_read returns (all host pointers):
+ * PSFD_C64_* plans, whose FP64 residual applies are not counted).  While
+ * timing is on, the solver launches its iteration chunks directly instead of
+ * replaying captured graphs (the kernels are the same); launches of
+ * iterations queued after the problem stopped (the kernels return at once)
+ * are not counted.  Enabling resets the counters.  psfd_profile_read returns
+ * (all host pointers):
  * total event time in ms, number of timed launches, and the algorithmic
  * bytes those launches move (each launch counts the complex elements it
  * must read and write once, at its element size). */

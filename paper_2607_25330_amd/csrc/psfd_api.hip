@@ -16,6 +16,7 @@
 #include <tuple>
 #include <cmath>
 #include <complex>
+#include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <new>
@@ -117,6 +118,14 @@ std::vector<cplx<double>> twiddles(int n) {
 }  // namespace
 
 
+// A timed launch: events before and after it, its algorithmic bytes, and the
+// Krylov iteration (within the chunk being launched) it belongs to, -1 outside.
+struct ProfPair {
+  hipEvent_t a = nullptr, b = nullptr;
+  double bytes = 0.0;
+  int iter = -1;
+};
+
 // Per-problem host data of a group.
 struct ProbInfo {
   double theta = 0, phi = 0, kx0 = 0, ky0 = 0, kz0 = 0;
@@ -178,12 +187,13 @@ struct psfd_plan {
   hipEvent_t join_ev = nullptr;
   hipGraphExec_t gexec[2][2] = {};  // captured iteration chunk [complex64?][adjoint?]
   bool use_graphs = true;
+  int cur_iter = -1;  // iteration (within the chunk being launched) of the next launches
 
   // kernel timing (psfd_profile_enable)
   int prof_kernel = 0;
   int prof_elem = 16;  // element size of the timed launches (the working precision)
   std::vector<hipEvent_t> ev_pool;
-  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_open;
+  std::vector<ProfPair> ev_open;
   double prof_ms = 0.0, prof_bytes = 0.0;
   int64_t prof_launches = 0;
 
@@ -199,7 +209,7 @@ struct psfd_plan {
         if (g) (void)hipGraphExecDestroy(g);
     if (own_st) (void)hipStreamDestroy(own_st);
     if (join_ev) (void)hipEventDestroy(join_ev);
-    for (auto& pr : ev_open) { ev_pool.push_back(pr.first); ev_pool.push_back(pr.second); }
+    for (auto& pr : ev_open) { ev_pool.push_back(pr.a); ev_pool.push_back(pr.b); }
     for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
     for (auto& a : allocs)
       if (!cache_put(alloc_dev, a.second, a.first)) (void)hipFree(a.first);
@@ -340,7 +350,9 @@ hipEvent_t take_event(struct psfd_plan* P) {
 
 // When kernel `which` is being timed (psfd_profile_enable), give the tables a
 // pair of events for the next launch: the launch packet records them at the
-// kernel's start and end, so the pair brackets the kernel alone.
+// kernel's start and end, so the pair brackets the kernel alone.  (Event-
+// record nodes captured into a graph do not update the events' timestamps on
+// replay with this HIP runtime, so timing runs the chunks without graphs.)
 template <typename T>
 hipError_t arm_events(struct psfd_plan* P, OpTables<T>& t, int which, double bytes) {
   t.prof_start = t.prof_stop = nullptr;
@@ -349,21 +361,43 @@ hipError_t arm_events(struct psfd_plan* P, OpTables<T>& t, int which, double byt
   if (!a || !b) return hipErrorOutOfMemory;
   t.prof_start = a;
   t.prof_stop = b;
-  P->ev_open.emplace_back(a, b);
-  P->prof_bytes += bytes;
-  P->prof_launches += 1;
+  P->ev_open.push_back(ProfPair{a, b, bytes, P->cur_iter});
   return hipSuccess;
 }
 
-// Fold completed event pairs into the totals (call after a stream sync).
-void collect_events(struct psfd_plan* P) {
+// Fold completed timed launches into the totals (after a stream sync).  A
+// chunk launches its iterations whether or not the problem is still running
+// (the kernels of a finished problem return at once): only launches of the
+// first `executed` iterations of the chunk count.
+void fold_pair(struct psfd_plan* P, const ProfPair& pr, int executed) {
+  if (pr.iter >= executed) return;
+  float ms = 0.f;
+  const hipError_t e = hipEventElapsedTime(&ms, pr.a, pr.b);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();  // the failed query must not surface at the next launch
+    return;
+  }
+  P->prof_ms += ms;
+  P->prof_bytes += pr.bytes;
+  P->prof_launches += 1;
+}
+
+void collect_events(struct psfd_plan* P, int executed = 1 << 30) {
   for (auto& pr : P->ev_open) {
-    float ms = 0.f;
-    if (hipEventElapsedTime(&ms, pr.first, pr.second) == hipSuccess) P->prof_ms += ms;
-    P->ev_pool.push_back(pr.first);
-    P->ev_pool.push_back(pr.second);
+    fold_pair(P, pr, executed);
+    P->ev_pool.push_back(pr.a);
+    P->ev_pool.push_back(pr.b);
   }
   P->ev_open.clear();
+}
+
+// Destroy the captured chunks (they hold the old schedules).
+void drop_graphs(struct psfd_plan* P) {
+  for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 2; ++j) {
+      if (P->gexec[i][j]) (void)hipGraphExecDestroy(P->gexec[i][j]);
+      P->gexec[i][j] = nullptr;
+    }
 }
 
 // Fusion hooks of one operator application: a vector update folded into the
@@ -473,7 +507,6 @@ psfd_status ensure_solver_common(struct psfd_plan* P) {
 psfd_status read_state(struct psfd_plan* P) {
   CHK(hipMemcpyAsync(P->ks_host, P->ks, sizeof(KState) * P->G, hipMemcpyDeviceToHost, P->st));
   CHK(hipStreamSynchronize(P->st));
-  if (!P->ev_open.empty()) collect_events(P);
   return PSFD_OK;
 }
 
@@ -543,6 +576,7 @@ psfd_status run_bicgstab(struct psfd_plan* P, bool adjoint, int maxit, U&& on_up
   int nb_v = 0, nb_t = 0, nb_s = 0;
   auto launch_iters = [&](int count) -> psfd_status {
     for (int i = 0; i < count; ++i) {
+      P->cur_iter = i;
       Fuse<T> fa;
       if (fuse_p) {
         fa.pre.mode = PRE_P;
@@ -580,6 +614,7 @@ psfd_status run_bicgstab(struct psfd_plan* P, bool adjoint, int maxit, U&& on_up
                                 st));
       CHK(launch_finalize(FIN_RHO, ks, part, red_blocks(n, G), G, P->pp, st));
     }
+    P->cur_iter = -1;
     return PSFD_OK;
   };
   // A full chunk is captured once per plan into a HIP graph and replayed:
@@ -589,6 +624,7 @@ psfd_status run_bicgstab(struct psfd_plan* P, bool adjoint, int maxit, U&& on_up
   hipGraphExec_t& gx = P->gexec[sizeof(T) == 4 ? 1 : 0][adjoint ? 1 : 0];
   const bool graphs = P->use_graphs && P->prof_kernel == PROF_OFF;
   int launched = 0;
+  int iter_seen = 0;  // iterations of this run (FIN_INIT set the counter to 0)
   while (launched < maxit) {
     if (graphs) {
       if (!gx) {
@@ -613,6 +649,11 @@ psfd_status run_bicgstab(struct psfd_plan* P, bool adjoint, int maxit, U&& on_up
       launched += chunk;
     }
     CHKS(read_state(P));
+    if (P->prof_kernel != PROF_OFF) {
+      // timed launches: single-problem plans count the chunk's executed iterations
+      collect_events(P, G == 1 ? P->ks_host[0].iter - iter_seen : (1 << 30));
+    }
+    if (G == 1) iter_seen = P->ks_host[0].iter;
     bool upd = false;
     for (int b = 0; b < G; ++b) upd = upd || P->ks_host[b].done == KS_UPDATE;
     if (upd) CHKS(on_update());
@@ -891,7 +932,15 @@ psfd_status solve_body(struct psfd_plan* P, const cplx<double>* b_in, const cplx
   // trip, which on the batched uneven workload cost 83 s against 47 s.
   // PSFD_RELIABLE=0 / 1 selects the restart form / reliable updates for
   // every plan.
-  constexpr double kDelta = 0.1;
+  static const double kDelta = [] {  // PSFD_RELIABLE_DELTA overrides (measurement aid)
+    const char* e = std::getenv("PSFD_RELIABLE_DELTA");
+    return (e && *e) ? std::atof(e) : 0.01;
+  }();
+  // PSFD_TRACE=1: one line per Krylov run end and per reliable update on stderr
+  static const bool trace = [] {
+    const char* e = std::getenv("PSFD_TRACE");
+    return e && *e && *e != '0';
+  }();
   const bool reliable = mixed && [G] {
     const char* e = std::getenv("PSFD_RELIABLE");
     return (e && *e) ? std::atoi(e) != 0 : G == 1;
@@ -901,20 +950,38 @@ psfd_status solve_body(struct psfd_plan* P, const cplx<double>* b_in, const cplx
   // problem whose residual does not drop below the one at its last accepted
   // point gets its previous E back (a diverged or drifted Krylov run never
   // worsens the returned field), and a mixed plan continues in FP64.
-  std::vector<double> rr_acc(G, 0.0);  // ||b - A E||^2 at the last accepted point
-  for (int i = 0; i < G; ++i) rr_acc[i] = rn[i] * rn[i];
+  // rr_acc: ||b - A E||^2 of the current field; rr_best: of the field kept in
+  // ebak64, the best accepted so far (copied there before a fold whenever the
+  // current field is the best).
+  std::vector<double> rr_acc(G, 0.0), rr_best(G, 0.0);
+  for (int i = 0; i < G; ++i) rr_acc[i] = rr_best[i] = rn[i] * rn[i];
   std::vector<int> rejected(G, 0);
   std::vector<int> stall(G, 0);  // complex64 runs in a row without progress
   const size_t fbytes = sizeof(cplx<double>) * (size_t)n;
   auto save_E = [&]() -> psfd_status {
-    CHK(hipMemcpyAsync(P->ebak64, E, fbytes * G, hipMemcpyDeviceToDevice, st));
+    for (int i = 0; i < G; ++i) {
+      if (!(rr_acc[i] <= rr_best[i])) continue;
+      CHK(hipMemcpyAsync(P->ebak64 + i * n, E + i * n, fbytes, hipMemcpyDeviceToDevice, st));
+      rr_best[i] = rr_acc[i];
+    }
     return PSFD_OK;
   };
-  auto keep_or_restore = [&](const std::vector<int>& mask, std::vector<int>& rej) -> psfd_status {
+  // After a fold E += s M y: the end of a Krylov run keeps the new field only if
+  // its residual fell below the current one; a reliable update inside a running
+  // Krylov process (relaxed) keeps it unless the residual is not finite or has
+  // grown 100-fold over the best (BiCGSTAB residuals are not monotone: an update
+  // on the way down from a spike may sit above the last one, and ending the run
+  // there would throw its Krylov space away).  A rejected fold gets the best field
+  // back.
+  constexpr double kGrow2 = 1e4;
+  auto keep_or_restore = [&](const std::vector<int>& mask, std::vector<int>& rej,
+                             bool relaxed) -> psfd_status {
     bool any = false;
     for (int i = 0; i < G; ++i) {
       rej[i] = 0;
-      if (!mask[i] || P->ks_host[i].red[0] < rr_acc[i]) continue;
+      if (!mask[i]) continue;
+      const double rr2 = P->ks_host[i].red[0];
+      if (relaxed ? (rr2 < kGrow2 * rr_best[i]) : (rr2 < rr_acc[i])) continue;
       CHK(hipMemcpyAsync(E + i * n, P->ebak64 + i * n, fbytes, hipMemcpyDeviceToDevice, st));
       rej[i] = 1;
       any = true;
@@ -952,11 +1019,15 @@ psfd_status solve_body(struct psfd_plan* P, const cplx<double>* b_in, const cplx
     CHK(launch_k_scale_copy<float, float>(y, y, P->pp, n, G, st));
     CHKS(true_residual(P, b, E, r64, adjoint));
     std::vector<int> rej(G, 0);
-    CHKS(keep_or_restore(upd, rej));
+    CHKS(keep_or_restore(upd, rej, true));
     for (int i = 0; i < G; ++i) {
       if (!upd[i]) continue;
       loc[i].applies += 2;
       const double rr2 = P->ks_host[i].red[0];
+      if (trace)
+        fprintf(stderr, "psfd trace: p%d update at run iter %d: recursive %.3e true %.3e %s\n", i,
+                P->ks_host[i].iter, std::sqrt(P->ks_host[i].rnorm2 / P->ks_host[i].bnorm2) * rn0[i] /
+                std::sqrt(bn2[i]), std::sqrt(rr2 / bn2[i]), rej[i] ? "REJECTED" : "ok");
       rrel[i] = std::sqrt(rr2 / bn2[i]);
       P->pp_host[i].iscale = std::isfinite(rr2) ? 1.0 / rn0[i] : 0.0;  // r = r_true / rn0
     }
@@ -1065,7 +1136,7 @@ psfd_status solve_body(struct psfd_plan* P, const cplx<double>* b_in, const cplx
     {
       std::vector<int> act(G, 0), rej(G, 0);
       for (int i = 0; i < G; ++i) act[i] = !fin[i];
-      CHKS(keep_or_restore(act, rej));
+      CHKS(keep_or_restore(act, rej, false));
     }
     bool escalate = false;
     for (int i = 0; i < G; ++i) {
@@ -1090,6 +1161,10 @@ psfd_status solve_body(struct psfd_plan* P, const cplx<double>* b_in, const cplx
       const bool progressed = rr2 < 0.0625 * rr_start[i];
       const bool failed = rejected[i] || run_done[i] == KS_BREAK;
       stall[i] = (failed && !progressed) ? stall[i] + 1 : 0;
+      if (trace)
+        fprintf(stderr, "psfd trace: p%d run %d (%s) ended: %d iters, done %d status %d, true rrel %.3e%s, "
+                "stall %d\n", i, outer[i], mixed ? "c64" : "fp64", P->ks_host[i].iter, run_done[i],
+                P->ks_host[i].status, rrel[i], rejected[i] ? " (fold rejected)" : "", stall[i]);
       if (mixed && rrel[i] > tol && stall[i] >= 2) escalate = true;
     }
     if (escalate) {
@@ -1100,6 +1175,11 @@ psfd_status solve_body(struct psfd_plan* P, const cplx<double>* b_in, const cplx
     }
   }
   for (int i = 0; i < G; ++i) {
+    // an unconverged problem returns its best field
+    if (status[i] != PSFD_OK && rr_best[i] < rr_acc[i] && std::isfinite(rr_best[i])) {
+      CHK(hipMemcpyAsync(E + i * n, P->ebak64 + i * n, fbytes, hipMemcpyDeviceToDevice, st));
+      rrel[i] = std::sqrt(rr_best[i] / bn2[i]);
+    }
     loc[i].iters = total[i];
     loc[i].rrel_true = rrel[i];
     loc[i].status = status[i];
@@ -2059,12 +2139,7 @@ psfd_status psfd_profile_read(psfd_plan_t p, double* total_ms, int64_t* launches
 psfd_status psfd_tune(psfd_plan_t p) {
   if (!p || p->is_batch) return fail(PSFD_ERR_ARG, "NULL argument or batch handle");
   return guarded([&]() -> psfd_status {
-    for (auto& row : p->gexec)  // captured chunks hold the old schedules
-      for (auto& g : row)
-        if (g) {
-          (void)hipGraphExecDestroy(g);
-          g = nullptr;
-        }
+    drop_graphs(p);  // captured chunks hold the old schedules
     CHKS(tune_plan(p));
     CHK(hipStreamSynchronize(p->st));
     return PSFD_OK;
@@ -2077,12 +2152,7 @@ psfd_status psfd_set_schedule(psfd_plan_t p, const int32_t* sched) {
     if (sched[k] < 0 || sched[k] > 3) return fail(PSFD_ERR_ARG, "schedule out of range");
   return guarded([&]() -> psfd_status {
     CHK(p->st ? hipStreamSynchronize(p->st) : hipDeviceSynchronize());
-    for (auto& row : p->gexec)
-      for (auto& g : row)
-        if (g) {
-          (void)hipGraphExecDestroy(g);
-          g = nullptr;
-        }
+    drop_graphs(p);
     TuneVal v;
     for (int k = 0; k < 4; ++k) v.v[k] = sched[k];
     set_sched(p->t64, v);

@@ -1,6 +1,6 @@
-"""Host-side logic of bench.py (no GPU): the traffic figure is taken from the
-committed counter summary only for the schedule it was measured with and only
-while the kernel sources are unchanged; runs on more than one GPU are refused."""
+"""Host-side logic of bench.py (no GPU): a counter figure is taken from the
+committed summary only for the schedule it was measured with and only while the
+kernel's sources are unchanged; runs on more than one GPU are refused."""
 
 import os
 import subprocess
@@ -11,21 +11,39 @@ import bench
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
-def test_traffic_lookup_matches_schedule_and_sources():
-    v = bench.measured_traffic("xinv", 3)
-    assert v is None or v > 0
-    assert bench.measured_traffic("xinv", 2) is None
-    assert bench.measured_traffic("axial", 3) is None
+def _summary(tmp_path, hashes, rows):
+    lines = [f"sources_sha256 {k}: {h}" for k, h in hashes.items()] + rows
+    p = tmp_path / "traffic.md"
+    p.write_text("\n".join(lines) + "\n")
+    return str(p)
 
 
-def test_traffic_lookup_void_when_sources_change(monkeypatch):
-    monkeypatch.setattr(bench, "_sources_hash", lambda: "0" * 64)
-    assert bench.measured_traffic("xinv", 3) is None
+def test_traffic_lookup_matches_schedule_and_sources(tmp_path, monkeypatch):
+    hashes = {k: bench._sources_hash(k) for k in bench.KERNEL_SOURCES}
+    monkeypatch.setattr(bench, "TRAFFIC_FILE", _summary(tmp_path, hashes, [
+        "traffic_bytes_per_launch axial sched 0: 1.5e8",
+        "traffic_bytes_per_iteration: 2.2e9"]))
+    assert bench.measured_traffic("axial", 0) == 1.5e8
+    assert bench.measured_traffic("axial", 1) is None
+    assert bench.measured_traffic("xinv", 0) is None
+    assert bench.measured_iteration_traffic() == 2.2e9
+
+
+def test_traffic_lookup_void_when_sources_change(tmp_path, monkeypatch):
+    hashes = {k: bench._sources_hash(k) for k in bench.KERNEL_SOURCES}
+    hashes["axial"] = "0" * 64
+    monkeypatch.setattr(bench, "TRAFFIC_FILE", _summary(tmp_path, hashes, [
+        "traffic_bytes_per_launch axial sched 0: 1.5e8",
+        "traffic_bytes_per_iteration: 2.2e9"]))
+    assert bench.measured_traffic("axial", 0) is None
+    assert bench.measured_iteration_traffic() is None
 
 
 def test_sources_hash_is_stable_and_covers_the_kernels():
-    h1 = bench._sources_hash()
-    assert h1 == bench._sources_hash() and len(h1) == 64
+    for k in bench.KERNEL_SOURCES:
+        h1 = bench._sources_hash(k)
+        assert h1 == bench._sources_hash(k) and len(h1) == 64
+    assert bench._sources_hash("axial") != bench._sources_hash("xinv")
 
 
 def test_more_than_one_gpu_is_refused():
