@@ -410,15 +410,25 @@ psfd_status psfd_profile_read(psfd_plan_t p, double* total_ms, int64_t* launches
  * (register-resident with L, 2L or L/2 lanes per column, or LDS-staged) -- and
  * keeps the fastest; results are cached per (precision, nx, ny, Nz, nz_abs,
  * group size) for the life of the process.  Synchronises the plan's stream.
- * Schedules change the rounding of the FFTs, never the operator.  A plan made
- * by psfd_plan uses the default schedules unless psfd_tune is called or
- * PSFD_TUNE=1 is set.  psfd_schedule writes the plan's current schedules to
+ * Schedules change the rounding of the FFTs, never the operator.  A table of
+ * earlier choices is read once per process from tune_table.txt next to the
+ * library (or the file PSFD_TUNE_FILE names; an empty name disables it):
+ * shapes it lists take their schedules without timing, in every plan.  Other
+ * shapes use the default schedules unless psfd_tune is called or PSFD_TUNE=1
+ * is set (batch groups are tuned unless PSFD_TUNE=0).  psfd_tune_save writes
+ * the process's table (the file's entries plus everything tuned since) to
+ * `path` (host string), in the file's format: one line per shape,
+ * "elem nx ny nz nabs group : xf xi y ax" (elem 4: complex64 plans, 8:
+ * complex128; group: problems per plan rounded up to a power of two).
+ * psfd_schedule writes the plan's
+ * current schedules to
  * sched[4] (host): forward x pass, inverse x pass, y pass (bit 0: radix-4
  * schedule, bit 1: half the rows / tile width), axial variant (0: L lanes,
  * 1: 2L lanes, 2: LDS-staged, 3: L/2 lanes).  psfd_set_schedule sets them
  * (both precisions) from sched[4] (host; values 0..3, else PSFD_ERR_ARG)
  * after draining the plan's stream. */
 psfd_status psfd_tune(psfd_plan_t p);
+psfd_status psfd_tune_save(const char* path);
 psfd_status psfd_schedule(psfd_plan_t p, int32_t* sched);
 psfd_status psfd_set_schedule(psfd_plan_t p, const int32_t* sched);
 

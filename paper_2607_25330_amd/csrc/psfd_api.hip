@@ -7,6 +7,7 @@
 // groups of compatible problems.  Every launch covers the whole group, the
 // Krylov scalars are per problem on the device, and a converged problem is
 // skipped by every kernel while the rest of its group iterates.
+#include <dlfcn.h>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -705,7 +706,10 @@ psfd_status rhs_group(struct psfd_plan* P, cplx<double>* b) {
 // schedule and tile width of the y pass, axial kernel variant) are chosen per
 // (precision, nx, ny, Nz, N_abs, group size rounded up to a power of two) by
 // timing the working-precision operator of the solve on the plan itself,
-// one knob at a time; the result is kept for the life of the process.
+// one knob at a time; the result is kept for the life of the process.  A
+// table of earlier choices (tune_table.txt next to the library, or the file
+// PSFD_TUNE_FILE names; written by psfd_tune_save) is read once per process:
+// shapes it lists take its schedules without timing.
 struct TuneKey {
   int elem, nx, ny, nz, nabs, gb;
   bool operator<(const TuneKey& o) const {
@@ -717,6 +721,43 @@ struct TuneVal {
 };
 std::mutex g_tune_mu;
 std::map<TuneKey, TuneVal> g_tune;
+std::once_flag g_tune_load_once;
+
+std::string tune_file_path() {
+  if (const char* e = std::getenv("PSFD_TUNE_FILE")) return e;  // "" disables the table
+  Dl_info info;
+  if (dladdr(reinterpret_cast<void*>(&tune_file_path), &info) && info.dli_fname) {
+    std::string so(info.dli_fname);
+    const size_t slash = so.rfind('/');
+    return (slash == std::string::npos ? std::string(".") : so.substr(0, slash)) + "/tune_table.txt";
+  }
+  return "";
+}
+
+// Lines "elem nx ny nz nabs group : xf xi y ax" ('#' starts a comment; elem is
+// 4 for complex64 plans, 8 for complex128); entries out of range are ignored.
+void load_tune_table() {
+  std::call_once(g_tune_load_once, [] {
+    const std::string path = tune_file_path();
+    if (path.empty()) return;
+    FILE* f = std::fopen(path.c_str(), "r");
+    if (!f) return;
+    char line[256];
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    while (std::fgets(line, sizeof line, f)) {
+      if (line[0] == '#') continue;
+      TuneKey k{};
+      TuneVal v;
+      if (std::sscanf(line, "%d %d %d %d %d %d : %d %d %d %d", &k.elem, &k.nx, &k.ny, &k.nz, &k.nabs,
+                      &k.gb, &v.v[0], &v.v[1], &v.v[2], &v.v[3]) != 10)
+        continue;
+      bool ok = k.elem == 4 || k.elem == 8;  // bytes of the real type
+      for (int i = 0; i < 4; ++i) ok = ok && v.v[i] >= 0 && v.v[i] <= 3;
+      if (ok) g_tune[k] = v;
+    }
+    std::fclose(f);
+  });
+}
 
 template <typename T>
 void set_sched(OpTables<T>& t, const TuneVal& v) {
@@ -726,8 +767,11 @@ void set_sched(OpTables<T>& t, const TuneVal& v) {
   t.sched_ax = v.v[3];
 }
 
+// Schedules from the table (or from an earlier tuning in this process); with
+// `timing`, a shape not yet known is tuned now, else it keeps the defaults.
 template <typename T>
-psfd_status autotune(struct psfd_plan* P) {
+psfd_status autotune(struct psfd_plan* P, bool timing) {
+  load_tune_table();
   int gb = 1;
   while (gb < P->G) gb *= 2;
   const TuneKey key{(int)sizeof(T), P->nx, P->ny, P->nz, P->nabs, gb};
@@ -739,6 +783,7 @@ psfd_status autotune(struct psfd_plan* P) {
       return PSFD_OK;
     }
   }
+  if (!timing) return PSFD_OK;
   CHKS(ensure_solver_common(P));
   if (sizeof(T) == 4) CHKS(ensure_fp32(P));
   CHKS(ensure_krylov<T>(P));
@@ -812,9 +857,9 @@ psfd_status autotune(struct psfd_plan* P) {
   return PSFD_OK;
 }
 
-psfd_status tune_plan(struct psfd_plan* P) {
-  if (P->prec == PSFD_C128) return autotune<double>(P);
-  return autotune<float>(P);
+psfd_status tune_plan(struct psfd_plan* P, bool timing) {
+  if (P->prec == PSFD_C128) return autotune<double>(P, timing);
+  return autotune<float>(P, timing);
 }
 
 // PSFD_TUNE=1 / 0 forces tuning on / off; otherwise `dflt`.
@@ -1357,7 +1402,7 @@ psfd_status plan_group_impl(int G, const psfd_desc* descs, const void* const* ep
   CHK(hipEventCreateWithFlags(&P->join_ev, hipEventDisableTiming));
   P->use_graphs = std::getenv("PSFD_NO_GRAPH") == nullptr;
   CHKS(set_eps_impl(P, eps));
-  if (tune_wanted(G > 1)) CHKS(tune_plan(P));
+  CHKS(tune_plan(P, tune_wanted(G > 1)));
   CHK(hipStreamSynchronize(P->st));
   guard.p = nullptr;
   *out = P;
@@ -1757,7 +1802,7 @@ psfd_status solve_batch_impl(struct psfd_plan* B, const void* const* x0, void* c
       std::vector<psfd_info> inf(G);
       struct psfd_plan* p = nullptr;
       psfd_status st = guarded([&] { return plan_group_impl(G, ds.data(), es.data(), ws, &p); });
-      if (st == PSFD_OK && G == 1 && tune_wanted(true)) st = guarded([&] { return tune_plan(p); });
+      if (st == PSFD_OK && G == 1) st = guarded([&] { return tune_plan(p, tune_wanted(true)); });
       if (st == PSFD_OK) {
         st = guarded([&]() -> psfd_status {
           CHKS(dalloc(p, &p->E64, (size_t)(p->nfield * G)));
@@ -2140,9 +2185,27 @@ psfd_status psfd_tune(psfd_plan_t p) {
   if (!p || p->is_batch) return fail(PSFD_ERR_ARG, "NULL argument or batch handle");
   return guarded([&]() -> psfd_status {
     drop_graphs(p);  // captured chunks hold the old schedules
-    CHKS(tune_plan(p));
+    CHKS(tune_plan(p, true));
     CHK(hipStreamSynchronize(p->st));
     return PSFD_OK;
+  });
+}
+
+psfd_status psfd_tune_save(const char* path) {
+  if (!path || !*path) return fail(PSFD_ERR_ARG, "NULL or empty path");
+  return guarded([&]() -> psfd_status {
+    load_tune_table();
+    FILE* f = std::fopen(path, "w");
+    if (!f) return fail(PSFD_ERR_ARG, std::string("cannot write ") + path);
+    std::fprintf(f, "# libpsfd kernel schedules (elem: 4 complex64 plans, 8 complex128): "
+                    "elem nx ny nz nabs group : xf xi y ax\n");
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    for (const auto& kv : g_tune)
+      std::fprintf(f, "%d %d %d %d %d %d : %d %d %d %d\n", kv.first.elem, kv.first.nx, kv.first.ny,
+                   kv.first.nz, kv.first.nabs, kv.first.gb, kv.second.v[0], kv.second.v[1],
+                   kv.second.v[2], kv.second.v[3]);
+    const bool ok = std::fclose(f) == 0;
+    return ok ? PSFD_OK : fail(PSFD_ERR_ARG, std::string("cannot write ") + path);
   });
 }
 

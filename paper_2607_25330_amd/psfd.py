@@ -98,6 +98,7 @@ _SIGS = {
     "psfd_ffno_sizes": [ctypes.POINTER(FfnoDesc), ctypes.POINTER(c_int64), ctypes.POINTER(c_int64)],
     "psfd_ffno_forward": [ctypes.POINTER(FfnoDesc), c_void_p, c_void_p, c_void_p, c_void_p, c_void_p],
     "psfd_tune": [c_void_p],
+    "psfd_tune_save": [ctypes.c_char_p],
     "psfd_schedule": [c_void_p, ctypes.POINTER(c_int32)],
     "psfd_set_schedule": [c_void_p, ctypes.POINTER(c_int32)],
 }
@@ -206,6 +207,11 @@ def psfd_layout_eps_noalloc(cfg, a_bin, eps_abs, sigma=None, out=None):
           c_double(sig), _ptr(out, torch.complex128, (cfg["nz_abs"], cfg["ny"], cfg["nx"]), "out"),
           _stream_handle())
     return out
+
+
+def tune_save(path):
+    """Write the process's kernel-schedule table (psfd_tune_save) to `path`."""
+    _call("psfd_tune_save", os.fsencode(str(path)))
 
 
 def trim_cache():
