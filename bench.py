@@ -325,22 +325,25 @@ def _log(msg):
 
 def workload_c4(psfd, args):
     """1024x1024 lateral, 48 absorber cells / 70 nm (Nz = 64), curvilinear layout, 6 deg, TE and
-    TM: FP64 reference to 1e-10, then mixed solves (complex64 Krylov; bf16-rounded damping
-    multiplier as the bf16 preconditioner trial) from null and from a warm start (reference +
-    smooth complex noise scaled to r_rel ~ 0.1)."""
+    TM: FP64 reference to 1e-9, then mixed solves (complex64 Krylov; and the bf16 preconditioner
+    trial, the damped spectrum held in bfloat16) from null and from a warm start (reference +
+    smooth complex noise scaled to r_rel ~ 0.1), and the plain FP64 solve."""
     import numpy as np
     import torch
     from psfd_synth import config_c4, curvilinear, eps_absorber_default
     dev = torch.device("cuda:0")
+    # the solver reports its residual every 512 iterations on stderr (long solves at this size)
+    os.environ.setdefault("PSFD_TRACE", "2")
     a = torch.from_numpy(curvilinear(1024, 1024, np.random.default_rng(400))).to(dev)
     out = {"metric": METRIC, "unit": "solves/s", "dtype": "f32+f64",
            "config": {"workload": "1024x1024x(48+16), 2 nm, 70 nm absorber, curvilinear, 6 deg, "
-                                  "grazing cutoff 0.1, tol %g" % args.tol}, "legs": {}}
+                                  "no grazing cutoff, tol %g" % args.tol}, "legs": {}}
     for pol in (0, 1):
         cfg = dict(config_c4(pol), ml_kz_min=ML_KZ_MIN)
         eps = psfd.psfd_layout_eps(cfg, a, eps_absorber_default())
         ref = psfd.Plan(cfg, eps, psfd.PSFD_C128)
-        (E_ref, i_ref), t_ref = _sync_time(lambda: ref.solve(tol=1e-10, maxit=args.maxit, check=False))
+
+        (E_ref, i_ref), t_ref = _sync_time(lambda: ref.solve(tol=1e-9, maxit=args.maxit, check=False))
         _log(f"c4 pol {pol} fp64 reference: {i_ref['iters']} it, {t_ref:.2f} s, {i_ref['status']}")
         b = ref.rhs()
         bn = float(torch.linalg.vector_norm(b))
@@ -410,7 +413,8 @@ def workload_fd(psfd, args):
         background-decomposed grid (Nz 96) against the full-domain grid with the stack under the
         absorber (Nz 384): iterations, solve time, device memory, specular reflection at the
         absorber's top face, and the tall axial kernel's bandwidth (launch-packet events).  The
-        decomposed grid runs with the grazing cutoff of the other workloads and without it."""
+        decomposed grid runs on the operator as defined and, for comparison, with a 0.1 k0
+        grazing cutoff."""
     import math
     import numpy as np
     import torch
@@ -422,8 +426,8 @@ def workload_fd(psfd, args):
            "dtype": "f64", "legs": {"bare_stack": [], "absorber": {}},
            "config": {"workload": "bare 40-bilayer Mo/Si stack, 16x16 lateral, dz 1 and 0.5 nm, TE, "
                                   "4 angles, tol 1e-8; 128x128x(50 nm absorber) at 1 nm, TE normal "
-                                  "incidence, decomposed (Nz 96, grazing cutoff 0.1 and none) vs "
-                                  "full-domain (Nz 384), tol %g"
+                                  "incidence, decomposed (Nz 96, no grazing cutoff, and cutoff 0.1 "
+                                  "for comparison) vs full-domain (Nz 384), tol %g"
                                   % args.tol}}
     t_bare = 0.0
     for dz in (1.0, 0.5):
@@ -453,8 +457,8 @@ def workload_fd(psfd, args):
     cfg_s = dict(cfg_f, nz_abs=280)
     eps_f = torch.cat([psfd.psfd_layered_eps(cfg_s, eps_l, d_l, dev), eps_abs], dim=0).contiguous()
     res = {}
-    cfg_dc = dict(cfg_d, ml_kz_min=ML_KZ_MIN)
-    for name, cfg, eps in (("decomposed", cfg_dc, eps_abs), ("decomposed_no_cutoff", cfg_d, eps_abs),
+    cfg_dc = dict(cfg_d, ml_kz_min=0.1)
+    for name, cfg, eps in (("decomposed", cfg_d, eps_abs), ("decomposed_cutoff_0.1", cfg_dc, eps_abs),
                            ("full_domain", cfg_f, eps_f)):
         for prec_name, prec in (("fp64", psfd.PSFD_C128), ("mixed", psfd.PSFD_C64_REFINE64)):
             torch.cuda.synchronize()
@@ -492,7 +496,7 @@ def workload_fd(psfd, args):
 
 def workload_contour(psfd, args):
     """Practical convergence by threshold-contour widths: 8 seeded 256x256x48 clips (line/space
-    and contacts alternating), TE 6 deg, grazing cutoff 0.1.  Reference: FP64 solve to r_rel 1e-7.
+    and contacts alternating), TE 6 deg, grazing cutoff --ml-kz-min.  Reference: FP64 solve to r_rel 1e-7.
     Mixed solves stopped after k iterations (k = 50 ... 1600) and run to 1e-6: |delta d| at wafer
     scale (/4) over 100 horizontal + 100 vertical scan lines of |E_y|^2 on the observation row
     (S(I) with I_th 0.15, w 0.05), and the metric kernels' own time for the 8 planes."""
@@ -550,9 +554,9 @@ def workload_contour(psfd, args):
                          "note": "one launch per call: latency-bound, not bandwidth-bound"},
             "deviation_ms_8_planes": round(1e3 * dt2 / 20, 4),
             "segments_per_ref_plane": float(seg_ref[1].sum().item()) / 8,
-            "config": {"workload": "8 seeded 256x256x(32+16) clips, TE 6 deg, cutoff 0.1; reference "
-                                   "FP64 1e-7; mixed stopped at k iterations; 100+100 scan lines, "
-                                   "I_th 0.15, w 0.05, /4 demag"}}
+            "config": {"workload": f"8 seeded 256x256x(32+16) clips, TE 6 deg, cutoff {ML_KZ_MIN:g}; "
+                                   "reference FP64 1e-7; mixed stopped at k iterations; 100+100 scan "
+                                   "lines, I_th 0.15, w 0.05, /4 demag"}}
 
 
 def workload_pino(psfd, args):
@@ -663,7 +667,7 @@ def workload_ffno(psfd, args):
 def workload_paper_grid(psfd, args):
     """The paper's solver workload at the nearest supported grid: its 1200x1200 nm cell at
     1 nm and 100 axial rows of 2 nm become 1024x1024 lateral (1.17 nm) x 96 rows (2 nm): a 50 nm
-    absorber (25 rows), 12-row PMLs, gaps; TE normal incidence, grazing cutoff 0.1; one seeded
+    absorber (25 rows), 12-row PMLs, gaps; TE normal incidence, grazing cutoff --ml-kz-min; one seeded
     curvilinear layout.  Mixed and FP64 solves to r_rel 5e-2 (the paper's criterion for its
     iteration counts) and to 1e-4 (iteration budget 1500): iterations, seconds, seconds per
     iteration."""
@@ -692,7 +696,7 @@ def workload_paper_grid(psfd, args):
         del E
     out["value"] = out["legs"]["mixed_tol0.05"]["s_per_iter"]
     out["config"] = {"workload": "1024x1024x96 (1.17 x 1.17 x 2 nm), 50 nm absorber, TE normal "
-                                 "incidence, curvilinear layout, cutoff 0.1; the paper: "
+                                 f"incidence, curvilinear layout, cutoff {ML_KZ_MIN:g}; the paper: "
                                  "1200x1200x100 at 1 x 1 x 2 nm"}
     return out
 

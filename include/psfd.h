@@ -65,8 +65,17 @@ typedef enum {
   PSFD_C128 = 0,              /* complex128 everywhere                                  */
   PSFD_C64_REFINE64 = 1,      /* complex64 operator/preconditioner/Krylov vectors,
                                  FP64 true residual and refinement updates              */
-  PSFD_C64_BF16PC_REFINE64 = 2 /* as 1, preconditioner multiplier rounded to bfloat16   */
+  PSFD_C64_BF16PC_REFINE64 = 2 /* as 1, with the preconditioner's output spectrum     */
+                                /* m(k) F3 x held in bfloat16 (see below)                */
 } psfd_precision;
+
+/* PSFD_C64_BF16PC_REFINE64, the bfloat16 preconditioner trial: inside every
+ * complex64 M and A.M apply the damped spectrum m(k) F3 x -- the
+ * preconditioner's data -- is rounded to bfloat16 right after the damping
+ * and used in that form from there on (its x and y components are parked in
+ * LDS as packed bfloat16 pairs).  M is then a rounded, not exactly linear,
+ * operator; the FP64 reliable updates keep the recursive and the true
+ * residual together.  A itself and the FP64 applies are unchanged. */
 
 /* Plan descriptor.  Lengths in nm, angles in radians.
  * Supported sizes: nx, ny in {16, 32, 64, 128, 192, 256, 512, 1024};

@@ -21,6 +21,8 @@
 // The adjoint replaces D by -D^H = G diag(1/conj(s)) and the multilayer
 // branch by its adjoint applied to F2[conj(k0^2 d_eps) x] (extra input planes),
 // which lands on the evaluation row.
+#include <type_traits>
+
 #include "fft_core.h"
 #include "lane_fft.h"
 #include "psfd_internal.h"
@@ -53,6 +55,15 @@ __device__ __forceinline__ float round_bf16(float x) {
   return __uint_as_float(u & 0xFFFF0000u);
 }
 __device__ __forceinline__ double round_bf16(double x) { return (double)round_bf16((float)x); }
+template <typename T>
+__device__ __forceinline__ cplx<T> round_bf16(cplx<T> v) { return {round_bf16(v.re), round_bf16(v.im)}; }
+// A complex value whose parts are bfloat16 numbers, packed into 32 bits and back.
+__device__ __forceinline__ uint32_t pack_bf16(cplx<float> v) {
+  return (__float_as_uint(v.re) >> 16) | (__float_as_uint(v.im) & 0xFFFF0000u);
+}
+__device__ __forceinline__ cplx<float> unpack_bf16(uint32_t u) {
+  return {__uint_as_float(u << 16), __uint_as_float(u & 0xFFFF0000u)};
+}
 
 template <typename T>
 __device__ __forceinline__ T damping(T k2, const OpTables<T>& t) {
@@ -61,9 +72,7 @@ __device__ __forceinline__ T damping(T k2, const OpTables<T>& t) {
     const T q = t.pc_kref2 / (k2 + t.pc_reg);
     core = (t.pc_gamma == T(1)) ? q : pow(q, t.pc_gamma);
   }
-  T m = t.pc_mmin + (T(1) - t.pc_mmin) * core;
-  if (t.pc_bf16) m = round_bf16(m);
-  return m;
+  return t.pc_mmin + (T(1) - t.pc_mmin) * core;
 }
 
 // Multiplier of the M mode: the damping m(k), or for the physics loss's
@@ -192,7 +201,12 @@ k_axial(const cplx<T>* __restrict__ S_all, cplx<T>* __restrict__ UW_all, const O
       const T kzl = kzs[l];
       const T m = (MODE == AX_M ? spec_mult(kt2 + kzl * kzl, t) : damping(kt2 + kzl * kzl, t)) * inz;
       cplx<T>* b0 = &buf[l * PITCH + cc];
-      const cplx<T> p0 = m * b0[0], p1 = m * b0[VS], p2 = m * b0[2 * VS];
+      cplx<T> p0 = m * b0[0], p1 = m * b0[VS], p2 = m * b0[2 * VS];
+      if (sizeof(T) == 4 && t.pc_bf16 && !t.hf_mode) {  // bf16 trial: M's spectrum in bfloat16
+        p0 = round_bf16(p0);
+        p1 = round_bf16(p1);
+        p2 = round_bf16(p2);
+      }
       b0[0] = p0;
       b0[VS] = p1;
       b0[2 * VS] = p2;
@@ -351,7 +365,10 @@ k_axial(const cplx<T>* __restrict__ S_all, cplx<T>* __restrict__ UW_all, const O
 // a wave-uniform part r0 * plane and a per-lane byte offset
 // (lt * plane + g) * sizeof, below 4 GiB for every supported size: each
 // access is a scalar base plus one 32-bit lane offset.
-template <typename T, int NZ, int L, int MODE>
+// BF (complex64, A.M and M modes): the bf16 preconditioner trial; the damped
+// spectrum P^ = m X^ is rounded to bfloat16 right after the damping and its
+// x, y components are parked in LDS as packed bfloat16 pairs.
+template <typename T, int NZ, int L, int MODE, bool BF = false>
 __global__ void __launch_bounds__(256)
 k_axial_reg(const cplx<T>* __restrict__ S_all, cplx<T>* __restrict__ UW_all, const OpTables<T> t) {
   constexpr int E = NZ / L;
@@ -399,6 +416,11 @@ k_axial_reg(const cplx<T>* __restrict__ S_all, cplx<T>* __restrict__ UW_all, con
       px[k2] = m * px[k2];
       py[k2] = m * py[k2];
       pz[k2] = m * pz[k2];
+      if constexpr (BF) {
+        px[k2] = round_bf16(px[k2]);
+        py[k2] = round_bf16(py[k2]);
+        pz[k2] = round_bf16(pz[k2]);
+      }
     }
     F.inv(px);
     F.inv(py);
@@ -413,14 +435,21 @@ k_axial_reg(const cplx<T>* __restrict__ S_all, cplx<T>* __restrict__ UW_all, con
   } else {
     // Column data parked in LDS: each lane stores and reloads only its own
     // slots ([slot][register][lane], conflict-free), so no barrier is needed.
-    __shared__ cplx<T> park[2 * E * 256];
+    using Park = typename std::conditional<BF, uint32_t, cplx<T>>::type;
+    __shared__ Park park[2 * E * 256];
     auto park_st = [&](int slot, const cplx<T>(&v)[E]) {
 #pragma unroll
-      for (int k = 0; k < E; ++k) park[(slot * E + k) * 256 + threadIdx.x] = v[k];
+      for (int k = 0; k < E; ++k) {
+        if constexpr (BF) park[(slot * E + k) * 256 + threadIdx.x] = pack_bf16(v[k]);
+        else park[(slot * E + k) * 256 + threadIdx.x] = v[k];
+      }
     };
     auto park_ld = [&](int slot, cplx<T>(&v)[E]) {
 #pragma unroll
-      for (int k = 0; k < E; ++k) v[k] = park[(slot * E + k) * 256 + threadIdx.x];
+      for (int k = 0; k < E; ++k) {
+        if constexpr (BF) v[k] = unpack_bf16(park[(slot * E + k) * 256 + threadIdx.x]);
+        else v[k] = park[(slot * E + k) * 256 + threadIdx.x];
+      }
     };
     // P at the evaluation row (the multilayer branch reads it there)
     cplx<T> ex = {T(0), T(0)}, ey = {T(0), T(0)}, ez = {T(0), T(0)};
@@ -436,6 +465,11 @@ k_axial_reg(const cplx<T>* __restrict__ S_all, cplx<T>* __restrict__ UW_all, con
         px[k2] = m * px[k2];
         py[k2] = m * py[k2];
         pz[k2] = m * pz[k2];
+        if constexpr (BF) {
+          px[k2] = round_bf16(px[k2]);
+          py[k2] = round_bf16(py[k2]);
+          pz[k2] = round_bf16(pz[k2]);
+        }
       }
       // P(jev) = sum_k P^[k] exp(+2 pi i k jev / NZ): this lane's terms, then the group sum
 #pragma unroll
@@ -587,10 +621,18 @@ static hipError_t axial_reg_launch(const OpTables<T>& t, const cplx<T>* S, cplx<
   const int64_t cols = (int64_t)t.nx * t.ny;
   if ((cols * L) % 256) return hipErrorInvalidValue;
   dim3 g((unsigned)(cols * L / 256 * t.nprob)), b(256);
+  constexpr bool F32 = sizeof(T) == 4;
+  const bool bf = F32 && t.pc_bf16 && !t.hf_mode;
   switch (mode) {
     case AX_A: PSFD_LAUNCH(t, (k_axial_reg<T, NZ, L, AX_A>), g, b, st, S, UW, t); break;
-    case AX_AM: PSFD_LAUNCH(t, (k_axial_reg<T, NZ, L, AX_AM>), g, b, st, S, UW, t); break;
-    default: PSFD_LAUNCH(t, (k_axial_reg<T, NZ, L, AX_M>), g, b, st, S, UW, t); break;
+    case AX_AM:
+      if (bf) PSFD_LAUNCH(t, (k_axial_reg<T, NZ, L, AX_AM, F32>), g, b, st, S, UW, t);
+      else PSFD_LAUNCH(t, (k_axial_reg<T, NZ, L, AX_AM>), g, b, st, S, UW, t);
+      break;
+    default:
+      if (bf) PSFD_LAUNCH(t, (k_axial_reg<T, NZ, L, AX_M, F32>), g, b, st, S, UW, t);
+      else PSFD_LAUNCH(t, (k_axial_reg<T, NZ, L, AX_M>), g, b, st, S, UW, t);
+      break;
   }
   return hipGetLastError();
 }

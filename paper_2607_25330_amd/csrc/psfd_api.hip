@@ -650,6 +650,20 @@ psfd_status run_bicgstab(struct psfd_plan* P, bool adjoint, int maxit, U&& on_up
       launched += chunk;
     }
     CHKS(read_state(P));
+    {
+      // PSFD_TRACE=2: the recursive residual of each problem every 512 iterations
+      static const bool trace2 = [] {
+        const char* e = std::getenv("PSFD_TRACE");
+        return e && std::atoi(e) >= 2;
+      }();
+      if (trace2)
+        for (int b = 0; b < G; ++b) {
+          const KState& k = P->ks_host[b];
+          if (k.iter / 512 != (k.iter - kChunk) / 512 && k.iter >= 512 && k.bnorm2 > 0)
+            fprintf(stderr, "psfd trace: p%d %s iteration %d of this run: recursive r/r_run0 %.3e\n", b,
+                    sizeof(T) == 4 ? "c64" : "fp64", k.iter, std::sqrt(k.rnorm2 / k.bnorm2));
+        }
+    }
     if (P->prof_kernel != PROF_OFF) {
       // timed launches: single-problem plans count the chunk's executed iterations
       collect_events(P, G == 1 ? P->ks_host[0].iter - iter_seen : (1 << 30));
@@ -982,6 +996,7 @@ psfd_status solve_body(struct psfd_plan* P, const cplx<double>* b_in, const cplx
     return (e && *e) ? std::atof(e) : 0.01;
   }();
   // PSFD_TRACE=1: one line per Krylov run end and per reliable update on stderr
+  // (2: also the recursive residual every 512 iterations)
   static const bool trace = [] {
     const char* e = std::getenv("PSFD_TRACE");
     return e && *e && *e != '0';

@@ -43,7 +43,7 @@ struct OpTables {
   T dz;
   // spectral damping multiplier m(k)
   T pc_mmin, pc_kref2, pc_gamma, pc_reg;
-  int pc_bf16;              // round m(k) to bfloat16
+  int pc_bf16;              // bf16 trial: the preconditioned spectrum m X^ held in bfloat16
   int hf_mode;              // 1: the M-mode multiplier is the loss weight w(nu)^2 instead of m(k)
   T hf_w0, hf_eta;          // w(nu) = hf_w0 + hf_eta |nu|,  |nu| = |k| / (2 pi)
   int ax_lds;               // 1: always use the LDS-staged axial kernel
