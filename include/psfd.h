@@ -424,7 +424,8 @@ psfd_status psfd_profile_read(psfd_plan_t p, double* total_ms, int64_t* launches
  * library (or the file PSFD_TUNE_FILE names; an empty name disables it):
  * shapes it lists take their schedules without timing, in every plan.  Other
  * shapes use the default schedules unless psfd_tune is called or PSFD_TUNE=1
- * is set (batch groups are tuned unless PSFD_TUNE=0).  psfd_tune_save writes
+ * is set (batch groups are tuned unless PSFD_TUNE=0).  With PSFD_TUNE=0 plans
+ * created afterwards keep the default schedules, table or not.  psfd_tune_save writes
  * the process's table (the file's entries plus everything tuned since) to
  * `path` (host string), in the file's format: one line per shape,
  * "elem nx ny nz nabs group : xf xi y ax" (elem 4: complex64 plans, 8:

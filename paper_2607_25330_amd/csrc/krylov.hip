@@ -66,7 +66,21 @@ __device__ __forceinline__ void sum_partials(const double* __restrict__ part, in
                                              double (&acc)[NV]) {
 #pragma unroll
   for (int k = 0; k < NV; ++k) acc[k] = 0.0;
-  for (int b = threadIdx.x; b < nblocks; b += 1024) {
+  // the loads of four partials are issued before their sums (latency, not
+  // bandwidth, bounds this loop); the order of the additions is unchanged
+  int b = threadIdx.x;
+  for (; b + 3 * 1024 < nblocks; b += 4 * 1024) {
+    double v[4][NV];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int k = 0; k < NV; ++k) v[u][k] = part[(size_t)(b + u * 1024) * KPART + k];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int k = 0; k < NV; ++k) acc[k] += v[u][k];
+  }
+  for (; b < nblocks; b += 1024) {
 #pragma unroll
     for (int k = 0; k < NV; ++k) acc[k] += part[(size_t)b * KPART + k];
   }

@@ -871,7 +871,14 @@ psfd_status autotune(struct psfd_plan* P, bool timing) {
   return PSFD_OK;
 }
 
+bool tune_forced_off() {
+  const char* s = std::getenv("PSFD_TUNE");
+  return s && *s && std::atoi(s) == 0;
+}
+
+// Schedules of a new plan; PSFD_TUNE=0 keeps the defaults (no table, no timing).
 psfd_status tune_plan(struct psfd_plan* P, bool timing) {
+  if (tune_forced_off()) return PSFD_OK;
   if (P->prec == PSFD_C128) return autotune<double>(P, timing);
   return autotune<float>(P, timing);
 }
@@ -2200,7 +2207,7 @@ psfd_status psfd_tune(psfd_plan_t p) {
   if (!p || p->is_batch) return fail(PSFD_ERR_ARG, "NULL argument or batch handle");
   return guarded([&]() -> psfd_status {
     drop_graphs(p);  // captured chunks hold the old schedules
-    CHKS(tune_plan(p, true));
+    CHKS(p->prec == PSFD_C128 ? autotune<double>(p, true) : autotune<float>(p, true));
     CHK(hipStreamSynchronize(p->st));
     return PSFD_OK;
   });
