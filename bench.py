@@ -733,7 +733,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--ml-kz-min", type=float, default=0.0,
                     help="grazing cutoff of the multilayer response in units of k0 (0: none)")
-    ap.add_argument("--steps", type=int, default=4)
+    ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--tol", type=float, default=1e-6)
     ap.add_argument("--maxit", type=int, default=20000)
@@ -852,8 +852,9 @@ def main():
     prof_kernel = None if args.no_profile else args.roofline_kernel
     prof = (0.0, 0, 0.0)
     if prof_kernel is not None:
-        infos_p, prof = run_steps(psfd, cfgs, a_dev, range(K), prec_mixed, args.tol, args.maxit,
-                                  profile=prof_kernel, sched=forced)
+        # (the first four steps: the kernel's average per launch does not need all of them)
+        infos_p, prof = run_steps(psfd, cfgs, a_dev, range(min(K, 4)), prec_mixed, args.tol,
+                                  args.maxit, profile=prof_kernel, sched=forced)
         torch.cuda.synchronize()
         print(f"bench: profiled leg: {prof[1]} launches of {prof_kernel}", file=sys.stderr, flush=True)
 
