@@ -511,9 +511,14 @@ psfd_status read_state(struct psfd_plan* P) {
   return PSFD_OK;
 }
 
+// pp_host and idle_host are pinned: an asynchronous copy reads them when it
+// runs, not when it is queued, so the copy is waited for before the host may
+// change them again (without the wait, a group's reliable update could send
+// the parameters written after it, and every member's residual was rescaled).
 psfd_status push_params(struct psfd_plan* P) {
   CHK(hipMemcpyAsync(P->pp, P->pp_host, sizeof(ProbParams) * P->G, hipMemcpyHostToDevice, P->st));
   CHK(hipMemcpyAsync(P->idle, P->idle_host, sizeof(int) * P->G, hipMemcpyHostToDevice, P->st));
+  CHK(hipStreamSynchronize(P->st));
   return PSFD_OK;
 }
 

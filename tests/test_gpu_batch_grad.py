@@ -101,6 +101,41 @@ def test_group_of_same_shape_problems_matches_individual_solves(psfd, prec, form
     assert len(iters) > 1  # the members really stopped at different iterations
 
 
+def test_group_reliable_updates_keep_other_members_intact(psfd, monkeypatch):
+    """A group of twenty 128x128x(32+16) problems (two layouts x 5 angles x TE/TM)
+    with reliable updates: each member's update folds and replaces that member
+    only, while the others keep iterating.  Regression test for the parameter
+    upload of an update racing with the host's next write of the pinned
+    parameter block, which rescaled every member's residual: the group then
+    needed 2.7x the iterations of single solves, with rejected folds.  Checked:
+    every member converges, the group needs at most 1.25x the iterations of the
+    same problems solved one by one, and the fields agree to the mixed bar."""
+    monkeypatch.setenv("PSFD_TUNE", "0")
+    monkeypatch.setenv("PSFD_RELIABLE", "1")
+    cfgs, eps = [], []
+    for c in range(2):
+        a = dev(rect_layout(128, 128, np.random.default_rng(70 + c), wmin=4, wmax=24))
+        for th in (0.0, 2.5, 5.0, 7.5, 10.0):
+            for pol in (0, 1):
+                cfg = dict(base_config(128, 128, 32, 60.0, theta_deg=th, pol=pol), ml_kz_min=0.0)
+                cfgs.append(cfg)
+                eps.append(psfd.psfd_layout_eps(cfg, a, EPS_ABS))
+    batch = psfd.Batch(cfgs, eps, prec=psfd.PSFD_C64_REFINE64)
+    E_b, infos = batch.solve(tol=1e-6)
+    batch.close()
+    it_group, it_single = 0, 0
+    for i, c in enumerate(cfgs):
+        plan = psfd.Plan(c, eps[i], prec=psfd.PSFD_C64_REFINE64)
+        E_i, info = plan.solve(tol=1e-6)
+        plan.close()
+        assert infos[i]["status"] == "OK" and infos[i]["rrel"] <= 1e-6
+        it_group += infos[i]["iters"]
+        it_single += info["iters"]
+        err = float((E_b[i] - E_i).abs().max() / E_i.abs().max())
+        assert err <= 1e-4, (i, err)
+    assert it_group <= 1.25 * it_single, (it_group, it_single)
+
+
 def test_group_budget_per_problem(psfd):
     """A budget smaller than any member needs stops every member of the group
     at that budget with NOT_CONVERGED, reported per problem."""
