@@ -357,7 +357,9 @@ k_init(cplx<T>* __restrict__ rh, const cplx<T>* __restrict__ r, cplx<T>* __restr
 template <typename T>
 __global__ void __launch_bounds__(KRED_THREADS)
 k_residual(cplx<T>* __restrict__ out, const cplx<T>* __restrict__ a, const cplx<T>* __restrict__ b,
-           int64_t n, int nprob, double* __restrict__ part) {
+           int64_t n, int nprob, const int* __restrict__ skip, double* __restrict__ part) {
+  // problems flagged in skip (whose operator apply was skipped) are left alone
+  if (skip && skip[blockIdx.x / (gridDim.x / nprob)]) return;
   double acc[1] = {0.0};
   PSFD_GROUP_LOOP(i) {
     const cplx<T> d = a[i] - b[i];
@@ -441,8 +443,8 @@ hipError_t launch_k_init(cplx<T>* rh, const cplx<T>* r, cplx<T>* p, cplx<T>* v, 
 }
 template <typename T>
 hipError_t launch_k_residual(cplx<T>* out, const cplx<T>* a, const cplx<T>* b, int64_t n,
-                             int nprob, double* part, hipStream_t st) {
-  hipLaunchKernelGGL((k_residual<T>), KGRID, out, a, b, n, nprob, part);
+                             int nprob, const int* skip, double* part, hipStream_t st) {
+  hipLaunchKernelGGL((k_residual<T>), KGRID, out, a, b, n, nprob, skip, part);
   return hipGetLastError();
 }
 template <typename T>
@@ -478,7 +480,7 @@ hipError_t launch_k_scale_copy(cplx<TY>* y, const cplx<TX>* x, const ProbParams*
   template hipError_t launch_k_init<T>(cplx<T>*, const cplx<T>*, cplx<T>*, cplx<T>*,          \
                                        cplx<T>*, int64_t, int, double*, hipStream_t);         \
   template hipError_t launch_k_residual<T>(cplx<T>*, const cplx<T>*, const cplx<T>*, int64_t, \
-                                           int, double*, hipStream_t);                        \
+                                           int, const int*, double*, hipStream_t);            \
   template hipError_t launch_k_norm2<T>(const cplx<T>*, int64_t, int, double*, hipStream_t);   \
   template hipError_t launch_k_dot_rr<T>(const cplx<T>*, const cplx<T>*, int64_t, int, double*, \
                                          hipStream_t);

@@ -687,11 +687,12 @@ psfd_status run_bicgstab(struct psfd_plan* P, bool adjoint, int maxit, U&& on_up
 psfd_status no_update() { return PSFD_OK; }
 
 // r = b - op(E) in FP64 (op = A or A^H, no preconditioner) for every problem
-// not marked idle; ||r_b||^2 lands in ks_host[b].red[0].
+// not marked idle; ||r_b||^2 lands in ks_host[b].red[0].  An idle problem's r
+// is left as it was and its red[0] means nothing.
 psfd_status true_residual(struct psfd_plan* P, const cplx<double>* b, const cplx<double>* E,
                           cplx<double>* r, bool adjoint) {
   CHK(op_apply<double>(P, E, P->tmp64, adjoint ? OP_AH : OP_A, P->idle, 1));
-  CHK(launch_k_residual<double>(r, b, P->tmp64, P->nfield, P->G, P->part, P->st));
+  CHK(launch_k_residual<double>(r, b, P->tmp64, P->nfield, P->G, P->idle, P->part, P->st));
   CHK(launch_finalize(FIN_RED0, P->ks, P->part, red_blocks(P->nfield, P->G), P->G, P->pp, P->st));
   return read_state(P);
 }
@@ -999,8 +1000,8 @@ psfd_status solve_body(struct psfd_plan* P, const cplx<double>* b_in, const cplx
   // since the last replacement, so one run reaches the final tolerance with
   // the Krylov recurrence intact.  Group plans use the plain restart form
   // (inner runs to a loose relative tolerance, then a fresh start): there
-  // every member's update would stop the whole group's chunk and host round
-  // trip, which on the batched uneven workload cost 83 s against 47 s.
+  // every member's update stops the whole group's chunk for a host round
+  // trip (160 batched uneven solves: 83 s with updates, 79 s with restarts).
   // PSFD_RELIABLE=0 / 1 selects the restart form / reliable updates for
   // every plan.
   static const double kDelta = [] {  // PSFD_RELIABLE_DELTA overrides (measurement aid)

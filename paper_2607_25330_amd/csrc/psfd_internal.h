@@ -283,10 +283,11 @@ hipError_t launch_k_p_update(cplx<T>* p, const cplx<T>* r, const cplx<T>* v, int
 template <typename T>
 hipError_t launch_k_init(cplx<T>* rh, const cplx<T>* r, cplx<T>* p, cplx<T>* v, cplx<T>* y,
                          int64_t n, int nprob, double* part, hipStream_t st);
-// out = a - b, partials ||out||^2 (then FIN_RED0)
+// out = a - b, partials ||out||^2 (then FIN_RED0); problems with skip[b] != 0
+// (skip may be NULL) are left untouched and write no partials
 template <typename T>
 hipError_t launch_k_residual(cplx<T>* out, const cplx<T>* a, const cplx<T>* b, int64_t n,
-                             int nprob, double* part, hipStream_t st);
+                             int nprob, const int* skip, double* part, hipStream_t st);
 // partials ||r||^2, sum conj(rh) r of a replaced residual (then FIN_REPLACE)
 template <typename T>
 hipError_t launch_k_dot_rr(const cplx<T>* rh, const cplx<T>* r, int64_t n, int nprob,
