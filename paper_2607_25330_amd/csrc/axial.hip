@@ -390,8 +390,19 @@ k_axial_reg(const cplx<T>* __restrict__ S_all, cplx<T>* __restrict__ UW_all, con
     *reinterpret_cast<cplx<T>*>(reinterpret_cast<char*>(UW) + row * pbytes + lane_bo) = v;
   };
   const T inz = T(1) / T(NZ);
+  // the z tables (twiddles, kz, 1/s) in LDS: every lane reads them at its own
+  // index many times, and LDS reads keep those lookups off the vector memory
+  // path that carries the column data
+  __shared__ cplx<T> twz_s[NZ], invs_s[NZ];
+  __shared__ T kz_s[NZ];
+  for (int i = threadIdx.x; i < NZ; i += 256) {
+    twz_s[i] = t.tw_z[i];
+    invs_s[i] = t.inv_s[i];
+    kz_s[i] = t.kz[i];
+  }
+  __syncthreads();
   LaneFft<T, NZ, L> F;
-  F.init(t.tw_z, lt);
+  F.init(twz_s, lt);
   const int kofs = E * lane_brev<L>(lt);  // k of register k2 is k2 + kofs
 
   cplx<T> px[E], py[E], pz[E];
@@ -411,7 +422,7 @@ k_axial_reg(const cplx<T>* __restrict__ S_all, cplx<T>* __restrict__ UW_all, con
     F.fwd(pz);
 #pragma unroll
     for (int k2 = 0; k2 < E; ++k2) {
-      const T kzl = t.kz[k2 + kofs];
+      const T kzl = kz_s[k2 + kofs];
       const T m = spec_mult(kt2 + kzl * kzl, t) * inz;
       px[k2] = m * px[k2];
       py[k2] = m * py[k2];
@@ -460,7 +471,7 @@ k_axial_reg(const cplx<T>* __restrict__ S_all, cplx<T>* __restrict__ UW_all, con
       F.fwd(pz);
 #pragma unroll
       for (int k2 = 0; k2 < E; ++k2) {
-        const T kzl = t.kz[k2 + kofs];
+        const T kzl = kz_s[k2 + kofs];
         const T m = damping(kt2 + kzl * kzl, t) * inz;
         px[k2] = m * px[k2];
         py[k2] = m * py[k2];
@@ -474,7 +485,7 @@ k_axial_reg(const cplx<T>* __restrict__ S_all, cplx<T>* __restrict__ UW_all, con
       // P(jev) = sum_k P^[k] exp(+2 pi i k jev / NZ): this lane's terms, then the group sum
 #pragma unroll
       for (int k2 = 0; k2 < E; ++k2) {
-        const cplx<T> w = conj(t.tw_z[((k2 + kofs) * t.jev) % NZ]);
+        const cplx<T> w = conj(twz_s[((k2 + kofs) * t.jev) % NZ]);
         ex = ex + px[k2] * w;
         ey = ey + py[k2] * w;
         ez = ez + pz[k2] * w;
@@ -483,10 +494,10 @@ k_axial_reg(const cplx<T>* __restrict__ S_all, cplx<T>* __restrict__ UW_all, con
       ey = lane_group_sum<L>(ey);
       ez = lane_group_sum<L>(ez);
 #pragma unroll
-      for (int k2 = 0; k2 < E; ++k2) dx[k2] = t.kz[k2 + kofs] * mul_i(px[k2]);
+      for (int k2 = 0; k2 < E; ++k2) dx[k2] = kz_s[k2 + kofs] * mul_i(px[k2]);
       park_st(0, px);
 #pragma unroll
-      for (int k2 = 0; k2 < E; ++k2) dy[k2] = t.kz[k2 + kofs] * mul_i(py[k2]);
+      for (int k2 = 0; k2 < E; ++k2) dy[k2] = kz_s[k2 + kofs] * mul_i(py[k2]);
       park_st(1, py);
       F.inv(pz);
     } else {
@@ -513,7 +524,7 @@ k_axial_reg(const cplx<T>* __restrict__ S_all, cplx<T>* __restrict__ UW_all, con
       F.fwd(dy);
 #pragma unroll
       for (int k2 = 0; k2 < E; ++k2) {
-        const T f = t.kz[k2 + kofs] * inz;
+        const T f = kz_s[k2 + kofs] * inz;
         dx[k2] = f * mul_i(dx[k2]);
         dy[k2] = f * mul_i(dy[k2]);
       }
@@ -541,7 +552,7 @@ k_axial_reg(const cplx<T>* __restrict__ S_all, cplx<T>* __restrict__ UW_all, con
 #pragma unroll
       for (int m = 0; m < E; ++m) {
         const int z = lt + L * m;
-        const cplx<T> is = t.inv_s[z];
+        const cplx<T> is = invs_s[z];
         const cplx<T> dpx = dx[m] * is, dpy = dy[m] * is;
         stv(2 * NZ + L * m, kx * mul_i(dpx) + ky * mul_i(dpy) + (kt2 - t.kbg2) * pz[m]);
         dx[m] = kx * mul_i(pz[m]) - dpx;
@@ -557,7 +568,7 @@ k_axial_reg(const cplx<T>* __restrict__ S_all, cplx<T>* __restrict__ UW_all, con
     F.fwd(dy);
 #pragma unroll
     for (int k2 = 0; k2 < E; ++k2) {
-      const T f = t.kz[k2 + kofs] * inz;
+      const T f = kz_s[k2 + kofs] * inz;
       dx[k2] = f * mul_i(dx[k2]);
       dy[k2] = f * mul_i(dy[k2]);
     }
@@ -575,7 +586,7 @@ k_axial_reg(const cplx<T>* __restrict__ S_all, cplx<T>* __restrict__ UW_all, con
 #pragma unroll
       for (int m = 0; m < E; ++m) {
         const int z = lt + L * m;
-        const cplx<T> is = t.inv_s[z];
+        const cplx<T> is = invs_s[z];
         dx[m] = dx[m] * is + cxx * q[m];
         dy[m] = dy[m] * is + cxy * q[m];
         const int ja = z - t.j0;
