@@ -737,7 +737,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--tol", type=float, default=1e-6)
     ap.add_argument("--maxit", type=int, default=20000)
-    ap.add_argument("--roofline-kernel", default="axial", choices=["axial", "yfft", "xfwd", "xinv"],
+    ap.add_argument("--roofline-kernel", default="xinv", choices=["axial", "yfft", "xfwd", "xinv"],
                     help="kernel class timed for the roofline object (the dominant one by rocprof)")
     ap.add_argument("--no-profile", action="store_true",
                     help="skip the untimed kernel-timing leg (no roofline object)")
