@@ -356,7 +356,8 @@ k_axial(const cplx<T>* __restrict__ S_all, cplx<T>* __restrict__ UW_all, const O
 // ------------------------------------------------------------------------
 // Register-resident variant for the forward modes (A, AM, M): L lanes own a
 // column (lane t keeps z = t + L m), every z transform is a LaneFft, so the
-// column never goes through LDS and the kernel has no barrier.  Same
+// column never goes through LDS; the only barrier follows the staging of the
+// z tables in LDS.  Same
 // arithmetic as k_axial above, in the order that keeps at most five column
 // vectors live: P^ (k layout) -> D P -> P_z -> U_z and w -> D w -> P_x, P_y
 // -> U_x, U_y and the absorber-row W planes.
