@@ -218,6 +218,18 @@ __device__ __forceinline__ void stockham_pass(cplx<T>* s, const cplx<T>* __restr
   __syncthreads();
 }
 
+// Passes I .. np - 2 (all but the last).
+template <typename T, int N, int I, int NB, int NT, bool INV, bool BFAST, int S, class Addr>
+__device__ __forceinline__ void stockham_mid(cplx<T>* s, const cplx<T>* __restrict__ tw, Addr addr,
+                                             int tid) {
+  if constexpr (I < Radices<N, S>::P.np - 1) {
+    constexpr int R = Radices<N, S>::P.r[I];
+    constexpr int NS = Radices<N, S>::P.ns[I];
+    stockham_pass<T, N, R, NS, NB, NT, INV, BFAST, S>(s, tw, addr, tid);
+    stockham_mid<T, N, I + 1, NB, NT, INV, BFAST, S>(s, tw, addr, tid);
+  }
+}
+
 template <typename T, int N, int I, int NB, int NT, bool INV, bool BFAST, int S, class Addr>
 __device__ __forceinline__ void stockham_passes(cplx<T>* s, const cplx<T>* __restrict__ tw,
                                                 Addr addr, int tid) {
@@ -226,6 +238,80 @@ __device__ __forceinline__ void stockham_passes(cplx<T>* s, const cplx<T>* __res
     constexpr int NS = Radices<N, S>::P.ns[I];
     stockham_pass<T, N, R, NS, NB, NT, INV, BFAST, S>(s, tw, addr, tid);
     stockham_passes<T, N, I + 1, NB, NT, INV, BFAST, S>(s, tw, addr, tid);
+  }
+}
+
+// Items per thread of an NB-transform batch split over NT threads.
+template <int N, int NB, int NT, int S>
+constexpr int lds_fft_items() {
+  return (NB * Radices<N, S>::TPR + NT - 1) / NT;
+}
+
+// lds_fft with the first pass fed from registers and the last pass left in
+// registers: two LDS round trips (and two barriers) fewer.  Item w of the
+// thread is item = tid + w * NT, i.e. transform b and thread-in-transform t
+// as in stockham_pass.  On entry v[w][u * R0 + q] holds element
+// j + q N / R0 of transform b (j = t + u TPR, R0 the first radix); on exit
+// v[w][u * RL + q] holds output element j + q N / RL (RL the last radix).
+// Needs at least two passes; synchronises like lds_fft.
+template <typename T, int N, int NB, int NT, bool INV, bool BFAST, int S, class Addr, int WPT,
+          int EPT>
+__device__ __forceinline__ void lds_fft_regs(cplx<T> (&v)[WPT][EPT], cplx<T>* s,
+                                             const cplx<T>* __restrict__ tw, Addr addr, int tid) {
+  constexpr RadixPlan PL = Radices<N, S>::P;
+  static_assert(PL.np >= 2, "at least two passes");
+  static_assert(EPT == Radices<N, S>::EPT && WPT == lds_fft_items<N, NB, NT, S>(),
+                "register array of the batch split");
+  constexpr int TPR = Radices<N, S>::TPR;
+  constexpr int NW = NB * TPR;
+  constexpr int R0 = PL.r[0];
+  constexpr int RL = PL.r[PL.np - 1];
+  // first pass (span 1: no twiddles), from registers into LDS
+#pragma unroll
+  for (int w = 0; w < WPT; ++w) {
+    const int item = tid + w * NT;
+    if ((NW % NT == 0) || item < NW) {
+      const int b = BFAST ? item % NB : item / TPR;
+      const int t = BFAST ? item / NB : item % TPR;
+#pragma unroll
+      for (int u = 0; u < EPT / R0; ++u) {
+        const int j = t + u * TPR;
+        cplx<T> x[R0];
+#pragma unroll
+        for (int q = 0; q < R0; ++q) x[q] = v[w][u * R0 + q];
+        Dft<T, R0, INV>::run(x);
+#pragma unroll
+        for (int q = 0; q < R0; ++q) s[addr(b, j * R0 + q)] = x[q];
+      }
+    }
+  }
+  __syncthreads();
+  // middle passes in LDS
+  if constexpr (PL.np > 2) stockham_mid<T, N, 1, NB, NT, INV, BFAST, S>(s, tw, addr, tid);
+  // last pass (span N / RL), from LDS into registers
+#pragma unroll
+  for (int w = 0; w < WPT; ++w) {
+    const int item = tid + w * NT;
+    if ((NW % NT == 0) || item < NW) {
+      const int b = BFAST ? item % NB : item / TPR;
+      const int t = BFAST ? item / NB : item % TPR;
+#pragma unroll
+      for (int u = 0; u < EPT / RL; ++u) {
+        const int j = t + u * TPR;  // < N / RL: the butterfly index and its twiddle power
+        cplx<T> x[RL];
+#pragma unroll
+        for (int q = 0; q < RL; ++q) x[q] = s[addr(b, j + q * (N / RL))];
+#pragma unroll
+        for (int q = 1; q < RL; ++q) {
+          cplx<T> wq = tw[q * j];
+          if (INV) wq = conj(wq);
+          x[q] = x[q] * wq;
+        }
+        Dft<T, RL, INV>::run(x);
+#pragma unroll
+        for (int q = 0; q < RL; ++q) v[w][u * RL + q] = x[q];
+      }
+    }
   }
 }
 

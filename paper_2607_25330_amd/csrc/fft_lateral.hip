@@ -269,36 +269,42 @@ k_xfft_inv(const cplx<T>* __restrict__ UW_all, cplx<T>* __restrict__ y_all,
 }
 
 // y pass: problem pb's planes start at pb * stride; grid.y = nprob * nplanes.
+// The tile's columns go straight from the global loads into the first
+// Stockham pass and from the last pass into the global stores (the loads of
+// a thread are the inputs of its first butterflies, its stores the outputs
+// of its last ones; consecutive threads take consecutive columns, so every
+// access covers TX adjacent columns of one row).
 template <typename T, int N, int TX, bool INV, int S>
 __global__ void __launch_bounds__((TX * Radices<N, S>::TPR))
 k_yfft(cplx<T>* __restrict__ buf, const cplx<T>* __restrict__ tw, int nx, int nplanes,
        int64_t stride, const int* __restrict__ skip, int skip_stride) {
   const int pb = blockIdx.y / nplanes;
   if (skip && skip[(int64_t)pb * skip_stride]) return;
-  constexpr int NT = TX * Radices<N, S>::TPR;
+  constexpr RadixPlan PL = Radices<N, S>::P;
+  constexpr int TPR = Radices<N, S>::TPR;
+  constexpr int EPT = Radices<N, S>::EPT;
+  constexpr int NT = TX * TPR;
+  constexpr int R0 = PL.r[0], RL = PL.r[PL.np - 1];
+  static_assert(lds_fft_items<N, TX, NT, S>() == 1, "one item per thread");
   __shared__ cplx<T> s[N * TX];
   __shared__ cplx<T> tws[N];
   const int tid = threadIdx.x;
   const int64_t base = pb * stride + (int64_t)(blockIdx.y % nplanes) * N * nx +
                        (int64_t)blockIdx.x * TX;
   for (int i = tid; i < N; i += NT) tws[i] = tw[i];
-  constexpr int EPT = (N * TX) / NT;
-  static_assert((N * TX) % NT == 0, "tile must split evenly over the block");
-  cplx<T> v[EPT];
+  const int b = tid % TX, t = tid / TX;  // column of the tile, thread within the column
+  cplx<T> v[1][EPT];
 #pragma unroll
-  for (int k = 0; k < EPT; ++k) {
-    const int e = tid + k * NT;
-    v[k] = buf[base + (int64_t)(e / TX) * nx + (e % TX)];
-  }
+  for (int u = 0; u < EPT / R0; ++u)
 #pragma unroll
-  for (int k = 0; k < EPT; ++k) s[tid + k * NT] = v[k];
-  __syncthreads();
-  lds_fft<T, N, TX, NT, INV, true, S>(s, tws, AddrCol<TX>{}, tid);
+    for (int q = 0; q < R0; ++q)
+      v[0][u * R0 + q] = buf[base + (int64_t)(t + u * TPR + q * (N / R0)) * nx + b];
+  lds_fft_regs<T, N, TX, NT, INV, true, S>(v, s, tws, AddrCol<TX>{}, tid);
 #pragma unroll
-  for (int k = 0; k < EPT; ++k) {
-    const int e = tid + k * NT;
-    buf[base + (int64_t)(e / TX) * nx + (e % TX)] = s[e];
-  }
+  for (int u = 0; u < EPT / RL; ++u)
+#pragma unroll
+    for (int q = 0; q < RL; ++q)
+      buf[base + (int64_t)(t + u * TPR + q * (N / RL)) * nx + b] = v[0][u * RL + q];
 }
 
 // ---------------------------------------------------------------- launchers
