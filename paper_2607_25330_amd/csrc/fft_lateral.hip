@@ -121,43 +121,48 @@ k_xfft_fwd(const cplx<T>* __restrict__ in_all, cplx<T>* __restrict__ out_all,
     else return in[idx];
   };
   __syncthreads();
-  // all loads of the block are issued before the first LDS write
-  constexpr int EPT = (B * N) / NT;
-  static_assert((B * N) % NT == 0, "rows must split evenly over the block");
-  cplx<T> val[EPT];
+  // Thread t of row b loads the inputs of its first Stockham butterflies
+  // (elements t + u TPR + q N / R0: consecutive threads, consecutive
+  // elements), applies the fused update to them, and after the last pass
+  // stores its outputs (t + u TPR + q N / RL) straight from registers.
+  constexpr RadixPlan PL = Radices<N, S>::P;
+  constexpr int TPR = Radices<N, S>::TPR;
+  constexpr int EPT = Radices<N, S>::EPT;
+  constexpr int R0 = PL.r[0], RL = PL.r[PL.np - 1];
+  static_assert(lds_fft_items<N, B, NT, S>() == 1, "one item per thread");
+  const int b = tid / TPR, t = tid % TPR;
+  const int64_t src = rsrc[b], kro = rkd[b];
+  cplx<T> v[1][EPT];
 #pragma unroll
-  for (int k = 0; k < EPT; ++k) {
-    const int e = tid + k * NT;
-    const int rr = e / N, xi = e % N;
-    const int64_t src = rsrc[rr];
-    val[k] = {T(0), T(0)};
-    if (src >= 0) {
-      const int64_t kro = rkd[rr];
-      if (kro < 0) val[k] = value(src + xi);
-      else val[k] = cmulc(kd[kro + xi], value(src + xi));
+  for (int u = 0; u < EPT / R0; ++u)
+#pragma unroll
+    for (int q = 0; q < R0; ++q) {
+      const int xi = t + u * TPR + q * (N / R0);
+      cplx<T> val = {T(0), T(0)};
+      if (src >= 0) val = kro < 0 ? value(src + xi) : cmulc(kd[kro + xi], value(src + xi));
+      v[0][u * R0 + q] = val;
     }
-  }
   double acc[1] = {0.0};
+  if constexpr (PRE != PRE_NONE) {
+    if (src >= 0 && kro < 0) {
 #pragma unroll
-  for (int k = 0; k < EPT; ++k) {
-    const int e = tid + k * NT;
-    const int rr = e / N, xi = e % N;
-    if constexpr (PRE != PRE_NONE) {
-      const int64_t src = rsrc[rr];
-      if (src >= 0 && rkd[rr] < 0) {
-        pre.pv[vo + src + xi] = val[k];
-        if constexpr (PRE == PRE_S) acc[0] += norm2(cast<double>(val[k]));
-      }
+      for (int u = 0; u < EPT / R0; ++u)
+#pragma unroll
+        for (int q = 0; q < R0; ++q) {
+          const int xi = t + u * TPR + q * (N / R0);
+          pre.pv[vo + src + xi] = v[0][u * R0 + q];
+          if constexpr (PRE == PRE_S) acc[0] += norm2(cast<double>(v[0][u * R0 + q]));
+        }
     }
-    s[Addr{}(rr, xi)] = val[k];
   }
   if constexpr (PRE == PRE_S) block_partials<1, NT>(acc, pre.part);
-  __syncthreads();
-  lds_fft<T, N, B, NT, false, false, S>(s, tws, Addr{}, tid);
-  for (int e = tid; e < B * N; e += NT) {
-    const int rr = e / N;
-    const int64_t row = row0 + rr;
-    if (row < g.ntot) out[row * N + (e % N)] = s[Addr{}(rr, e % N)];
+  lds_fft_regs<T, N, B, NT, false, false, S>(v, s, tws, Addr{}, tid);
+  const int64_t row = row0 + b;
+  if (row < g.ntot) {
+#pragma unroll
+    for (int u = 0; u < EPT / RL; ++u)
+#pragma unroll
+      for (int q = 0; q < RL; ++q) out[row * N + t + u * TPR + q * (N / RL)] = v[0][u * RL + q];
   }
 }
 
@@ -199,71 +204,71 @@ k_xfft_inv(const cplx<T>* __restrict__ UW_all, cplx<T>* __restrict__ y_all,
     rkd[tid] = ko;
   }
   __syncthreads();
-  // Every global operand of the block is requested before the first barrier:
-  // the U / W rows, and for the epilogue kd, x (adjoint) and the dot partner d,
-  // so that their latency overlaps instead of being paid again after the FFT.
-  constexpr int EPT = (B * N) / NT;
-  static_assert((B * N) % NT == 0, "rows must split evenly over the block");
-  cplx<T> ru[EPT], rwv[EPT], rkv[EPT], rxv[EPT], rdv[EPT];
+  // Thread t of row b loads the inputs of its first Stockham butterflies of
+  // the U row (and of the W row, the block's second batch of B rows: the
+  // same thread runs both), requests the epilogue operands (kd, x for the
+  // adjoint, the dot partner d) of the elements its last butterflies will
+  // produce, and combines and stores those outputs from registers.
+  constexpr RadixPlan PL = Radices<N, S>::P;
+  constexpr int TPR = Radices<N, S>::TPR;
+  constexpr int EPT = Radices<N, S>::EPT;
+  constexpr int R0 = PL.r[0], RL = PL.r[PL.np - 1];
+  static_assert(lds_fft_items<N, NBUF * B, NT, S>() == NBUF, "one item per row batch");
+  const int b = tid / TPR, t = tid % TPR;
+  const int64_t row = row0 + b;
+  const bool live = row < nrows;
+  const int64_t wo = rw[b], ko = rkd[b];
+  const cplx<T> z0 = {T(0), T(0)};
+  cplx<T> v[NBUF][EPT];
 #pragma unroll
-  for (int k = 0; k < EPT; ++k) {
-    const int e = tid + k * NT;
-    const int rr = e / N, xi = e % N;
-    const int64_t row = row0 + rr;
-    const int64_t idx = row * N + xi;
-    const cplx<T> z0 = {T(0), T(0)};
-    ru[k] = z0;
-    rwv[k] = z0;
-    rkv[k] = z0;
-    rxv[k] = z0;
-    rdv[k] = z0;
-    if (row < nrows) {
-      ru[k] = UW[idx];
-      if (CM == CB_FWD) {
-        const int64_t wo = rw[rr];
-        if (wo >= 0) rwv[k] = UW[wo + xi];
-      }
-      if (CM != CB_PLAIN) {
-        const int64_t ko = rkd[rr];
-        if (ko >= 0) {
-          rkv[k] = kd[ko + xi];
+  for (int u = 0; u < EPT / R0; ++u)
+#pragma unroll
+    for (int q = 0; q < R0; ++q) {
+      const int xi = t + u * TPR + q * (N / R0);
+      v[0][u * R0 + q] = live ? UW[row * N + xi] : z0;
+      if constexpr (CM == CB_FWD) v[NBUF - 1][u * R0 + q] = (live && wo >= 0) ? UW[wo + xi] : z0;
+    }
+  cplx<T> rkv[EPT], rxv[EPT], rdv[EPT];
+#pragma unroll
+  for (int u = 0; u < EPT / RL; ++u)
+#pragma unroll
+    for (int q = 0; q < RL; ++q) {
+      const int k = u * RL + q;
+      const int xo = t + u * TPR + q * (N / RL);
+      const int64_t idx = row * N + xo;
+      rkv[k] = z0;
+      rxv[k] = z0;
+      rdv[k] = z0;
+      if (live) {
+        if (CM != CB_PLAIN && ko >= 0) {
+          rkv[k] = kd[ko + xo];
           if (CM == CB_ADJ) rxv[k] = x_all[fo + idx];
         }
+        if constexpr (POST == POST_DOT) rdv[k] = post.d[fo + idx];
       }
-      if constexpr (POST == POST_DOT) rdv[k] = post.d[fo + idx];
     }
-  }
-#pragma unroll
-  for (int k = 0; k < EPT; ++k) {
-    const int e = tid + k * NT;
-    const int rr = e / N, xi = e % N;
-    s[Addr{}(rr, xi)] = ru[k];
-    if (CM == CB_FWD) s[Addr{}(B + rr, xi)] = rwv[k];
-  }
-  __syncthreads();
-  lds_fft<T, N, NBUF * B, NT, true, false, S>(s, tws, Addr{}, tid);
+  lds_fft_regs<T, N, NBUF * B, NT, true, false, S>(v, s, tws, Addr{}, tid);
   double acc[3] = {0.0, 0.0, 0.0};
+  if (live) {
 #pragma unroll
-  for (int k = 0; k < EPT; ++k) {
-    const int e = tid + k * NT;
-    const int rr = e / N, xi = e % N;
-    const int64_t row = row0 + rr;
-    if (row >= nrows) continue;
-    const int64_t idx = row * N + xi;
-    cplx<T> o = scale * s[Addr{}(rr, xi)];
-    if (CM != CB_PLAIN) {
-      if (rkd[rr] >= 0) {
-        if (CM == CB_FWD) o = o - scale * (rkv[k] * s[Addr{}(B + rr, xi)]);
-        else o = o - cmulc(rkv[k], rxv[k]);
+    for (int u = 0; u < EPT / RL; ++u)
+#pragma unroll
+      for (int q = 0; q < RL; ++q) {
+        const int k = u * RL + q;
+        const int64_t idx = row * N + t + u * TPR + q * (N / RL);
+        cplx<T> o = scale * v[0][k];
+        if (CM != CB_PLAIN && ko >= 0) {
+          if (CM == CB_FWD) o = o - scale * (rkv[k] * v[NBUF - 1][k]);
+          else o = o - cmulc(rkv[k], rxv[k]);
+        }
+        y[idx] = o;
+        if constexpr (POST == POST_DOT) {
+          const cplx<double> a = cast<double>(rdv[k]), bb = cast<double>(o);
+          acc[0] += a.re * bb.re + a.im * bb.im;
+          acc[1] += a.re * bb.im - a.im * bb.re;
+          acc[2] += bb.re * bb.re + bb.im * bb.im;
+        }
       }
-    }
-    y[idx] = o;
-    if constexpr (POST == POST_DOT) {
-      const cplx<double> a = cast<double>(rdv[k]), b = cast<double>(o);
-      acc[0] += a.re * b.re + a.im * b.im;
-      acc[1] += a.re * b.im - a.im * b.re;
-      acc[2] += b.re * b.re + b.im * b.im;
-    }
   }
   if constexpr (POST == POST_DOT) block_partials<3, NT>(acc, post.part);
 }
