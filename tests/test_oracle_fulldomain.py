@@ -168,3 +168,38 @@ def test_full_domain_3d_equals_1d():
     E3 = np.linalg.solve(A, R.rhs(P).ravel()).reshape(P.g.shape)
     E1 = _solve_1d(P)[:, :, 0, 0]
     assert np.abs(E3 - E1[:, :, None, None]).max() < 1e-12 * np.abs(E1).max()
+
+
+def _golden_angles():
+    vals = {}
+    path = __file__.rsplit("/", 1)[0] + "/golden/representable_angles.txt"
+    with open(path) as f:
+        for line in f:
+            line = line.split("#", 1)[0].split()
+            if line:
+                vals[line[0]] = [float(v) for v in line[1:]]
+    return vals
+
+
+@pytest.mark.parametrize("dx", [1.0, 0.5])
+def test_grid_represents_the_printed_incidence_angles(dx):
+    """The lateral wavenumbers of a 150 nm cell give exactly the incidence
+    angles the paper prints for its bare-multilayer comparison, and the
+    oracle's Bloch shift puts each of them on a grid order."""
+    gold = _golden_angles()
+    assert dx in gold["dx_nm"]
+    lam, (lo, hi), printed = gold["lambda_nm"][0], gold["range_deg"], gold["theta_deg"]
+    nx = int(round(150.0 / dx))
+    g = R.Grid(full_domain_config(dx, 0.0, 0, nx=nx))
+    assert abs(g.k0 - 2 * np.pi / lam) < 1e-15
+    kx = np.sort(g.kx[(g.kx >= 0) & (g.kx <= g.k0 * np.sin(np.radians(hi)))])
+    got = np.degrees(np.arcsin(kx / g.k0))
+    assert got[0] >= lo and len(got) == len(printed)
+    assert np.all(np.abs(np.round(got, 2) - printed) < 1e-9), (got, printed)
+    dk = 2 * np.pi / (nx * dx)
+    for m, th in enumerate(printed):
+        gt = R.Grid(full_domain_config(dx, th, 0, nx=nx))
+        # the printed two decimals put k0 sin(theta) within 2e-3 of order m
+        assert abs(gt.kx0 / dk - m) < 2e-3
+        assert abs(gt.kx[0] - gt.kx0) == 0.0 and abs(gt.ky0) == 0.0
+    assert np.allclose(FULL_DOMAIN_THETAS_DEG, printed, atol=5e-3)
