@@ -886,7 +886,7 @@ def main():
     ok_m = all(i["status"] == "OK" and i["rrel"] <= args.tol for i in infos_m)
     value = nsolve / t_mixed
     it_m = max(1, sum(i["iters"] for i in infos_m))
-    # SURVEY-defined algorithmic bytes: one complex64 A.M apply moves 48 B per voxel
+    # algorithmic bytes: one complex64 A.M apply moves 48 B per voxel
     # (read x, write y: 3 components x 8 B each way); one BiCGSTAB iteration 480 B.
     alg_apply = 48.0 * vox
     alg_iter = 480.0 * vox
